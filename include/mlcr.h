@@ -1,0 +1,132 @@
+/*
+ * mlcr.h -- C ABI of the multi-level constrained-realization (CR) library
+ * for AMD MI355X (gfx950).
+ *
+ * The library applies the CR system operator of Seljebotn, Mardal, Jewell,
+ * Eriksen & Bull (2013), "A multi-level solver for Gaussian constrained CMB
+ * realizations":
+ *
+ *     A   = S^-1 + B Y^T N^-1 Y B                 (Sec. 2.3, eq. system-explicit)
+ *     A_h = D_h + B_h Y^T N^-1 Y B_h              (Sec. 3.2, eq. A_h)
+ *
+ * and solves A x = b with the multi-level cycle of Fig. code:mg.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Harmonic vectors are "real packed, m-major", float64, length
+ *   (lmax+1)^2 per right-hand side: first x_l0 for l = 0..lmax, then for
+ *   m = 1..lmax a cosine block (l = m..lmax) followed by a sine block
+ *   (l = m..lmax).  The basis is real and orthonormal on the sphere:
+ *       f = sum_l x_l0 L_l0 + sum_{m>=1} sqrt(2) L_lm (x^c_lm cos m phi + x^s_lm sin m phi),
+ *   L_lm the normalized associated Legendre function of Sec. 3.2 (the
+ *   formula beside eq. Ni-dense), Condon-Shortley phase included.
+ * - Maps are float64 HEALPix RING order (Gorski et al. 2005; Sec. 2.1),
+ *   12 nside^2 pixels per right-hand side.
+ * - Batches are contiguous: right-hand side r starts at r * (lmax+1)^2
+ *   (harmonic) or r * 12 nside^2 (pixel).
+ * - Pointers named dev_* are device pointers owned by the caller (maps and
+ *   N^-1 must be 16-byte aligned, as every torch/hipMalloc allocation is); the
+ *   library never frees them.  Pointers named host_* are host memory read
+ *   during the call only.  `stream` is a hipStream_t (NULL = default
+ *   stream); all device work of a call is enqueued on it.
+ * - prec selects the arithmetic of the Legendre contraction only
+ *   (MLCR_FP64 or MLCR_FP32); inputs/outputs are always float64.
+ * - Return value: 0 on success, a negative MLCR_E* code otherwise; a
+ *   description is available from mlcr_last_error() (thread-local).
+ *   Argument errors are detected before any device work is enqueued.
+ */
+#ifndef MLCR_H
+#define MLCR_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MLCR_OK = 0,
+    MLCR_EINVAL = -1,       /* bad argument (null pointer, size out of range, ...) */
+    MLCR_ENOMEM = -2,       /* device or host allocation failed                    */
+    MLCR_EHIP = -3,         /* HIP runtime error                                   */
+    MLCR_ENOTPD = -4,       /* Cholesky of a matrix that is not positive definite  */
+    MLCR_ENOCONV = -5,      /* solver did not reach the tolerance                  */
+    MLCR_EUNSUPPORTED = -6  /* valid request this build does not implement        */
+};
+
+enum { MLCR_FP64 = 0, MLCR_FP32 = 1 };
+
+typedef struct mlcr_geom mlcr_geom;
+typedef struct mlcr_op mlcr_op;
+typedef struct mlcr_solver mlcr_solver;
+
+/* Thread-local text of the last error of this thread ("" if none). */
+const char *mlcr_last_error(void);
+
+/* Library version string. */
+const char *mlcr_version(void);
+
+/* ------------------------------------------------------------------------
+ * Geometry: HEALPix RING grid of resolution nside (Sec. 2.1) together with
+ * the tables of the Legendre recurrence up to lmax and of the per-ring
+ * FFTs.  1 <= nside <= 2048 (a power of two is not required; the largest
+ * ring FFT must fit in one workgroup's LDS);
+ * 0 <= lmax <= 16384.  Allocates device memory for the tables
+ * (about 16 (lmax+1)^2 / 2 + 48 * 12 nside^2 bytes) and a workspace that
+ * grows on demand.  The handle may be used from one host thread at a time.
+ * ---------------------------------------------------------------------- */
+int mlcr_geom_create(int nside, int lmax, mlcr_geom **out);
+void mlcr_geom_destroy(mlcr_geom *g);
+/* nside, lmax, pixel count and ring count of a geometry; any out pointer may be NULL. */
+int mlcr_geom_info(const mlcr_geom *g, int *nside, int *lmax, long long *npix, int *nrings);
+
+/* Spherical harmonic synthesis map = Y alm (Sec. 2.1, eq. sh-synthesis),
+ * evaluated exactly at the pixel centres (no quadrature, any lmax <= the
+ * geometry's lmax, including lmax > 3 nside).
+ *   dev_alm: [nrhs][(lmax+1)^2] float64;  dev_map: [nrhs][12 nside^2] float64.
+ * nrhs >= 1.  EINVAL on null pointers or lmax out of range. */
+int sht_synth(mlcr_geom *g, int lmax, int nrhs, const double *dev_alm, double *dev_map,
+              int prec, void *stream);
+
+/* Adjoint synthesis alm = Y^T map (Sec. 2.1: the transpose of Y, with no
+ * quadrature weights; used in place of analysis throughout the method).
+ * Same layouts as sht_synth. */
+int sht_adjoint(mlcr_geom *g, int lmax, int nrhs, const double *dev_map, double *dev_alm,
+                int prec, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Operator A = S^-1 + B Y^T N^-1 Y B on the observation grid g
+ * (Sec. 2.3, eq. system-explicit).
+ *   host_cl[lmax+1]:  prior power spectrum C_l >= 0; C_l = 0 removes all
+ *                     modes of that l from the unknowns (their inputs are
+ *                     ignored and their outputs are 0).
+ *   host_bl[lmax+1]:  beam times pixel window b_l p_l (Sec. 2.2).
+ *   dev_ninv[12 nside^2]: inverse noise variance per pixel, 0 in the mask
+ *                     (Sec. 2.3), must stay valid while the operator lives.
+ *   lmax: band limit of the unknowns (<= the geometry's lmax).
+ *   max_nrhs: largest batch later passed to apply_A / wcycle_solve.
+ * The operator keeps a reference to g (which must outlive it) and copies
+ * host_cl and host_bl.  EINVAL on negative C_l or sizes out of range. */
+int mlcr_op_create(mlcr_geom *g, int lmax, const double *host_cl, const double *host_bl,
+                   const double *dev_ninv, int max_nrhs, mlcr_op **out);
+void mlcr_op_destroy(mlcr_op *op);
+
+/* y = A_h x for a batch (Sec. 3.2, eq. A_h).  level 0 is the top level
+ * (f_l = 1, so A_0 = A); level h >= 1 exists after mlcr_op_set_level().
+ *   dev_x, dev_y: [nrhs][(lmax_h+1)^2] float64 packed vectors (x != y).
+ * 1 <= nrhs <= max_nrhs. */
+int apply_A(mlcr_op *op, int level, int nrhs, const double *dev_x, double *dev_y,
+            int prec, void *stream);
+
+/* Define level h >= 1 of the operator: band limit lmax_h and the
+ * cumulative low-pass filter f^h_l (host_fl[lmax_h+1], f^h_l = 0 allowed),
+ * so that A_h = D_h + B_h Y^T N^-1 Y B_h with D_h = diag(f^2 / C_l) and
+ * B_h = diag(f b_l p_l) (Sec. 3.2, eq. A_h).  1 <= h < 16. */
+int mlcr_op_set_level(mlcr_op *op, int h, int lmax_h, const double *host_fl);
+
+/* Band limit of level h (0 = top), or a negative error code. */
+int mlcr_op_level_lmax(const mlcr_op *op, int h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLCR_H */

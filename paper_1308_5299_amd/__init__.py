@@ -1,0 +1,12 @@
+"""MI355X-native multi-level constrained-realization solver.
+
+Hot path of Seljebotn et al. (2013): applying A = S^-1 + B Y^T N^-1 Y B and
+its level operators on HEALPix RING grids with hand-written gfx950 HIP
+kernels behind a C ABI (include/mlcr.h).  This package is a thin binding:
+torch supplies device memory and streams, every step runs in libmlcr.so.
+"""
+from ._lib import MLCRError, load as load_library  # noqa: F401
+from .api import FP32, FP64, Geometry, Operator, apply_A, sht_adjoint, sht_synth  # noqa: F401
+
+__all__ = ["MLCRError", "load_library", "FP32", "FP64", "Geometry", "Operator",
+           "apply_A", "sht_adjoint", "sht_synth"]

@@ -1,0 +1,63 @@
+"""ctypes binding of libmlcr.so (argument marshalling only).
+
+Loading fails loudly if the library has not been built: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmlcr.so")
+
+c_int, c_ll, c_dbl_p, c_void_p = ctypes.c_int, ctypes.c_longlong, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "mlcr_last_error": (ctypes.c_char_p, []),
+    "mlcr_version": (ctypes.c_char_p, []),
+    "mlcr_geom_create": (c_int, [c_int, c_int, ctypes.POINTER(c_void_p)]),
+    "mlcr_geom_destroy": (None, [c_void_p]),
+    "mlcr_geom_info": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                               ctypes.POINTER(c_ll), ctypes.POINTER(c_int)]),
+    "sht_synth": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_int, c_void_p]),
+    "sht_adjoint": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_int, c_void_p]),
+    "mlcr_op_create": (c_int, [c_void_p, c_int, c_dbl_p, c_dbl_p, c_void_p, c_int,
+                               ctypes.POINTER(c_void_p)]),
+    "mlcr_op_destroy": (None, [c_void_p]),
+    "mlcr_op_set_level": (c_int, [c_void_p, c_int, c_int, c_dbl_p]),
+    "mlcr_op_level_lmax": (c_int, [c_void_p, c_int]),
+    "apply_A": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_int, c_void_p]),
+}
+
+_lib = None
+
+
+class MLCRError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mlcr error {code}: {msg}")
+        self.code = code
+
+
+def load() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_1308_5299_amd.build` "
+            "(or __graft_entry__.build()); there is no non-HIP fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(rc: int) -> None:
+    if rc != 0:
+        msg = load().mlcr_last_error().decode()
+        raise MLCRError(rc, msg)

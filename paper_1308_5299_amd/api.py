@@ -1,0 +1,154 @@
+"""Python front end of the C ABI (include/mlcr.h).
+
+Tensors are float64 CUDA (HIP) tensors: harmonic vectors [nrhs, (lmax+1)^2]
+in real packed m-major order, maps [nrhs, 12 nside^2] in RING order.  Work
+is enqueued on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from ._lib import check, load
+
+FP64 = 0
+FP32 = 1
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _batch(t: torch.Tensor, per: int, name: str) -> int:
+    if t.numel() % per != 0 or t.numel() == 0:
+        raise ValueError(f"{name} has {t.numel()} elements, not a positive multiple of {per}")
+    return t.numel() // per
+
+
+class Geometry:
+    """HEALPix RING grid plus Legendre and FFT tables up to lmax."""
+
+    def __init__(self, nside: int, lmax: int):
+        lib = load()
+        h = ctypes.c_void_p()
+        check(lib.mlcr_geom_create(int(nside), int(lmax), ctypes.byref(h)))
+        self._h = h
+        self.nside = int(nside)
+        self.lmax = int(lmax)
+        self.npix = 12 * self.nside * self.nside
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().mlcr_geom_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def nalm(lmax: int) -> int:
+    return (lmax + 1) ** 2
+
+
+def sht_synth(geom: Geometry, alm: torch.Tensor, lmax: int | None = None, prec: int = FP64,
+              out: torch.Tensor | None = None) -> torch.Tensor:
+    lmax = geom.lmax if lmax is None else int(lmax)
+    _dev(alm, "alm")
+    nrhs = _batch(alm, nalm(lmax), "alm")
+    if out is None:
+        out = torch.empty((nrhs, geom.npix), dtype=torch.float64, device=alm.device)
+    _dev(out, "out")
+    check(load().sht_synth(geom.handle, lmax, nrhs, ctypes.c_void_p(alm.data_ptr()),
+                           ctypes.c_void_p(out.data_ptr()), prec, _stream()))
+    return out
+
+
+def sht_adjoint(geom: Geometry, maps: torch.Tensor, lmax: int | None = None, prec: int = FP64,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+    lmax = geom.lmax if lmax is None else int(lmax)
+    _dev(maps, "maps")
+    nrhs = _batch(maps, geom.npix, "maps")
+    if out is None:
+        out = torch.empty((nrhs, nalm(lmax)), dtype=torch.float64, device=maps.device)
+    _dev(out, "out")
+    check(load().sht_adjoint(geom.handle, lmax, nrhs, ctypes.c_void_p(maps.data_ptr()),
+                             ctypes.c_void_p(out.data_ptr()), prec, _stream()))
+    return out
+
+
+class Operator:
+    """A = S^-1 + B Y^T N^-1 Y B on the observation geometry (plus levels)."""
+
+    def __init__(self, geom: Geometry, cl, bl, ninv: torch.Tensor, max_nrhs: int = 1,
+                 lmax: int | None = None):
+        lib = load()
+        self.geom = geom
+        self.lmax = geom.lmax if lmax is None else int(lmax)
+        cl = np.ascontiguousarray(np.asarray(cl, dtype=np.float64)[: self.lmax + 1])
+        bl = np.ascontiguousarray(np.asarray(bl, dtype=np.float64)[: self.lmax + 1])
+        if cl.size != self.lmax + 1 or bl.size != self.lmax + 1:
+            raise ValueError("cl and bl need lmax+1 entries")
+        self.ninv = _dev(ninv, "ninv")
+        if ninv.numel() != geom.npix:
+            raise ValueError("ninv must have 12 nside^2 entries")
+        self.cl, self.bl = cl, bl
+        self.max_nrhs = int(max_nrhs)
+        h = ctypes.c_void_p()
+        dp = ctypes.POINTER(ctypes.c_double)
+        check(lib.mlcr_op_create(geom.handle, self.lmax, cl.ctypes.data_as(dp), bl.ctypes.data_as(dp),
+                                 ctypes.c_void_p(ninv.data_ptr()), self.max_nrhs, ctypes.byref(h)))
+        self._h = h
+        self.level_lmax = {0: self.lmax}
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_level(self, h: int, lmax_h: int, fl) -> None:
+        fl = np.ascontiguousarray(np.asarray(fl, dtype=np.float64)[: lmax_h + 1])
+        check(load().mlcr_op_set_level(self._h, int(h), int(lmax_h),
+                                       fl.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        self.level_lmax[int(h)] = int(lmax_h)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().mlcr_op_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def apply_A(op: Operator, x: torch.Tensor, level: int = 0, prec: int = FP64,
+            out: torch.Tensor | None = None) -> torch.Tensor:
+    lmax = op.level_lmax[level]
+    _dev(x, "x")
+    nrhs = _batch(x, nalm(lmax), "x")
+    if out is None:
+        out = torch.empty((nrhs, nalm(lmax)), dtype=torch.float64, device=x.device)
+    _dev(out, "out")
+    check(load().apply_A(op.handle, int(level), nrhs, ctypes.c_void_p(x.data_ptr()),
+                         ctypes.c_void_p(out.data_ptr()), prec, _stream()))
+    return out

@@ -1,0 +1,266 @@
+// C ABI: handles, argument checks and the sequence of launches of each
+// entry point.  Every step of the computation runs in the library's HIP
+// kernels; this file only validates, sizes workspaces and enqueues.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "mlcr_internal.h"
+
+namespace mlcr {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int DevBuf::reserve(size_t nbytes) {
+    if (nbytes <= bytes && ptr) return MLCR_OK;
+    if (ptr) {
+        // a previous launch may still read the old buffer
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ptr);
+    }
+    ptr = nullptr;
+    bytes = 0;
+    if (nbytes == 0) nbytes = 16;
+    if (hipMalloc(&ptr, nbytes) != hipSuccess) {
+        ptr = nullptr;
+        return MLCR_ENOMEM;
+    }
+    bytes = nbytes;
+    return MLCR_OK;
+}
+
+void DevBuf::release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+static void release_geom(mlcr_geom *g) {
+    DevBuf *bufs[] = {&g->ring_z, &g->ring_s, &g->rings, &g->lens, &g->order, &g->T, &g->Bf,
+                      &g->W, &g->ab, &g->aboff, &g->seed, &g->zeros, &g->wsF, &g->wsP, &g->wsU};
+    for (DevBuf *b : bufs) b->release();
+}
+
+// Pixel kernels read maps and N^-1 ring by ring as 16-byte pairs.
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+static long long nalm_of(int lmax) { return (long long)(lmax + 1) * (lmax + 1); }
+
+// Workspaces of one transform of nrhs right-hand sides at band limit lmax.
+static int reserve_ws(mlcr_geom *g, int lmax, int nrhs, bool need_u) {
+    const size_t fbytes = (size_t)nrhs * g->nrings * (lmax + 1) * sizeof(double2);
+    const size_t pbytes = (size_t)adjoint_chunks(g, lmax) * nrhs * nalm_of(lmax) * sizeof(double);
+    if (g->wsF.reserve(fbytes)) return fail(MLCR_ENOMEM, "workspace allocation failed (F)");
+    if (g->wsP.reserve(pbytes)) return fail(MLCR_ENOMEM, "workspace allocation failed (P)");
+    if (need_u && g->wsU.reserve((size_t)nrhs * nalm_of(lmax) * sizeof(double)))
+        return fail(MLCR_ENOMEM, "workspace allocation failed (U)");
+    return MLCR_OK;
+}
+
+static int check_prec(int prec) {
+    if (prec == MLCR_FP64) return MLCR_OK;
+    if (prec == MLCR_FP32) return fail(MLCR_EUNSUPPORTED, "MLCR_FP32 is not available in this build");
+    return fail(MLCR_EINVAL, "unknown precision");
+}
+
+}  // namespace mlcr
+
+using namespace mlcr;
+
+extern "C" {
+
+const char *mlcr_last_error(void) { return g_err.c_str(); }
+const char *mlcr_version(void) { return "mlcr 0.1 (gfx950)"; }
+
+int mlcr_geom_create(int nside, int lmax, mlcr_geom **out) {
+    if (!out) return fail(MLCR_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nside < 1 || nside > 2048)
+        return fail(MLCR_EINVAL, "nside must be in [1, 2048] (ring FFT buffers must fit in LDS)");
+    if (lmax < 0 || lmax > 16384) return fail(MLCR_EINVAL, "lmax must be in [0, 16384]");
+    mlcr_geom *g = new (std::nothrow) mlcr_geom();
+    if (!g) return fail(MLCR_ENOMEM, "host allocation failed");
+    int rc = build_geometry(g, nside, lmax);
+    if (rc) {
+        release_geom(g);
+        delete g;
+        return rc;
+    }
+    *out = g;
+    g_err.clear();
+    return MLCR_OK;
+}
+
+void mlcr_geom_destroy(mlcr_geom *g) {
+    if (!g) return;
+    (void)hipDeviceSynchronize();
+    release_geom(g);
+    delete g;
+}
+
+int mlcr_geom_info(const mlcr_geom *g, int *nside, int *lmax, long long *npix, int *nrings) {
+    if (!g) return fail(MLCR_EINVAL, "geometry is NULL");
+    if (nside) *nside = g->nside;
+    if (lmax) *lmax = g->lmax;
+    if (npix) *npix = g->npix;
+    if (nrings) *nrings = g->nrings;
+    return MLCR_OK;
+}
+
+int sht_synth(mlcr_geom *g, int lmax, int nrhs, const double *alm, double *map, int prec,
+              void *stream) {
+    if (!g || !alm || !map) return fail(MLCR_EINVAL, "NULL argument");
+    if (!aligned16(map)) return fail(MLCR_EINVAL, "map must be 16-byte aligned");
+    if (lmax < 0 || lmax > g->lmax) return fail(MLCR_EINVAL, "lmax exceeds the geometry's lmax");
+    if (nrhs < 1) return fail(MLCR_EINVAL, "nrhs must be >= 1");
+    int rc;
+    if ((rc = check_prec(prec))) return rc;
+    if ((rc = reserve_ws(g, lmax, nrhs, false))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    LegendreArgs a{g, lmax, nrhs, s};
+    double2 *F = g->wsF.as<double2>();
+    if ((rc = launch_legendre_synth(a, alm, F))) return rc;
+    if ((rc = launch_ring_synth(g, lmax, nrhs, F, map, s))) return rc;
+    return MLCR_OK;
+}
+
+int sht_adjoint(mlcr_geom *g, int lmax, int nrhs, const double *map, double *alm, int prec,
+                void *stream) {
+    if (!g || !alm || !map) return fail(MLCR_EINVAL, "NULL argument");
+    if (!aligned16(map)) return fail(MLCR_EINVAL, "map must be 16-byte aligned");
+    if (lmax < 0 || lmax > g->lmax) return fail(MLCR_EINVAL, "lmax exceeds the geometry's lmax");
+    if (nrhs < 1) return fail(MLCR_EINVAL, "nrhs must be >= 1");
+    int rc;
+    if ((rc = check_prec(prec))) return rc;
+    if ((rc = reserve_ws(g, lmax, nrhs, false))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    LegendreArgs a{g, lmax, nrhs, s};
+    double2 *G = g->wsF.as<double2>();
+    double *P = g->wsP.as<double>();
+    int nch = 0;
+    if ((rc = launch_ring_adjoint(g, lmax, nrhs, map, G, s))) return rc;
+    if ((rc = launch_legendre_adjoint(a, G, P, &nch))) return rc;
+    if ((rc = launch_reduce_epilogue(lmax, nrhs, nch, P, nullptr, nullptr, nullptr, alm, s)))
+        return rc;
+    return MLCR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// operator
+// ---------------------------------------------------------------------------
+static int upload_level(mlcr_level &L, int lmax_h, const std::vector<double> &cl,
+                        const std::vector<double> &bl, const double *fl) {
+    std::vector<double> d(lmax_h + 1), bh(lmax_h + 1);
+    for (int l = 0; l <= lmax_h; l++) {
+        const double f = fl ? fl[l] : 1.0;
+        if (cl[l] > 0.0) {
+            d[l] = f * f / cl[l];
+            bh[l] = f * bl[l];
+        } else {
+            d[l] = 0.0;
+            bh[l] = 0.0;
+        }
+    }
+    if (L.d.reserve(d.size() * sizeof(double)) || L.bh.reserve(bh.size() * sizeof(double)))
+        return fail(MLCR_ENOMEM, "level table allocation failed");
+    MLCR_HIP_CHECK(hipMemcpy(L.d.ptr, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice));
+    MLCR_HIP_CHECK(hipMemcpy(L.bh.ptr, bh.data(), bh.size() * sizeof(double), hipMemcpyHostToDevice));
+    L.lmax = lmax_h;
+    return MLCR_OK;
+}
+
+int mlcr_op_create(mlcr_geom *g, int lmax, const double *cl, const double *bl, const double *ninv,
+                   int max_nrhs, mlcr_op **out) {
+    if (!out) return fail(MLCR_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!g || !cl || !bl || !ninv) return fail(MLCR_EINVAL, "NULL argument");
+    if (!aligned16(ninv)) return fail(MLCR_EINVAL, "ninv must be 16-byte aligned");
+    if (lmax < 0 || lmax > g->lmax) return fail(MLCR_EINVAL, "lmax exceeds the geometry's lmax");
+    if (max_nrhs < 1) return fail(MLCR_EINVAL, "max_nrhs must be >= 1");
+    for (int l = 0; l <= lmax; l++) {
+        if (!(cl[l] >= 0.0) || !std::isfinite(cl[l]))
+            return fail(MLCR_EINVAL, "C_l must be finite and >= 0");
+        if (!std::isfinite(bl[l])) return fail(MLCR_EINVAL, "b_l must be finite");
+    }
+    mlcr_op *op = new (std::nothrow) mlcr_op();
+    if (!op) return fail(MLCR_ENOMEM, "host allocation failed");
+    op->g = g;
+    op->lmax = lmax;
+    op->max_nrhs = max_nrhs;
+    op->ninv = ninv;
+    op->cl.assign(cl, cl + lmax + 1);
+    op->bl.assign(bl, bl + lmax + 1);
+    int rc = upload_level(op->levels[0], lmax, op->cl, op->bl, nullptr);
+    if (!rc) rc = reserve_ws(g, lmax, max_nrhs, true);
+    if (rc) {
+        mlcr_op_destroy(op);
+        return rc;
+    }
+    *out = op;
+    return MLCR_OK;
+}
+
+void mlcr_op_destroy(mlcr_op *op) {
+    if (!op) return;
+    (void)hipDeviceSynchronize();
+    for (auto &L : op->levels) {
+        L.d.release();
+        L.bh.release();
+    }
+    delete op;
+}
+
+int mlcr_op_set_level(mlcr_op *op, int h, int lmax_h, const double *fl) {
+    if (!op || !fl) return fail(MLCR_EINVAL, "NULL argument");
+    if (h < 1 || h >= 16) return fail(MLCR_EINVAL, "level index must be in [1, 15]");
+    if (lmax_h < 0 || lmax_h > op->lmax) return fail(MLCR_EINVAL, "lmax_h out of range");
+    for (int l = 0; l <= lmax_h; l++)
+        if (!std::isfinite(fl[l])) return fail(MLCR_EINVAL, "filter must be finite");
+    return upload_level(op->levels[h], lmax_h, op->cl, op->bl, fl);
+}
+
+int mlcr_op_level_lmax(const mlcr_op *op, int h) {
+    if (!op || h < 0 || h >= 16) return fail(MLCR_EINVAL, "bad operator or level");
+    if (op->levels[h].lmax < 0) return fail(MLCR_EINVAL, "level not defined");
+    return op->levels[h].lmax;
+}
+
+int apply_A(mlcr_op *op, int level, int nrhs, const double *x, double *y, int prec, void *stream) {
+    if (!op || !x || !y) return fail(MLCR_EINVAL, "NULL argument");
+    if (x == y) return fail(MLCR_EINVAL, "x and y must not alias");
+    if (level < 0 || level >= 16 || op->levels[level].lmax < 0)
+        return fail(MLCR_EINVAL, "level not defined");
+    if (nrhs < 1 || nrhs > op->max_nrhs) return fail(MLCR_EINVAL, "nrhs out of [1, max_nrhs]");
+    int rc;
+    if ((rc = check_prec(prec))) return rc;
+    mlcr_geom *g = op->g;
+    const mlcr_level &L = op->levels[level];
+    const int lmax = L.lmax;
+    if ((rc = reserve_ws(g, lmax, nrhs, true))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    double *u = g->wsU.as<double>();
+    double2 *F = g->wsF.as<double2>();
+    double *P = g->wsP.as<double>();
+    LegendreArgs a{g, lmax, nrhs, s};
+    int nch = 0;
+    if ((rc = launch_scale_l(lmax, nrhs, x, L.bh.as<double>(), u, s))) return rc;
+    if ((rc = launch_legendre_synth(a, u, F))) return rc;
+    if ((rc = launch_ring_apply(g, lmax, nrhs, F, op->ninv, s))) return rc;
+    if ((rc = launch_legendre_adjoint(a, F, P, &nch))) return rc;
+    if ((rc = launch_reduce_epilogue(lmax, nrhs, nch, P, x, L.d.as<double>(), L.bh.as<double>(), y,
+                                     s)))
+        return rc;
+    return MLCR_OK;
+}
+
+}  // extern "C"

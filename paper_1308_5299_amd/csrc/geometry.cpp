@@ -1,0 +1,221 @@
+// Host-side tables of a geometry: HEALPix RING rings, per-length FFT tables
+// and the coefficients of the normalized associated-Legendre recurrence.
+// All values are formed in long double and rounded once to double.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <thread>
+#include <vector>
+
+#include "mlcr_internal.h"
+
+namespace mlcr {
+
+using cld = std::complex<long double>;
+static const long double kPi = 3.141592653589793238462643383279502884L;
+
+static int next_pow2(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// In-place iterative radix-2 forward DFT, X_k = sum_j x_j e^{-2 pi i jk/M}.
+static void fft_ld(std::vector<cld> &x) {
+    const int M = (int)x.size();
+    for (int i = 1, j = 0; i < M; i++) {
+        int bit = M >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(x[i], x[j]);
+    }
+    for (int len = 2; len <= M; len <<= 1) {
+        const int h = len / 2;
+        std::vector<cld> w(h);
+        for (int k = 0; k < h; k++) {
+            long double a = -2.0L * kPi * (long double)k / (long double)len;
+            w[k] = cld(cosl(a), sinl(a));
+        }
+        for (int i = 0; i < M; i += len)
+            for (int k = 0; k < h; k++) {
+                cld u = x[i + k], v = x[i + k + h] * w[k];
+                x[i + k] = u + v;
+                x[i + k + h] = u - v;
+            }
+    }
+}
+
+int build_geometry(mlcr_geom *g, int nside, int lmax) {
+    g->nside = nside;
+    g->lmax = lmax;
+    g->nrings = 4 * nside - 1;
+    g->npairs = 2 * nside;
+    g->npix = 12LL * nside * nside;
+    const int nr = g->nrings;
+
+    // ---- rings (Sec. 2.1; Gorski et al. 2005) ----
+    std::vector<double> z(nr), s(nr);
+    std::vector<RingInfo> ri(nr);
+    long long start = 0;
+    for (int i = 1; i <= nr; i++) {
+        RingInfo &r = ri[i - 1];
+        long double zabs, one_minus;
+        int cls;
+        if (i < nside || i > 3 * nside) {
+            int ii = (i < nside) ? i : 4 * nside - i;
+            one_minus = (long double)ii * ii / (3.0L * nside * nside);
+            zabs = 1.0L - one_minus;
+            r.nphi = 4 * ii;
+            r.phase = 1;                       // phi0 = pi / (4 ii) = pi / N
+            cls = ii;
+        } else {
+            long double zz = (long double)(4 * nside - 2 * i) / (3.0L * nside);
+            zabs = fabsl(zz);
+            one_minus = 1.0L - zabs;
+            r.nphi = 4 * nside;
+            int sft = (i - nside + 1) % 2;     // phi0 = (pi / (2 nside)) (1 - s/2)
+            r.phase = sft ? 1 : 2;
+            cls = nside;
+        }
+        z[i - 1] = (double)((i > 2 * nside) ? -zabs : zabs);
+        s[i - 1] = (double)sqrtl(one_minus * (1.0L + zabs));
+        r.start = start;
+        r.tab = cls - 1;
+        r.pad = 0;
+        start += r.nphi;
+    }
+
+    // ---- length classes N = 4 i: twiddles T_N and Bluestein filters ----
+    std::vector<LenInfo> li(nside);
+    long long toff = 0, boff = 0;
+    int maxfft = 1;
+    for (int i = 1; i <= nside; i++) {
+        LenInfo &L = li[i - 1];
+        const int N = 4 * i, n = N / 2;
+        L.toff = toff;
+        toff += 2LL * N;
+        if (is_pow2(n)) {
+            L.boff = -1;
+            L.M = n;
+        } else {
+            L.M = next_pow2(2 * n - 1);
+            L.boff = boff;
+            boff += L.M;
+        }
+        L.pad = 0;
+        maxfft = std::max(maxfft, L.M);
+    }
+    g->lds_cplx = maxfft;
+    g->Wmax = maxfft;
+
+    std::vector<double2> T(toff), Bf(std::max<long long>(boff, 1)), W(maxfft);
+    auto fill_class = [&](int i) {
+        const int N = 4 * i, n = N / 2;
+        const LenInfo &L = li[i - 1];
+        for (int j = 0; j < 2 * N; j++) {
+            long double a = kPi * (long double)j / (long double)N;
+            T[L.toff + j] = make_double2((double)cosl(a), (double)sinl(a));
+        }
+        if (L.boff >= 0) {
+            // b_j = e^{-i pi j^2 / n} for |j| < n, wrapped cyclically into length M
+            std::vector<cld> b(L.M, cld(0, 0));
+            for (int j = 0; j < n; j++) {
+                long long r2 = ((long long)j * j) % (2LL * n);
+                long double a = -kPi * (long double)r2 / (long double)n;
+                cld v(cosl(a), sinl(a));
+                b[j] = v;
+                if (j > 0) b[L.M - j] = v;
+            }
+            fft_ld(b);
+            for (int k = 0; k < L.M; k++)
+                Bf[L.boff + k] = make_double2((double)b[k].real(), (double)b[k].imag());
+        }
+    };
+    {
+        unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nt; t++)
+            th.emplace_back([&, t] {
+                for (int i = 1 + (int)t; i <= nside; i += (int)nt) fill_class(i);
+            });
+        for (auto &t : th) t.join();
+    }
+    for (int j = 0; j < maxfft; j++) {
+        long double a = -2.0L * kPi * (long double)j / (long double)maxfft;
+        W[j] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+
+    // ---- Legendre recurrence (Sec. 3.2 normalization) ----
+    // lambda_lm = A_lm z lambda_{l-1,m} - B_lm lambda_{l-2,m}, l >= m+1, with
+    // A_lm = sqrt((4 l^2 - 1) / (l^2 - m^2)), B_lm = A_lm / A_{l-1,m}, B_{m+1,m} = 0.
+    const long long nab = (long long)lmax * (lmax + 1) / 2;
+    std::vector<double2> ab(std::max<long long>(nab, 1));
+    std::vector<long long> aboff(lmax + 1);
+    std::vector<double> seed(lmax + 1);
+    long double prod = 1.0L;     // prod_{k=1..m} (2k-1)/(2k)
+    for (int m = 0; m <= lmax; m++) {
+        if (m > 0) prod *= (long double)(2 * m - 1) / (long double)(2 * m);
+        long double c = sqrtl((2.0L * m + 1.0L) / (4.0L * kPi) * prod);
+        seed[m] = (double)((m & 1) ? -c : c);
+        aboff[m] = (long long)m * lmax - (long long)m * (m - 1) / 2;
+    }
+    {
+        auto fill_m = [&](int m) {
+            long double aprev = 0.0L;
+            for (int l = m + 1; l <= lmax; l++) {
+                long double a = sqrtl((4.0L * l * l - 1.0L) / ((long double)(l - m) * (l + m)));
+                long double b = (l == m + 1) ? 0.0L : a / aprev;
+                ab[aboff[m] + (l - m - 1)] = make_double2((double)a, (double)b);
+                aprev = a;
+            }
+        };
+        unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nt; t++)
+            th.emplace_back([&, t] {
+                for (int m = (int)t; m <= lmax; m += (int)nt) fill_m(m);
+            });
+        for (auto &t : th) t.join();
+    }
+
+    // ---- ring order for the FFT kernels: most expensive first ----
+    std::vector<int> order(nr);
+    {
+        std::vector<double> cost(nr);
+        for (int k = 0; k < nr; k++) {
+            const LenInfo &L = li[ri[k].tab];
+            const double M = (double)L.M;
+            cost[k] = (L.boff >= 0 ? 3.0 : 1.0) * M * std::log2(std::max(2.0, M));
+            order[k] = k;
+        }
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return cost[a] > cost[b]; });
+    }
+
+    // ---- upload ----
+    auto up = [](DevBuf &b, const void *src, size_t bytes) -> int {
+        if (b.reserve(bytes)) return fail(MLCR_ENOMEM, "geometry table allocation failed");
+        MLCR_HIP_CHECK(hipMemcpy(b.ptr, src, bytes, hipMemcpyHostToDevice));
+        return MLCR_OK;
+    };
+    int rc;
+    if ((rc = up(g->ring_z, z.data(), nr * sizeof(double)))) return rc;
+    if ((rc = up(g->ring_s, s.data(), nr * sizeof(double)))) return rc;
+    if ((rc = up(g->rings, ri.data(), nr * sizeof(RingInfo)))) return rc;
+    if ((rc = up(g->lens, li.data(), nside * sizeof(LenInfo)))) return rc;
+    if ((rc = up(g->order, order.data(), nr * sizeof(int)))) return rc;
+    if ((rc = up(g->T, T.data(), T.size() * sizeof(double2)))) return rc;
+    if ((rc = up(g->Bf, Bf.data(), Bf.size() * sizeof(double2)))) return rc;
+    if ((rc = up(g->W, W.data(), W.size() * sizeof(double2)))) return rc;
+    if ((rc = up(g->ab, ab.data(), ab.size() * sizeof(double2)))) return rc;
+    if ((rc = up(g->aboff, aboff.data(), aboff.size() * sizeof(long long)))) return rc;
+    if ((rc = up(g->seed, seed.data(), seed.size() * sizeof(double)))) return rc;
+    std::vector<double> zeros(lmax + 1, 0.0);
+    if ((rc = up(g->zeros, zeros.data(), zeros.size() * sizeof(double)))) return rc;
+    return MLCR_OK;
+}
+
+}  // namespace mlcr

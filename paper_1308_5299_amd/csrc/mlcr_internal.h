@@ -1,0 +1,129 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mlcr.h"
+
+namespace mlcr {
+
+// ---------------------------------------------------------------------------
+// error handling
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+#define MLCR_HIP_CHECK(expr)                                                       \
+    do {                                                                           \
+        hipError_t _e = (expr);                                                    \
+        if (_e != hipSuccess)                                                      \
+            return ::mlcr::fail(MLCR_EHIP, std::string(#expr) + ": " +            \
+                                               hipGetErrorString(_e));             \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device buffer with grow-on-demand semantics
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    int reserve(size_t nbytes);     // MLCR_OK or MLCR_ENOMEM
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// Per-ring information used by the ring (FFT) kernels.
+struct RingInfo {
+    long long start;    // RING index of the first pixel
+    int nphi;           // pixels in the ring, N = 4 i
+    int phase;          // p: e^{i m phi0} = e^{i pi m p / N}
+    int tab;            // index i - 1 of the length class N = 4 i
+    int pad;
+};
+
+// Offset of the cosine block of order m >= 1 in a real packed vector
+// (the m = 0 block starts at 0).
+__host__ __device__ inline long long cos_base(int m, int lmax) {
+    return m == 0 ? 0 : (long long)(lmax + 1) + (long long)(m - 1) * (2 * lmax - m + 2);
+}
+
+// Per length class N = 4 i (i = 1..nside): twiddle table and Bluestein filter.
+struct LenInfo {
+    long long toff;     // offset of T_N[j] = e^{i pi j / N}, j = 0..2N-1
+    long long boff;     // offset of the Bluestein filter (-1: n = N/2 is a power of two)
+    int M;              // Bluestein FFT size (power of two >= 2n - 1), or n when pow2
+    int pad;
+};
+
+}  // namespace mlcr
+
+struct mlcr_geom {
+    int nside = 0, lmax = 0, nrings = 0, npairs = 0;
+    long long npix = 0;
+    int lds_cplx = 0;       // largest complex FFT buffer of any ring
+    int Wmax = 0;           // size of the power-of-two twiddle table
+
+    // device tables
+    mlcr::DevBuf ring_z, ring_s;        // per ring: cos, sin theta (double)
+    mlcr::DevBuf rings;                 // RingInfo[nrings]
+    mlcr::DevBuf lens;                  // LenInfo[nside]
+    mlcr::DevBuf order;                 // int[nrings]: rings by decreasing FFT cost
+    mlcr::DevBuf T;                     // double2, all twiddle tables
+    mlcr::DevBuf Bf;                    // double2, all Bluestein filters
+    mlcr::DevBuf W;                     // double2, e^{-2 pi i j / Wmax}, j < Wmax
+    mlcr::DevBuf ab;                    // double2 (A_lm, B_lm) recurrence coefficients
+    mlcr::DevBuf aboff;                 // long long per m
+    mlcr::DevBuf seed;                  // double per m: seed constant of lambda_mm
+    mlcr::DevBuf zeros;                 // double[lmax+1] of zeros (absent sine block of m = 0)
+
+    // workspaces, grown on demand
+    mlcr::DevBuf wsF;                   // ring-major Fourier coefficients
+    mlcr::DevBuf wsP;                   // partial adjoint sums
+    mlcr::DevBuf wsU;                   // beam-weighted input
+};
+
+struct mlcr_level {
+    int lmax = -1;
+    mlcr::DevBuf d;     // double[lmax+1]: f^2 / C_l (0 for excluded modes)
+    mlcr::DevBuf bh;    // double[lmax+1]: f b_l p_l (0 for excluded modes)
+};
+
+struct mlcr_op {
+    mlcr_geom *g = nullptr;
+    int lmax = 0, max_nrhs = 0;
+    const double *ninv = nullptr;
+    std::vector<double> cl, bl;
+    mlcr_level levels[16];
+};
+
+namespace mlcr {
+
+// geometry.cpp
+int build_geometry(mlcr_geom *g, int nside, int lmax);
+
+// launch wrappers (kernels.hip)
+struct LegendreArgs {
+    const mlcr_geom *g;
+    int lmax;        // band limit of this transform (<= g->lmax)
+    int nrhs;
+    hipStream_t stream;
+};
+int launch_legendre_synth(const LegendreArgs &a, const double *u, double2 *F);
+int launch_legendre_adjoint(const LegendreArgs &a, const double2 *G, double *P, int *nchunks_out);
+int launch_ring_synth(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, double *map,
+                      hipStream_t s);
+int launch_ring_adjoint(const mlcr_geom *g, int lmax, int nrhs, const double *map, double2 *G,
+                        hipStream_t s);
+int launch_ring_apply(const mlcr_geom *g, int lmax, int nrhs, double2 *FG, const double *ninv,
+                      hipStream_t s);
+int launch_scale_l(int lmax, int nrhs, const double *x, const double *dl, double *u,
+                   hipStream_t s);
+int launch_reduce_epilogue(int lmax, int nrhs, int nchunks, const double *P, const double *x,
+                           const double *d, const double *bh, double *y, hipStream_t s);
+int adjoint_chunks(const mlcr_geom *g, int lmax);
+
+}  // namespace mlcr

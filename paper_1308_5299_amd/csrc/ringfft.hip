@@ -1,0 +1,299 @@
+// Ring step of the spherical harmonic transforms, and the pixel diagonal.
+//
+// For ring k with N = 4i pixels at phi_j = phi0 + 2 pi j / N, synthesis is
+//     f_j = sum_m w_m (F^c_m cos m phi_j + F^s_m sin m phi_j),  w_0 = 1, w_m = sqrt 2,
+// the real part of a length-N inverse DFT of the coefficients
+// H_m = w_m (F^c_m - i F^s_m) e^{i m phi0} folded modulo N (eq. sh-synthesis
+// restricted to one iso-latitude ring; m >= N/2 is aliased exactly, which
+// the method's under-pixelized grids need, Sec. 3.3).  Adjoint synthesis
+// (Sec. 2.1) is its exact transpose:
+//     G^c_m + i G^s_m = w_m e^{i m phi0} conj(Y_{m mod N}),  Y_q = sum_j y_j e^{-2 pi i q j / N}.
+//
+// Both directions use one complex DFT of length n = N/2 on the packed map
+// z_t = f_2t + i f_2t+1.  When n is a power of two it is a radix-2 Stockham
+// FFT in LDS; otherwise Bluestein's chirp-z convolution with a power-of-two
+// FFT of size M >= 2n - 1 and a precomputed filter.  The phase e^{i m phi0}
+// is e^{i pi m p / N} with p in {1, 2}, so every twiddle, phase and chirp of
+// a ring comes from one table T_N[j] = e^{i pi j / N}.
+//
+// In the fused operator kernel the map never leaves LDS: F is read, the map
+// is multiplied by N^-1 (0 in the mask, Sec. 2.3), and G is written over F.
+// One workgroup of 512 threads per (ring, right-hand side).
+#include "mlcr_internal.h"
+
+namespace mlcr {
+
+static constexpr int kRingThreads = 512;
+static constexpr int kMaxBfly = 8;                 // n/2 <= kMaxBfly * kRingThreads
+static constexpr double kSqrt2 = 1.4142135623730950488;
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+// Unnormalized DFT of size M (power of two) held in LDS, in place, all
+// threads of the block taking part.  Forward: X_k = sum_j x_j e^{-2 pi i jk/M};
+// inverse uses e^{+...}.  W[j] = e^{-2 pi i j / Wmax}, Wmax a multiple of M.
+__device__ void lds_fft(double2 *buf, int M, bool inverse, const double2 *__restrict__ W,
+                        int Wmax) {
+    const int half = M >> 1;
+    const int tid = threadIdx.x;
+    for (int p = 1; p < M; p <<= 1) {
+        const int ts = Wmax / (2 * p);
+        double2 a[kMaxBfly], b[kMaxBfly];
+#pragma unroll
+        for (int c = 0; c < kMaxBfly; c++) {
+            const int i = tid + c * kRingThreads;
+            if (i < half) {
+                a[c] = buf[i];
+                b[c] = buf[i + half];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < kMaxBfly; c++) {
+            const int i = tid + c * kRingThreads;
+            if (i < half) {
+                const int k = i & (p - 1);
+                double2 w = W[(long long)k * ts];
+                if (inverse) w.y = -w.y;
+                const double2 t = cmul(b[c], w);
+                const int j = (i << 1) - k;
+                buf[j] = cadd(a[c], t);
+                buf[j + p] = csub(a[c], t);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Folded, phased coefficient  Hhat_q = sum_{m = q mod N} H_m  for 0 <= q < N.
+__device__ __forceinline__ double2 hhat(const double2 *__restrict__ Fk, int q, int N, int p,
+                                        int lmax, const double2 *__restrict__ TN) {
+    double ax = 0.0, ay = 0.0;
+    int j = 0;
+    for (int m = q; m <= lmax; m += N, j++) {
+        const double2 f = Fk[m];
+        double w = (m == 0) ? 1.0 : kSqrt2;
+        if ((j * p) & 1) w = -w;        // e^{i pi (q + jN) p / N} = e^{i pi q p / N} (-1)^{jp}
+        ax = fma(w, f.x, ax);
+        ay = fma(-w, f.y, ay);
+    }
+    return cmul(make_double2(ax, ay), TN[(q * p) % (2 * N)]);
+}
+
+// chirp q_t = e^{i pi t^2 / n} = T_N[2 t^2 mod 2N]
+__device__ __forceinline__ double2 chirp(const double2 *__restrict__ TN, int t, int N) {
+    return TN[(int)((2LL * t * t) % (2LL * N))];
+}
+
+// MODE 0: F -> map.  MODE 1: map -> G.  MODE 2: F -> N^-1 map -> G (G over F).
+template <int MODE>
+__global__ __launch_bounds__(kRingThreads) void k_ring(
+    const double2 *Fin, double2 *Gout, const double *__restrict__ map_in,
+    double *__restrict__ map_out, const double *__restrict__ ninv,
+    const RingInfo *__restrict__ rings, const LenInfo *__restrict__ lens,
+    const int *__restrict__ order, const double2 *__restrict__ T, const double2 *__restrict__ Bf,
+    const double2 *__restrict__ W, int Wmax, int lmax, long long fstride, long long npix) {
+    extern __shared__ double2 buf[];
+    const int k = order[blockIdx.x];
+    const int r = blockIdx.y;
+    const int tid = threadIdx.x;
+    const RingInfo ri = rings[k];
+    const LenInfo L = lens[ri.tab];
+    const int N = ri.nphi, n = N >> 1, p = ri.phase;
+    const double2 *TN = T + L.toff;
+    const bool blue = L.boff >= 0;
+    const int M = L.M;
+    const double2 *Bk = Bf + (blue ? L.boff : 0);
+    const double invM = 1.0 / (double)M;
+    const int ld = lmax + 1;
+    const long long pix0 = (long long)r * npix + ri.start;
+
+    if (MODE != 1) {
+        const double2 *Fk = Fin + (long long)r * fstride + (long long)k * ld;
+        if (blue)
+            for (int t = n + tid; t < M; t += kRingThreads) buf[t] = make_double2(0.0, 0.0);
+        // Z_k = (G_k + G_{k+n}) + i w^k (G_k - G_{k+n}),  G_q = (Hhat_q + conj Hhat_{N-q}) / 2,
+        // w = e^{2 pi i / N}: the length-n DFT input whose inverse is z_t = f_2t + i f_2t+1.
+        for (int kk = tid; 2 * kk <= n; kk += kRingThreads) {
+            const int i1 = kk == 0 ? 0 : N - kk;
+            const double2 H0 = hhat(Fk, kk, N, p, lmax, TN);
+            const double2 H1 = hhat(Fk, i1, N, p, lmax, TN);
+            const double2 H2 = hhat(Fk, kk + n, N, p, lmax, TN);
+            const double2 H3 = hhat(Fk, n - kk, N, p, lmax, TN);
+            {
+                const double2 g0 = cscale(cadd(H0, cconj(H1)), 0.5);
+                const double2 g1 = cscale(cadd(H2, cconj(H3)), 0.5);
+                const double2 d = cmul(TN[2 * kk], csub(g0, g1));
+                double2 Z = make_double2(g0.x + g1.x - d.y, g0.y + g1.y + d.x);
+                if (blue) Z = cmul(Z, chirp(TN, kk, N));
+                buf[kk] = Z;
+            }
+            const int k2 = n - kk;
+            if (kk > 0 && k2 > kk) {
+                const double2 g0 = cscale(cadd(H3, cconj(H2)), 0.5);
+                const double2 g1 = cscale(cadd(H1, cconj(H0)), 0.5);
+                const double2 d = cmul(TN[2 * k2], csub(g0, g1));
+                double2 Z = make_double2(g0.x + g1.x - d.y, g0.y + g1.y + d.x);
+                if (blue) Z = cmul(Z, chirp(TN, k2, N));
+                buf[k2] = Z;
+            }
+        }
+        __syncthreads();
+        if (!blue) {
+            lds_fft(buf, n, true, W, Wmax);
+        } else {
+            lds_fft(buf, M, false, W, Wmax);
+            for (int t = tid; t < M; t += kRingThreads) buf[t] = cmul(buf[t], Bk[t]);
+            __syncthreads();
+            lds_fft(buf, M, true, W, Wmax);
+            for (int t = tid; t < n; t += kRingThreads)
+                buf[t] = cscale(cmul(buf[t], chirp(TN, t, N)), invM);
+            __syncthreads();
+        }
+        if (MODE == 0) {
+            double2 *out = reinterpret_cast<double2 *>(map_out + pix0);
+            for (int t = tid; t < n; t += kRingThreads) out[t] = buf[t];
+            return;
+        }
+        const double2 *ni = reinterpret_cast<const double2 *>(ninv + ri.start);
+        for (int t = tid; t < n; t += kRingThreads) {
+            const double2 w = ni[t];
+            const double2 v = buf[t];
+            buf[t] = make_double2(v.x * w.x, v.y * w.y);
+        }
+    } else {
+        const double2 *in = reinterpret_cast<const double2 *>(map_in + pix0);
+        for (int t = tid; t < n; t += kRingThreads) buf[t] = in[t];
+    }
+    // forward DFT of z (adjoint direction)
+    if (!blue) {
+        __syncthreads();
+        lds_fft(buf, n, false, W, Wmax);
+    } else {
+        for (int t = tid; t < M; t += kRingThreads)
+            buf[t] = (t < n) ? cmul(buf[t], cconj(chirp(TN, t, N))) : make_double2(0.0, 0.0);
+        __syncthreads();
+        lds_fft(buf, M, false, W, Wmax);
+        for (int t = tid; t < M; t += kRingThreads) buf[t] = cmul(buf[t], cconj(Bk[t]));
+        __syncthreads();
+        lds_fft(buf, M, true, W, Wmax);
+        for (int t = tid; t < n; t += kRingThreads)
+            buf[t] = cscale(cmul(buf[t], cconj(chirp(TN, t, N))), invM);
+        __syncthreads();
+    }
+    // unfold: Y_q from the half-length transform, then G_m for m = 0..lmax
+    double2 *Gk = Gout + (long long)r * fstride + (long long)k * ld;
+    for (int m = tid; m <= lmax; m += kRingThreads) {
+        const int q = m % N;
+        const int kq = q % n;
+        const int kc = kq == 0 ? 0 : n - kq;
+        const double2 A = buf[kq], B = cconj(buf[kc]);
+        const double2 E = cscale(cadd(A, B), 0.5);
+        const double2 D = csub(A, B);
+        const double2 O = make_double2(0.5 * D.y, -0.5 * D.x);     // (A - B) / (2i)
+        const double2 t = cmul(cconj(TN[2 * kq]), O);
+        const double2 Y = (q < n) ? cadd(E, t) : csub(E, t);
+        const double2 V = cmul(TN[(m * p) % (2 * N)], cconj(Y));
+        const double w = (m == 0) ? 1.0 : kSqrt2;
+        Gk[m] = make_double2(w * V.x, w * V.y);
+    }
+}
+
+template <int MODE>
+static int launch_ring(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, double2 *G,
+                       const double *map_in, double *map_out, const double *ninv,
+                       hipStream_t s) {
+    const size_t lds = (size_t)g->lds_cplx * sizeof(double2);
+    static bool attr_set = false;
+    if (!attr_set) {
+        MLCR_HIP_CHECK(hipFuncSetAttribute((const void *)k_ring<MODE>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024));
+        attr_set = true;
+    }
+    const long long fstride = (long long)g->nrings * (lmax + 1);
+    hipLaunchKernelGGL(k_ring<MODE>, dim3(g->nrings, nrhs), dim3(kRingThreads), lds, s, F, G,
+                       map_in, map_out, ninv, g->rings.as<RingInfo>(), g->lens.as<LenInfo>(),
+                       g->order.as<int>(), g->T.as<double2>(), g->Bf.as<double2>(),
+                       g->W.as<double2>(), g->Wmax, lmax, fstride, g->npix);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_ring_synth(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, double *map,
+                      hipStream_t s) {
+    return launch_ring<0>(g, lmax, nrhs, F, nullptr, nullptr, map, nullptr, s);
+}
+int launch_ring_adjoint(const mlcr_geom *g, int lmax, int nrhs, const double *map, double2 *G,
+                        hipStream_t s) {
+    return launch_ring<1>(g, lmax, nrhs, nullptr, G, map, nullptr, nullptr, s);
+}
+int launch_ring_apply(const mlcr_geom *g, int lmax, int nrhs, double2 *FG, const double *ninv,
+                      hipStream_t s) {
+    return launch_ring<2>(g, lmax, nrhs, FG, FG, nullptr, nullptr, ninv, s);
+}
+
+// ---------------------------------------------------------------------------
+// l-diagonal kernels on packed vectors: one workgroup per (m, RHS)
+// ---------------------------------------------------------------------------
+// u = diag(dl) x  (dl == nullptr: copy)
+__global__ __launch_bounds__(256) void k_scale_l(const double *__restrict__ x,
+                                                 const double *__restrict__ dl,
+                                                 double *__restrict__ u, int lmax, long long nalm) {
+    const int m = blockIdx.x, r = blockIdx.y;
+    const int nl = lmax - m + 1;
+    const int cnt = (m == 0) ? nl : 2 * nl;
+    const long long off = (long long)r * nalm + cos_base(m, lmax);
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const int l = m + (i < nl ? i : i - nl);
+        const double v = x[off + i];
+        u[off + i] = dl ? dl[l] * v : v;
+    }
+}
+
+// y = diag(d) x + diag(bh) sum_c P_c   (d, x may be null; bh null means 1)
+__global__ __launch_bounds__(256) void k_reduce_epi(const double *__restrict__ P, int nchunks,
+                                                    int nrhs, const double *__restrict__ x,
+                                                    const double *__restrict__ d,
+                                                    const double *__restrict__ bh,
+                                                    double *__restrict__ y, int lmax,
+                                                    long long nalm) {
+    const int m = blockIdx.x, r = blockIdx.y;
+    const int nl = lmax - m + 1;
+    const int cnt = (m == 0) ? nl : 2 * nl;
+    const long long off = (long long)r * nalm + cos_base(m, lmax);
+    const long long cstride = (long long)nrhs * nalm;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const int l = m + (i < nl ? i : i - nl);
+        double s = 0.0;
+        for (int c = 0; c < nchunks; c++) s += P[c * cstride + off + i];
+        double v = bh ? bh[l] * s : s;
+        if (d) v = fma(d[l], x[off + i], v);
+        y[off + i] = v;
+    }
+}
+
+int launch_scale_l(int lmax, int nrhs, const double *x, const double *dl, double *u,
+                   hipStream_t s) {
+    const long long nalm = (long long)(lmax + 1) * (lmax + 1);
+    hipLaunchKernelGGL(k_scale_l, dim3(lmax + 1, nrhs), dim3(256), 0, s, x, dl, u, lmax, nalm);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_reduce_epilogue(int lmax, int nrhs, int nchunks, const double *P, const double *x,
+                           const double *d, const double *bh, double *y, hipStream_t s) {
+    const long long nalm = (long long)(lmax + 1) * (lmax + 1);
+    hipLaunchKernelGGL(k_reduce_epi, dim3(lmax + 1, nrhs), dim3(256), 0, s, P, nchunks, nrhs, x,
+                       d, bh, y, lmax, nalm);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+}  // namespace mlcr
