@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Throughput of the CR operator apply A x = (S^-1 + B Y^T N^-1 Y B) x.
+
+One step = one apply_A of a batch of R right-hand sides on the full
+workload (default: N_side 2048, lmax 4096, R = 8): beam prologue, Legendre
+synthesis, ring FFT + N^-1 + adjoint ring FFT, Legendre adjoint and the
+prior/beam epilogue -- every step of the hot path, all in the HIP library.
+Inputs (x ~ N(0, S), N^-1 with mask) are resident in HBM before timing.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "A·x applies/s (SHT pair) at Nside 2048, ℓmax 4096; FP64 vs mixed at 1e-3 μK"
+PEAK_FP64_VALU = 78.6e12      # MI355X FP64 vector FLOP/s
+PEAK_HBM = 8.0e12             # MI355X HBM3E bytes/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_work(name: str, nside: int, lmax: int, R: int):
+    """(bound, amount, unit) of one launch of a kernel, from the method's counts.
+
+    Legendre kernels: 4 flops (two FMAs, cos and sin) per (l, m, ring pair,
+    RHS) over the full triangle 0 <= m <= l <= lmax and all 2 N_side ring
+    pairs; the recurrence that generates lambda_lm is not counted.
+    Ring kernels: bytes of the Fourier coefficients read and written (16 B
+    per (ring, m, RHS) each way) plus the map or N^-1 (8 B per pixel).
+    """
+    ntri = (lmax + 1) * (lmax + 2) // 2
+    npairs = 2 * nside
+    nrings = 4 * nside - 1
+    npix = 12 * nside * nside
+    if name.startswith("legendre"):
+        return "alu", 4.0 * ntri * npairs * R, "flop"
+    if name == "ring_apply":
+        return "hbm", 2.0 * 16 * nrings * (lmax + 1) * R + 8.0 * npix, "byte"
+    if name in ("ring_synth", "ring_adjoint"):
+        return "hbm", 16.0 * nrings * (lmax + 1) * R + 8.0 * npix * R, "byte"
+    nalm = (lmax + 1) ** 2
+    return "hbm", 3.0 * 8 * nalm * R, "byte"
+
+
+def cpu_baseline(cfg, R: int, seed_x, ninv_host, budget_s: float = 20.0):
+    """Time the CPU oracle on a bounded sample of the same apply and scale.
+
+    Sample: the oracle's per-order Legendre step (both directions, R RHS) for
+    a handful of orders m spread over [0, lmax], and its ring step (both
+    directions) on a spread of rings.  The full apply time is extrapolated
+    by the work of each part: Legendre work of order m is proportional to
+    (lmax - m + 1); ring work is summed over sampled rings and scaled by the
+    ratio of total to sampled ring pixels.  Single thread (BLAS limited to 1).
+    """
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import geometry as ogeo
+    from oracle import sht as osht
+
+    lmax, nside = cfg.lmax, cfg.nside
+    geom = ogeo.healpix_rings(nside)
+    with threadpool_limits(limits=1):
+        # Legendre sample
+        ms = sorted(set(int(v) for v in np.linspace(0, lmax - 8, 16)))
+        xs = seed_x
+        t_m = []
+        t_start = time.perf_counter()
+        for m in ms:
+            Gc = np.zeros((R, geom.nrings))
+            t0 = time.perf_counter()
+            osht.legendre_pair_m(xs, (Gc, Gc), m, lmax, geom)
+            t_m.append(time.perf_counter() - t0)
+            if time.perf_counter() - t_start > budget_s:
+                break
+        ms = ms[: len(t_m)]
+        # per-order time ~ a + b (lmax - m + 1): least squares, then sum over m
+        w = np.array([lmax - m + 1 for m in ms], dtype=float)
+        A = np.stack([np.ones_like(w), w], axis=1)
+        coef, *_ = np.linalg.lstsq(A, np.array(t_m), rcond=None)
+        allw = np.arange(lmax + 1, 0, -1, dtype=float)
+        t_leg = float(np.sum(np.maximum(coef[0] + coef[1] * allw, 0.0)))
+        # ring sample: synth + adjoint ring step on spread rings
+        rings = np.unique(np.linspace(0, geom.nrings - 1, 64).astype(int))
+        sub_pix = int(geom.nphi[rings].sum())
+        F = np.random.default_rng(0).standard_normal((R, 1, lmax + 1))
+        t0 = time.perf_counter()
+        for k in rings:
+            g1 = ogeo.RingGeometry(nside, geom.z[k:k + 1], geom.sint[k:k + 1], geom.nphi[k:k + 1],
+                                   geom.phi0[k:k + 1], np.array([0]))
+            mp = osht.ring_synth(F, F, g1)
+            osht.ring_adjoint(mp * ninv_host[geom.start[k]: geom.start[k] + geom.nphi[k]], lmax, g1)
+        t_ring = (time.perf_counter() - t0) * (geom.npix / sub_pix)
+    total = t_leg + t_ring
+    return {
+        "value": R / total,
+        "unit": "RHS-applies/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle per-order Legendre step (both directions, {R} RHS) at m in {ms} "
+                   f"and ring step on {len(rings)} rings of the N_side {nside}, lmax {lmax} "
+                   f"workload, extrapolated by work to one full apply of {R} RHS "
+                   f"(estimated {total:.0f} s per apply; numpy, 1 thread)"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c5")
+    ap.add_argument("--nrhs", type=int, default=0)
+    ap.add_argument("--prec", default="fp64", choices=["fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design "
+              "(RHS sharding, or an m/ring all-to-all per SHT) is described in DESIGN.md and "
+              "is not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1308_5299_amd as mlcr
+    import workloads
+
+    cfg = workloads.get_config(args.config)
+    R = args.nrhs or cfg.nrhs
+    prec = {"fp64": mlcr.FP64}[args.prec]
+    log(f"[bench] config {cfg.name}: nside {cfg.nside} lmax {cfg.lmax} R {R} prec {args.prec}")
+    t0 = time.time()
+    d = workloads.workload_inputs(cfg)
+    x_host = np.stack([workloads.prior_sample(cfg, r) for r in range(R)])
+    log(f"[bench] inputs ready in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    ninv = torch.from_numpy(d["ninv"]).to(dev)
+    x = torch.from_numpy(x_host).to(dev)
+    t0 = time.time()
+    geom = mlcr.Geometry(cfg.nside, cfg.lmax)
+    op = mlcr.Operator(geom, d["cl"], d["bl"], ninv, max_nrhs=R)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    log(f"[bench] geometry + operator ready in {time.time() - t0:.1f}s")
+
+    for i in range(args.warmup):
+        mlcr.apply_A(op, x, prec=prec, out=y)
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {i + 1}/{args.warmup} done")
+
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    with mlcr.KernelTimer() as kt:
+        e0.record(stream)
+        for i in range(args.steps):
+            mlcr.apply_A(op, x, prec=prec, out=y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / args.steps
+    value = R * args.steps / (ms_total / 1e3)
+    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, {value:.2f} RHS-applies/s")
+    kernels = {k: (v[0] / v[1]) for k, v in kt.result.items()}
+    for k, v in sorted(kernels.items(), key=lambda t: -t[1]):
+        log(f"[bench]   {k:18s} {v:9.3f} ms/launch")
+    dom = max(kernels, key=lambda k: kernels[k])
+    bound, work, unit = algorithmic_work(dom, cfg.nside, cfg.lmax, R)
+    sec = kernels[dom] / 1e3
+    if bound == "alu":
+        roof = {"bound": "alu", "kernel": dom, "achieved": work / sec / 1e12,
+                "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "kernel": dom, "achieved": work / sec / 1e9,
+                "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel_ms"] = {k: round(v, 4) for k, v in kernels.items()}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(cfg, R, x_host, d["ninv"])
+        log(f"[bench] cpu baseline {cpu['value']:.3e} {cpu['unit']}")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "RHS-applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: HEALPix Nside {cfg.nside}, lmax {cfg.lmax}, "
+                               f"{R} RHS per apply, {args.prec} Legendre path",
+                   "nside": cfg.nside, "lmax": cfg.lmax, "nrhs": R, "prec": args.prec,
+                   "global_batch": R},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

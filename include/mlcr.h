@@ -64,6 +64,15 @@ const char *mlcr_last_error(void);
 /* Library version string. */
 const char *mlcr_version(void);
 
+/* Per-kernel timing (measurement support, Sec. 4.1 reports per-step cost):
+ * when enabled, every kernel launch of the library is bracketed by a pair
+ * of HIP events on its stream; totals accumulate per kernel name.
+ * mlcr_timing_get synchronizes on the recorded events.  Not thread-safe. */
+int mlcr_timing_enable(int on);
+int mlcr_timing_reset(void);
+int mlcr_timing_count(void);
+int mlcr_timing_get(int i, char *name, int name_len, double *total_ms, long long *calls);
+
 /* ------------------------------------------------------------------------
  * Geometry: HEALPix RING grid of resolution nside (Sec. 2.1) together with
  * the tables of the Legendre recurrence up to lmax and of the per-ring

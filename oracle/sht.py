@@ -66,6 +66,24 @@ def packed_index(lmax: int):
 # --------------------------------------------------------------------------
 # Legendre step
 # --------------------------------------------------------------------------
+def legendre_pair_m(x: np.ndarray, G, m: int, lmax: int, geom: RingGeometry):
+    """Legendre step of one order m in both directions.
+
+    Returns (F^c_m, F^s_m) = (sum_l lambda_lm x^c_lm, sum_l lambda_lm x^s_lm) per ring
+    for the packed input x (..., nalm), and, if G = (G^c_m, G^s_m) per ring is
+    given, the adjoint blocks (sum_k lambda_lm(theta_k) G^c_m(k), ...) per l.
+    """
+    lam = lambda_table(m, lmax, geom.z, geom.sint)          # (nl, nrings)
+    F = None
+    if x is not None:
+        xc, xs = split_m(x, m, lmax)
+        F = (xc @ lam, xs @ lam)
+    A = None
+    if G is not None:
+        A = (G[0] @ lam.T, G[1] @ lam.T)
+    return F, A
+
+
 def legendre_synth(x: np.ndarray, lmax: int, geom: RingGeometry):
     """F^c, F^s of shape (..., nrings, lmax+1) from packed x of shape (..., nalm)."""
     x = np.asarray(x, dtype=np.float64)
@@ -73,10 +91,9 @@ def legendre_synth(x: np.ndarray, lmax: int, geom: RingGeometry):
     Fc = np.zeros(lead + (geom.nrings, lmax + 1))
     Fs = np.zeros_like(Fc)
     for m in range(lmax + 1):
-        lam = lambda_table(m, lmax, geom.z, geom.sint)          # (nl, nrings)
-        xc, xs = split_m(x, m, lmax)
-        Fc[..., :, m] = xc @ lam
-        Fs[..., :, m] = xs @ lam
+        (fc, fs), _ = legendre_pair_m(x, None, m, lmax, geom)
+        Fc[..., :, m] = fc
+        Fs[..., :, m] = fs
     return Fc, Fs
 
 
@@ -85,14 +102,14 @@ def legendre_adjoint(Gc: np.ndarray, Gs: np.ndarray, lmax: int, geom: RingGeomet
     lead = Gc.shape[:-2]
     x = np.zeros(lead + (nalm(lmax),))
     for m in range(lmax + 1):
-        lam = lambda_table(m, lmax, geom.z, geom.sint)
+        _, (ac, as_) = legendre_pair_m(None, (Gc[..., :, m], Gs[..., :, m]), m, lmax, geom)
         if m == 0:
-            x[..., : lmax + 1] = Gc[..., :, 0] @ lam.T
+            x[..., : lmax + 1] = ac
         else:
             b = block_base(m, lmax)
             n = lmax - m + 1
-            x[..., b: b + n] = Gc[..., :, m] @ lam.T
-            x[..., b + n: b + 2 * n] = Gs[..., :, m] @ lam.T
+            x[..., b: b + n] = ac
+            x[..., b + n: b + 2 * n] = as_
     return x
 
 

@@ -29,6 +29,11 @@ SIGNATURES = {
     "mlcr_op_set_level": (c_int, [c_void_p, c_int, c_int, c_dbl_p]),
     "mlcr_op_level_lmax": (c_int, [c_void_p, c_int]),
     "apply_A": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_int, c_void_p]),
+    "mlcr_timing_enable": (c_int, [c_int]),
+    "mlcr_timing_reset": (c_int, []),
+    "mlcr_timing_count": (c_int, []),
+    "mlcr_timing_get": (c_int, [c_int, ctypes.c_char_p, c_int, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(c_ll)]),
 }
 
 _lib = None

@@ -152,3 +152,29 @@ def apply_A(op: Operator, x: torch.Tensor, level: int = 0, prec: int = FP64,
     check(load().apply_A(op.handle, int(level), nrhs, ctypes.c_void_p(x.data_ptr()),
                          ctypes.c_void_p(out.data_ptr()), prec, _stream()))
     return out
+
+
+class KernelTimer:
+    """Per-kernel HIP-event timing inside the library (context manager).
+
+    with KernelTimer() as kt: ...; kt.result -> {name: (total_ms, calls)}
+    """
+
+    def __enter__(self):
+        lib = load()
+        check(lib.mlcr_timing_reset())
+        check(lib.mlcr_timing_enable(1))
+        self.result = {}
+        return self
+
+    def __exit__(self, *exc):
+        lib = load()
+        check(lib.mlcr_timing_enable(0))
+        n = lib.mlcr_timing_count()
+        buf = ctypes.create_string_buffer(64)
+        for i in range(n):
+            ms = ctypes.c_double()
+            calls = ctypes.c_longlong()
+            check(lib.mlcr_timing_get(i, buf, 64, ctypes.byref(ms), ctypes.byref(calls)))
+            self.result[buf.value.decode()] = (ms.value, calls.value)
+        return False

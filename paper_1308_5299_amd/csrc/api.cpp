@@ -67,6 +67,55 @@ static int reserve_ws(mlcr_geom *g, int lmax, int nrhs, bool need_u) {
     return MLCR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// optional per-kernel timing with HIP events on the launch stream
+// ---------------------------------------------------------------------------
+struct TimingRec {
+    const char *name;
+    hipEvent_t a, b;
+};
+static std::vector<TimingRec> g_pending;
+static std::vector<std::pair<std::string, std::pair<double, long long>>> g_acc;
+static bool g_timing = false;
+
+struct KTimer {
+    const char *name;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    KTimer(const char *n, hipStream_t st) : name(n), s(st) {
+        if (!g_timing) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            a = b = nullptr;
+            return;
+        }
+        (void)hipEventRecord(a, s);
+    }
+    ~KTimer() {
+        if (!a) return;
+        (void)hipEventRecord(b, s);
+        g_pending.push_back({name, a, b});
+    }
+};
+
+static void drain_timing() {
+    for (auto &t : g_pending) {
+        float ms = 0.f;
+        (void)hipEventSynchronize(t.b);
+        (void)hipEventElapsedTime(&ms, t.a, t.b);
+        bool found = false;
+        for (auto &e : g_acc)
+            if (e.first == t.name) {
+                e.second.first += ms;
+                e.second.second += 1;
+                found = true;
+            }
+        if (!found) g_acc.push_back({t.name, {(double)ms, 1}});
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    g_pending.clear();
+}
+
 static int check_prec(int prec) {
     if (prec == MLCR_FP64) return MLCR_OK;
     if (prec == MLCR_FP32) return fail(MLCR_EUNSUPPORTED, "MLCR_FP32 is not available in this build");
@@ -81,6 +130,34 @@ extern "C" {
 
 const char *mlcr_last_error(void) { return g_err.c_str(); }
 const char *mlcr_version(void) { return "mlcr 0.1 (gfx950)"; }
+
+int mlcr_timing_enable(int on) {
+    drain_timing();
+    g_timing = on != 0;
+    return MLCR_OK;
+}
+
+int mlcr_timing_reset(void) {
+    drain_timing();
+    g_acc.clear();
+    return MLCR_OK;
+}
+
+int mlcr_timing_count(void) {
+    drain_timing();
+    return (int)g_acc.size();
+}
+
+int mlcr_timing_get(int i, char *name, int name_len, double *total_ms, long long *calls) {
+    drain_timing();
+    if (i < 0 || i >= (int)g_acc.size() || !name || name_len < 1)
+        return fail(MLCR_EINVAL, "bad timing index or buffer");
+    std::strncpy(name, g_acc[i].first.c_str(), (size_t)name_len - 1);
+    name[name_len - 1] = 0;
+    if (total_ms) *total_ms = g_acc[i].second.first;
+    if (calls) *calls = g_acc[i].second.second;
+    return MLCR_OK;
+}
 
 int mlcr_geom_create(int nside, int lmax, mlcr_geom **out) {
     if (!out) return fail(MLCR_EINVAL, "out is NULL");
@@ -129,8 +206,14 @@ int sht_synth(mlcr_geom *g, int lmax, int nrhs, const double *alm, double *map, 
     hipStream_t s = (hipStream_t)stream;
     LegendreArgs a{g, lmax, nrhs, s};
     double2 *F = g->wsF.as<double2>();
-    if ((rc = launch_legendre_synth(a, alm, F))) return rc;
-    if ((rc = launch_ring_synth(g, lmax, nrhs, F, map, s))) return rc;
+    {
+        KTimer t("legendre_synth", s);
+        if ((rc = launch_legendre_synth(a, alm, F))) return rc;
+    }
+    {
+        KTimer t("ring_synth", s);
+        if ((rc = launch_ring_synth(g, lmax, nrhs, F, map, s))) return rc;
+    }
     return MLCR_OK;
 }
 
@@ -148,10 +231,19 @@ int sht_adjoint(mlcr_geom *g, int lmax, int nrhs, const double *map, double *alm
     double2 *G = g->wsF.as<double2>();
     double *P = g->wsP.as<double>();
     int nch = 0;
-    if ((rc = launch_ring_adjoint(g, lmax, nrhs, map, G, s))) return rc;
-    if ((rc = launch_legendre_adjoint(a, G, P, &nch))) return rc;
-    if ((rc = launch_reduce_epilogue(lmax, nrhs, nch, P, nullptr, nullptr, nullptr, alm, s)))
-        return rc;
+    {
+        KTimer t("ring_adjoint", s);
+        if ((rc = launch_ring_adjoint(g, lmax, nrhs, map, G, s))) return rc;
+    }
+    {
+        KTimer t("legendre_adjoint", s);
+        if ((rc = launch_legendre_adjoint(a, G, P, &nch))) return rc;
+    }
+    {
+        KTimer t("reduce_epilogue", s);
+        if ((rc = launch_reduce_epilogue(lmax, nrhs, nch, P, nullptr, nullptr, nullptr, alm, s)))
+            return rc;
+    }
     return MLCR_OK;
 }
 
@@ -253,13 +345,28 @@ int apply_A(mlcr_op *op, int level, int nrhs, const double *x, double *y, int pr
     double *P = g->wsP.as<double>();
     LegendreArgs a{g, lmax, nrhs, s};
     int nch = 0;
-    if ((rc = launch_scale_l(lmax, nrhs, x, L.bh.as<double>(), u, s))) return rc;
-    if ((rc = launch_legendre_synth(a, u, F))) return rc;
-    if ((rc = launch_ring_apply(g, lmax, nrhs, F, op->ninv, s))) return rc;
-    if ((rc = launch_legendre_adjoint(a, F, P, &nch))) return rc;
-    if ((rc = launch_reduce_epilogue(lmax, nrhs, nch, P, x, L.d.as<double>(), L.bh.as<double>(), y,
-                                     s)))
-        return rc;
+    {
+        KTimer t("beam_prologue", s);
+        if ((rc = launch_scale_l(lmax, nrhs, x, L.bh.as<double>(), u, s))) return rc;
+    }
+    {
+        KTimer t("legendre_synth", s);
+        if ((rc = launch_legendre_synth(a, u, F))) return rc;
+    }
+    {
+        KTimer t("ring_apply", s);
+        if ((rc = launch_ring_apply(g, lmax, nrhs, F, op->ninv, s))) return rc;
+    }
+    {
+        KTimer t("legendre_adjoint", s);
+        if ((rc = launch_legendre_adjoint(a, F, P, &nch))) return rc;
+    }
+    {
+        KTimer t("reduce_epilogue", s);
+        if ((rc = launch_reduce_epilogue(lmax, nrhs, nch, P, x, L.d.as<double>(),
+                                         L.bh.as<double>(), y, s)))
+            return rc;
+    }
     return MLCR_OK;
 }
 

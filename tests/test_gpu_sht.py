@@ -100,6 +100,8 @@ def test_errors(mlcr):
     from paper_1308_5299_amd import MLCRError
     g = mlcr.Geometry(4, 8)
     with pytest.raises(MLCRError):
-        mlcr.sht_synth(g, dev(np.zeros(81)), lmax=9)
+        mlcr.sht_synth(g, dev(np.zeros(100)), lmax=9)      # above the geometry's lmax
     with pytest.raises(MLCRError):
         mlcr.sht_synth(g, dev(np.zeros(81)), prec=7)
+    with pytest.raises(ValueError):
+        mlcr.sht_synth(g, dev(np.zeros(80)))                # not a whole vector
