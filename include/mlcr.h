@@ -134,6 +134,79 @@ int mlcr_op_set_level(mlcr_op *op, int h, int lmax_h, const double *host_fl);
 /* Band limit of level h (0 = top), or a negative error code. */
 int mlcr_op_level_lmax(const mlcr_op *op, int h);
 
+/* ------------------------------------------------------------------------
+ * Multi-level solver (Sec. 3.2, Fig. code:mg; Sec. 4.1 for the cycle shape).
+ *
+ * Levels: the top spherical-harmonic level (lmax of the operator) with a
+ * high-pass filtered diagonal smoother diag(A)^-1; pixel levels h = 1..H,
+ * each a band-limited level operator A_h (Sec. 3.2, eq. A_h) with a sibling
+ * HEALPix grid of resolution N_side/2, N_side/4, ... and an error smoother
+ * on k x k pixel tiles (k = 8, Sec. 3.4); and a dense bottom level solved
+ * exactly for l <= 40.  Default ladder (Sec. 3.2-3.4): pixel level 1 keeps
+ * lmax, level 2 is limited to 4 N_side^h, coarser ones to 6 N_side^h, down
+ * to N_side^h = 32; the first two cumulative filters are q_l of eq.
+ * fourth-power-beam with q = 0.1 at 2570/3000 and 1536/2048 of their band
+ * limits, coarser ones Gaussians of FWHM two pixels.  Recursion counts: the
+ * top and the finest pixel level run once down and once up, the others
+ * twice (partial W-cycle, Sec. 4.1), the last pixel level once into the
+ * dense bottom.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int cycles;         /* outer cycles performed for this RHS until it converged     */
+    int converged;      /* 1 if rho <= rtol                                            */
+    double rho0;        /* sqrt(r^T S^-1 r / b^T S^-1 b) for the start vector          */
+    double rho;         /* the same ratio at return                                    */
+    double s_half_res;  /* ||S^{1/2} (b - A x)||_2; times sigma_prior = sqrt(sum_l      */
+                        /* (2l+1) C_l / 4 pi) it bounds the max pixel error of x       */
+} mlcr_solve_info;
+
+/* Build the solver for op: level geometries and operators, smoothers, the
+ * top-level diagonal and the dense bottom factor (all computed on the GPU,
+ * in float64; smoothers stored in float32, Sec. 3.4).  The operator and its
+ * geometry must outlive the solver.  ENOTPD if the bottom matrix or a tile
+ * cannot be factored even with a ridge. */
+int mlcr_solver_create(mlcr_op *op, int max_nrhs, mlcr_solver **out);
+void mlcr_solver_destroy(mlcr_solver *s);
+/* Pixel level count, bottom band limit, bottom unknowns and the largest tile
+ * ridge alpha used (relative to the largest diagonal element of the block). */
+int mlcr_solver_info(const mlcr_solver *s, int *nlevels, int *lmax_bottom, int *n_bottom,
+                     float *max_ridge);
+
+/* Copy of the top-level smoother's diagonal, 1 / diag(A) on active modes and
+ * 0 elsewhere (dev_out: [(lmax+1)^2]); diag(Y^T N^-1 Y) comes from the ring
+ * sums of eq. Ni-dense at frequencies 0 and 2m.  EINVAL for a dense-only solver. */
+int mlcr_solver_top_dinv(const mlcr_solver *s, double *dev_out, void *stream);
+
+/* CR-Solve (Fig. code:mg) in correction form: r = b - A x in float64, one
+ * CR-Cycle from zero on r, x += correction, repeat until
+ *     rho = sqrt(r^T S^-1 r / b^T S^-1 b) <= rtol        (Sec. 3.2)
+ * for every RHS or max_cycles cycles are done.  prec selects the arithmetic
+ * of the cycle's transforms; the residual and the update stay float64, so a
+ * float32 cycle is iterative refinement.
+ *   dev_b, dev_x: [nrhs][(lmax+1)^2] packed; dev_x holds the start vector
+ *   on entry (zeros allowed) and the solution on return.  Excluded modes of
+ *   x are set to 0.  host_info: [nrhs] or NULL.
+ * Returns MLCR_ENOCONV (x and info still valid) if rtol is not reached. */
+int wcycle_solve(mlcr_solver *s, int nrhs, const double *dev_b, double *dev_x, double rtol,
+                 int max_cycles, int prec, mlcr_solve_info *host_info, void *stream);
+
+/* ---- host-only helpers (no GPU needed) ---- */
+/* HEALPix NESTED to RING pixel index (Gorski et al. 2005); the tiles of the
+ * pixel-level smoothers are nested blocks of k^2 pixels. */
+int mlcr_nest2ring(int nside, long long n, const long long *host_nest, long long *host_ring);
+/* The default ladder for an observation grid nside and band limit lmax:
+ * level count, and per pixel level N_side^h, lmax^h and recursion count
+ * (arrays of 8), the top recursion count and the bottom band limit. */
+int mlcr_ladder_plan(int nside, int lmax, int *nlevels, int *nsides, int *lmaxs, int *nrec,
+                     int *nrec_top, int *lmax_bottom);
+/* Operation counts of ncycles CR-Solve cycles with the given recursion
+ * counts, walking the same recursion as wcycle_solve.  counts[4 * level +
+ * {0,1,2,3}] = visits, applications of A_h, level-transfer SHTs (Y_h) and
+ * smoother (or dense-solve) applications; level 0 = top, 1..nlevels pixel
+ * levels, nlevels + 1 = bottom.  The top count includes the float64
+ * residual of each cycle.  counts must hold 4 (nlevels + 2) entries. */
+int mlcr_cycle_counts(int nlevels, const int *nrec, int nrec_top, int ncycles, long long *counts);
+
 #ifdef __cplusplus
 }
 #endif

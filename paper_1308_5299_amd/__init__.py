@@ -6,7 +6,9 @@ kernels behind a C ABI (include/mlcr.h).  This package is a thin binding:
 torch supplies device memory and streams, every step runs in libmlcr.so.
 """
 from ._lib import MLCRError, load as load_library  # noqa: F401
-from .api import FP32, FP64, Geometry, KernelTimer, Operator, apply_A, sht_adjoint, sht_synth  # noqa: F401
+from .api import (FP32, FP64, Geometry, KernelTimer, Operator, Solver, apply_A,  # noqa: F401
+                  cycle_counts, ladder_plan, nest2ring, sht_adjoint, sht_synth)
 
 __all__ = ["MLCRError", "load_library", "FP32", "FP64", "Geometry", "Operator",
-           "apply_A", "sht_adjoint", "sht_synth", "KernelTimer"]
+           "apply_A", "sht_adjoint", "sht_synth", "KernelTimer", "Solver", "nest2ring",
+           "ladder_plan", "cycle_counts"]

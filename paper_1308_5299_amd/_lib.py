@@ -29,6 +29,17 @@ SIGNATURES = {
     "mlcr_op_set_level": (c_int, [c_void_p, c_int, c_int, c_dbl_p]),
     "mlcr_op_level_lmax": (c_int, [c_void_p, c_int]),
     "apply_A": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_int, c_void_p]),
+    "mlcr_solver_create": (c_int, [c_void_p, c_int, ctypes.POINTER(c_void_p)]),
+    "mlcr_solver_destroy": (None, [c_void_p]),
+    "mlcr_solver_info": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                                 ctypes.POINTER(c_int), ctypes.POINTER(ctypes.c_float)]),
+    "mlcr_solver_top_dinv": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "wcycle_solve": (c_int, [c_void_p, c_int, c_void_p, c_void_p, ctypes.c_double, c_int, c_int,
+                             c_void_p, c_void_p]),
+    "mlcr_nest2ring": (c_int, [c_int, c_ll, c_void_p, c_void_p]),
+    "mlcr_ladder_plan": (c_int, [c_int, c_int, ctypes.POINTER(c_int), c_void_p, c_void_p, c_void_p,
+                                 ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
+    "mlcr_cycle_counts": (c_int, [c_int, c_void_p, c_int, c_int, c_void_p]),
     "mlcr_timing_enable": (c_int, [c_int]),
     "mlcr_timing_reset": (c_int, []),
     "mlcr_timing_count": (c_int, []),
@@ -37,6 +48,12 @@ SIGNATURES = {
 }
 
 _lib = None
+
+
+class SolveInfo(ctypes.Structure):
+    """mlcr_solve_info (include/mlcr.h)."""
+    _fields_ = [("cycles", ctypes.c_int), ("converged", ctypes.c_int), ("rho0", ctypes.c_double),
+                ("rho", ctypes.c_double), ("s_half_res", ctypes.c_double)]
 
 
 class MLCRError(RuntimeError):

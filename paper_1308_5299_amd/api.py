@@ -178,3 +178,83 @@ class KernelTimer:
             check(lib.mlcr_timing_get(i, buf, 64, ctypes.byref(ms), ctypes.byref(calls)))
             self.result[buf.value.decode()] = (ms.value, calls.value)
         return False
+
+
+class Solver:
+    """Multi-level CR solver (W-cycle) for an Operator; see include/mlcr.h."""
+
+    def __init__(self, op: Operator, max_nrhs: int = 1):
+        lib = load()
+        self.op = op
+        self.max_nrhs = int(max_nrhs)
+        h = ctypes.c_void_p()
+        check(lib.mlcr_solver_create(op.handle, self.max_nrhs, ctypes.byref(h)))
+        self._h = h
+
+    def info(self) -> dict:
+        nl, lb, nb = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        rg = ctypes.c_float()
+        check(load().mlcr_solver_info(self._h, ctypes.byref(nl), ctypes.byref(lb), ctypes.byref(nb),
+                                      ctypes.byref(rg)))
+        return {"nlevels": nl.value, "lmax_bottom": lb.value, "n_bottom": nb.value,
+                "max_ridge": rg.value}
+
+    def top_dinv(self) -> torch.Tensor:
+        out = torch.empty((nalm(self.op.lmax),), dtype=torch.float64, device=self.op.ninv.device)
+        check(load().mlcr_solver_top_dinv(self._h, ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def solve(self, b: torch.Tensor, x0: torch.Tensor | None = None, rtol: float = 1e-8,
+              max_cycles: int = 50, prec: int = FP64, raise_on_noconv: bool = True):
+        """Returns (x, infos); infos is a list of dicts, one per RHS."""
+        from ._lib import MLCRError, SolveInfo
+
+        _dev(b, "b")
+        nrhs = _batch(b, nalm(self.op.lmax), "b")
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        infos = (SolveInfo * nrhs)()
+        rc = load().wcycle_solve(self._h, nrhs, ctypes.c_void_p(b.data_ptr()),
+                                 ctypes.c_void_p(x.data_ptr()), float(rtol), int(max_cycles),
+                                 int(prec), ctypes.cast(infos, ctypes.c_void_p), _stream())
+        out = [{k: getattr(i, k) for k, _ in SolveInfo._fields_} for i in infos]
+        if rc != 0 and not (rc == -5 and not raise_on_noconv):
+            check(rc)
+        return x, out
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().mlcr_solver_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def nest2ring(nside: int, nest) -> np.ndarray:
+    nest = np.ascontiguousarray(np.asarray(nest, dtype=np.int64))
+    out = np.empty_like(nest)
+    check(load().mlcr_nest2ring(int(nside), nest.size, nest.ctypes.data, out.ctypes.data))
+    return out
+
+
+def ladder_plan(nside: int, lmax: int) -> dict:
+    nl, nt, lb = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    ns = np.zeros(8, dtype=np.int32)
+    lm = np.zeros(8, dtype=np.int32)
+    nr = np.zeros(8, dtype=np.int32)
+    check(load().mlcr_ladder_plan(int(nside), int(lmax), ctypes.byref(nl), ns.ctypes.data,
+                                  lm.ctypes.data, nr.ctypes.data, ctypes.byref(nt), ctypes.byref(lb)))
+    n = nl.value
+    return {"nlevels": n, "nside": ns[:n].tolist(), "lmax": lm[:n].tolist(),
+            "nrec": nr[:n].tolist(), "nrec_top": nt.value, "lmax_bottom": lb.value}
+
+
+def cycle_counts(nrec, nrec_top: int, ncycles: int = 1) -> np.ndarray:
+    nrec = np.ascontiguousarray(np.asarray(nrec, dtype=np.int32))
+    nl = nrec.size
+    out = np.zeros(4 * (nl + 2), dtype=np.int64)
+    check(load().mlcr_cycle_counts(nl, nrec.ctypes.data, int(nrec_top), int(ncycles), out.ctypes.data))
+    return out.reshape(nl + 2, 4)

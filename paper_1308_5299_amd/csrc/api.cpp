@@ -10,6 +10,7 @@
 #include <string>
 
 #include "mlcr_internal.h"
+#include "solver_internal.h"
 
 namespace mlcr {
 
@@ -43,6 +44,16 @@ void DevBuf::release() {
     if (ptr) (void)hipFree(ptr);
     ptr = nullptr;
     bytes = 0;
+}
+
+int ensure_dynamic_lds(const void *func, size_t bytes) {
+    if (bytes <= 64 * 1024) return MLCR_OK;
+    static std::vector<std::pair<const void *, size_t>> done;
+    for (auto &d : done)
+        if (d.first == func && d.second >= bytes) return MLCR_OK;
+    MLCR_HIP_CHECK(hipFuncSetAttribute(func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    done.push_back({func, bytes});
+    return MLCR_OK;
 }
 
 static void release_geom(mlcr_geom *g) {
@@ -120,6 +131,53 @@ static int check_prec(int prec) {
     if (prec == MLCR_FP64) return MLCR_OK;
     if (prec == MLCR_FP32) return fail(MLCR_EUNSUPPORTED, "MLCR_FP32 is not available in this build");
     return fail(MLCR_EINVAL, "unknown precision");
+}
+
+}  // namespace mlcr
+
+namespace mlcr {
+
+int apply_level(mlcr_op *op, int level, int nrhs, const double *x, double *y, int prec,
+                hipStream_t s) {
+    if (!op || !x || !y) return fail(MLCR_EINVAL, "NULL argument");
+    if (x == y) return fail(MLCR_EINVAL, "x and y must not alias");
+    if (level < 0 || level >= 16 || op->levels[level].lmax < 0)
+        return fail(MLCR_EINVAL, "level not defined");
+    if (nrhs < 1) return fail(MLCR_EINVAL, "nrhs must be >= 1");
+    int rc;
+    if ((rc = check_prec(prec))) return rc;
+    mlcr_geom *g = op->g;
+    const mlcr_level &L = op->levels[level];
+    const int lmax = L.lmax;
+    if ((rc = reserve_ws(g, lmax, nrhs, true))) return rc;
+    double *u = g->wsU.as<double>();
+    double2 *F = g->wsF.as<double2>();
+    double *P = g->wsP.as<double>();
+    LegendreArgs a{g, lmax, nrhs, s};
+    int nch = 0;
+    {
+        KTimer t("beam_prologue", s);
+        if ((rc = launch_scale_l(lmax, nrhs, x, L.bh.as<double>(), u, s))) return rc;
+    }
+    {
+        KTimer t("legendre_synth", s);
+        if ((rc = launch_legendre_synth(a, u, F))) return rc;
+    }
+    {
+        KTimer t("ring_apply", s);
+        if ((rc = launch_ring_apply(g, lmax, nrhs, F, op->ninv, s))) return rc;
+    }
+    {
+        KTimer t("legendre_adjoint", s);
+        if ((rc = launch_legendre_adjoint(a, F, P, &nch))) return rc;
+    }
+    {
+        KTimer t("reduce_epilogue", s);
+        if ((rc = launch_reduce_epilogue(lmax, nrhs, nch, P, x, L.d.as<double>(),
+                                         L.bh.as<double>(), y, s)))
+            return rc;
+    }
+    return MLCR_OK;
 }
 
 }  // namespace mlcr
@@ -329,45 +387,8 @@ int mlcr_op_level_lmax(const mlcr_op *op, int h) {
 
 int apply_A(mlcr_op *op, int level, int nrhs, const double *x, double *y, int prec, void *stream) {
     if (!op || !x || !y) return fail(MLCR_EINVAL, "NULL argument");
-    if (x == y) return fail(MLCR_EINVAL, "x and y must not alias");
-    if (level < 0 || level >= 16 || op->levels[level].lmax < 0)
-        return fail(MLCR_EINVAL, "level not defined");
     if (nrhs < 1 || nrhs > op->max_nrhs) return fail(MLCR_EINVAL, "nrhs out of [1, max_nrhs]");
-    int rc;
-    if ((rc = check_prec(prec))) return rc;
-    mlcr_geom *g = op->g;
-    const mlcr_level &L = op->levels[level];
-    const int lmax = L.lmax;
-    if ((rc = reserve_ws(g, lmax, nrhs, true))) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    double *u = g->wsU.as<double>();
-    double2 *F = g->wsF.as<double2>();
-    double *P = g->wsP.as<double>();
-    LegendreArgs a{g, lmax, nrhs, s};
-    int nch = 0;
-    {
-        KTimer t("beam_prologue", s);
-        if ((rc = launch_scale_l(lmax, nrhs, x, L.bh.as<double>(), u, s))) return rc;
-    }
-    {
-        KTimer t("legendre_synth", s);
-        if ((rc = launch_legendre_synth(a, u, F))) return rc;
-    }
-    {
-        KTimer t("ring_apply", s);
-        if ((rc = launch_ring_apply(g, lmax, nrhs, F, op->ninv, s))) return rc;
-    }
-    {
-        KTimer t("legendre_adjoint", s);
-        if ((rc = launch_legendre_adjoint(a, F, P, &nch))) return rc;
-    }
-    {
-        KTimer t("reduce_epilogue", s);
-        if ((rc = launch_reduce_epilogue(lmax, nrhs, nch, P, x, L.d.as<double>(),
-                                         L.bh.as<double>(), y, s)))
-            return rc;
-    }
-    return MLCR_OK;
+    return apply_level(op, level, nrhs, x, y, prec, (hipStream_t)stream);
 }
 
 }  // extern "C"

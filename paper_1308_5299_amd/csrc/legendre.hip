@@ -290,7 +290,7 @@ __global__ __launch_bounds__(64) void k_lsynth_f64(
 // and stored to (first block of the chunk) or added to the partial result
 // of this chunk of ring pairs.  Every output address is owned by one lane,
 // so the chunk's partial sums are formed in a fixed order.
-template <int NR, int RC, int LB>
+template <int NR, int RC, int LB, bool SQ>
 __global__ __launch_bounds__(64) void k_ladj_f64(
     const double2 *__restrict__ G, long long fstride, int nrhs, double *__restrict__ P,
     long long nalm, int pb_per_chunk, int lmax, const double *__restrict__ rz,
@@ -394,7 +394,8 @@ __global__ __launch_bounds__(64) void k_ladj_f64(
             for (int r = 0; r < RC; r++) tc[r] = ts[r] = 0.0;
 #pragma unroll
             for (int j = 0; j < NR; j++) {
-                const double v = masked ? L.w(j) : L.l1[j];
+                double v = masked ? L.w(j) : L.l1[j];
+                if (SQ) v = v * v;
 #pragma unroll
                 for (int r = 0; r < RC; r++) {
                     tc[r] = fma(v, gc[j][r], tc[r]);
@@ -413,13 +414,13 @@ __global__ __launch_bounds__(64) void k_ladj_f64(
         // phase B: mixed
         while (l <= lmax && !__all(L.all_normal())) {
             if (((l - m) & 1) == 0) put(l, true, gec, ges);
-            else put(l, true, goc, gos);
+            else put(l, true, SQ ? gec : goc, SQ ? ges : gos);
             if (l < lmax) L.step_rescale(abm[l + 1]);
             l++;
         }
         // phase C: align to even l-m, then two steps per trip
         if (l <= lmax && ((l - m) & 1)) {
-            put(l, false, goc, gos);
+            put(l, false, SQ ? gec : goc, SQ ? ges : gos);
             if (l < lmax) L.step(abm[l + 1]);
             l++;
         }
@@ -429,7 +430,7 @@ __global__ __launch_bounds__(64) void k_ladj_f64(
                 const double2 na = abm[min(l + 3, lmax)], nb = abm[min(l + 4, lmax)];
                 put(l, false, gec, ges);
                 L.step(ca);
-                put(l + 1, false, goc, gos);
+                put(l + 1, false, SQ ? gec : goc, SQ ? ges : gos);
                 L.step(cb);
                 ca = na;
                 cb = nb;
@@ -470,7 +471,8 @@ int launch_legendre_synth(const LegendreArgs &a, const double *u, double2 *F) {
     return MLCR_OK;
 }
 
-int launch_legendre_adjoint(const LegendreArgs &a, const double2 *G, double *P, int *nchunks_out) {
+template <bool SQ>
+static int launch_ladj(const LegendreArgs &a, const double2 *G, double *P, int *nchunks_out) {
     const mlcr_geom *g = a.g;
     const int npb = (g->npairs + 64 * kAdjNR - 1) / (64 * kAdjNR);
     const int nchunks = adjoint_chunks(g, a.lmax);
@@ -480,7 +482,7 @@ int launch_legendre_adjoint(const LegendreArgs &a, const double2 *G, double *P, 
     const long long grid = ((total + 7) / 8) * 8;
     const long long nalm = (long long)(a.lmax + 1) * (a.lmax + 1);
     const long long fstride = (long long)g->nrings * (a.lmax + 1);
-    hipLaunchKernelGGL((k_ladj_f64<kAdjNR, kAdjRC, kAdjLB>), dim3((unsigned)grid), dim3(64), 0,
+    hipLaunchKernelGGL((k_ladj_f64<kAdjNR, kAdjRC, kAdjLB, SQ>), dim3((unsigned)grid), dim3(64), 0,
                        a.stream, G, fstride, a.nrhs, P, nalm, per, a.lmax,
                        g->ring_z.as<double>(), g->ring_s.as<double>(), g->ab.as<double2>(),
                        g->aboff.as<long long>(), g->seed.as<double>(), g->nrings, g->npairs, npb,
@@ -488,6 +490,17 @@ int launch_legendre_adjoint(const LegendreArgs &a, const double2 *G, double *P, 
     MLCR_HIP_CHECK(hipGetLastError());
     *nchunks_out = nchunks;
     return MLCR_OK;
+}
+
+int launch_legendre_adjoint(const LegendreArgs &a, const double2 *G, double *P, int *nchunks_out) {
+    return launch_ladj<false>(a, G, P, nchunks_out);
+}
+
+// Same reduction with lambda^2 in place of lambda and the even ring sums for
+// every l (the parity sign squares away): sum_k lambda_lm(theta_k)^2 G_m(theta_k).
+int launch_legendre_adjoint_sq(const LegendreArgs &a, const double2 *G, double *P,
+                               int *nchunks_out) {
+    return launch_ladj<true>(a, G, P, nchunks_out);
 }
 
 }  // namespace mlcr

@@ -102,6 +102,10 @@ struct mlcr_op {
 
 namespace mlcr {
 
+// Raise a kernel's dynamic LDS limit to `bytes` when it exceeds the 64 KiB
+// default (gfx950 allows up to 160 KiB per workgroup, static plus dynamic).
+int ensure_dynamic_lds(const void *func, size_t bytes);
+
 // geometry.cpp
 int build_geometry(mlcr_geom *g, int nside, int lmax);
 

@@ -210,13 +210,8 @@ static int launch_ring(const mlcr_geom *g, int lmax, int nrhs, const double2 *F,
                        const double *map_in, double *map_out, const double *ninv,
                        hipStream_t s) {
     const size_t lds = (size_t)g->lds_cplx * sizeof(double2);
-    static bool attr_set = false;
-    if (!attr_set) {
-        MLCR_HIP_CHECK(hipFuncSetAttribute((const void *)k_ring<MODE>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           160 * 1024));
-        attr_set = true;
-    }
+    int rc = ensure_dynamic_lds((const void *)k_ring<MODE>, lds);
+    if (rc) return rc;
     const long long fstride = (long long)g->nrings * (lmax + 1);
     hipLaunchKernelGGL(k_ring<MODE>, dim3(g->nrings, nrhs), dim3(kRingThreads), lds, s, F, G,
                        map_in, map_out, ninv, g->rings.as<RingInfo>(), g->lens.as<LenInfo>(),

@@ -1,0 +1,701 @@
+// Multi-level CR solver (Sec. 3.2, Fig. code:mg) on top of the operator
+// kernels: level ladder, smoother construction, the recursive CR-Cycle and
+// the float64 outer CR-Solve loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "solver_internal.h"
+
+namespace mlcr {
+
+// ---------------------------------------------------------------------------
+// HEALPix NESTED -> RING (Gorski et al. 2005): a nested index holds the base
+// face and the bit-interleaved (x, y) position inside it; ring number and
+// position in the ring follow from the face's row/column offsets.
+// ---------------------------------------------------------------------------
+long long nest2ring(int nside, long long ipnest) {
+    static const int jrll[12] = {2, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4};
+    static const int jpll[12] = {1, 3, 5, 7, 0, 2, 4, 6, 1, 3, 5, 7};
+    const long long npface = (long long)nside * nside;
+    const int face = (int)(ipnest / npface);
+    long long ipf = ipnest % npface;
+    long long ix = 0, iy = 0;
+    for (int b = 0; ipf; b++) {
+        ix |= (ipf & 1LL) << b;
+        ipf >>= 1;
+        iy |= (ipf & 1LL) << b;
+        ipf >>= 1;
+    }
+    const long long jr = (long long)jrll[face] * nside - ix - iy - 1;
+    const long long npix = 12 * npface;
+    long long nr, n_before;
+    int kshift;
+    if (jr < nside) {
+        nr = jr;
+        n_before = 2 * nr * (nr - 1);
+        kshift = 0;
+    } else if (jr > 3LL * nside) {
+        nr = 4LL * nside - jr;
+        n_before = npix - 2 * (nr + 1) * nr;
+        kshift = 0;
+    } else {
+        nr = nside;
+        n_before = 2LL * nside * (nside - 1) + (jr - nside) * 4LL * nside;
+        kshift = (int)((jr - nside) & 1);
+    }
+    long long jp = (jpll[face] * nr + ix - iy + 1 + kshift) / 2;
+    if (jp > 4 * nr) jp -= 4 * nr;
+    if (jp < 1) jp += 4 * nr;
+    return n_before + jp - 1;
+}
+
+// ---------------------------------------------------------------------------
+// ladder (Sec. 3.2 level structure; Sec. 3.3 filters; Sec. 3.4 band limits)
+// ---------------------------------------------------------------------------
+static constexpr int kDenseL = 40;     // bottom level: dense solve for l <= 40 (Sec. 3.2)
+static constexpr int kTile = 8;        // k = 8 pixel tiles (Sec. 3.4)
+static const double kPi = 3.14159265358979323846;
+
+struct Plan {
+    int H = 0;
+    int nside[8] = {0}, lmax[8] = {0}, nrec[8] = {0};
+    int nrec_top = 1;
+    int lmax_b = 0;
+    std::vector<double> fl[8];
+    std::vector<double> highpass;
+    double omega = 1.0, omega_top = 1.0;
+};
+
+// q_l = exp(-l^2 (l+1)^2 lambda) with q_{lstar} = 0.1 (eq. fourth-power-beam)
+static std::vector<double> qfilter(int lmax, int lstar) {
+    std::vector<double> f(lmax + 1);
+    const double ls = (double)lstar;
+    const double lam = std::log(10.0) / (ls * ls * (ls + 1) * (ls + 1));
+    for (int l = 0; l <= lmax; l++) {
+        const double t = (double)l * l * (l + 1.0) * (l + 1.0) * lam;
+        f[l] = std::exp(-t);
+    }
+    return f;
+}
+
+// Gaussian of FWHM two pixels of the level's grid (Sec. 3.3; p_l = 1)
+static std::vector<double> gauss2px(int lmax, int nside) {
+    std::vector<double> f(lmax + 1);
+    const double pix = std::sqrt(4.0 * kPi / (12.0 * nside * nside));
+    const double sig = 2.0 * pix / std::sqrt(8.0 * std::log(2.0));
+    for (int l = 0; l <= lmax; l++) f[l] = std::exp(-0.5 * l * (l + 1.0) * sig * sig);
+    return f;
+}
+
+static void default_plan(int nside_obs, int lmax, Plan &p) {
+    p = Plan();
+    if (lmax <= kDenseL) {
+        p.H = 0;
+        p.lmax_b = lmax;
+        return;
+    }
+    int ns = nside_obs / 2, lprev = lmax;
+    while (ns >= 32 && p.H < 8 && ns % kTile == 0) {
+        int lh;
+        if (p.H == 0) lh = lmax;                         // finest level keeps the full band
+        else if (p.H == 1) lh = std::min(lprev, 4 * ns); // 4 N_side at the second level
+        else lh = std::min(lprev, 6 * ns);               // up to 6 N_side on coarse levels
+        if (lh <= kDenseL) break;
+        p.nside[p.H] = ns;
+        p.lmax[p.H] = lh;
+        p.nrec[p.H] = 2;
+        p.H++;
+        lprev = lh;
+        ns /= 2;
+    }
+    if (p.H == 0) {
+        p.lmax_b = lmax;
+        return;
+    }
+    p.nrec[p.H - 1] = 1;          // the dense bottom solve is exact: one visit
+    p.nrec_top = 1;               // finest level runs once down, once up
+    for (int h = 0; h < p.H; h++) {
+        if (h == 0) p.fl[h] = qfilter(p.lmax[h], (int)std::lround(p.lmax[h] * 2570.0 / 3000.0));
+        else if (h == 1) p.fl[h] = qfilter(p.lmax[h], (int)std::lround(p.lmax[h] * 1536.0 / 2048.0));
+        else p.fl[h] = gauss2px(p.lmax[h], p.nside[h]);
+    }
+    p.lmax_b = std::min(kDenseL, p.lmax[p.H - 1]);
+    p.highpass.resize(lmax + 1);
+    for (int l = 0; l <= lmax; l++) p.highpass[l] = 1.0 - (l <= p.lmax[0] ? p.fl[0][l] : 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// CR-Cycle recursion (Fig. code:mg), shared by the GPU and the counting backend
+// Levels: 0 = top spherical-harmonic level (diagonal smoother), 1..H pixel
+// levels, B = H + 1 dense bottom (or 0 when there is no pixel level).
+// ---------------------------------------------------------------------------
+struct CycleOps {
+    virtual ~CycleOps() {}
+    virtual int residual(int h, bool xzero) = 0;   // r_h = b_h - A_h x_h
+    virtual int smooth(int h) = 0;                 // x_h += M_h r_h
+    virtual int restrict_down(int h) = 0;          // b_{h+1} = I r_h, x_{h+1} = 0
+    virtual int prolong_up(int h) = 0;             // x_h += I^T x_{h+1}
+    virtual int bottom(int h) = 0;                 // x_h = A_h^-1 b_h
+    virtual void visit(int h) = 0;
+};
+
+static int cr_cycle(CycleOps &o, int h, int B, const std::vector<int> &nrec, bool xzero) {
+    int rc;
+    o.visit(h);
+    if (h == B) return o.bottom(h);
+    if ((rc = o.residual(h, xzero))) return rc;      // pre-smoothing
+    if ((rc = o.smooth(h))) return rc;
+    if ((rc = o.residual(h, false))) return rc;      // restricted residual
+    if ((rc = o.restrict_down(h))) return rc;
+    for (int i = 0; i < nrec[h]; i++)                // recurse, c_H starts at 0
+        if ((rc = cr_cycle(o, h + 1, B, nrec, i == 0))) return rc;
+    if ((rc = o.prolong_up(h))) return rc;           // apply correction
+    if ((rc = o.residual(h, false))) return rc;      // post-smoothing
+    return o.smooth(h);
+}
+
+struct CountOps : CycleOps {
+    // per level: visits, A_h applications, level-transfer SHTs (Y_h), smoother/bottom applications
+    std::vector<long long> c;
+    int B;
+    explicit CountOps(int nl, int b) : c(4 * nl, 0), B(b) {}
+    int residual(int h, bool xzero) override {
+        if (!xzero) c[4 * h + 1]++;
+        return 0;
+    }
+    int smooth(int h) override {
+        c[4 * h + 3]++;
+        if (h > 0) c[4 * h + 2] += 2;
+        return 0;
+    }
+    int restrict_down(int) override { return 0; }
+    int prolong_up(int) override { return 0; }
+    int bottom(int h) override {
+        c[4 * h + 3]++;
+        return 0;
+    }
+    void visit(int h) override { c[4 * h]++; }
+};
+
+}  // namespace mlcr
+
+// ---------------------------------------------------------------------------
+// solver object
+// ---------------------------------------------------------------------------
+using namespace mlcr;
+
+struct PixLevel {
+    int nside = 0, lmax = 0, opl = 0;
+    mlcr_geom *geom = nullptr;
+    int ntiles = 0, kk = kTile * kTile;
+    DevBuf wdown, act, one, tilepix, minv, ridge;
+    DevBuf x, b, r, t, map, cmap;
+};
+
+struct mlcr_solver {
+    mlcr_op *op = nullptr;
+    int max_nrhs = 0;
+    Plan plan;
+    bool direct = false;
+    std::vector<std::unique_ptr<PixLevel>> lev;       // pixel levels 1..H
+    // top
+    DevBuf top_wdown, top_dinv, top_hp, top_act, x0, b0, r0, t0;
+    // bottom
+    int lmax_b = 0, opl_b = 0, na = 0;
+    DevBuf b_idx, b_inv, xb, bb;
+    // outer loop
+    DevBuf sinv, chalf, partial, norms, ro, to;
+    std::vector<float> ridge_summary;
+    int mode = 0;
+    ~mlcr_solver() {
+        for (auto &L : lev)
+            if (L->geom) mlcr_geom_destroy(L->geom);
+    }
+};
+
+namespace mlcr {
+
+static long long nalm_l(int lmax) { return (long long)(lmax + 1) * (lmax + 1); }
+
+static int up(DevBuf &b, const void *src, size_t bytes) {
+    if (b.reserve(bytes)) return fail(MLCR_ENOMEM, "solver allocation failed");
+    MLCR_HIP_CHECK(hipMemcpy(b.ptr, src, bytes, hipMemcpyHostToDevice));
+    return MLCR_OK;
+}
+static int alloc(DevBuf &b, size_t bytes) {
+    if (b.reserve(bytes)) return fail(MLCR_ENOMEM, "solver allocation failed");
+    return MLCR_OK;
+}
+
+struct GpuOps : CycleOps {
+    mlcr_solver *S;
+    int R, prec;
+    hipStream_t s;
+    GpuOps(mlcr_solver *s_, int r, int p, hipStream_t st) : S(s_), R(r), prec(p), s(st) {}
+    int H() const { return S->plan.H; }
+    void visit(int) override {}
+
+    // buffers of level h
+    double *X(int h) { return h == 0 ? S->x0.as<double>() : S->lev[h - 1]->x.as<double>(); }
+    double *Bv(int h) { return h == 0 ? S->b0.as<double>() : S->lev[h - 1]->b.as<double>(); }
+    double *Rv(int h) { return h == 0 ? S->r0.as<double>() : S->lev[h - 1]->r.as<double>(); }
+    double *Tv(int h) { return h == 0 ? S->t0.as<double>() : S->lev[h - 1]->t.as<double>(); }
+    int Lmax(int h) { return h == 0 ? S->op->lmax : S->lev[h - 1]->lmax; }
+    int Opl(int h) { return h == 0 ? 0 : S->lev[h - 1]->opl; }
+    const double *Act(int h) {
+        return h == 0 ? S->top_act.as<double>() : S->lev[h - 1]->act.as<double>();
+    }
+
+    int residual(int h, bool xzero) override {
+        int rc;
+        if (xzero) return launch_residual(Bv(h), nullptr, Rv(h), Act(h), Lmax(h), R, s);
+        if ((rc = apply_level(S->op, Opl(h), R, X(h), Tv(h), prec, s))) return rc;
+        return launch_residual(Bv(h), Tv(h), Rv(h), Act(h), Lmax(h), R, s);
+    }
+    int smooth(int h) override {
+        if (h == 0)
+            return launch_axpy_l(X(0), Rv(0), S->top_hp.as<double>(), S->top_dinv.as<double>(),
+                                 Lmax(0), R, s);
+        PixLevel &L = *S->lev[h - 1];
+        int rc;
+        // x_h += Y_h^T M_h Y_h r_h  (eqs. pixel-correction-1..3)
+        if ((rc = sht_synth(L.geom, L.lmax, R, L.r.as<double>(), L.map.as<double>(), prec, s)))
+            return rc;
+        if ((rc = launch_tile_apply(L.map.as<double>(), L.cmap.as<double>(), L.geom->npix, R,
+                                    L.tilepix.as<int>(), L.minv.as<float>(), L.ntiles, L.kk, 1.0,
+                                    s)))
+            return rc;
+        if ((rc = sht_adjoint(L.geom, L.lmax, R, L.cmap.as<double>(), L.t.as<double>(), prec, s)))
+            return rc;
+        return launch_axpy_l(L.x.as<double>(), L.t.as<double>(), L.one.as<double>(), nullptr,
+                             L.lmax, R, s);
+    }
+    int restrict_down(int h) override {
+        const double *w = h == 0 ? S->top_wdown.as<double>() : S->lev[h - 1]->wdown.as<double>();
+        int rc;
+        if (h + 1 == H() + 1) {          // into the dense bottom level
+            if ((rc = launch_transfer(Rv(h), Lmax(h), S->bb.as<double>(), S->lmax_b, w, S->lmax_b,
+                                      false, R, s)))
+                return rc;
+            return MLCR_OK;
+        }
+        if ((rc = launch_transfer(Rv(h), Lmax(h), Bv(h + 1), Lmax(h + 1), w, Lmax(h + 1), false, R,
+                                  s)))
+            return rc;
+        MLCR_HIP_CHECK(hipMemsetAsync(X(h + 1), 0, (size_t)R * nalm_l(Lmax(h + 1)) * sizeof(double), s));
+        return MLCR_OK;
+    }
+    int prolong_up(int h) override {
+        const double *w = h == 0 ? S->top_wdown.as<double>() : S->lev[h - 1]->wdown.as<double>();
+        if (h + 1 == H() + 1)
+            return launch_transfer(S->xb.as<double>(), S->lmax_b, X(h), Lmax(h), w, S->lmax_b,
+                                   true, R, s);
+        return launch_transfer(X(h + 1), Lmax(h + 1), X(h), Lmax(h), w, Lmax(h + 1), true, R, s);
+    }
+    int bottom(int h) override {
+        if (S->direct)       // the top level itself is dense: x_0 = A^-1 b_0
+            return launch_dense_apply(S->b_inv.as<double>(), S->na, S->b_idx.as<int>(),
+                                      S->b0.as<double>(), S->x0.as<double>(), nalm_l(S->lmax_b),
+                                      R, s);
+        (void)h;
+        return launch_dense_apply(S->b_inv.as<double>(), S->na, S->b_idx.as<int>(),
+                                  S->bb.as<double>(), S->xb.as<double>(), nalm_l(S->lmax_b), R, s);
+    }
+};
+
+// ---- setup pieces ----------------------------------------------------------
+static int setup_top_diag(mlcr_solver *S, hipStream_t s) {
+    mlcr_op *op = S->op;
+    mlcr_geom *g = op->g;
+    const int lmax = op->lmax;
+    const int l2 = 2 * lmax;
+    // ring sums Xi_k(D), D <= 2 lmax, of the map xi = N^-1 (eq. Ni-dense)
+    DevBuf Xi, G2, q;
+    int rc;
+    if ((rc = alloc(Xi, (size_t)g->nrings * (l2 + 1) * sizeof(double2)))) return rc;
+    if ((rc = alloc(G2, (size_t)g->nrings * (lmax + 1) * sizeof(double2)))) return rc;
+    if ((rc = alloc(q, (size_t)nalm_l(lmax) * sizeof(double)))) return rc;
+    if (g->wsP.reserve((size_t)adjoint_chunks(g, lmax) * nalm_l(lmax) * sizeof(double)))
+        return fail(MLCR_ENOMEM, "workspace allocation failed");
+    if ((rc = launch_ring_adjoint(g, l2, 1, op->ninv, Xi.as<double2>(), s))) return rc;
+    if ((rc = launch_diag_pairs(Xi.as<double2>(), l2 + 1, G2.as<double2>(), lmax, g->nrings, s)))
+        return rc;
+    LegendreArgs a{g, lmax, 1, s};
+    int nch = 0;
+    if ((rc = launch_legendre_adjoint_sq(a, G2.as<double2>(), g->wsP.as<double>(), &nch))) return rc;
+    if ((rc = launch_reduce_epilogue(lmax, 1, nch, g->wsP.as<double>(), nullptr, nullptr, nullptr,
+                                     q.as<double>(), s)))
+        return rc;
+    if ((rc = alloc(S->top_dinv, (size_t)nalm_l(lmax) * sizeof(double)))) return rc;
+    const mlcr_level &L0 = op->levels[0];
+    if ((rc = launch_diag_inverse(q.as<double>(), L0.d.as<double>(), L0.bh.as<double>(),
+                                  S->top_dinv.as<double>(), lmax, s)))
+        return rc;
+    MLCR_HIP_CHECK(hipStreamSynchronize(s));
+    return MLCR_OK;
+}
+
+static int setup_smoother(mlcr_solver *S, PixLevel &L, hipStream_t s) {
+    int rc;
+    const int kk = L.kk;
+    const int nt = 12 * (L.nside / kTile) * (L.nside / kTile);
+    L.ntiles = nt;
+    std::vector<int> tp((size_t)nt * kk);
+    for (long long i = 0; i < (long long)nt * kk; i++) tp[i] = (int)nest2ring(L.nside, i);
+    if ((rc = up(L.tilepix, tp.data(), tp.size() * sizeof(int)))) return rc;
+    const long long npix = L.geom->npix, na = nalm_l(L.lmax);
+    const int P = 16;          // probes per batch
+    DevBuf maps, U, V, blocks;
+    if ((rc = alloc(maps, (size_t)P * npix * sizeof(double)))) return rc;
+    if ((rc = alloc(U, (size_t)P * na * sizeof(double)))) return rc;
+    if ((rc = alloc(V, (size_t)P * na * sizeof(double)))) return rc;
+    if ((rc = alloc(blocks, (size_t)nt * kk * kk * sizeof(double)))) return rc;
+    // column c of the block of tile t: (Y_h A_h Y_h^T e_c)[tile t], with e_c the
+    // indicator of position c in every tile (tiles at least k pixels apart)
+    for (int c0 = 0; c0 < kk; c0 += P) {
+        const int np = std::min(P, kk - c0);
+        if ((rc = launch_probe_maps(maps.as<double>(), npix, L.tilepix.as<int>(), nt, kk, c0, np, s)))
+            return rc;
+        if ((rc = sht_adjoint(L.geom, L.lmax, np, maps.as<double>(), U.as<double>(), MLCR_FP64, s)))
+            return rc;
+        if ((rc = apply_level(S->op, L.opl, np, U.as<double>(), V.as<double>(), MLCR_FP64, s)))
+            return rc;
+        if ((rc = sht_synth(L.geom, L.lmax, np, V.as<double>(), maps.as<double>(), MLCR_FP64, s)))
+            return rc;
+        if ((rc = launch_probe_collect(maps.as<double>(), npix, L.tilepix.as<int>(), nt, kk, c0, np,
+                                       blocks.as<double>(), s)))
+            return rc;
+    }
+    if ((rc = alloc(L.minv, (size_t)nt * kk * kk * sizeof(float)))) return rc;
+    if ((rc = alloc(L.ridge, (size_t)nt * sizeof(float)))) return rc;
+    if ((rc = launch_tile_factor(blocks.as<double>(), nt, kk, L.minv.as<float>(),
+                                 L.ridge.as<float>(), s)))
+        return rc;
+    MLCR_HIP_CHECK(hipStreamSynchronize(s));
+    std::vector<float> rg(nt);
+    MLCR_HIP_CHECK(hipMemcpy(rg.data(), L.ridge.ptr, nt * sizeof(float), hipMemcpyDeviceToHost));
+    float worst = 0.f;
+    for (float v : rg) {
+        if (v < 0) return fail(MLCR_ENOTPD, "tile factorization failed even with a ridge");
+        worst = std::max(worst, v);
+    }
+    S->ridge_summary.push_back(worst);
+    return MLCR_OK;
+}
+
+static int setup_bottom(mlcr_solver *S, hipStream_t s) {
+    mlcr_op *op = S->op;
+    const int lb = S->lmax_b;
+    const long long nb = nalm_l(lb);
+    // active modes of the bottom level in packed order
+    std::vector<int> idx;
+    {
+        long long pos = 0;
+        for (int l = 0; l <= lb; l++, pos++)
+            if (op->cl[l] > 0) idx.push_back((int)pos);
+        for (int m = 1; m <= lb; m++)
+            for (int cs = 0; cs < 2; cs++)
+                for (int l = m; l <= lb; l++, pos++)
+                    if (op->cl[l] > 0) idx.push_back((int)pos);
+    }
+    const int na = (int)idx.size();
+    S->na = na;
+    int rc;
+    if ((rc = up(S->b_idx, idx.data(), idx.size() * sizeof(int)))) return rc;
+    if (na == 0) return fail(MLCR_EINVAL, "no active modes at the bottom level");
+    DevBuf cols, X, Ad, info;
+    const int P = 64;
+    if ((rc = alloc(cols, (size_t)na * nb * sizeof(double)))) return rc;
+    if ((rc = alloc(X, (size_t)P * nb * sizeof(double)))) return rc;
+    for (int j0 = 0; j0 < na; j0 += P) {
+        const int np = std::min(P, na - j0);
+        if ((rc = launch_unit_vectors(X.as<double>(), nb, S->b_idx.as<int>(), j0, np, s))) return rc;
+        if ((rc = apply_level(op, S->opl_b, np, X.as<double>(), cols.as<double>() + (size_t)j0 * nb,
+                              MLCR_FP64, s)))
+            return rc;
+    }
+    if ((rc = alloc(Ad, (size_t)na * na * sizeof(double)))) return rc;
+    if ((rc = alloc(info, sizeof(int)))) return rc;
+    if ((rc = launch_dense_gather(cols.as<double>(), nb, S->b_idx.as<int>(), na, Ad.as<double>(), s)))
+        return rc;
+    if ((rc = launch_dense_cholesky(Ad.as<double>(), na, info.as<int>(), s))) return rc;
+    int hinfo = 0;
+    MLCR_HIP_CHECK(hipMemcpyAsync(&hinfo, info.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+    MLCR_HIP_CHECK(hipStreamSynchronize(s));
+    if (hinfo) return fail(MLCR_ENOTPD, "dense bottom-level matrix is not positive definite");
+    if ((rc = alloc(S->b_inv, (size_t)na * na * sizeof(double)))) return rc;
+    if ((rc = launch_dense_inverse(Ad.as<double>(), na, S->b_inv.as<double>(), s))) return rc;
+    MLCR_HIP_CHECK(hipStreamSynchronize(s));
+    return MLCR_OK;
+}
+
+static int solver_build(mlcr_solver *S, const Plan &p, hipStream_t s) {
+    mlcr_op *op = S->op;
+    const int R = S->max_nrhs;
+    const int lmax = op->lmax;
+    int rc;
+    S->plan = p;
+    S->direct = (p.H == 0);
+    std::vector<double> act0(lmax + 1);
+    for (int l = 0; l <= lmax; l++) act0[l] = op->cl[l] > 0 ? 1.0 : 0.0;
+    if ((rc = up(S->top_act, act0.data(), act0.size() * sizeof(double)))) return rc;
+    const size_t top_bytes = (size_t)R * nalm_l(lmax) * sizeof(double);
+    for (DevBuf *b : {&S->x0, &S->b0, &S->r0, &S->t0, &S->ro, &S->to})
+        if ((rc = alloc(*b, top_bytes))) return rc;
+    std::vector<double> sinv(lmax + 1), ch(lmax + 1);
+    for (int l = 0; l <= lmax; l++) {
+        sinv[l] = op->cl[l] > 0 ? 1.0 / op->cl[l] : 0.0;
+        ch[l] = op->cl[l];
+    }
+    if ((rc = up(S->sinv, sinv.data(), sinv.size() * sizeof(double)))) return rc;
+    if ((rc = up(S->chalf, ch.data(), ch.size() * sizeof(double)))) return rc;
+    if ((rc = alloc(S->partial, (size_t)R * (lmax + 1) * 2 * sizeof(double)))) return rc;
+    if ((rc = alloc(S->norms, (size_t)R * 2 * sizeof(double)))) return rc;
+
+    if (S->direct) {
+        S->lmax_b = lmax;
+        S->opl_b = 0;
+        return setup_bottom(S, s);
+    }
+    // pixel levels
+    for (int h = 0; h < p.H; h++) {
+        auto L = std::make_unique<PixLevel>();
+        L->nside = p.nside[h];
+        L->lmax = p.lmax[h];
+        L->opl = h + 1;
+        if ((rc = mlcr_geom_create(L->nside, L->lmax, &L->geom))) return rc;
+        if ((rc = mlcr_op_set_level(op, L->opl, L->lmax, p.fl[h].data()))) return rc;
+        std::vector<double> act(L->lmax + 1), one(L->lmax + 1);
+        for (int l = 0; l <= L->lmax; l++) {
+            act[l] = op->cl[l] > 0 ? 1.0 : 0.0;
+            one[l] = p.omega * act[l];
+        }
+        if ((rc = up(L->act, act.data(), act.size() * sizeof(double)))) return rc;
+        if ((rc = up(L->one, one.data(), one.size() * sizeof(double)))) return rc;
+        const size_t vb = (size_t)R * nalm_l(L->lmax) * sizeof(double);
+        for (DevBuf *b : {&L->x, &L->b, &L->r, &L->t})
+            if ((rc = alloc(*b, vb))) return rc;
+        const size_t mb = (size_t)R * L->geom->npix * sizeof(double);
+        if ((rc = alloc(L->map, mb)) || (rc = alloc(L->cmap, mb))) return rc;
+        S->lev.push_back(std::move(L));
+    }
+    // restriction weights f~^H / f~^h (Sec. 3.2, eq. f_l)
+    {
+        std::vector<double> w(p.lmax[0] + 1);
+        for (int l = 0; l <= p.lmax[0]; l++) w[l] = p.fl[0][l];
+        if ((rc = up(S->top_wdown, w.data(), w.size() * sizeof(double)))) return rc;
+    }
+    for (int h = 0; h < p.H; h++) {
+        const bool last = (h == p.H - 1);
+        const int ln = last ? p.lmax_b : p.lmax[h + 1];
+        std::vector<double> w(ln + 1);
+        for (int l = 0; l <= ln; l++) {
+            const double fh = p.fl[h][l];
+            const double fH = last ? fh : p.fl[h + 1][l];
+            w[l] = fh > 0.0 ? fH / fh : 0.0;
+        }
+        if ((rc = up(S->lev[h]->wdown, w.data(), w.size() * sizeof(double)))) return rc;
+    }
+    {
+        std::vector<double> hp(lmax + 1);
+        for (int l = 0; l <= lmax; l++) hp[l] = p.omega_top * p.highpass[l];
+        if ((rc = up(S->top_hp, hp.data(), hp.size() * sizeof(double)))) return rc;
+    }
+    // bottom level A_B = restriction of the last pixel level to l <= lmax_b
+    S->lmax_b = p.lmax_b;
+    S->opl_b = p.H + 1;
+    {
+        std::vector<double> fb(p.fl[p.H - 1].begin(), p.fl[p.H - 1].begin() + p.lmax_b + 1);
+        if ((rc = mlcr_op_set_level(op, S->opl_b, S->lmax_b, fb.data()))) return rc;
+    }
+    const size_t bbytes = (size_t)R * nalm_l(S->lmax_b) * sizeof(double);
+    if ((rc = alloc(S->xb, bbytes)) || (rc = alloc(S->bb, bbytes))) return rc;
+    if ((rc = setup_top_diag(S, s))) return rc;
+    for (auto &L : S->lev)
+        if ((rc = setup_smoother(S, *L, s))) return rc;
+    return setup_bottom(S, s);
+}
+
+}  // namespace mlcr
+
+extern "C" {
+
+int mlcr_nest2ring(int nside, long long n, const long long *nest, long long *ring) {
+    if (nside < 1 || n < 0 || (n > 0 && (!nest || !ring))) return fail(MLCR_EINVAL, "bad argument");
+    const long long npix = 12LL * nside * nside;
+    for (long long i = 0; i < n; i++) {
+        if (nest[i] < 0 || nest[i] >= npix) return fail(MLCR_EINVAL, "nested index out of range");
+        ring[i] = nest2ring(nside, nest[i]);
+    }
+    return MLCR_OK;
+}
+
+int mlcr_ladder_plan(int nside, int lmax, int *nlevels, int *nsides, int *lmaxs, int *nrec,
+                     int *nrec_top, int *lmax_bottom) {
+    if (nside < 1 || lmax < 0 || !nlevels) return fail(MLCR_EINVAL, "bad argument");
+    Plan p;
+    default_plan(nside, lmax, p);
+    *nlevels = p.H;
+    for (int h = 0; h < p.H; h++) {
+        if (nsides) nsides[h] = p.nside[h];
+        if (lmaxs) lmaxs[h] = p.lmax[h];
+        if (nrec) nrec[h] = p.nrec[h];
+    }
+    if (nrec_top) *nrec_top = p.nrec_top;
+    if (lmax_bottom) *lmax_bottom = p.lmax_b;
+    return MLCR_OK;
+}
+
+int mlcr_cycle_counts(int nlevels, const int *nrec, int nrec_top, int ncycles, long long *counts) {
+    if (nlevels < 0 || nlevels > 8 || ncycles < 1 || !counts || (nlevels > 0 && !nrec))
+        return fail(MLCR_EINVAL, "bad argument");
+    const int B = nlevels == 0 ? 0 : nlevels + 1;
+    std::vector<int> nr(nlevels + 1);
+    nr[0] = nrec_top;
+    for (int h = 0; h < nlevels; h++) nr[h + 1] = nrec[h];
+    CountOps ops(B + 1, B);
+    for (int c = 0; c < ncycles; c++) {
+        cr_cycle(ops, 0, B, nr, true);
+        ops.c[1]++;     // float64 residual b - A x of CR-Solve at the top level
+    }
+    for (size_t i = 0; i < ops.c.size(); i++) counts[i] = ops.c[i];
+    return MLCR_OK;
+}
+
+int mlcr_solver_create(mlcr_op *op, int max_nrhs, mlcr_solver **out) {
+    if (!out) return fail(MLCR_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!op) return fail(MLCR_EINVAL, "operator is NULL");
+    if (max_nrhs < 1) return fail(MLCR_EINVAL, "max_nrhs must be >= 1");
+    mlcr_solver *S = new (std::nothrow) mlcr_solver();
+    if (!S) return fail(MLCR_ENOMEM, "host allocation failed");
+    S->op = op;
+    S->max_nrhs = max_nrhs;
+    Plan p;
+    default_plan(op->g->nside, op->lmax, p);
+    int rc = solver_build(S, p, nullptr);
+    if (rc) {
+        (void)hipDeviceSynchronize();
+        delete S;
+        return rc;
+    }
+    *out = S;
+    return MLCR_OK;
+}
+
+void mlcr_solver_destroy(mlcr_solver *S) {
+    if (!S) return;
+    (void)hipDeviceSynchronize();
+    delete S;
+}
+
+int mlcr_solver_info(const mlcr_solver *S, int *nlevels, int *lmax_bottom, int *n_bottom,
+                     float *max_ridge) {
+    if (!S) return fail(MLCR_EINVAL, "solver is NULL");
+    if (nlevels) *nlevels = S->plan.H;
+    if (lmax_bottom) *lmax_bottom = S->lmax_b;
+    if (n_bottom) *n_bottom = S->na;
+    if (max_ridge) {
+        float w = 0.f;
+        for (float v : S->ridge_summary) w = std::max(w, v);
+        *max_ridge = w;
+    }
+    return MLCR_OK;
+}
+
+int mlcr_solver_top_dinv(const mlcr_solver *S, double *out, void *stream) {
+    if (!S || !out) return fail(MLCR_EINVAL, "NULL argument");
+    if (S->direct) return fail(MLCR_EINVAL, "solver has no top-level smoother (dense solve)");
+    MLCR_HIP_CHECK(hipMemcpyAsync(out, S->top_dinv.ptr, (size_t)nalm_l(S->op->lmax) * sizeof(double),
+                                  hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return MLCR_OK;
+}
+
+int wcycle_solve(mlcr_solver *S, int nrhs, const double *b, double *x, double rtol, int max_cycles,
+                 int prec, mlcr_solve_info *info, void *stream) {
+    if (!S || !b || !x) return fail(MLCR_EINVAL, "NULL argument");
+    if (nrhs < 1 || nrhs > S->max_nrhs) return fail(MLCR_EINVAL, "nrhs out of [1, max_nrhs]");
+    if (max_cycles < 1) return fail(MLCR_EINVAL, "max_cycles must be >= 1");
+    if (!(rtol >= 0.0)) return fail(MLCR_EINVAL, "rtol must be >= 0");
+    if (prec != MLCR_FP64 && prec != MLCR_FP32) return fail(MLCR_EINVAL, "unknown precision");
+    hipStream_t s = (hipStream_t)stream;
+    mlcr_op *op = S->op;
+    const int lmax = op->lmax;
+    const long long na = nalm_l(lmax);
+    int rc;
+    // x holds the start vector; excluded modes are projected out
+    if ((rc = launch_residual(x, nullptr, x, S->top_act.as<double>(), lmax, nrhs, s))) return rc;
+    std::vector<double> hn(2 * nrhs), rho0(nrhs), rho(nrhs, 0.0);
+    std::vector<int> done(nrhs, 0), cyc(nrhs, 0);
+    auto residual_norms = [&](std::vector<double> &out) -> int {
+        int r2;
+        if ((r2 = apply_level(op, 0, nrhs, x, S->to.as<double>(), MLCR_FP64, s))) return r2;
+        if ((r2 = launch_residual(b, S->to.as<double>(), S->ro.as<double>(), S->top_act.as<double>(),
+                                  lmax, nrhs, s)))
+            return r2;
+        if ((r2 = launch_wnorms(S->ro.as<double>(), b, S->sinv.as<double>(), lmax, nrhs,
+                                S->partial.as<double>(), S->norms.as<double>(), s)))
+            return r2;
+        MLCR_HIP_CHECK(hipMemcpyAsync(hn.data(), S->norms.ptr, 2 * nrhs * sizeof(double),
+                                      hipMemcpyDeviceToHost, s));
+        MLCR_HIP_CHECK(hipStreamSynchronize(s));
+        for (int r = 0; r < nrhs; r++)
+            out[r] = hn[2 * r + 1] > 0 ? std::sqrt(hn[2 * r] / hn[2 * r + 1]) : 0.0;
+        return MLCR_OK;
+    };
+    if ((rc = residual_norms(rho0))) return rc;
+    rho = rho0;
+    GpuOps ops(S, nrhs, prec, s);
+    std::vector<int> nr(S->plan.H + 1);
+    nr[0] = S->plan.nrec_top;
+    for (int h = 0; h < S->plan.H; h++) nr[h + 1] = S->plan.nrec[h];
+    const int B = S->direct ? 0 : S->plan.H + 1;
+    bool all = true;
+    for (int r = 0; r < nrhs; r++) all = all && rho[r] <= rtol;
+    int it = 0;
+    while (!all && it < max_cycles) {
+        // correction form of CR-Solve: solve A c = r with one cycle from c = 0,
+        // then x += c and r = b - A x in float64 (iterative refinement)
+        MLCR_HIP_CHECK(hipMemcpyAsync(S->b0.ptr, S->ro.ptr, (size_t)nrhs * na * sizeof(double),
+                                      hipMemcpyDeviceToDevice, s));
+        MLCR_HIP_CHECK(hipMemsetAsync(S->x0.ptr, 0, (size_t)nrhs * na * sizeof(double), s));
+        if ((rc = cr_cycle(ops, 0, B, nr, true))) return rc;
+        if ((rc = launch_axpy_l(x, S->x0.as<double>(), S->top_act.as<double>(), nullptr, lmax, nrhs,
+                                s)))
+            return rc;
+        it++;
+        if ((rc = residual_norms(rho))) return rc;
+        all = true;
+        for (int r = 0; r < nrhs; r++) {
+            if (!done[r]) cyc[r] = it;
+            if (rho[r] <= rtol) done[r] = 1;
+            all = all && done[r];
+        }
+    }
+    // ||S^{1/2} r|| for the a-posteriori max-pixel-error bound
+    if ((rc = launch_wnorms(S->ro.as<double>(), nullptr, S->chalf.as<double>(), lmax, nrhs,
+                            S->partial.as<double>(), S->norms.as<double>(), s)))
+        return rc;
+    MLCR_HIP_CHECK(hipMemcpyAsync(hn.data(), S->norms.ptr, 2 * nrhs * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+    MLCR_HIP_CHECK(hipStreamSynchronize(s));
+    if (info)
+        for (int r = 0; r < nrhs; r++) {
+            info[r].cycles = cyc[r];
+            info[r].rho0 = rho0[r];
+            info[r].rho = rho[r];
+            info[r].s_half_res = std::sqrt(hn[2 * r]);
+            info[r].converged = rho[r] <= rtol;
+        }
+    if (!all) return fail(MLCR_ENOCONV, "rtol not reached within max_cycles");
+    return MLCR_OK;
+}
+
+}  // extern "C"

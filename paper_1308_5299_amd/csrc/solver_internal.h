@@ -1,0 +1,50 @@
+// Internal declarations of the multi-level solver.
+#pragma once
+
+#include <vector>
+
+#include "mlcr_internal.h"
+
+namespace mlcr {
+
+// solver_kernels.hip
+int launch_transfer(const double *src, int lmax_src, double *dst, int lmax_dst, const double *w,
+                    int lmax_w, bool add, int nrhs, hipStream_t s);
+int launch_axpy_l(double *x, const double *r, const double *c, const double *d, int lmax, int nrhs,
+                  hipStream_t s);
+int launch_residual(const double *b, const double *y, double *r, const double *act, int lmax,
+                    int nrhs, hipStream_t s);
+int launch_wnorms(const double *a, const double *b, const double *w, int lmax, int nrhs,
+                  double *partial, double *out, hipStream_t s);
+int launch_diag_pairs(const double2 *Xi, int ldx, double2 *G, int lmax, int nrings,
+                      hipStream_t s);
+int launch_diag_inverse(const double *q, const double *d, const double *bh, double *dinv, int lmax,
+                        hipStream_t s);
+int launch_probe_maps(double *maps, long long npix, const int *tilepix, int ntiles, int kk, int c0,
+                      int nprobe, hipStream_t s);
+int launch_probe_collect(const double *z, long long npix, const int *tilepix, int ntiles, int kk,
+                         int c0, int nprobe, double *blocks, hipStream_t s);
+int launch_tile_factor(const double *blocks, int ntiles, int kk, float *minv, float *ridge,
+                       hipStream_t s);
+int launch_tile_apply(const double *r, double *c, long long npix, int nrhs, const int *tilepix,
+                      const float *minv, int ntiles, int kk, double omega, hipStream_t s);
+int launch_dense_gather(const double *cols, long long ld, const int *act_idx, int na, double *Ad,
+                        hipStream_t s);
+int launch_dense_cholesky(double *a, int n, int *info, hipStream_t s);
+int launch_dense_inverse(const double *L, int n, double *inv, hipStream_t s);
+int launch_dense_apply(const double *Ainv, int n, const int *act_idx, const double *b, double *x,
+                       long long nalm, int nrhs, hipStream_t s);
+int launch_unit_vectors(double *x, long long nalm, const int *idx, int j0, int np, hipStream_t s);
+
+// legendre.hip: adjoint with lambda^2 (diagonal of Y^T N^-1 Y)
+int launch_legendre_adjoint_sq(const LegendreArgs &a, const double2 *G, double *P,
+                               int *nchunks_out);
+
+// api.cpp: operator apply without the max_nrhs limit (workspaces grow)
+int apply_level(mlcr_op *op, int level, int nrhs, const double *x, double *y, int prec,
+                hipStream_t s);
+
+// HEALPix NESTED -> RING index (Gorski et al. 2005)
+long long nest2ring(int nside, long long ipnest);
+
+}  // namespace mlcr

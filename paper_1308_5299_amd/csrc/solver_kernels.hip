@@ -1,0 +1,577 @@
+// Device kernels of the multi-level solve (Fig. code:mg): level transfers,
+// smoother construction and application, dense bottom solve, norms.
+#include <algorithm>
+#include <cfloat>
+
+#include "mlcr_internal.h"
+#include "solver_internal.h"
+
+namespace mlcr {
+
+// ---------------------------------------------------------------------------
+// packed-vector kernels, one workgroup per (m, RHS)
+// ---------------------------------------------------------------------------
+// dst[idx_H(l,m,.)] = w[l] * src[idx_h(l,m,.)]  for l <= lmax_H  (restriction I_h^H)
+// or, with add = true, dst_h += w[l] * src_H                       (interpolation (I_h^H)^T)
+__global__ __launch_bounds__(256) void k_transfer(const double *__restrict__ src, int lmax_src,
+                                                  double *__restrict__ dst, int lmax_dst,
+                                                  const double *__restrict__ w, int lmax_w,
+                                                  int add) {
+    const int m = blockIdx.x, r = blockIdx.y;
+    if (m > lmax_w) return;
+    const long long nsrc = (long long)(lmax_src + 1) * (lmax_src + 1);
+    const long long ndst = (long long)(lmax_dst + 1) * (lmax_dst + 1);
+    const int nls = lmax_src - m + 1, nld = lmax_dst - m + 1, nlw = lmax_w - m + 1;
+    const long long bs = (long long)r * nsrc + cos_base(m, lmax_src);
+    const long long bd = (long long)r * ndst + cos_base(m, lmax_dst);
+    const int cnt = (m == 0) ? nlw : 2 * nlw;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const int cs = i >= nlw;
+        const int dl = cs ? i - nlw : i;           // l - m
+        const double v = w[m + dl] * src[bs + (cs ? nls : 0) + dl];
+        double *p = dst + bd + (cs ? nld : 0) + dl;
+        if (add) *p += v;
+        else *p = v;
+    }
+    // entries of a larger destination above lmax_w are cleared on restriction
+    if (!add && lmax_dst > lmax_w) {
+        const int extra = nld - nlw;
+        const int cnt2 = (m == 0) ? extra : 2 * extra;
+        for (int i = threadIdx.x; i < cnt2; i += blockDim.x) {
+            const int cs = i >= extra;
+            const int dl = nlw + (cs ? i - extra : i);
+            dst[bd + (cs ? nld : 0) + dl] = 0.0;
+        }
+    }
+}
+
+// x += c[l] * d[idx] * r   (d may be null: 1)
+__global__ __launch_bounds__(256) void k_axpy_l(double *__restrict__ x, const double *__restrict__ r,
+                                                const double *__restrict__ c,
+                                                const double *__restrict__ d, int lmax) {
+    const int m = blockIdx.x, rr = blockIdx.y;
+    const long long nalm = (long long)(lmax + 1) * (lmax + 1);
+    const int nl = lmax - m + 1;
+    const int cnt = (m == 0) ? nl : 2 * nl;
+    const long long off = cos_base(m, lmax);
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const int l = m + (i < nl ? i : i - nl);
+        double v = c[l] * r[(long long)rr * nalm + off + i];
+        if (d) v *= d[off + i];
+        x[(long long)rr * nalm + off + i] += v;
+    }
+}
+
+// r = b - y (flat), with optional mask per l (0 removes the mode)
+__global__ __launch_bounds__(256) void k_residual(const double *__restrict__ b,
+                                                  const double *__restrict__ y,
+                                                  double *__restrict__ r,
+                                                  const double *__restrict__ act, int lmax) {
+    const int m = blockIdx.x, rr = blockIdx.y;
+    const long long nalm = (long long)(lmax + 1) * (lmax + 1);
+    const int nl = lmax - m + 1;
+    const int cnt = (m == 0) ? nl : 2 * nl;
+    const long long off = (long long)rr * nalm + cos_base(m, lmax);
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const int l = m + (i < nl ? i : i - nl);
+        const double v = b[off + i] - (y ? y[off + i] : 0.0);
+        r[off + i] = act ? act[l] * v : v;
+    }
+}
+
+// per RHS: out[2 r] = sum w[l] a^2, out[2 r + 1] = sum w[l] b^2  (S^-1 weighted norms)
+__global__ __launch_bounds__(256) void k_wnorms(const double *__restrict__ a,
+                                                const double *__restrict__ b,
+                                                const double *__restrict__ w, int lmax,
+                                                double *__restrict__ partial) {
+    // grid (lmax+1, nrhs): partial[(r * (lmax+1) + m) * 2 + {0,1}]
+    const int m = blockIdx.x, rr = blockIdx.y;
+    const long long nalm = (long long)(lmax + 1) * (lmax + 1);
+    const int nl = lmax - m + 1;
+    const int cnt = (m == 0) ? nl : 2 * nl;
+    const long long off = (long long)rr * nalm + cos_base(m, lmax);
+    double sa = 0.0, sb = 0.0;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const int l = m + (i < nl ? i : i - nl);
+        const double va = a[off + i], vb = b ? b[off + i] : 0.0;
+        sa = fma(w[l] * va, va, sa);
+        sb = fma(w[l] * vb, vb, sb);
+    }
+    __shared__ double ra[256], rb[256];
+    ra[threadIdx.x] = sa;
+    rb[threadIdx.x] = sb;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            ra[threadIdx.x] += ra[threadIdx.x + s];
+            rb[threadIdx.x] += rb[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[((long long)rr * (lmax + 1) + m) * 2] = ra[0];
+        partial[((long long)rr * (lmax + 1) + m) * 2 + 1] = rb[0];
+    }
+}
+
+// second stage: one block per RHS sums the per-m partials in a fixed order
+__global__ __launch_bounds__(256) void k_wnorms_final(const double *__restrict__ partial, int nm,
+                                                      double *__restrict__ out) {
+    const int rr = blockIdx.x;
+    double sa = 0.0, sb = 0.0;
+    for (int i = threadIdx.x; i < nm; i += blockDim.x) {
+        sa += partial[((long long)rr * nm + i) * 2];
+        sb += partial[((long long)rr * nm + i) * 2 + 1];
+    }
+    __shared__ double ra[256], rb[256];
+    ra[threadIdx.x] = sa;
+    rb[threadIdx.x] = sb;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            ra[threadIdx.x] += ra[threadIdx.x + s];
+            rb[threadIdx.x] += rb[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * rr] = ra[0];
+        out[2 * rr + 1] = rb[0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// top-level diagonal: the ring sums of eq. Ni-dense at frequencies 0 and 2m
+// ---------------------------------------------------------------------------
+// Xi holds, per ring, w_D (Re, Im) of sum_j xi_j e^{i D phi_j} for D <= 2 lmax
+// (the adjoint ring step applied to the map xi).  Output per ring and m:
+// (Re Xi(0) + Re Xi(2m), Re Xi(0) - Re Xi(2m)) for m >= 1 and (Re Xi(0), 0) for m = 0.
+__global__ __launch_bounds__(256) void k_diag_pairs(const double2 *__restrict__ Xi, int ldx,
+                                                    double2 *__restrict__ G, int lmax) {
+    const int k = blockIdx.x;
+    const double x0 = Xi[(long long)k * ldx].x;     // w_0 = 1
+    for (int m = threadIdx.x; m <= lmax; m += blockDim.x) {
+        double2 out;
+        if (m == 0) {
+            out = make_double2(x0, 0.0);
+        } else {
+            const double x2 = Xi[(long long)k * ldx + 2 * m].x * 0.70710678118654752440;
+            out = make_double2(x0 + x2, x0 - x2);
+        }
+        G[(long long)k * (lmax + 1) + m] = out;
+    }
+}
+
+// dinv[idx] = act / (d[l] + bh[l]^2 q[idx])  (0 for excluded modes)
+__global__ __launch_bounds__(256) void k_diag_inverse(const double *__restrict__ q,
+                                                      const double *__restrict__ d,
+                                                      const double *__restrict__ bh,
+                                                      double *__restrict__ dinv, int lmax) {
+    const int m = blockIdx.x;
+    const int nl = lmax - m + 1;
+    const int cnt = (m == 0) ? nl : 2 * nl;
+    const long long off = cos_base(m, lmax);
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const int l = m + (i < nl ? i : i - nl);
+        const double a = d[l] + bh[l] * bh[l] * q[off + i];
+        dinv[off + i] = (d[l] > 0.0 && a > 0.0) ? 1.0 / a : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pixel-level smoother on k x k tiles (tiles = pixels of the grid N_side / k)
+// ---------------------------------------------------------------------------
+// probe maps: map[p][tilepix[t * kk + c0 + p]] = 1 for every tile t
+__global__ __launch_bounds__(256) void k_probe_maps(double *__restrict__ maps, long long npix,
+                                                    const int *__restrict__ tilepix, int ntiles,
+                                                    int kk, int c0, int nprobe) {
+    const long long n = (long long)ntiles * nprobe;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int p = (int)(i / ntiles), t = (int)(i % ntiles);
+        maps[(long long)p * npix + tilepix[(long long)t * kk + c0 + p]] = 1.0;
+    }
+}
+
+// blocks[t][i][c0 + p] = z_p[tilepix[t * kk + i]]
+__global__ __launch_bounds__(256) void k_probe_collect(const double *__restrict__ z,
+                                                       long long npix,
+                                                       const int *__restrict__ tilepix,
+                                                       int ntiles, int kk, int c0, int nprobe,
+                                                       double *__restrict__ blocks) {
+    const long long n = (long long)ntiles * kk * nprobe;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int p = (int)(i % nprobe);
+        const long long ti = i / nprobe;
+        const int row = (int)(ti % kk);
+        const int t = (int)(ti / kk);
+        blocks[((long long)t * kk + row) * kk + c0 + p] =
+            z[(long long)p * npix + tilepix[(long long)t * kk + row]];
+    }
+}
+
+// In-LDS Cholesky of a kk x kk SPD matrix (lower, row-major a[i*kk+j]);
+// returns false if a pivot is not positive.  All threads of the block.
+__device__ bool lds_cholesky(double *a, int kk, double *flag) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid == 0) *flag = 0.0;
+    __syncthreads();
+    for (int j = 0; j < kk; j++) {
+        if (tid == 0) {
+            const double piv = a[j * kk + j];
+            if (!(piv > 0.0)) *flag = 1.0;
+            a[j * kk + j] = piv > 0.0 ? sqrt(piv) : 1.0;
+        }
+        __syncthreads();
+        const double djj = a[j * kk + j];
+        for (int i = j + 1 + tid; i < kk; i += nt) a[i * kk + j] /= djj;
+        __syncthreads();
+        const int rem = kk - j - 1;
+        for (int e = tid; e < rem * rem; e += nt) {
+            const int i = j + 1 + e / rem, c = j + 1 + e % rem;
+            if (c <= i) a[i * kk + c] -= a[i * kk + j] * a[c * kk + j];
+        }
+        __syncthreads();
+    }
+    return *flag == 0.0;
+}
+
+// Per tile: symmetrize the probed block, factor with the smallest ridge
+// alpha (bisection in log alpha, then 1.5 alpha, Sec. 3.4) that makes the
+// Cholesky succeed, and store the inverse in float32 (column-major; it is
+// symmetric).  ridge_out[t] records the alpha used (relative to max |a_ii|).
+__global__ __launch_bounds__(256) void k_tile_factor(const double *__restrict__ blocks, int kk,
+                                                     float *__restrict__ minv,
+                                                     float *__restrict__ ridge_out) {
+    extern __shared__ double sm[];
+    double *a = sm;                  // kk*kk
+    double *inv = sm + kk * kk;      // kk*kk
+    double *flag = inv + kk * kk;    // 1
+    const int t = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const double *B = blocks + (long long)t * kk * kk;
+    __shared__ double dmax;
+    if (tid == 0) {
+        double m = 0.0;
+        for (int i = 0; i < kk; i++) m = fmax(m, fabs(B[i * kk + i]));
+        dmax = m > 0.0 ? m : 1.0;
+    }
+    __syncthreads();
+    auto load = [&](double alpha) {
+        for (int e = tid; e < kk * kk; e += nt) {
+            const int i = e / kk, j = e % kk;
+            double v = 0.5 * (B[i * kk + j] + B[j * kk + i]);
+            if (i == j) v += alpha * dmax;
+            a[e] = v;
+        }
+        __syncthreads();
+    };
+    load(0.0);
+    bool ok = lds_cholesky(a, kk, flag);
+    double alpha = 0.0;
+    if (!ok) {
+        double lo = -16.0, hi = 0.0;            // log10 of alpha
+        load(1.0);
+        if (lds_cholesky(a, kk, flag)) {
+            for (int it = 0; it < 30; it++) {
+                const double mid = 0.5 * (lo + hi);
+                load(pow(10.0, mid));
+                if (lds_cholesky(a, kk, flag)) hi = mid;
+                else lo = mid;
+            }
+            alpha = 1.5 * pow(10.0, hi);
+        } else {
+            alpha = 1.5;
+        }
+        load(alpha);
+        ok = lds_cholesky(a, kk, flag);
+    }
+    // inverse from the factor: solve L L^T X = I column by column
+    for (int e = tid; e < kk * kk; e += nt) inv[e] = (e / kk == e % kk) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int c = tid; c < kk; c += nt) {
+        // forward: L y = e_c ; backward: L^T x = y   (column c of inv, stored inv[i*kk + c])
+        for (int i = 0; i < kk; i++) {
+            double s = inv[i * kk + c];
+            for (int j = 0; j < i; j++) s -= a[i * kk + j] * inv[j * kk + c];
+            inv[i * kk + c] = s / a[i * kk + i];
+        }
+        for (int i = kk - 1; i >= 0; i--) {
+            double s = inv[i * kk + c];
+            for (int j = i + 1; j < kk; j++) s -= a[j * kk + i] * inv[j * kk + c];
+            inv[i * kk + c] = s / a[i * kk + i];
+        }
+    }
+    __syncthreads();
+    float *M = minv + (long long)t * kk * kk;
+    for (int e = tid; e < kk * kk; e += nt) {
+        const int i = e / kk, j = e % kk;
+        M[j * kk + i] = ok ? (float)(0.5 * (inv[i * kk + j] + inv[j * kk + i])) : 0.0f;
+    }
+    if (tid == 0) ridge_out[t] = ok ? (float)alpha : -1.0f;
+}
+
+// c[tilepix] = omega * M_t r[tilepix] for every RHS; one workgroup per tile,
+// thread i owns pixel i of the tile (float32 arithmetic, Sec. 3.4).
+__global__ __launch_bounds__(256) void k_tile_apply(const double *__restrict__ r,
+                                                    double *__restrict__ c, long long npix,
+                                                    int nrhs, const int *__restrict__ tilepix,
+                                                    const float *__restrict__ minv, int kk,
+                                                    double omega) {
+    __shared__ float rv[256];
+    const int t = blockIdx.x, i = threadIdx.x;
+    const float *M = minv + (long long)t * kk * kk;
+    const int pix = i < kk ? tilepix[(long long)t * kk + i] : 0;
+    for (int rr = 0; rr < nrhs; rr++) {
+        if (i < kk) rv[i] = (float)r[(long long)rr * npix + pix];
+        __syncthreads();
+        if (i < kk) {
+            float s = 0.0f;
+            for (int j = 0; j < kk; j++) s = fmaf(M[(long long)j * kk + i], rv[j], s);
+            c[(long long)rr * npix + pix] = omega * (double)s;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dense bottom level
+// ---------------------------------------------------------------------------
+// gather the active rows/columns of the probed dense matrix and symmetrize
+__global__ __launch_bounds__(256) void k_dense_gather(const double *__restrict__ cols, long long ld,
+                                                      const int *__restrict__ act_idx, int na,
+                                                      double *__restrict__ Ad) {
+    const long long n = (long long)na * na;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(e / na), j = (int)(e % na);
+        const double v1 = cols[(long long)j * ld + act_idx[i]];
+        const double v2 = cols[(long long)i * ld + act_idx[j]];
+        Ad[e] = 0.5 * (v1 + v2);
+    }
+}
+
+// Right-looking Cholesky (lower, row-major) of an n x n matrix in global
+// memory by one workgroup.  info[0] = 0 on success, j + 1 at a failed pivot.
+__global__ __launch_bounds__(1024) void k_dense_cholesky(double *__restrict__ a, int n,
+                                                         int *__restrict__ info) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    __shared__ int bad;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int j = 0; j < n; j++) {
+        if (tid == 0) {
+            const double piv = a[(long long)j * n + j];
+            if (!(piv > 0.0) && !bad) bad = j + 1;
+            a[(long long)j * n + j] = piv > 0.0 ? sqrt(piv) : 1.0;
+        }
+        __syncthreads();
+        const double djj = a[(long long)j * n + j];
+        for (int i = j + 1 + tid; i < n; i += nt) a[(long long)i * n + j] /= djj;
+        __syncthreads();
+        const int rem = n - j - 1;
+        const long long tot = (long long)rem * (rem + 1) / 2;
+        for (long long e = tid; e < tot; e += nt) {
+            // e -> (i, c) with j < c <= i, row-by-row over the lower triangle
+            const long long rr = (long long)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+            long long row = rr, base = rr * (rr + 1) / 2;
+            if (base > e) { row--; base = row * (row + 1) / 2; }
+            else if (base + row + 1 <= e) { row++; base = row * (row + 1) / 2; }
+            const int i = j + 1 + (int)row, c = j + 1 + (int)(e - base);
+            a[(long long)i * n + c] -= a[(long long)i * n + j] * a[(long long)c * n + j];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) info[0] = bad;
+}
+
+// Column c of (L L^T)^-1 (one workgroup per column), written to inv[c * n + i].
+__global__ __launch_bounds__(256) void k_dense_inverse(const double *__restrict__ L, int n,
+                                                       double *__restrict__ inv) {
+    extern __shared__ double v[];
+    __shared__ double red[256];
+    const int c = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    for (int i = tid; i < n; i += nt) v[i] = (i == c) ? 1.0 : 0.0;
+    __syncthreads();
+    // forward substitution L y = e_c (column-oriented; rows above c stay 0)
+    for (int j = c; j < n; j++) {
+        if (tid == 0) v[j] /= L[(long long)j * n + j];
+        __syncthreads();
+        const double vj = v[j];
+        for (int i = j + 1 + tid; i < n; i += nt) v[i] -= L[(long long)i * n + j] * vj;
+        __syncthreads();
+    }
+    // backward substitution L^T x = y (row-oriented dot products)
+    for (int i = n - 1; i >= 0; i--) {
+        double s = 0.0;
+        for (int j = i + 1 + tid; j < n; j += nt) s += L[(long long)j * n + i] * v[j];
+        red[tid] = s;
+        __syncthreads();
+        for (int st = nt / 2; st > 0; st >>= 1) {
+            if (tid < st) red[tid] += red[tid + st];
+            __syncthreads();
+        }
+        if (tid == 0) v[i] = (v[i] - red[0]) / L[(long long)i * n + i];
+        __syncthreads();
+    }
+    for (int i = tid; i < n; i += nt) inv[(long long)c * n + i] = v[i];
+}
+
+// x[act_idx[i]] = sum_j Ainv[j][i] b[act_idx[j]]  (Ainv symmetric; x pre-cleared)
+__global__ __launch_bounds__(256) void k_dense_apply(const double *__restrict__ Ainv, int n,
+                                                     const int *__restrict__ act_idx,
+                                                     const double *__restrict__ b,
+                                                     double *__restrict__ x, long long nalm) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, rr = blockIdx.y;
+    if (i >= n) return;
+    const double *br = b + (long long)rr * nalm;
+    double s = 0.0;
+    for (int j = 0; j < n; j++) s = fma(Ainv[(long long)j * n + i], br[act_idx[j]], s);
+    x[(long long)rr * nalm + act_idx[i]] = s;
+}
+
+// unit vectors: x[p][idx[j0 + p]] = 1
+__global__ void k_unit_vectors(double *__restrict__ x, long long nalm,
+                               const int *__restrict__ idx, int j0, int np) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < np) x[(long long)p * nalm + idx[j0 + p]] = 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(long long n, int bs) {
+    long long b = (n + bs - 1) / bs;
+    return (unsigned)std::min<long long>(std::max<long long>(b, 1), 65535LL * 4);
+}
+
+int launch_transfer(const double *src, int lmax_src, double *dst, int lmax_dst, const double *w,
+                    int lmax_w, bool add, int nrhs, hipStream_t s) {
+    const int grid_m = std::max(lmax_dst, lmax_w) + 1;
+    hipLaunchKernelGGL(k_transfer, dim3(grid_m, nrhs), dim3(256), 0, s, src, lmax_src, dst,
+                       lmax_dst, w, lmax_w, add ? 1 : 0);
+    MLCR_HIP_CHECK(hipGetLastError());
+    if (!add && lmax_dst > lmax_w) {
+        // orders m > lmax_w of the destination are cleared as a whole
+        const long long nd = (long long)(lmax_dst + 1) * (lmax_dst + 1);
+        for (int r = 0; r < nrhs; r++) {
+            const long long off = cos_base(lmax_w + 1, lmax_dst);
+            MLCR_HIP_CHECK(hipMemsetAsync(dst + r * nd + off, 0, (nd - off) * sizeof(double), s));
+        }
+    }
+    return MLCR_OK;
+}
+
+int launch_axpy_l(double *x, const double *r, const double *c, const double *d, int lmax, int nrhs,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy_l, dim3(lmax + 1, nrhs), dim3(256), 0, s, x, r, c, d, lmax);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_residual(const double *b, const double *y, double *r, const double *act, int lmax,
+                    int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_residual, dim3(lmax + 1, nrhs), dim3(256), 0, s, b, y, r, act, lmax);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_wnorms(const double *a, const double *b, const double *w, int lmax, int nrhs,
+                  double *partial, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_wnorms, dim3(lmax + 1, nrhs), dim3(256), 0, s, a, b, w, lmax, partial);
+    MLCR_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_wnorms_final, dim3(nrhs), dim3(256), 0, s, partial, lmax + 1, out);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_diag_pairs(const double2 *Xi, int ldx, double2 *G, int lmax, int nrings,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_diag_pairs, dim3(nrings), dim3(256), 0, s, Xi, ldx, G, lmax);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_diag_inverse(const double *q, const double *d, const double *bh, double *dinv, int lmax,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_diag_inverse, dim3(lmax + 1), dim3(256), 0, s, q, d, bh, dinv, lmax);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_probe_maps(double *maps, long long npix, const int *tilepix, int ntiles, int kk, int c0,
+                      int nprobe, hipStream_t s) {
+    MLCR_HIP_CHECK(hipMemsetAsync(maps, 0, (size_t)nprobe * npix * sizeof(double), s));
+    hipLaunchKernelGGL(k_probe_maps, dim3(nblk((long long)ntiles * nprobe, 256)), dim3(256), 0, s,
+                       maps, npix, tilepix, ntiles, kk, c0, nprobe);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_probe_collect(const double *z, long long npix, const int *tilepix, int ntiles, int kk,
+                         int c0, int nprobe, double *blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_probe_collect, dim3(nblk((long long)ntiles * kk * nprobe, 256)), dim3(256),
+                       0, s, z, npix, tilepix, ntiles, kk, c0, nprobe, blocks);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_tile_factor(const double *blocks, int ntiles, int kk, float *minv, float *ridge,
+                       hipStream_t s) {
+    const size_t lds = (2 * (size_t)kk * kk + 1) * sizeof(double);
+    int rc = ensure_dynamic_lds((const void *)k_tile_factor, lds);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_tile_factor, dim3(ntiles), dim3(256), lds, s, blocks, kk, minv, ridge);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_tile_apply(const double *r, double *c, long long npix, int nrhs, const int *tilepix,
+                      const float *minv, int ntiles, int kk, double omega, hipStream_t s) {
+    hipLaunchKernelGGL(k_tile_apply, dim3(ntiles), dim3(256), 0, s, r, c, npix, nrhs, tilepix,
+                       minv, kk, omega);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_dense_gather(const double *cols, long long ld, const int *act_idx, int na, double *Ad,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_gather, dim3(nblk((long long)na * na, 256)), dim3(256), 0, s, cols,
+                       ld, act_idx, na, Ad);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_dense_cholesky(double *a, int n, int *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_cholesky, dim3(1), dim3(1024), 0, s, a, n, info);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_dense_inverse(const double *L, int n, double *inv, hipStream_t s) {
+    const size_t lds = (size_t)n * sizeof(double);
+    if (lds > 150 * 1024) return fail(MLCR_EINVAL, "dense bottom level too large for LDS");
+    int rc = ensure_dynamic_lds((const void *)k_dense_inverse, lds);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_dense_inverse, dim3(n), dim3(256), lds, s, L, n, inv);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_dense_apply(const double *Ainv, int n, const int *act_idx, const double *b, double *x,
+                       long long nalm, int nrhs, hipStream_t s) {
+    MLCR_HIP_CHECK(hipMemsetAsync(x, 0, (size_t)nrhs * nalm * sizeof(double), s));
+    hipLaunchKernelGGL(k_dense_apply, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, Ainv, n,
+                       act_idx, b, x, nalm);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_unit_vectors(double *x, long long nalm, const int *idx, int j0, int np, hipStream_t s) {
+    MLCR_HIP_CHECK(hipMemsetAsync(x, 0, (size_t)np * nalm * sizeof(double), s));
+    hipLaunchKernelGGL(k_unit_vectors, dim3((np + 63) / 64), dim3(64), 0, s, x, nalm, idx, j0, np);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+}  // namespace mlcr

@@ -20,7 +20,7 @@ def test_header_symbols_exported():
     from paper_1308_5299_amd import _lib
     lib = _lib.load()
     names = _header_functions()
-    assert "apply_A" in names and "sht_synth" in names
+    assert "apply_A" in names and "sht_synth" in names and "wcycle_solve" in names
     for n in names:
         assert hasattr(lib, n), n
     # the binding covers every declared function
