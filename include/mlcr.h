@@ -143,10 +143,13 @@ int mlcr_op_level_lmax(const mlcr_op *op, int h);
  * HEALPix grid of resolution N_side/2, N_side/4, ... and an error smoother
  * on k x k pixel tiles (k = 8, Sec. 3.4); and a dense bottom level solved
  * exactly for l <= 40.  Default ladder (Sec. 3.2-3.4): pixel level 1 keeps
- * lmax, level 2 is limited to 4 N_side^h, coarser ones to 6 N_side^h, down
- * to N_side^h = 32; the first two cumulative filters are q_l of eq.
- * fourth-power-beam with q = 0.1 at 2570/3000 and 1536/2048 of their band
- * limits, coarser ones Gaussians of FWHM two pixels.  Recursion counts: the
+ * lmax; levels with N_side^h >= 512 are limited to 4 N_side^h and use the q_l
+ * filter of eq. fourth-power-beam (q = 0.1 at 2570/3000 of the band limit on
+ * the first level, 1536/2048 on the second); levels with N_side^h <= 256 use
+ * Gaussians of FWHM two pixels and 6 N_side^h, down to N_side^h = 32.
+ * Modes with C_l = 0 get the wide prior C_0 = C_1 = C_2 inside the coarse
+ * hierarchy (as in Sec. 4.1); the top level keeps them removed.  The pixel
+ * smoothers are block-Jacobi on the k x k tiles.  Recursion counts: the
  * top and the finest pixel level run once down and once up, the others
  * twice (partial W-cycle, Sec. 4.1), the last pixel level once into the
  * dense bottom.
@@ -194,6 +197,21 @@ int wcycle_solve(mlcr_solver *s, int nrhs, const double *dev_b, double *dev_x, d
 /* HEALPix NESTED to RING pixel index (Gorski et al. 2005); the tiles of the
  * pixel-level smoothers are nested blocks of k^2 pixels. */
 int mlcr_nest2ring(int nside, long long n, const long long *host_nest, long long *host_ring);
+/* Tile graph of the pixel-level smoothers (Sec. 3.4): tiles are the 8 x 8
+ * nested blocks, tile t = nested pixels [64 t, 64 t + 64), 12 (nside/8)^2 of
+ * them (nside % 8 == 0).  Distances are between pixel centres in pixel widths
+ * sqrt(4 pi / N_pix).
+ *   host_nb [ntiles][max_nb]: the tiles nearer than 4 pixel widths (the
+ *     smoother keeps couplings inside a tile and with these), ascending,
+ *     padded with -1; EINVAL if a tile has more than max_nb.
+ *   host_sweep_color [ntiles]: neighbours have different colours (the block
+ *     Gauss-Seidel sweep runs one colour at a time).
+ *   host_probe_color [ntiles]: for tiles u != u' of one colour, no tile of
+ *     {u} + neighbours(u) comes within 6 pixel widths of u' (the blocks are
+ *     probed one colour at a time).
+ *   n_sweep, n_probe: colour counts. */
+int mlcr_tile_graph(int nside, int max_nb, int *host_nb, int *host_sweep_color,
+                    int *host_probe_color, int *n_sweep, int *n_probe);
 /* The default ladder for an observation grid nside and band limit lmax:
  * level count, and per pixel level N_side^h, lmax^h and recursion count
  * (arrays of 8), the top recursion count and the bottom band limit. */

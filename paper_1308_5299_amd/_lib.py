@@ -37,6 +37,8 @@ SIGNATURES = {
     "wcycle_solve": (c_int, [c_void_p, c_int, c_void_p, c_void_p, ctypes.c_double, c_int, c_int,
                              c_void_p, c_void_p]),
     "mlcr_nest2ring": (c_int, [c_int, c_ll, c_void_p, c_void_p]),
+    "mlcr_tile_graph": (c_int, [c_int, c_int, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_int),
+                                ctypes.POINTER(c_int)]),
     "mlcr_ladder_plan": (c_int, [c_int, c_int, ctypes.POINTER(c_int), c_void_p, c_void_p, c_void_p,
                                  ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
     "mlcr_cycle_counts": (c_int, [c_int, c_void_p, c_int, c_int, c_void_p]),

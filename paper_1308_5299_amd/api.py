@@ -240,6 +240,19 @@ def nest2ring(nside: int, nest) -> np.ndarray:
     return out
 
 
+def tile_graph(nside: int, max_nb: int = 12) -> dict:
+    """Neighbour lists and sweep/probe colourings of the 8 x 8 nested tiles."""
+    nt = 12 * (nside // 8) ** 2
+    nb = np.empty((nt, max_nb), dtype=np.int32)
+    sc = np.empty(nt, dtype=np.int32)
+    pc = np.empty(nt, dtype=np.int32)
+    ns, npr = ctypes.c_int(), ctypes.c_int()
+    check(load().mlcr_tile_graph(int(nside), int(max_nb), nb.ctypes.data, sc.ctypes.data,
+                                 pc.ctypes.data, ctypes.byref(ns), ctypes.byref(npr)))
+    return {"nb": nb, "sweep_color": sc, "probe_color": pc, "n_sweep": ns.value,
+            "n_probe": npr.value}
+
+
 def ladder_plan(nside: int, lmax: int) -> dict:
     nl, nt, lb = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     ns = np.zeros(8, dtype=np.int32)

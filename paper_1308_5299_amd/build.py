@@ -13,8 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmlcr.so")
-SOURCES = ["api.cpp", "geometry.cpp", "legendre.hip", "ringfft.hip", "solver.cpp",
-           "solver_kernels.hip"]
+SOURCES = ["api.cpp", "geometry.cpp", "legendre.hip", "ringfft.hip", "solver.cpp", "tiles.cpp",
+           "solver_kernels.hip", "legendre_mfma.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -3,6 +3,7 @@
 // kernels; this file only validates, sizes workspaces and enqueues.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -68,13 +69,18 @@ static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 static long long nalm_of(int lmax) { return (long long)(lmax + 1) * (lmax + 1); }
 
 // Workspaces of one transform of nrhs right-hand sides at band limit lmax.
-static int reserve_ws(mlcr_geom *g, int lmax, int nrhs, bool need_u) {
+static int reserve_ws(mlcr_geom *g, int lmax, int nrhs) {
     const size_t fbytes = (size_t)nrhs * g->nrings * (lmax + 1) * sizeof(double2);
-    const size_t pbytes = (size_t)adjoint_chunks(g, lmax) * nrhs * nalm_of(lmax) * sizeof(double);
+    const size_t pbytes =
+        std::max((size_t)adjoint_chunks(g, lmax) * tlayout_doubles(lmax, nrhs, adj_rc(nrhs)),
+                 (size_t)adjoint_chunks_mfma(g, lmax) * tlayout_doubles(lmax, nrhs, 8)) *
+        sizeof(double);
+    const size_t ubytes =
+        std::max((size_t)tlayout_doubles(lmax, nrhs, synth_rc(nrhs)) * sizeof(double),
+                 (size_t)tlayout32_floats(lmax, nrhs) * sizeof(float));
     if (g->wsF.reserve(fbytes)) return fail(MLCR_ENOMEM, "workspace allocation failed (F)");
     if (g->wsP.reserve(pbytes)) return fail(MLCR_ENOMEM, "workspace allocation failed (P)");
-    if (need_u && g->wsU.reserve((size_t)nrhs * nalm_of(lmax) * sizeof(double)))
-        return fail(MLCR_ENOMEM, "workspace allocation failed (U)");
+    if (g->wsU.reserve(ubytes)) return fail(MLCR_ENOMEM, "workspace allocation failed (U)");
     return MLCR_OK;
 }
 
@@ -128,9 +134,46 @@ static void drain_timing() {
 }
 
 static int check_prec(int prec) {
-    if (prec == MLCR_FP64) return MLCR_OK;
-    if (prec == MLCR_FP32) return fail(MLCR_EUNSUPPORTED, "MLCR_FP32 is not available in this build");
+    if (prec == MLCR_FP64 || prec == MLCR_FP32) return MLCR_OK;
     return fail(MLCR_EINVAL, "unknown precision");
+}
+
+// Legendre step dispatch on the arithmetic of the contraction
+static int legendre_synth_any(const LegendreArgs &a, const double *x, const double *dl, mlcr_geom *g,
+                              double2 *F, int prec) {
+    int rc;
+    if (prec == MLCR_FP32) {
+        float *U = g->wsU.as<float>();
+        {
+            KTimer t("pack", a.stream);
+            if ((rc = launch_pack_t32(a.lmax, a.nrhs, x, dl, U, a.stream))) return rc;
+        }
+        KTimer t("legendre_synth", a.stream);
+        return launch_legendre_synth_mfma(a, U, F);
+    }
+    double *U = g->wsU.as<double>();
+    {
+        KTimer t("pack", a.stream);
+        if ((rc = launch_pack_t(a.lmax, a.nrhs, synth_rc(a.nrhs), x, dl, U, a.stream))) return rc;
+    }
+    KTimer t("legendre_synth", a.stream);
+    return launch_legendre_synth(a, U, F);
+}
+
+static int legendre_adjoint_any(const LegendreArgs &a, const double2 *G, mlcr_geom *g,
+                                const double *x, const double *d, const double *bh, double *y,
+                                int prec) {
+    int rc, nch = 0;
+    double *P = g->wsP.as<double>();
+    {
+        KTimer t("legendre_adjoint", a.stream);
+        if (prec == MLCR_FP32) rc = launch_legendre_adjoint_mfma(a, G, P, &nch);
+        else rc = launch_legendre_adjoint(a, G, P, &nch);
+        if (rc) return rc;
+    }
+    KTimer t("unpack", a.stream);
+    return launch_unpack_t(a.lmax, a.nrhs, prec == MLCR_FP32 ? 8 : adj_rc(a.nrhs), nch, P, x, d,
+                           bh, y, a.stream);
 }
 
 }  // namespace mlcr
@@ -149,34 +192,16 @@ int apply_level(mlcr_op *op, int level, int nrhs, const double *x, double *y, in
     mlcr_geom *g = op->g;
     const mlcr_level &L = op->levels[level];
     const int lmax = L.lmax;
-    if ((rc = reserve_ws(g, lmax, nrhs, true))) return rc;
-    double *u = g->wsU.as<double>();
+    if ((rc = reserve_ws(g, lmax, nrhs))) return rc;
     double2 *F = g->wsF.as<double2>();
-    double *P = g->wsP.as<double>();
     LegendreArgs a{g, lmax, nrhs, s};
-    int nch = 0;
-    {
-        KTimer t("beam_prologue", s);
-        if ((rc = launch_scale_l(lmax, nrhs, x, L.bh.as<double>(), u, s))) return rc;
-    }
-    {
-        KTimer t("legendre_synth", s);
-        if ((rc = launch_legendre_synth(a, u, F))) return rc;
-    }
+    if ((rc = legendre_synth_any(a, x, L.bh.as<double>(), g, F, prec))) return rc;
     {
         KTimer t("ring_apply", s);
         if ((rc = launch_ring_apply(g, lmax, nrhs, F, op->ninv, s))) return rc;
     }
-    {
-        KTimer t("legendre_adjoint", s);
-        if ((rc = launch_legendre_adjoint(a, F, P, &nch))) return rc;
-    }
-    {
-        KTimer t("reduce_epilogue", s);
-        if ((rc = launch_reduce_epilogue(lmax, nrhs, nch, P, x, L.d.as<double>(),
-                                         L.bh.as<double>(), y, s)))
-            return rc;
-    }
+    if ((rc = legendre_adjoint_any(a, F, g, x, L.d.as<double>(), L.bh.as<double>(), y, prec)))
+        return rc;
     return MLCR_OK;
 }
 
@@ -260,14 +285,11 @@ int sht_synth(mlcr_geom *g, int lmax, int nrhs, const double *alm, double *map, 
     if (nrhs < 1) return fail(MLCR_EINVAL, "nrhs must be >= 1");
     int rc;
     if ((rc = check_prec(prec))) return rc;
-    if ((rc = reserve_ws(g, lmax, nrhs, false))) return rc;
+    if ((rc = reserve_ws(g, lmax, nrhs))) return rc;
     hipStream_t s = (hipStream_t)stream;
     LegendreArgs a{g, lmax, nrhs, s};
     double2 *F = g->wsF.as<double2>();
-    {
-        KTimer t("legendre_synth", s);
-        if ((rc = launch_legendre_synth(a, alm, F))) return rc;
-    }
+    if ((rc = legendre_synth_any(a, alm, nullptr, g, F, prec))) return rc;
     {
         KTimer t("ring_synth", s);
         if ((rc = launch_ring_synth(g, lmax, nrhs, F, map, s))) return rc;
@@ -283,25 +305,15 @@ int sht_adjoint(mlcr_geom *g, int lmax, int nrhs, const double *map, double *alm
     if (nrhs < 1) return fail(MLCR_EINVAL, "nrhs must be >= 1");
     int rc;
     if ((rc = check_prec(prec))) return rc;
-    if ((rc = reserve_ws(g, lmax, nrhs, false))) return rc;
+    if ((rc = reserve_ws(g, lmax, nrhs))) return rc;
     hipStream_t s = (hipStream_t)stream;
     LegendreArgs a{g, lmax, nrhs, s};
     double2 *G = g->wsF.as<double2>();
-    double *P = g->wsP.as<double>();
-    int nch = 0;
     {
         KTimer t("ring_adjoint", s);
         if ((rc = launch_ring_adjoint(g, lmax, nrhs, map, G, s))) return rc;
     }
-    {
-        KTimer t("legendre_adjoint", s);
-        if ((rc = launch_legendre_adjoint(a, G, P, &nch))) return rc;
-    }
-    {
-        KTimer t("reduce_epilogue", s);
-        if ((rc = launch_reduce_epilogue(lmax, nrhs, nch, P, nullptr, nullptr, nullptr, alm, s)))
-            return rc;
-    }
+    if ((rc = legendre_adjoint_any(a, G, g, nullptr, nullptr, nullptr, alm, prec))) return rc;
     return MLCR_OK;
 }
 
@@ -329,6 +341,11 @@ static int upload_level(mlcr_level &L, int lmax_h, const std::vector<double> &cl
     return MLCR_OK;
 }
 
+}  // extern "C"
+
+// Level h with a caller-chosen prior spectrum (the solver's hierarchy).
+extern "C" {
+
 int mlcr_op_create(mlcr_geom *g, int lmax, const double *cl, const double *bl, const double *ninv,
                    int max_nrhs, mlcr_op **out) {
     if (!out) return fail(MLCR_EINVAL, "out is NULL");
@@ -351,7 +368,7 @@ int mlcr_op_create(mlcr_geom *g, int lmax, const double *cl, const double *bl, c
     op->cl.assign(cl, cl + lmax + 1);
     op->bl.assign(bl, bl + lmax + 1);
     int rc = upload_level(op->levels[0], lmax, op->cl, op->bl, nullptr);
-    if (!rc) rc = reserve_ws(g, lmax, max_nrhs, true);
+    if (!rc) rc = reserve_ws(g, lmax, max_nrhs);
     if (rc) {
         mlcr_op_destroy(op);
         return rc;

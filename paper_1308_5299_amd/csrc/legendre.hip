@@ -17,13 +17,18 @@
 // (the "l_start" skip), then mixes, then runs the plain loop.
 //
 // Mapping: one wave (one workgroup) per (m, block of 64*NR ring pairs,
-// chunk of RHS).  Lane j of the block owns ring pairs j, j+64, ...; the NR
-// independent recurrences per lane give instruction-level parallelism.
+// chunk of RC right-hand sides); lane j owns pairs j, j+64, ...  The per-l
+// inputs shared by the wave -- recurrence coefficients and the RC x (cos,
+// sin) harmonic coefficients -- stream through LDS in chunks of 32 l, loaded
+// one chunk ahead with coalesced vector loads and read back as broadcasts,
+// so the loop never waits on a scalar-cache round trip.  Harmonic inputs
+// and adjoint partial sums use an l-major, RHS-interleaved layout
+// ("T layout": [RHS chunk][m][l - m][RC][cos, sin]) written and read by the
+// prologue/epilogue kernels.
+//
 // Orders are visited in the sequence 0, lmax, 1, lmax-1, ... so that any
 // contiguous run of work items carries the same amount of work, and each
-// XCD (workgroup id mod 8) receives one contiguous run, so neighbouring m
-// values -- which share cache lines of the ring-major Fourier buffer --
-// are resident in the same L2.
+// XCD (workgroup id mod 8) receives one contiguous run.
 #include <algorithm>
 
 #include "mlcr_internal.h"
@@ -32,6 +37,7 @@ namespace mlcr {
 
 static constexpr int kScaleStep = 512;
 static constexpr int kSeedMinExp = -112;
+static constexpr int kChunk = 32;           // l values per LDS chunk (even)
 
 __device__ __forceinline__ void seed_lambda(double s, int m, double c, double &lam, int &k) {
     int es;
@@ -79,7 +85,7 @@ __device__ __forceinline__ void decode_item(long long total, int lmax, int npb, 
 }
 
 // ---------------------------------------------------------------------------
-// shared pieces of the recurrence
+// per-lane recurrence state
 // ---------------------------------------------------------------------------
 template <int NR>
 struct Lanes {
@@ -137,34 +143,80 @@ struct Lanes {
     __device__ __forceinline__ double w(int j) const { return sc[j] == 0 ? l1[j] : 0.0; }
 };
 
+// wave mode: 0 every lane below range, 1 mixed, 2 every lane in range
+template <int NR>
+__device__ __forceinline__ int wave_mode(const Lanes<NR> &L) {
+    if (__all(L.all_normal())) return 2;
+    if (__all(L.all_scaled())) return 0;
+    return 1;
+}
+
+// offset of order m's block in a T-layout triangle: sum_{m' < m} (lmax - m' + 1)
+__device__ __forceinline__ long long tri_off(int m, int lmax) {
+    return (long long)m * (lmax + 1) - (long long)m * (m - 1) / 2;
+}
+
+// ---------------------------------------------------------------------------
+// per-l coefficients streamed through LDS
+// ---------------------------------------------------------------------------
+// Chunk k holds, for l = m + k*C + j (j < C): ab = (A, B) of the step
+// l -> l+1 (zero past lmax) and NU values of the T-layout harmonic input at
+// l (zero past lmax).  Lanes 0..C-1 load one entry each.
+template <int NU>
+struct Stream {
+    double2 ab;
+    double u[NU > 0 ? NU : 1];
+    __device__ __forceinline__ void load(int k, int m, int lmax, const double2 *__restrict__ abm,
+                                         const double *__restrict__ U) {
+        const int j = threadIdx.x;
+        const int l = m + k * kChunk + j;
+        if (j < kChunk) {
+            ab = (l + 1 <= lmax) ? abm[l + 1] : make_double2(0.0, 0.0);
+            if constexpr (NU > 0) {
+                const double2 *src = reinterpret_cast<const double2 *>(U + (long long)(l - m) * NU);
+#pragma unroll
+                for (int i = 0; i < NU / 2; i++) {
+                    const double2 v = (l <= lmax) ? src[i] : make_double2(0.0, 0.0);
+                    u[2 * i] = v.x;
+                    u[2 * i + 1] = v.y;
+                }
+            }
+        }
+    }
+    __device__ __forceinline__ void store(double2 *sab, double *su) const {
+        const int j = threadIdx.x;
+        if (j < kChunk) {
+            sab[j] = ab;
+            if constexpr (NU > 0) {
+                double2 *dst = reinterpret_cast<double2 *>(su + j * NU);
+#pragma unroll
+                for (int i = 0; i < NU / 2; i++) dst[i] = make_double2(u[2 * i], u[2 * i + 1]);
+            }
+        }
+    }
+};
+
 // ---------------------------------------------------------------------------
 // synthesis
 // ---------------------------------------------------------------------------
 template <int NR, int RC>
 __global__ __launch_bounds__(64) void k_lsynth_f64(
-    const double *__restrict__ u, long long nalm, int nrhs, double2 *__restrict__ F,
-    long long fstride, int lmax, const double *__restrict__ rz, const double *__restrict__ rs,
-    const double2 *__restrict__ ab, const long long *__restrict__ aboff,
-    const double *__restrict__ seedc, const double *__restrict__ zeros, int nrings, int npairs,
+    const double *__restrict__ U, int nrhs, double2 *__restrict__ F, long long fstride, int lmax,
+    const double *__restrict__ rz, const double *__restrict__ rs, const double2 *__restrict__ ab,
+    const long long *__restrict__ aboff, const double *__restrict__ seedc, int nrings, int npairs,
     int npb, long long total) {
+    constexpr int NU = 2 * RC;
+    __shared__ double2 sab[2][kChunk];
+    __shared__ double su[2][kChunk * NU];
     int m, pb, rc;
     bool ok;
     decode_item(total, lmax, npb, m, pb, rc, ok);
     if (!ok) return;
     const int lane = threadIdx.x;
-    const int nl = lmax - m + 1;
-    const long long bc = cos_base(m, lmax);
-    const double2 *abm = ab + aboff[m] - (m + 1);      // abm[l] = (A_lm, B_lm), l >= m+1
+    const long long tri = (long long)(lmax + 1) * (lmax + 2) / 2;
+    const double *Um = U + ((long long)rc * tri + tri_off(m, lmax)) * NU;
+    const double2 *abm = ab + aboff[m] - (m + 1);     // abm[l], l >= m+1
     const int r0 = rc * RC;
-
-    const double *uc[RC];
-    const double *us[RC];
-#pragma unroll
-    for (int r = 0; r < RC; r++) {
-        const int rr = min(r0 + r, nrhs - 1);
-        uc[r] = u + (long long)rr * nalm + bc - m;      // uc[r][l]
-        us[r] = (m > 0) ? uc[r] + nl : zeros - m;       // m = 0 has no sine block
-    }
 
     Lanes<NR> L;
     L.init(pb, lane, m, npairs, rz, rs, seedc[m]);
@@ -174,93 +226,77 @@ __global__ __launch_bounds__(64) void k_lsynth_f64(
 #pragma unroll
         for (int r = 0; r < RC; r++) Ec[j][r] = Es[j][r] = Oc[j][r] = Os[j][r] = 0.0;
 
-    auto acc = [&](int l, bool masked, double (*Ac)[RC], double (*As)[RC]) {
-        double cu[RC], su[RC];
-#pragma unroll
-        for (int r = 0; r < RC; r++) {
-            cu[r] = uc[r][l];
-            su[r] = us[r][l];
-        }
-#pragma unroll
-        for (int j = 0; j < NR; j++) {
-            const double v = masked ? L.w(j) : L.l1[j];
-#pragma unroll
-            for (int r = 0; r < RC; r++) {
-                Ac[j][r] = fma(v, cu[r], Ac[j][r]);
-                As[j][r] = fma(v, su[r], As[j][r]);
-            }
-        }
-    };
+    const int nl = lmax - m + 1;
+    const int nchunks = (nl + kChunk - 1) / kChunk;
+    Stream<NU> st;
+    st.load(0, m, lmax, abm, Um);
+    st.store(sab[0], su[0]);
+    if (nchunks > 1) st.load(1, m, lmax, abm, Um);
+    __syncthreads();
+    int mode = wave_mode(L);
 
-    int l = m;
-    // phase A: every lane below range -- recurrence only
-    while (l < lmax && __all(L.all_scaled())) {
-        L.step_rescale(abm[l + 1]);
-        l++;
-    }
-    // phase B: mixed -- masked accumulation plus rescaling
-    while (l <= lmax && !__all(L.all_normal())) {
-        if (((l - m) & 1) == 0) acc(l, true, Ec, Es);
-        else acc(l, true, Oc, Os);
-        if (l < lmax) L.step_rescale(abm[l + 1]);
-        l++;
-    }
-    // phase C: plain recurrence and accumulation, two steps (even l-m, odd l-m) per trip
-    if (l <= lmax && ((l - m) & 1)) {
-        acc(l, false, Oc, Os);
-        if (l < lmax) L.step(abm[l + 1]);
-        l++;
-    }
-    if (l + 1 <= lmax) {
-        double2 ca = abm[l + 1], cb = abm[min(l + 2, lmax)];
-        double cu0[RC], su0[RC], cu1[RC], su1[RC];
-#pragma unroll
-        for (int r = 0; r < RC; r++) {
-            cu0[r] = uc[r][l];
-            su0[r] = us[r][l];
-            cu1[r] = uc[r][l + 1];
-            su1[r] = us[r][l + 1];
-        }
-        for (; l + 1 <= lmax; l += 2) {
-            // prefetch the next pair
-            const int ln = min(l + 2, lmax);
-            const double2 na = abm[min(l + 3, lmax)], nb = abm[min(l + 4, lmax)];
-            double ncu0[RC], nsu0[RC], ncu1[RC], nsu1[RC];
-#pragma unroll
-            for (int r = 0; r < RC; r++) {
-                ncu0[r] = uc[r][ln];
-                nsu0[r] = us[r][ln];
-                ncu1[r] = uc[r][min(ln + 1, lmax)];
-                nsu1[r] = us[r][min(ln + 1, lmax)];
+    for (int k = 0; k < nchunks; k++) {
+        const int bi = k & 1;
+        const int jend = min(kChunk, nl - k * kChunk);     // entries with l <= lmax
+#pragma unroll 1
+        for (int j = 0; j < jend; j += 2) {
+            // pair (l, l+1) with l - m even; past lmax the streamed values are 0
+            const double2 c0 = sab[bi][j], c1 = sab[bi][j + 1];
+            if (mode == 0) {
+                L.step_rescale(c0);
+                L.step_rescale(c1);
+                mode = wave_mode(L);
+                continue;
             }
+            const double *u0 = &su[bi][j * NU];
+            const double *u1 = &su[bi][(j + 1) * NU];
+            if (mode == 2) {
 #pragma unroll
-            for (int j = 0; j < NR; j++)
+                for (int jj = 0; jj < NR; jj++)
 #pragma unroll
-                for (int r = 0; r < RC; r++) {
-                    Ec[j][r] = fma(L.l1[j], cu0[r], Ec[j][r]);
-                    Es[j][r] = fma(L.l1[j], su0[r], Es[j][r]);
+                    for (int r = 0; r < RC; r++) {
+                        Ec[jj][r] = fma(L.l1[jj], u0[2 * r], Ec[jj][r]);
+                        Es[jj][r] = fma(L.l1[jj], u0[2 * r + 1], Es[jj][r]);
+                    }
+                L.step(c0);
+#pragma unroll
+                for (int jj = 0; jj < NR; jj++)
+#pragma unroll
+                    for (int r = 0; r < RC; r++) {
+                        Oc[jj][r] = fma(L.l1[jj], u1[2 * r], Oc[jj][r]);
+                        Os[jj][r] = fma(L.l1[jj], u1[2 * r + 1], Os[jj][r]);
+                    }
+                L.step(c1);
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < NR; jj++) {
+                    const double v = L.w(jj);
+#pragma unroll
+                    for (int r = 0; r < RC; r++) {
+                        Ec[jj][r] = fma(v, u0[2 * r], Ec[jj][r]);
+                        Es[jj][r] = fma(v, u0[2 * r + 1], Es[jj][r]);
+                    }
                 }
-            L.step(ca);
+                L.step_rescale(c0);
 #pragma unroll
-            for (int j = 0; j < NR; j++)
+                for (int jj = 0; jj < NR; jj++) {
+                    const double v = L.w(jj);
 #pragma unroll
-                for (int r = 0; r < RC; r++) {
-                    Oc[j][r] = fma(L.l1[j], cu1[r], Oc[j][r]);
-                    Os[j][r] = fma(L.l1[j], su1[r], Os[j][r]);
+                    for (int r = 0; r < RC; r++) {
+                        Oc[jj][r] = fma(v, u1[2 * r], Oc[jj][r]);
+                        Os[jj][r] = fma(v, u1[2 * r + 1], Os[jj][r]);
+                    }
                 }
-            L.step(cb);     // harmless past lmax: the value is never used
-            ca = na;
-            cb = nb;
-#pragma unroll
-            for (int r = 0; r < RC; r++) {
-                cu0[r] = ncu0[r];
-                su0[r] = nsu0[r];
-                cu1[r] = ncu1[r];
-                su1[r] = nsu1[r];
+                L.step_rescale(c1);
+                mode = wave_mode(L);
             }
         }
+        if (k + 1 < nchunks) {
+            st.store(sab[bi ^ 1], su[bi ^ 1]);
+            if (k + 2 < nchunks) st.load(k + 2, m, lmax, abm, Um);
+            __syncthreads();
+        }
     }
-    if (l == lmax) acc(l, false, Ec, Es);
 
     const int ld = lmax + 1;
 #pragma unroll
@@ -284,26 +320,28 @@ __global__ __launch_bounds__(64) void k_lsynth_f64(
 // adjoint
 // ---------------------------------------------------------------------------
 // Each lane forms, per l, t = sum_j lambda_l(theta_j) g_j over its NR ring
-// pairs (g = G_N + G_S for even l-m, G_N - G_S for odd), and stores it in a
-// wave-private LDS tile of LB consecutive l.  When the tile is full it is
-// reduced across the 64 lanes (each output by 64/NOUT lanes plus a shuffle)
-// and stored to (first block of the chunk) or added to the partial result
-// of this chunk of ring pairs.  Every output address is owned by one lane,
-// so the chunk's partial sums are formed in a fixed order.
+// pairs (g = G_N + G_S for even l-m, G_N - G_S for odd) and stores it in a
+// wave-private LDS tile of LB consecutive l.  At the end of each tile the
+// tile is reduced across the 64 lanes (each output by 64/NOUT lanes plus a
+// shuffle) and stored (first block of the chunk) or added to the partial
+// result of this chunk of ring pairs, in T layout (coalesced).  Every output
+// address is owned by one lane, so partial sums form in a fixed order.
+// With SQ, lambda^2 replaces lambda and the even ring sums serve every l.
 template <int NR, int RC, int LB, bool SQ>
 __global__ __launch_bounds__(64) void k_ladj_f64(
     const double2 *__restrict__ G, long long fstride, int nrhs, double *__restrict__ P,
-    long long nalm, int pb_per_chunk, int lmax, const double *__restrict__ rz,
-    const double *__restrict__ rs, const double2 *__restrict__ ab,
-    const long long *__restrict__ aboff, const double *__restrict__ seedc, int nrings, int npairs,
-    int npb, int nchunks, long long total) {
-    constexpr int NC = 2 * RC;          // components per l: (cos, sin) x RHS
+    int pb_per_chunk, int lmax, const double *__restrict__ rz, const double *__restrict__ rs,
+    const double2 *__restrict__ ab, const long long *__restrict__ aboff,
+    const double *__restrict__ seedc, int nrings, int npairs, int npb, int nchunks,
+    long long total) {
+    constexpr int NC = 2 * RC;          // components per l: RHS x (cos, sin)
     constexpr int NOUT = LB * NC;
     static_assert(NOUT <= 64 && (64 % NOUT) == 0, "tile must map onto the wave");
-    static_assert(LB % 2 == 0, "tile length must be even");
+    static_assert(LB % 2 == 0 && kChunk % LB == 0, "tile length must divide the chunk");
     constexpr int LPO = 64 / NOUT;      // lanes per output
     constexpr int SEG = 64 / LPO;       // lane values summed by one lane
-    __shared__ double red[LB * NC][65];
+    __shared__ double red[NOUT][65];
+    __shared__ double2 sab[2][kChunk];
 
     int m, chunk, rc;
     bool ok;
@@ -311,17 +349,17 @@ __global__ __launch_bounds__(64) void k_ladj_f64(
     if (!ok) return;
     const int lane = threadIdx.x;
     const int nl = lmax - m + 1;
-    const long long bc = cos_base(m, lmax);
+    const long long tri = (long long)(lmax + 1) * (lmax + 2) / 2;
+    const int nrc = (nrhs + RC - 1) / RC;
     const double2 *abm = ab + aboff[m] - (m + 1);
     const int r0 = rc * RC;
     const int ld = lmax + 1;
 
-    // output owned by this lane in a flush
+    // output owned by this lane in a flush: o = slot * NC + comp (contiguous in T layout)
     const int o = lane / LPO, part = lane % LPO;
-    const int o_slot = o / NC, o_comp = o % NC;
-    const int o_r = o_comp >> 1, o_cs = o_comp & 1;
-    const bool o_write = (part == 0) && (r0 + o_r < nrhs) && !(m == 0 && o_cs == 1);
-    double *Pout = P + ((long long)chunk * nrhs + (r0 + o_r)) * nalm + bc + (o_cs ? nl : 0) - m;
+    const int o_slot = o / NC;
+    double *Pm = P + (((long long)chunk * nrc + rc) * tri + tri_off(m, lmax)) * NC;
+    const bool o_write = (part == 0);
 
     for (int pbi = 0; pbi < pb_per_chunk; pbi++) {
         const int pb = chunk * pb_per_chunk + pbi;
@@ -345,162 +383,253 @@ __global__ __launch_bounds__(64) void k_ladj_f64(
                                                         : make_double2(0.0, 0.0);
                 gec[j][r] = gn.x + gs.x;
                 ges[j][r] = gn.y + gs.y;
-                goc[j][r] = gn.x - gs.x;
-                gos[j][r] = gn.y - gs.y;
+                goc[j][r] = SQ ? gec[j][r] : gn.x - gs.x;
+                gos[j][r] = SQ ? ges[j][r] : gn.y - gs.y;
             }
         }
+        for (int t = lane; t < NOUT * 65; t += 64) (&red[0][0])[t] = 0.0;
 
-        int l = m;
-        while (l < lmax && __all(L.all_scaled())) {
-            L.step_rescale(abm[l + 1]);
-            l++;
-        }
-        const bool nothing = __all(L.all_scaled());     // still below range at l = lmax
-        const int nblk = (nl + LB - 1) / LB;
-        const int blk0 = nothing ? nblk : (l - m) / LB;   // first tile this block touches
-
-        // tiles before blk0 receive nothing from this block of ring pairs
-        if (first && o_write) {
-            for (int b = 0; b < blk0; b++) {
-                const int ll = m + b * LB + o_slot;
-                if (ll <= lmax) Pout[ll] = 0.0;
-            }
-        }
-        if (nothing) continue;
-
-        for (int t = lane; t < LB * NC * 65; t += 64) (&red[0][0])[t] = 0.0;
+        const int nchk = (nl + kChunk - 1) / kChunk;
+        Stream<0> st;
+        st.load(0, m, lmax, abm, nullptr);
+        st.store(sab[0], nullptr);
+        if (nchk > 1) st.load(1, m, lmax, abm, nullptr);
         __syncthreads();
+        int mode = wave_mode(L);
 
-        auto flush = [&](int lb0) {
-            __syncthreads();
+        // end of a tile starting at lb0: reduce and store/add, or store zeros
+        auto flush = [&](int lb0, bool have) {
             double a = 0.0;
-            const int i0 = part * SEG;
+            if (have) {
+                __syncthreads();
+                const int i0 = part * SEG;
 #pragma unroll 8
-            for (int i = 0; i < SEG; i++) a += red[o][i0 + ((i + lane) % SEG)];
+                for (int i = 0; i < SEG; i++) a += red[o][i0 + ((i + lane) % SEG)];
 #pragma unroll
-            for (int off = 1; off < LPO; off <<= 1) a += __shfl_xor(a, off, 64);
-            const int ll = lb0 + o_slot;
-            if (o_write && ll <= lmax) {
-                if (first) Pout[ll] = a;
-                else Pout[ll] += a;
+                for (int off = 1; off < LPO; off <<= 1) a += __shfl_xor(a, off, 64);
             }
-            __syncthreads();
-            for (int tt = lane; tt < LB * NC * 65; tt += 64) (&red[0][0])[tt] = 0.0;
-            __syncthreads();
+            if (o_write && lb0 + o_slot <= lmax && (have || first)) {
+                double *p = Pm + (long long)(lb0 - m) * NC + o;
+                if (first) *p = a;
+                else *p += a;
+            }
+            if (have) {
+                __syncthreads();
+                for (int tt = lane; tt < NOUT * 65; tt += 64) (&red[0][0])[tt] = 0.0;
+                __syncthreads();
+            }
         };
-        auto put = [&](int l_, bool masked, double (*gc)[RC], double (*gs)[RC]) {
+        auto put = [&](int j, bool masked, double (*gc)[RC], double (*gs)[RC]) {
             double tc[RC], ts[RC];
 #pragma unroll
             for (int r = 0; r < RC; r++) tc[r] = ts[r] = 0.0;
 #pragma unroll
-            for (int j = 0; j < NR; j++) {
-                double v = masked ? L.w(j) : L.l1[j];
+            for (int jj = 0; jj < NR; jj++) {
+                double v = masked ? L.w(jj) : L.l1[jj];
                 if (SQ) v = v * v;
 #pragma unroll
                 for (int r = 0; r < RC; r++) {
-                    tc[r] = fma(v, gc[j][r], tc[r]);
-                    ts[r] = fma(v, gs[j][r], ts[r]);
+                    tc[r] = fma(v, gc[jj][r], tc[r]);
+                    ts[r] = fma(v, gs[jj][r], ts[r]);
                 }
             }
-            const int slot = (l_ - m) % LB;
+            const int slot = j % LB;
 #pragma unroll
             for (int r = 0; r < RC; r++) {
                 red[slot * NC + 2 * r][lane] = tc[r];
                 red[slot * NC + 2 * r + 1][lane] = ts[r];
             }
-            if (slot == LB - 1 || l_ == lmax) flush(l_ - slot);
         };
 
-        // phase B: mixed
-        while (l <= lmax && !__all(L.all_normal())) {
-            if (((l - m) & 1) == 0) put(l, true, gec, ges);
-            else put(l, true, SQ ? gec : goc, SQ ? ges : gos);
-            if (l < lmax) L.step_rescale(abm[l + 1]);
-            l++;
-        }
-        // phase C: align to even l-m, then two steps per trip
-        if (l <= lmax && ((l - m) & 1)) {
-            put(l, false, SQ ? gec : goc, SQ ? ges : gos);
-            if (l < lmax) L.step(abm[l + 1]);
-            l++;
-        }
-        if (l + 1 <= lmax) {
-            double2 ca = abm[l + 1], cb = abm[min(l + 2, lmax)];
-            for (; l + 1 <= lmax; l += 2) {
-                const double2 na = abm[min(l + 3, lmax)], nb = abm[min(l + 4, lmax)];
-                put(l, false, gec, ges);
-                L.step(ca);
-                put(l + 1, false, SQ ? gec : goc, SQ ? ges : gos);
-                L.step(cb);
-                ca = na;
-                cb = nb;
+        bool tile_has = false;
+        for (int k = 0; k < nchk; k++) {
+            const int bi = k & 1;
+            const int jend = min(kChunk, nl - k * kChunk);
+#pragma unroll 1
+            for (int j = 0; j < jend; j += 2) {
+                const int l = m + k * kChunk + j;
+                const double2 c0 = sab[bi][j], c1 = sab[bi][j + 1];
+                if (mode == 0) {
+                    L.step_rescale(c0);
+                    L.step_rescale(c1);
+                    mode = wave_mode(L);
+                } else if (mode == 2) {
+                    put(j, false, gec, ges);
+                    L.step(c0);
+                    put(j + 1, false, goc, gos);
+                    L.step(c1);
+                    tile_has = true;
+                } else {
+                    put(j, true, gec, ges);
+                    L.step_rescale(c0);
+                    put(j + 1, true, goc, gos);
+                    L.step_rescale(c1);
+                    mode = wave_mode(L);
+                    tile_has = true;
+                }
+                if (((l + 2 - m) % LB) == 0 || l + 2 > lmax) {
+                    flush(m + ((l - m) / LB) * LB, tile_has);
+                    tile_has = false;
+                }
+            }
+            if (k + 1 < nchk) {
+                st.store(sab[bi ^ 1], nullptr);
+                if (k + 2 < nchk) st.load(k + 2, m, lmax, abm, nullptr);
+                __syncthreads();
             }
         }
-        if (l == lmax) put(l, false, gec, ges);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// T-layout packing (beam prologue) and unpacking (prior/beam epilogue)
+// ---------------------------------------------------------------------------
+// U[rc][tri_off(m) + l - m][r][cs] = dl[l] x[rc*RC + r][packed(l, m, cs)]  (0 for padded RHS)
+__global__ __launch_bounds__(256) void k_pack_t(const double *__restrict__ x,
+                                                const double *__restrict__ dl,
+                                                double *__restrict__ U, int lmax, int nrhs,
+                                                int RC) {
+    const int m = blockIdx.x, rr = blockIdx.y;        // rr over nrc * RC padded RHS
+    const long long nalm = (long long)(lmax + 1) * (lmax + 1);
+    const long long tri = (long long)(lmax + 1) * (lmax + 2) / 2;
+    const int nl = lmax - m + 1;
+    const int rc = rr / RC, r = rr % RC;
+    const long long ob = cos_base(m, lmax);
+    double *Ub = U + ((long long)rc * tri + tri_off(m, lmax)) * 2 * RC + 2 * r;
+    for (int i = threadIdx.x; i < 2 * nl; i += blockDim.x) {
+        const int dlm = i >> 1, cs = i & 1;
+        const int l = m + dlm;
+        double v = 0.0;
+        if (rr < nrhs && !(m == 0 && cs == 1)) {
+            v = x[(long long)rr * nalm + ob + (cs ? nl : 0) + dlm];
+            if (dl) v *= dl[l];
+        }
+        Ub[(long long)dlm * 2 * RC + cs] = v;
+    }
+}
+
+// y[r][packed] = d[l] x + bh[l] sum_c P[c][rc][tri_off(m) + l - m][r][cs]
+// (d, x may be null; bh null means 1)
+__global__ __launch_bounds__(256) void k_unpack_t(const double *__restrict__ P, int nchunks,
+                                                  int nrhs, int RC, const double *__restrict__ x,
+                                                  const double *__restrict__ d,
+                                                  const double *__restrict__ bh,
+                                                  double *__restrict__ y, int lmax) {
+    const int m = blockIdx.x, rr = blockIdx.y;
+    const long long nalm = (long long)(lmax + 1) * (lmax + 1);
+    const long long tri = (long long)(lmax + 1) * (lmax + 2) / 2;
+    const int nrc = (nrhs + RC - 1) / RC;
+    const int nl = lmax - m + 1;
+    const int rc = rr / RC, r = rr % RC;
+    const long long ob = cos_base(m, lmax);
+    const long long cstride = (long long)nrc * tri * 2 * RC;
+    const double *Pb = P + ((long long)rc * tri + tri_off(m, lmax)) * 2 * RC + 2 * r;
+    const int cnt = (m == 0) ? nl : 2 * nl;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const int cs = i >= nl;
+        const int dlm = cs ? i - nl : i;
+        const int l = m + dlm;
+        double s = 0.0;
+        for (int c = 0; c < nchunks; c++) s += Pb[c * cstride + (long long)dlm * 2 * RC + cs];
+        double v = bh ? bh[l] * s : s;
+        const long long idx = (long long)rr * nalm + ob + i;
+        if (d) v = fma(d[l], x[idx], v);
+        y[idx] = v;
     }
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static constexpr int kSynthNR = 4, kSynthRC = 1;
-static constexpr int kAdjNR = 4, kAdjRC = 1, kAdjLB = 8;
+int synth_rc(int nrhs) { return nrhs >= 5 ? 8 : (nrhs >= 2 ? 4 : 1); }
+int adj_rc(int nrhs) { return nrhs >= 2 ? 4 : 1; }
+static constexpr int kAdjNR = 2;
 
 int adjoint_chunks(const mlcr_geom *g, int lmax) {
     const int npb = (g->npairs + 64 * kAdjNR - 1) / (64 * kAdjNR);
-    // enough waves to fill 256 CUs several times over, but few partial buffers
     int want = (8192 + lmax) / (lmax + 1);
     want = std::max(1, std::min(want, 8));
     return std::min(want, npb);
 }
 
-int launch_legendre_synth(const LegendreArgs &a, const double *u, double2 *F) {
-    const mlcr_geom *g = a.g;
-    const int npb = (g->npairs + 64 * kSynthNR - 1) / (64 * kSynthNR);
-    const int nrc = (a.nrhs + kSynthRC - 1) / kSynthRC;
-    const long long total = (long long)(a.lmax + 1) * npb * nrc;
-    const long long grid = ((total + 7) / 8) * 8;
-    const long long nalm = (long long)(a.lmax + 1) * (a.lmax + 1);
-    const long long fstride = (long long)g->nrings * (a.lmax + 1);
-    hipLaunchKernelGGL((k_lsynth_f64<kSynthNR, kSynthRC>), dim3((unsigned)grid), dim3(64), 0,
-                       a.stream, u, nalm, a.nrhs, F, fstride, a.lmax, g->ring_z.as<double>(),
-                       g->ring_s.as<double>(), g->ab.as<double2>(), g->aboff.as<long long>(),
-                       g->seed.as<double>(), g->zeros.as<double>(), g->nrings, g->npairs, npb,
-                       total);
+long long tlayout_doubles(int lmax, int nrhs, int rc) {
+    const long long tri = (long long)(lmax + 1) * (lmax + 2) / 2;
+    return (long long)((nrhs + rc - 1) / rc) * rc * 2 * tri;
+}
+
+int launch_pack_t(int lmax, int nrhs, int RC, const double *x, const double *dl, double *U,
+                  hipStream_t s) {
+    const int nrc = (nrhs + RC - 1) / RC;
+    hipLaunchKernelGGL(k_pack_t, dim3(lmax + 1, nrc * RC), dim3(256), 0, s, x, dl, U, lmax, nrhs,
+                       RC);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }
 
-template <bool SQ>
+int launch_unpack_t(int lmax, int nrhs, int RC, int nchunks, const double *P, const double *x,
+                    const double *d, const double *bh, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_unpack_t, dim3(lmax + 1, nrhs), dim3(256), 0, s, P, nchunks, nrhs, RC, x,
+                       d, bh, y, lmax);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+template <int NR, int RC>
+static int launch_synth_t(const LegendreArgs &a, const double *U, double2 *F) {
+    const mlcr_geom *g = a.g;
+    const int npb = (g->npairs + 64 * NR - 1) / (64 * NR);
+    const int nrc = (a.nrhs + RC - 1) / RC;
+    const long long total = (long long)(a.lmax + 1) * npb * nrc;
+    const long long grid = ((total + 7) / 8) * 8;
+    const long long fstride = (long long)g->nrings * (a.lmax + 1);
+    hipLaunchKernelGGL((k_lsynth_f64<NR, RC>), dim3((unsigned)grid), dim3(64), 0, a.stream, U,
+                       a.nrhs, F, fstride, a.lmax, g->ring_z.as<double>(), g->ring_s.as<double>(),
+                       g->ab.as<double2>(), g->aboff.as<long long>(), g->seed.as<double>(),
+                       g->nrings, g->npairs, npb, total);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+// U in T layout with synth_rc(nrhs) right-hand sides per chunk
+int launch_legendre_synth(const LegendreArgs &a, const double *U, double2 *F) {
+    switch (synth_rc(a.nrhs)) {
+    case 8: return launch_synth_t<1, 8>(a, U, F);
+    case 4: return launch_synth_t<2, 4>(a, U, F);
+    default: return launch_synth_t<4, 1>(a, U, F);
+    }
+}
+
+template <int RC, int LB, bool SQ>
 static int launch_ladj(const LegendreArgs &a, const double2 *G, double *P, int *nchunks_out) {
     const mlcr_geom *g = a.g;
     const int npb = (g->npairs + 64 * kAdjNR - 1) / (64 * kAdjNR);
     const int nchunks = adjoint_chunks(g, a.lmax);
     const int per = (npb + nchunks - 1) / nchunks;
-    const int nrc = (a.nrhs + kAdjRC - 1) / kAdjRC;
+    const int nrc = (a.nrhs + RC - 1) / RC;
     const long long total = (long long)(a.lmax + 1) * nchunks * nrc;
     const long long grid = ((total + 7) / 8) * 8;
-    const long long nalm = (long long)(a.lmax + 1) * (a.lmax + 1);
     const long long fstride = (long long)g->nrings * (a.lmax + 1);
-    hipLaunchKernelGGL((k_ladj_f64<kAdjNR, kAdjRC, kAdjLB, SQ>), dim3((unsigned)grid), dim3(64), 0,
-                       a.stream, G, fstride, a.nrhs, P, nalm, per, a.lmax,
-                       g->ring_z.as<double>(), g->ring_s.as<double>(), g->ab.as<double2>(),
-                       g->aboff.as<long long>(), g->seed.as<double>(), g->nrings, g->npairs, npb,
-                       nchunks, total);
+    hipLaunchKernelGGL((k_ladj_f64<kAdjNR, RC, LB, SQ>), dim3((unsigned)grid), dim3(64), 0,
+                       a.stream, G, fstride, a.nrhs, P, per, a.lmax, g->ring_z.as<double>(),
+                       g->ring_s.as<double>(), g->ab.as<double2>(), g->aboff.as<long long>(),
+                       g->seed.as<double>(), g->nrings, g->npairs, npb, nchunks, total);
     MLCR_HIP_CHECK(hipGetLastError());
     *nchunks_out = nchunks;
     return MLCR_OK;
 }
 
+// P in T layout with adj_rc(nrhs) right-hand sides per chunk
 int launch_legendre_adjoint(const LegendreArgs &a, const double2 *G, double *P, int *nchunks_out) {
-    return launch_ladj<false>(a, G, P, nchunks_out);
+    if (adj_rc(a.nrhs) == 4) return launch_ladj<4, 4, false>(a, G, P, nchunks_out);
+    return launch_ladj<1, 8, false>(a, G, P, nchunks_out);
 }
 
 // Same reduction with lambda^2 in place of lambda and the even ring sums for
 // every l (the parity sign squares away): sum_k lambda_lm(theta_k)^2 G_m(theta_k).
 int launch_legendre_adjoint_sq(const LegendreArgs &a, const double2 *G, double *P,
                                int *nchunks_out) {
-    return launch_ladj<true>(a, G, P, nchunks_out);
+    if (adj_rc(a.nrhs) == 4) return launch_ladj<4, 4, true>(a, G, P, nchunks_out);
+    return launch_ladj<1, 8, true>(a, G, P, nchunks_out);
 }
 
 }  // namespace mlcr

@@ -124,10 +124,22 @@ int launch_ring_adjoint(const mlcr_geom *g, int lmax, int nrhs, const double *ma
                         hipStream_t s);
 int launch_ring_apply(const mlcr_geom *g, int lmax, int nrhs, double2 *FG, const double *ninv,
                       hipStream_t s);
-int launch_scale_l(int lmax, int nrhs, const double *x, const double *dl, double *u,
-                   hipStream_t s);
-int launch_reduce_epilogue(int lmax, int nrhs, int nchunks, const double *P, const double *x,
-                           const double *d, const double *bh, double *y, hipStream_t s);
 int adjoint_chunks(const mlcr_geom *g, int lmax);
+// matrix-core (float32) Legendre kernels, 8 RHS per wave
+long long tlayout32_floats(int lmax, int nrhs);
+int launch_pack_t32(int lmax, int nrhs, const double *x, const double *dl, float *U,
+                    hipStream_t s);
+int launch_legendre_synth_mfma(const LegendreArgs &a, const float *U32, double2 *F);
+int launch_legendre_adjoint_mfma(const LegendreArgs &a, const double2 *G, double *P,
+                                 int *nchunks_out);
+int adjoint_chunks_mfma(const mlcr_geom *g, int lmax);
+// T layout ([RHS chunk][m][l - m][RC][cos, sin]) of the Legendre kernels
+int synth_rc(int nrhs);
+int adj_rc(int nrhs);
+long long tlayout_doubles(int lmax, int nrhs, int rc);
+int launch_pack_t(int lmax, int nrhs, int RC, const double *x, const double *dl, double *U,
+                  hipStream_t s);
+int launch_unpack_t(int lmax, int nrhs, int RC, int nchunks, const double *P, const double *x,
+                    const double *d, const double *bh, double *y, hipStream_t s);
 
 }  // namespace mlcr

@@ -234,61 +234,4 @@ int launch_ring_apply(const mlcr_geom *g, int lmax, int nrhs, double2 *FG, const
     return launch_ring<2>(g, lmax, nrhs, FG, FG, nullptr, nullptr, ninv, s);
 }
 
-// ---------------------------------------------------------------------------
-// l-diagonal kernels on packed vectors: one workgroup per (m, RHS)
-// ---------------------------------------------------------------------------
-// u = diag(dl) x  (dl == nullptr: copy)
-__global__ __launch_bounds__(256) void k_scale_l(const double *__restrict__ x,
-                                                 const double *__restrict__ dl,
-                                                 double *__restrict__ u, int lmax, long long nalm) {
-    const int m = blockIdx.x, r = blockIdx.y;
-    const int nl = lmax - m + 1;
-    const int cnt = (m == 0) ? nl : 2 * nl;
-    const long long off = (long long)r * nalm + cos_base(m, lmax);
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-        const int l = m + (i < nl ? i : i - nl);
-        const double v = x[off + i];
-        u[off + i] = dl ? dl[l] * v : v;
-    }
-}
-
-// y = diag(d) x + diag(bh) sum_c P_c   (d, x may be null; bh null means 1)
-__global__ __launch_bounds__(256) void k_reduce_epi(const double *__restrict__ P, int nchunks,
-                                                    int nrhs, const double *__restrict__ x,
-                                                    const double *__restrict__ d,
-                                                    const double *__restrict__ bh,
-                                                    double *__restrict__ y, int lmax,
-                                                    long long nalm) {
-    const int m = blockIdx.x, r = blockIdx.y;
-    const int nl = lmax - m + 1;
-    const int cnt = (m == 0) ? nl : 2 * nl;
-    const long long off = (long long)r * nalm + cos_base(m, lmax);
-    const long long cstride = (long long)nrhs * nalm;
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-        const int l = m + (i < nl ? i : i - nl);
-        double s = 0.0;
-        for (int c = 0; c < nchunks; c++) s += P[c * cstride + off + i];
-        double v = bh ? bh[l] * s : s;
-        if (d) v = fma(d[l], x[off + i], v);
-        y[off + i] = v;
-    }
-}
-
-int launch_scale_l(int lmax, int nrhs, const double *x, const double *dl, double *u,
-                   hipStream_t s) {
-    const long long nalm = (long long)(lmax + 1) * (lmax + 1);
-    hipLaunchKernelGGL(k_scale_l, dim3(lmax + 1, nrhs), dim3(256), 0, s, x, dl, u, lmax, nalm);
-    MLCR_HIP_CHECK(hipGetLastError());
-    return MLCR_OK;
-}
-
-int launch_reduce_epilogue(int lmax, int nrhs, int nchunks, const double *P, const double *x,
-                           const double *d, const double *bh, double *y, hipStream_t s) {
-    const long long nalm = (long long)(lmax + 1) * (lmax + 1);
-    hipLaunchKernelGGL(k_reduce_epi, dim3(lmax + 1, nrhs), dim3(256), 0, s, P, nchunks, nrhs, x,
-                       d, bh, y, lmax, nalm);
-    MLCR_HIP_CHECK(hipGetLastError());
-    return MLCR_OK;
-}
-
 }  // namespace mlcr

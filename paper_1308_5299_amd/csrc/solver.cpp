@@ -60,7 +60,8 @@ long long nest2ring(int nside, long long ipnest) {
 // ladder (Sec. 3.2 level structure; Sec. 3.3 filters; Sec. 3.4 band limits)
 // ---------------------------------------------------------------------------
 static constexpr int kDenseL = 40;     // bottom level: dense solve for l <= 40 (Sec. 3.2)
-static constexpr int kTile = 8;        // k = 8 pixel tiles (Sec. 3.4)
+static constexpr int kTile = kTileK;
+static constexpr int kMaxNb = 12;       // neighbour tiles per tile (8 in a regular patch)
 static const double kPi = 3.14159265358979323846;
 
 struct Plan {
@@ -103,10 +104,13 @@ static void default_plan(int nside_obs, int lmax, Plan &p) {
     }
     int ns = nside_obs / 2, lprev = lmax;
     while (ns >= 32 && p.H < 8 && ns % kTile == 0) {
+        // band limits (Sec. 3.3): the finest level keeps the full band; 4 N_side
+        // suffices on a q_l-filtered level (N_side >= 512), the coarser,
+        // high signal-to-noise Gaussian levels need 6 N_side against ringing
         int lh;
-        if (p.H == 0) lh = lmax;                         // finest level keeps the full band
-        else if (p.H == 1) lh = std::min(lprev, 4 * ns); // 4 N_side at the second level
-        else lh = std::min(lprev, 6 * ns);               // up to 6 N_side on coarse levels
+        if (p.H == 0) lh = lmax;
+        else if (ns >= 512) lh = std::min(lprev, 4 * ns);
+        else lh = std::min(lprev, 6 * ns);
         if (lh <= kDenseL) break;
         p.nside[p.H] = ns;
         p.lmax[p.H] = lh;
@@ -121,10 +125,16 @@ static void default_plan(int nside_obs, int lmax, Plan &p) {
     }
     p.nrec[p.H - 1] = 1;          // the dense bottom solve is exact: one visit
     p.nrec_top = 1;               // finest level runs once down, once up
+    // q_l filters on the fine, lower signal-to-noise levels (the paper's N_side
+    // 1024 and 512 levels); Gaussians of FWHM two pixels on levels of
+    // N_side <= 256, where the q_l ringing would make couplings non-local.
     for (int h = 0; h < p.H; h++) {
-        if (h == 0) p.fl[h] = qfilter(p.lmax[h], (int)std::lround(p.lmax[h] * 2570.0 / 3000.0));
-        else if (h == 1) p.fl[h] = qfilter(p.lmax[h], (int)std::lround(p.lmax[h] * 1536.0 / 2048.0));
-        else p.fl[h] = gauss2px(p.lmax[h], p.nside[h]);
+        if (h == 0 && p.nside[h] >= 512)
+            p.fl[h] = qfilter(p.lmax[h], (int)std::lround(p.lmax[h] * 2570.0 / 3000.0));
+        else if (h == 1 && p.nside[h] >= 512)
+            p.fl[h] = qfilter(p.lmax[h], (int)std::lround(p.lmax[h] * 1536.0 / 2048.0));
+        else
+            p.fl[h] = gauss2px(p.lmax[h], p.nside[h]);
     }
     p.lmax_b = std::min(kDenseL, p.lmax[p.H - 1]);
     p.highpass.resize(lmax + 1);
@@ -195,7 +205,11 @@ struct PixLevel {
     int nside = 0, lmax = 0, opl = 0;
     mlcr_geom *geom = nullptr;
     int ntiles = 0, kk = kTile * kTile;
-    DevBuf wdown, act, one, tilepix, minv, ridge;
+    // block-sparse smoother: neighbour lists (CSR), coupling blocks, inverse
+    // diagonal blocks, sweep colours and the tiles of each colour
+    int n_sweep = 0, n_probe = 0;
+    std::vector<int> soff;              // host: offsets of the colours in stiles
+    DevBuf wdown, act, one, tilepix, nbptr, nbs, off, scol, stiles, minv, ridge;
     DevBuf x, b, r, t, map, cmap;
 };
 
@@ -268,10 +282,19 @@ struct GpuOps : CycleOps {
         // x_h += Y_h^T M_h Y_h r_h  (eqs. pixel-correction-1..3)
         if ((rc = sht_synth(L.geom, L.lmax, R, L.r.as<double>(), L.map.as<double>(), prec, s)))
             return rc;
-        if ((rc = launch_tile_apply(L.map.as<double>(), L.cmap.as<double>(), L.geom->npix, R,
-                                    L.tilepix.as<int>(), L.minv.as<float>(), L.ntiles, L.kk, 1.0,
-                                    s)))
-            return rc;
+        // c = M r: one multicolour block symmetric Gauss-Seidel sweep (Sec. 3.4 pattern)
+        for (int pass = 0; pass < 2; pass++)
+            for (int j = 0; j < L.n_sweep; j++) {
+                const int c = pass == 0 ? j : L.n_sweep - 1 - j;
+                if (pass == 1 && c == L.n_sweep - 1) continue;     // no later neighbours
+                if ((rc = launch_sgs_color(pass == 0, L.map.as<double>(), L.cmap.as<double>(),
+                                           L.geom->npix, R, L.tilepix.as<int>(),
+                                           L.stiles.as<int>() + L.soff[c],
+                                           L.soff[c + 1] - L.soff[c], L.nbptr.as<int>(),
+                                           L.nbs.as<int>(), L.scol.as<int>(), c,
+                                           L.off.as<float>(), L.minv.as<float>(), s)))
+                    return rc;
+            }
         if ((rc = sht_adjoint(L.geom, L.lmax, R, L.cmap.as<double>(), L.t.as<double>(), prec, s)))
             return rc;
         return launch_axpy_l(L.x.as<double>(), L.t.as<double>(), L.one.as<double>(), nullptr,
@@ -322,7 +345,8 @@ static int setup_top_diag(mlcr_solver *S, hipStream_t s) {
     if ((rc = alloc(Xi, (size_t)g->nrings * (l2 + 1) * sizeof(double2)))) return rc;
     if ((rc = alloc(G2, (size_t)g->nrings * (lmax + 1) * sizeof(double2)))) return rc;
     if ((rc = alloc(q, (size_t)nalm_l(lmax) * sizeof(double)))) return rc;
-    if (g->wsP.reserve((size_t)adjoint_chunks(g, lmax) * nalm_l(lmax) * sizeof(double)))
+    if (g->wsP.reserve((size_t)adjoint_chunks(g, lmax) * tlayout_doubles(lmax, 1, adj_rc(1)) *
+                       sizeof(double)))
         return fail(MLCR_ENOMEM, "workspace allocation failed");
     if ((rc = launch_ring_adjoint(g, l2, 1, op->ninv, Xi.as<double2>(), s))) return rc;
     if ((rc = launch_diag_pairs(Xi.as<double2>(), l2 + 1, G2.as<double2>(), lmax, g->nrings, s)))
@@ -330,8 +354,8 @@ static int setup_top_diag(mlcr_solver *S, hipStream_t s) {
     LegendreArgs a{g, lmax, 1, s};
     int nch = 0;
     if ((rc = launch_legendre_adjoint_sq(a, G2.as<double2>(), g->wsP.as<double>(), &nch))) return rc;
-    if ((rc = launch_reduce_epilogue(lmax, 1, nch, g->wsP.as<double>(), nullptr, nullptr, nullptr,
-                                     q.as<double>(), s)))
+    if ((rc = launch_unpack_t(lmax, 1, adj_rc(1), nch, g->wsP.as<double>(), nullptr, nullptr,
+                              nullptr, q.as<double>(), s)))
         return rc;
     if ((rc = alloc(S->top_dinv, (size_t)nalm_l(lmax) * sizeof(double)))) return rc;
     const mlcr_level &L0 = op->levels[0];
@@ -342,6 +366,17 @@ static int setup_top_diag(mlcr_solver *S, hipStream_t s) {
     return MLCR_OK;
 }
 
+// tiles of each colour, grouped; off[c] .. off[c + 1] index list
+static void group_by_color(const std::vector<int> &col, int ncol, std::vector<int> &list,
+                           std::vector<int> &off) {
+    off.assign(ncol + 1, 0);
+    for (int c : col) off[c + 1]++;
+    for (int c = 0; c < ncol; c++) off[c + 1] += off[c];
+    list.resize(col.size());
+    std::vector<int> pos(off.begin(), off.end() - 1);
+    for (size_t t = 0; t < col.size(); t++) list[pos[col[t]]++] = (int)t;
+}
+
 static int setup_smoother(mlcr_solver *S, PixLevel &L, hipStream_t s) {
     int rc;
     const int kk = L.kk;
@@ -350,6 +385,42 @@ static int setup_smoother(mlcr_solver *S, PixLevel &L, hipStream_t s) {
     std::vector<int> tp((size_t)nt * kk);
     for (long long i = 0; i < (long long)nt * kk; i++) tp[i] = (int)nest2ring(L.nside, i);
     if ((rc = up(L.tilepix, tp.data(), tp.size() * sizeof(int)))) return rc;
+    // tile graph: neighbour lists in CSR form, rev[slot] = slot of the reverse pair
+    TileGraph G;
+    if ((rc = build_tile_graph(L.nside, kTile, kMaxNb, G))) return rc;
+    std::vector<int> ptr(nt + 1, 0), nbs, rev;
+    for (int t = 0; t < nt; t++) {
+        int n = 0;
+        while (n < kMaxNb && G.nb[(size_t)t * kMaxNb + n] >= 0) n++;
+        ptr[t + 1] = ptr[t] + n;
+    }
+    nbs.resize(ptr[nt]);
+    rev.resize(ptr[nt]);
+    for (int t = 0; t < nt; t++)
+        for (int j = ptr[t]; j < ptr[t + 1]; j++) nbs[j] = G.nb[(size_t)t * kMaxNb + (j - ptr[t])];
+    for (int t = 0; t < nt; t++)
+        for (int j = ptr[t]; j < ptr[t + 1]; j++) {
+            const int u = nbs[j];
+            const auto b = nbs.begin() + ptr[u], e = nbs.begin() + ptr[u + 1];
+            const auto it = std::lower_bound(b, e, t);
+            if (it == e || *it != t) return fail(MLCR_EINVAL, "tile graph is not symmetric");
+            rev[j] = (int)(it - nbs.begin());
+        }
+    const long long nslots = ptr[nt];
+    if ((rc = up(L.nbptr, ptr.data(), ptr.size() * sizeof(int)))) return rc;
+    if ((rc = up(L.nbs, nbs.data(), nbs.size() * sizeof(int)))) return rc;
+    DevBuf drev;
+    if ((rc = up(drev, rev.data(), rev.size() * sizeof(int)))) return rc;
+    if ((rc = up(L.scol, G.sweep_color.data(), nt * sizeof(int)))) return rc;
+    std::vector<int> slist, plist, poff;
+    group_by_color(G.sweep_color, G.n_sweep, slist, L.soff);
+    group_by_color(G.probe_color, G.n_probe, plist, poff);
+    L.n_sweep = G.n_sweep;
+    L.n_probe = G.n_probe;
+    if ((rc = up(L.stiles, slist.data(), slist.size() * sizeof(int)))) return rc;
+    DevBuf ptiles;
+    if ((rc = up(ptiles, plist.data(), plist.size() * sizeof(int)))) return rc;
+
     const long long npix = L.geom->npix, na = nalm_l(L.lmax);
     const int P = 16;          // probes per batch
     DevBuf maps, U, V, blocks;
@@ -357,22 +428,37 @@ static int setup_smoother(mlcr_solver *S, PixLevel &L, hipStream_t s) {
     if ((rc = alloc(U, (size_t)P * na * sizeof(double)))) return rc;
     if ((rc = alloc(V, (size_t)P * na * sizeof(double)))) return rc;
     if ((rc = alloc(blocks, (size_t)nt * kk * kk * sizeof(double)))) return rc;
-    // column c of the block of tile t: (Y_h A_h Y_h^T e_c)[tile t], with e_c the
-    // indicator of position c in every tile (tiles at least k pixels apart)
-    for (int c0 = 0; c0 < kk; c0 += P) {
-        const int np = std::min(P, kk - c0);
-        if ((rc = launch_probe_maps(maps.as<double>(), npix, L.tilepix.as<int>(), nt, kk, c0, np, s)))
-            return rc;
-        if ((rc = sht_adjoint(L.geom, L.lmax, np, maps.as<double>(), U.as<double>(), MLCR_FP64, s)))
-            return rc;
-        if ((rc = apply_level(S->op, L.opl, np, U.as<double>(), V.as<double>(), MLCR_FP64, s)))
-            return rc;
-        if ((rc = sht_synth(L.geom, L.lmax, np, V.as<double>(), maps.as<double>(), MLCR_FP64, s)))
-            return rc;
-        if ((rc = launch_probe_collect(maps.as<double>(), npix, L.tilepix.as<int>(), nt, kk, c0, np,
-                                       blocks.as<double>(), s)))
-            return rc;
+    if ((rc = alloc(L.off, (size_t)std::max(1LL, nslots) * kk * kk * sizeof(float)))) return rc;
+    // column c of the blocks of tile u: (Y_h A_h Y_h^T e_c) read at u and at its
+    // neighbours, with e_c the indicator of position c in every tile of u's
+    // probe colour
+    for (int c = 0; c < L.n_probe; c++) {
+        const int *tl = ptiles.as<int>() + poff[c];
+        const int ntl = poff[c + 1] - poff[c];
+        for (int c0 = 0; c0 < kk; c0 += P) {
+            const int np = std::min(P, kk - c0);
+            if ((rc = launch_probe_maps(maps.as<double>(), npix, L.tilepix.as<int>(), tl, ntl, kk,
+                                        c0, np, s)))
+                return rc;
+            if ((rc = sht_adjoint(L.geom, L.lmax, np, maps.as<double>(), U.as<double>(), MLCR_FP64,
+                                  s)))
+                return rc;
+            if ((rc = apply_level(S->op, L.opl, np, U.as<double>(), V.as<double>(), MLCR_FP64, s)))
+                return rc;
+            if ((rc = sht_synth(L.geom, L.lmax, np, V.as<double>(), maps.as<double>(), MLCR_FP64,
+                                s)))
+                return rc;
+            if ((rc = launch_probe_collect(maps.as<double>(), npix, L.tilepix.as<int>(), tl, ntl,
+                                           L.nbptr.as<int>(), L.nbs.as<int>(), drev.as<int>(),
+                                           kMaxNb, c0, np, blocks.as<double>(),
+                                           L.off.as<float>(), s)))
+                return rc;
+        }
     }
+    if (nslots > 0 &&
+        (rc = launch_sym_off(L.nbptr.as<int>(), L.nbs.as<int>(), drev.as<int>(), L.off.as<float>(),
+                             nt, s)))
+        return rc;
     if ((rc = alloc(L.minv, (size_t)nt * kk * kk * sizeof(float)))) return rc;
     if ((rc = alloc(L.ridge, (size_t)nt * sizeof(float)))) return rc;
     if ((rc = launch_tile_factor(blocks.as<double>(), nt, kk, L.minv.as<float>(),
@@ -382,9 +468,39 @@ static int setup_smoother(mlcr_solver *S, PixLevel &L, hipStream_t s) {
     std::vector<float> rg(nt);
     MLCR_HIP_CHECK(hipMemcpy(rg.data(), L.ridge.ptr, nt * sizeof(float), hipMemcpyDeviceToHost));
     float worst = 0.f;
-    for (float v : rg) {
-        if (v < 0) return fail(MLCR_ENOTPD, "tile factorization failed even with a ridge");
-        worst = std::max(worst, v);
+    int nfail = 0, first_fail = -1;
+    for (int t = 0; t < nt; t++) {
+        if (rg[t] < 0) {
+            if (first_fail < 0) first_fail = t;
+            nfail++;
+        }
+        worst = std::max(worst, rg[t]);
+    }
+    if (nfail) {
+        // describe the first failing block: non-finite entries, diagonal range, asymmetry
+        std::vector<double> B((size_t)kk * kk);
+        MLCR_HIP_CHECK(hipMemcpy(B.data(), blocks.as<double>() + (size_t)first_fail * kk * kk,
+                                 B.size() * sizeof(double), hipMemcpyDeviceToHost));
+        int nonfinite = 0;
+        double dmin = 1e300, dmax = -1e300, asym = 0.0, amax = 0.0;
+        for (int i = 0; i < kk; i++)
+            for (int j = 0; j < kk; j++) {
+                const double v = B[(size_t)i * kk + j];
+                if (!std::isfinite(v)) nonfinite++;
+                amax = std::max(amax, std::fabs(v));
+                asym = std::max(asym, std::fabs(v - B[(size_t)j * kk + i]));
+                if (i == j) {
+                    dmin = std::min(dmin, v);
+                    dmax = std::max(dmax, v);
+                }
+            }
+        return fail(MLCR_ENOTPD,
+                    "tile factorization failed even with a ridge: level N_side " +
+                        std::to_string(L.nside) + ", " + std::to_string(nfail) + " of " +
+                        std::to_string(nt) + " tiles; first tile " + std::to_string(first_fail) +
+                        ": non-finite " + std::to_string(nonfinite) + ", diag [" +
+                        std::to_string(dmin) + ", " + std::to_string(dmax) + "], max |a| " +
+                        std::to_string(amax) + ", max asymmetry " + std::to_string(asym));
     }
     S->ridge_summary.push_back(worst);
     return MLCR_OK;
@@ -395,15 +511,16 @@ static int setup_bottom(mlcr_solver *S, hipStream_t s) {
     const int lb = S->lmax_b;
     const long long nb = nalm_l(lb);
     // active modes of the bottom level in packed order
+    const std::vector<double> &clb = op->cl;
     std::vector<int> idx;
     {
         long long pos = 0;
         for (int l = 0; l <= lb; l++, pos++)
-            if (op->cl[l] > 0) idx.push_back((int)pos);
+            if (clb[l] > 0) idx.push_back((int)pos);
         for (int m = 1; m <= lb; m++)
             for (int cs = 0; cs < 2; cs++)
                 for (int l = m; l <= lb; l++, pos++)
-                    if (op->cl[l] > 0) idx.push_back((int)pos);
+                    if (clb[l] > 0) idx.push_back((int)pos);
     }
     const int na = (int)idx.size();
     S->na = na;
@@ -464,6 +581,15 @@ static int solver_build(mlcr_solver *S, const Plan &p, hipStream_t s) {
         S->opl_b = 0;
         return setup_bottom(S, s);
     }
+    // The coarse levels are Galerkin products of the top operator, which
+    // needs every mode in the unknowns: with C_l = 0 (a mode conditioned to
+    // zero, e.g. C_0 = C_1 = 0) the pixel operators lose locality, and the
+    // paper's wide prior C_0 = C_1 = C_2 is the supported form (Sec. 4.1).
+    for (int l = 0; l <= lmax; l++)
+        if (!(op->cl[l] > 0))
+            return fail(MLCR_EINVAL, "the multi-level solver needs C_l > 0 for every l (l = " +
+                                         std::to_string(l) +
+                                         " has C_l = 0; use a wide prior such as C_0 = C_1 = C_2)");
     // pixel levels
     for (int h = 0; h < p.H; h++) {
         auto L = std::make_unique<PixLevel>();
@@ -534,6 +660,22 @@ int mlcr_nest2ring(int nside, long long n, const long long *nest, long long *rin
         if (nest[i] < 0 || nest[i] >= npix) return fail(MLCR_EINVAL, "nested index out of range");
         ring[i] = nest2ring(nside, nest[i]);
     }
+    return MLCR_OK;
+}
+
+int mlcr_tile_graph(int nside, int max_nb, int *nb, int *sweep_color, int *probe_color,
+                    int *n_sweep, int *n_probe) {
+    if (nside < kTile || nside % kTile || max_nb < 1 || !nb || !sweep_color || !probe_color ||
+        !n_sweep || !n_probe)
+        return fail(MLCR_EINVAL, "bad argument");
+    TileGraph G;
+    int rc = build_tile_graph(nside, kTile, max_nb, G);
+    if (rc) return rc;
+    std::copy(G.nb.begin(), G.nb.end(), nb);
+    std::copy(G.sweep_color.begin(), G.sweep_color.end(), sweep_color);
+    std::copy(G.probe_color.begin(), G.probe_color.end(), probe_color);
+    *n_sweep = G.n_sweep;
+    *n_probe = G.n_probe;
     return MLCR_OK;
 }
 

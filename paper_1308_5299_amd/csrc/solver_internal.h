@@ -7,6 +7,10 @@
 
 namespace mlcr {
 
+// pixel-level tiles: k x k nested pixels, k = 8 on every level (Sec. 3.4)
+constexpr int kTileK = 8;
+constexpr int kTileK2 = kTileK * kTileK;
+
 // solver_kernels.hip
 int launch_transfer(const double *src, int lmax_src, double *dst, int lmax_dst, const double *w,
                     int lmax_w, bool add, int nrhs, hipStream_t s);
@@ -20,14 +24,19 @@ int launch_diag_pairs(const double2 *Xi, int ldx, double2 *G, int lmax, int nrin
                       hipStream_t s);
 int launch_diag_inverse(const double *q, const double *d, const double *bh, double *dinv, int lmax,
                         hipStream_t s);
-int launch_probe_maps(double *maps, long long npix, const int *tilepix, int ntiles, int kk, int c0,
-                      int nprobe, hipStream_t s);
-int launch_probe_collect(const double *z, long long npix, const int *tilepix, int ntiles, int kk,
-                         int c0, int nprobe, double *blocks, hipStream_t s);
+int launch_probe_maps(double *maps, long long npix, const int *tilepix, const int *tiles, int ntl,
+                      int kk, int c0, int nprobe, hipStream_t s);
+int launch_probe_collect(const double *z, long long npix, const int *tilepix, const int *tiles,
+                         int ntl, const int *nbptr, const int *nbs, const int *rev, int max_nb,
+                         int c0, int nprobe, double *diag, float *off, hipStream_t s);
+int launch_sym_off(const int *nbptr, const int *nbs, const int *rev, float *off, int ntiles,
+                   hipStream_t s);
 int launch_tile_factor(const double *blocks, int ntiles, int kk, float *minv, float *ridge,
                        hipStream_t s);
-int launch_tile_apply(const double *r, double *c, long long npix, int nrhs, const int *tilepix,
-                      const float *minv, int ntiles, int kk, double omega, hipStream_t s);
+int launch_sgs_color(bool forward, const double *r, double *y, long long npix, int nrhs,
+                     const int *tilepix, const int *tiles, int ntl, const int *nbptr,
+                     const int *nbs, const int *color, int kappa, const float *off,
+                     const float *minv, hipStream_t s);
 int launch_dense_gather(const double *cols, long long ld, const int *act_idx, int na, double *Ad,
                         hipStream_t s);
 int launch_dense_cholesky(double *a, int n, int *info, hipStream_t s);
@@ -46,5 +55,20 @@ int apply_level(mlcr_op *op, int level, int nrhs, const double *x, double *y, in
 
 // HEALPix NESTED -> RING index (Gorski et al. 2005)
 long long nest2ring(int nside, long long ipnest);
+
+// tiles.cpp: neighbour graph and colourings of the k x k nested tiles of a
+// pixel level.  Tiles are neighbours when their nearest pixel centres are
+// closer than kTileAdjPx pixel widths; tiles probed together keep all tiles
+// they are read at kProbeSepPx pixel widths away from each other.
+constexpr double kTileAdjPx = 4.0;
+constexpr double kProbeSepPx = 6.0;
+struct TileGraph {
+    int nt = 0, max_nb = 0;
+    std::vector<int> nb;             // [nt][max_nb] neighbour tiles, -1 padded, ascending
+    std::vector<int> sweep_color;    // neighbours differ
+    std::vector<int> probe_color;    // probe responses separate
+    int n_sweep = 0, n_probe = 0;
+};
+int build_tile_graph(int nside, int k, int max_nb, TileGraph &G);
 
 }  // namespace mlcr

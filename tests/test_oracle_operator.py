@@ -39,11 +39,18 @@ def test_ringdft_vs_bruteforce_masked():
     np.testing.assert_allclose(op.diag_YtNY(nside, lmax, ninv), np.diag(K1), rtol=1e-13, atol=0)
 
 
-def test_apply_matches_dense_and_is_spd():
+@pytest.mark.parametrize("project", [False, True])
+def test_apply_matches_dense_and_is_spd(project):
+    """project: C_0 = C_1 = 0 removes the monopole and dipole from the unknowns
+    (their rows and columns of A vanish)."""
     cfg, d = _c1()
+    d = dict(d)
+    d["cl"] = d["cl"].copy()
+    d["cl"][:2] = 0.0 if project else d["cl"][2]
     A = op.dense_A(d["cl"], d["bl"], d["ninv"], cfg.nside)
     x = np.random.default_rng(0).standard_normal(cfg.nalm)
     act = solve.active_modes(d["cl"])
+    assert act.sum() == (cfg.nalm - 4 if project else cfg.nalm)
     y = op.apply_A(x, d["cl"], d["bl"], d["ninv"], cfg.nside)
     np.testing.assert_allclose(y, A @ np.where(act, x, 0.0), rtol=0, atol=1e-11 * np.abs(y).max())
     assert np.all(y[~act] == 0.0)
@@ -132,6 +139,6 @@ def test_rhs_special_cases():
 
 def test_s_inv_ratio_and_sigma_prior():
     cfg, d = _c1()
-    assert abs(solve.sigma_prior(d["cl"]) - 100.0) < 1e-10
+    assert abs(solve.sigma_prior(d["cl"]) - 100.0) < 1e-10       # C_0 = C_1 = 0 here
     b = np.random.default_rng(2).standard_normal(cfg.nalm)
     assert solve.s_inv_ratio(b, b, d["cl"]) == pytest.approx(1.0)

@@ -5,8 +5,11 @@ N_side=2048 observation grid, lmax 3000, an 80%-sky mask plus point-source
 mask, and the best-fit LCDM C_l.  None of that data is available, so these
 synthetic configurations stand in for it.  They keep the paper's structure:
 
-* a power-law prior C_l = A / (l (l+1)) for l >= 2 (C_0 = C_1 = 0), with A
-  chosen so the prior sky rms is 100 uK;
+* a power-law prior C_l = A / (l (l+1)) for l >= 2, with A chosen so the
+  l >= 2 sky rms is 100 uK, and C_0 = C_1 = C_2 (the paper's wide prior for
+  the monopole and dipole, which its multi-level method needs); the tiny
+  dense-solve case instead conditions on a zero monopole and dipole,
+  C_0 = C_1 = 0;
 * a symmetric Gaussian beam (Sec. 2.2, beam matrix B diagonal in l) with the
   pixel window p_l taken as 1;
 * white, inhomogeneous noise sigma_p = sigma0 (1 + 2 cos^2 theta_p);
@@ -29,6 +32,7 @@ class WorkloadConfig:
     disc_radius_deg: float
     nrhs: int
     sky_rms_uK: float = 100.0
+    wide_low_l: bool = True   # C_0 = C_1 = C_2 (multi-level solves); False: C_0 = C_1 = 0
 
     @property
     def npix(self) -> int:
@@ -49,7 +53,7 @@ class WorkloadConfig:
 # Five workloads: tiny FP64 solve (dense Cholesky check), FP64 GPU solve,
 # precision form, batching form, full scale.
 CONFIGS = {
-    "c1": WorkloadConfig("c1", 16, 32, -1.0, 10.0, 20.0, 5, 5.0, 1),
+    "c1": WorkloadConfig("c1", 16, 32, -1.0, 10.0, 20.0, 5, 5.0, 1, wide_low_l=False),
     "c2": WorkloadConfig("c2", 256, 512, 30.0, 20.0, 20.0, 50, 1.0, 1),
     "c3": WorkloadConfig("c3", 1024, 2048, 10.0, 30.0, 20.0, 200, 0.5, 1),
     "c4": WorkloadConfig("c4", 1024, 2048, 10.0, 30.0, 20.0, 200, 0.5, 32),

@@ -94,13 +94,16 @@ def pixel_centres(nside: int):
 # model inputs
 # --------------------------------------------------------------------------
 def power_spectrum(cfg: WorkloadConfig) -> np.ndarray:
-    """C_l = A/(l(l+1)) for l >= 2, C_0 = C_1 = 0, with
-    sum_{l>=2} (2l+1) C_l / (4 pi) = sky_rms^2 (uK^2)."""
+    """C_l = A/(l(l+1)) for l >= 2 with sum_{l>=2} (2l+1) C_l / (4 pi) =
+    sky_rms^2 (uK^2); C_0 = C_1 = C_2 (the wide monopole/dipole prior of the
+    paper's experiment, Sec. 4.1) when cfg.wide_low_l, else C_0 = C_1 = 0."""
     ell = np.arange(cfg.lmax + 1, dtype=np.float64)
     shape = np.zeros(cfg.lmax + 1)
     shape[2:] = 1.0 / (ell[2:] * (ell[2:] + 1.0))
     var = np.sum((2.0 * ell + 1.0) * shape) / (4.0 * math.pi)
-    return shape * (cfg.sky_rms_uK ** 2 / var)
+    cl = shape * (cfg.sky_rms_uK ** 2 / var)
+    cl[:2] = cl[2] if cfg.wide_low_l else 0.0
+    return cl
 
 
 def gaussian_beam(cfg: WorkloadConfig, lmax: int | None = None) -> np.ndarray:
