@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "A·x applies/s (SHT pair) at Nside 2048, ℓmax 4096; FP64 vs mixed at 1e-3 μK"
 PEAK_FP64_VALU = 78.6e12      # MI355X FP64 vector FLOP/s
+PEAK_FP32 = 157.3e12          # MI355X FP32 (vector and dense MFMA) FLOP/s
 PEAK_HBM = 8.0e12             # MI355X HBM3E bytes/s
 
 
@@ -115,6 +116,50 @@ def cpu_baseline(cfg, R: int, seed_x, ninv_host, budget_s: float = 20.0):
     }
 
 
+def run_path(mlcr, torch, op, x, y, prec, steps, warmup, label):
+    """Warm up, then time `steps` applies; returns (ms per step, per-kernel ms per launch)."""
+    for i in range(warmup):
+        mlcr.apply_A(op, x, prec=prec, out=y)
+        torch.cuda.synchronize()
+        log(f"[bench] {label} warmup {i + 1}/{warmup} done")
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    with mlcr.KernelTimer() as kt:
+        e0.record(stream)
+        for i in range(steps):
+            mlcr.apply_A(op, x, prec=prec, out=y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / steps
+    kernels = {k: (v[0] / v[1]) for k, v in kt.result.items()}
+    log(f"[bench] {label}: {steps} steps, {ms_step:.3f} ms/step")
+    for k, v in sorted(kernels.items(), key=lambda t: -t[1]):
+        log(f"[bench]   {k:18s} {v:9.3f} ms/launch")
+    return ms_step, kernels
+
+
+def roofline(kernels, cfg, R, mixed: bool):
+    dom = max(kernels, key=lambda k: kernels[k])
+    bound, work, unit = algorithmic_work(dom, cfg.nside, cfg.lmax, R)
+    sec = kernels[dom] / 1e3
+    if bound == "alu":
+        if mixed:
+            roof = {"bound": "mfma", "kernel": dom, "achieved": work / sec / 1e12,
+                    "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s"}
+        else:
+            roof = {"bound": "alu", "kernel": dom, "achieved": work / sec / 1e12,
+                    "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "kernel": dom, "achieved": work / sec / 1e9,
+                "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel_ms"] = {k: round(v, 4) for k, v in kernels.items()}
+    return roof
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,7 +167,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c5")
     ap.add_argument("--nrhs", type=int, default=0)
-    ap.add_argument("--prec", default="fp64", choices=["fp64"])
+    ap.add_argument("--paths", default="fp32,fp64",
+                    help="Legendre paths to time; the first is the reported value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -139,8 +185,12 @@ def main():
 
     cfg = workloads.get_config(args.config)
     R = args.nrhs or cfg.nrhs
-    prec = {"fp64": mlcr.FP64}[args.prec]
-    log(f"[bench] config {cfg.name}: nside {cfg.nside} lmax {cfg.lmax} R {R} prec {args.prec}")
+    paths = [p.strip() for p in args.paths.split(",") if p.strip()]
+    precs = {"fp64": mlcr.FP64, "fp32": mlcr.FP32}
+    for p in paths:
+        if p not in precs:
+            sys.exit(f"unknown path {p}")
+    log(f"[bench] config {cfg.name}: nside {cfg.nside} lmax {cfg.lmax} R {R} paths {paths}")
     t0 = time.time()
     d = workloads.workload_inputs(cfg)
     x_host = np.stack([workloads.prior_sample(cfg, r) for r in range(R)])
@@ -151,44 +201,25 @@ def main():
     t0 = time.time()
     geom = mlcr.Geometry(cfg.nside, cfg.lmax)
     op = mlcr.Operator(geom, d["cl"], d["bl"], ninv, max_nrhs=R)
-    y = torch.empty_like(x)
     torch.cuda.synchronize()
     log(f"[bench] geometry + operator ready in {time.time() - t0:.1f}s")
 
-    for i in range(args.warmup):
-        mlcr.apply_A(op, x, prec=prec, out=y)
-        torch.cuda.synchronize()
-        log(f"[bench] warmup {i + 1}/{args.warmup} done")
+    res, outs = {}, {}
+    for p in paths:
+        y = torch.empty_like(x)
+        res[p] = run_path(mlcr, torch, op, x, y, precs[p], args.steps, args.warmup, p)
+        outs[p] = y
+    # the mixed result against the float64 GPU apply (itself at 1e-12 of the oracle)
+    err = None
+    if "fp64" in outs and "fp32" in outs:
+        dlt = (outs["fp32"] - outs["fp64"]).norm() / outs["fp64"].norm()
+        err = float(dlt)
+        log(f"[bench] fp32 path vs fp64 path: relative l2 difference {err:.3e}")
 
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    with mlcr.KernelTimer() as kt:
-        e0.record(stream)
-        for i in range(args.steps):
-            mlcr.apply_A(op, x, prec=prec, out=y)
-        e1.record(stream)
-        torch.cuda.synchronize()
-    ms_total = e0.elapsed_time(e1)
-    ms_step = ms_total / args.steps
-    value = R * args.steps / (ms_total / 1e3)
-    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, {value:.2f} RHS-applies/s")
-    kernels = {k: (v[0] / v[1]) for k, v in kt.result.items()}
-    for k, v in sorted(kernels.items(), key=lambda t: -t[1]):
-        log(f"[bench]   {k:18s} {v:9.3f} ms/launch")
-    dom = max(kernels, key=lambda k: kernels[k])
-    bound, work, unit = algorithmic_work(dom, cfg.nside, cfg.lmax, R)
-    sec = kernels[dom] / 1e3
-    if bound == "alu":
-        roof = {"bound": "alu", "kernel": dom, "achieved": work / sec / 1e12,
-                "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "hbm", "kernel": dom, "achieved": work / sec / 1e9,
-                "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel_ms"] = {k: round(v, 4) for k, v in kernels.items()}
+    head = paths[0]
+    ms_step, kernels = res[head]
+    value = R / (ms_step / 1e3)
+    roof = roofline(kernels, cfg, R, mixed=(head != "fp64"))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -196,6 +227,9 @@ def main():
         cpu = cpu_baseline(cfg, R, x_host, d["ninv"])
         log(f"[bench] cpu baseline {cpu['value']:.3e} {cpu['unit']}")
 
+    others = {p: {"value": R / (res[p][0] / 1e3), "ms_per_step": res[p][0],
+                  "roofline": roofline(res[p][1], cfg, R, mixed=(p != "fp64"))}
+              for p in paths[1:]}
     out = {
         "metric": METRIC,
         "value": value,
@@ -207,14 +241,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if head == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{cfg.name}: HEALPix Nside {cfg.nside}, lmax {cfg.lmax}, "
-                               f"{R} RHS per apply, {args.prec} Legendre path",
-                   "nside": cfg.nside, "lmax": cfg.lmax, "nrhs": R, "prec": args.prec,
+                               f"{R} RHS per apply, {head} Legendre path",
+                   "nside": cfg.nside, "lmax": cfg.lmax, "nrhs": R, "prec": head,
                    "global_batch": R},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "other_paths": others,
+        "fp32_vs_fp64_rel_l2": err,
     }
     print(json.dumps(out), flush=True)
 

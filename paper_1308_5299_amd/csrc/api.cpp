@@ -77,7 +77,7 @@ static int reserve_ws(mlcr_geom *g, int lmax, int nrhs) {
         sizeof(double);
     const size_t ubytes =
         std::max((size_t)tlayout_doubles(lmax, nrhs, synth_rc(nrhs)) * sizeof(double),
-                 (size_t)tlayout32_floats(lmax, nrhs) * sizeof(float));
+                 (size_t)tlayout_m_elems(lmax, nrhs) * sizeof(double));
     if (g->wsF.reserve(fbytes)) return fail(MLCR_ENOMEM, "workspace allocation failed (F)");
     if (g->wsP.reserve(pbytes)) return fail(MLCR_ENOMEM, "workspace allocation failed (P)");
     if (g->wsU.reserve(ubytes)) return fail(MLCR_ENOMEM, "workspace allocation failed (U)");
@@ -139,17 +139,27 @@ static int check_prec(int prec) {
 }
 
 // Legendre step dispatch on the arithmetic of the contraction
+// Float64 uses the matrix cores once a launch carries enough RHS to fill
+// their 16 columns (8 RHS x cos/sin) at least half; below that the per-lane
+// vector kernels do less work.
+static constexpr int kMfmaF64MinRhs = 4;
+
+static bool use_mfma(int prec, int nrhs) {
+    return prec == MLCR_FP32 || nrhs >= kMfmaF64MinRhs;
+}
+
 static int legendre_synth_any(const LegendreArgs &a, const double *x, const double *dl, mlcr_geom *g,
                               double2 *F, int prec) {
     int rc;
-    if (prec == MLCR_FP32) {
-        float *U = g->wsU.as<float>();
+    if (use_mfma(prec, a.nrhs)) {
+        const bool dbl = prec == MLCR_FP64;
+        void *U = g->wsU.ptr;
         {
             KTimer t("pack", a.stream);
-            if ((rc = launch_pack_t32(a.lmax, a.nrhs, x, dl, U, a.stream))) return rc;
+            if ((rc = launch_pack_tm(a.lmax, a.nrhs, x, dl, U, dbl, a.stream))) return rc;
         }
         KTimer t("legendre_synth", a.stream);
-        return launch_legendre_synth_mfma(a, U, F);
+        return launch_legendre_synth_mfma(a, U, F, dbl);
     }
     double *U = g->wsU.as<double>();
     {
@@ -165,15 +175,15 @@ static int legendre_adjoint_any(const LegendreArgs &a, const double2 *G, mlcr_ge
                                 int prec) {
     int rc, nch = 0;
     double *P = g->wsP.as<double>();
+    const bool mm = use_mfma(prec, a.nrhs);
     {
         KTimer t("legendre_adjoint", a.stream);
-        if (prec == MLCR_FP32) rc = launch_legendre_adjoint_mfma(a, G, P, &nch);
+        if (mm) rc = launch_legendre_adjoint_mfma(a, G, P, &nch, prec == MLCR_FP64);
         else rc = launch_legendre_adjoint(a, G, P, &nch);
         if (rc) return rc;
     }
     KTimer t("unpack", a.stream);
-    return launch_unpack_t(a.lmax, a.nrhs, prec == MLCR_FP32 ? 8 : adj_rc(a.nrhs), nch, P, x, d,
-                           bh, y, a.stream);
+    return launch_unpack_t(a.lmax, a.nrhs, mm ? 8 : adj_rc(a.nrhs), nch, P, x, d, bh, y, a.stream);
 }
 
 }  // namespace mlcr

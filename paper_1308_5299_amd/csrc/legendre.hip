@@ -509,32 +509,48 @@ __global__ __launch_bounds__(256) void k_pack_t(const double *__restrict__ x,
 }
 
 // y[r][packed] = d[l] x + bh[l] sum_c P[c][rc][tri_off(m) + l - m][r][cs]
-// (d, x may be null; bh null means 1)
+// (d, x may be null; bh null means 1).  One workgroup per (m, RHS chunk):
+// tiles of 64 l are read row by row (the T layout is contiguous in
+// (l, r, cs)), summed over the chunks, transposed in LDS and written out
+// along l, so both sides stream.
 __global__ __launch_bounds__(256) void k_unpack_t(const double *__restrict__ P, int nchunks,
                                                   int nrhs, int RC, const double *__restrict__ x,
                                                   const double *__restrict__ d,
                                                   const double *__restrict__ bh,
                                                   double *__restrict__ y, int lmax) {
-    const int m = blockIdx.x, rr = blockIdx.y;
+    constexpr int TL = 64;
+    __shared__ double tile[TL * 17];
+    const int m = blockIdx.x, rc = blockIdx.y;
     const long long nalm = (long long)(lmax + 1) * (lmax + 1);
     const long long tri = (long long)(lmax + 1) * (lmax + 2) / 2;
     const int nrc = (nrhs + RC - 1) / RC;
     const int nl = lmax - m + 1;
-    const int rc = rr / RC, r = rr % RC;
+    const int NC = 2 * RC;
     const long long ob = cos_base(m, lmax);
-    const long long cstride = (long long)nrc * tri * 2 * RC;
-    const double *Pb = P + ((long long)rc * tri + tri_off(m, lmax)) * 2 * RC + 2 * r;
-    const int cnt = (m == 0) ? nl : 2 * nl;
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-        const int cs = i >= nl;
-        const int dlm = cs ? i - nl : i;
-        const int l = m + dlm;
-        double s = 0.0;
-        for (int c = 0; c < nchunks; c++) s += Pb[c * cstride + (long long)dlm * 2 * RC + cs];
-        double v = bh ? bh[l] * s : s;
-        const long long idx = (long long)rr * nalm + ob + i;
-        if (d) v = fma(d[l], x[idx], v);
-        y[idx] = v;
+    const long long cstride = (long long)nrc * tri * NC;
+    const double *Pb = P + ((long long)rc * tri + tri_off(m, lmax)) * NC;
+    for (int base = 0; base < nl; base += TL) {
+        const int nt = min(TL, nl - base);
+        for (int e = threadIdx.x; e < nt * NC; e += blockDim.x) {
+            const int j = e / NC, comp = e % NC;
+            const double *src = Pb + (long long)base * NC + e;
+            double acc = 0.0;
+            for (int c = 0; c < nchunks; c++) acc += src[c * cstride];
+            tile[j * 17 + comp] = acc;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nt * NC; e += blockDim.x) {
+            const int comp = e / nt, j = e % nt;
+            const int r = rc * RC + comp / 2, cs = comp & 1;
+            if (r >= nrhs || (m == 0 && cs == 1)) continue;
+            const int l = m + base + j;
+            double v = tile[j * 17 + comp];
+            if (bh) v *= bh[l];
+            const long long idx = (long long)r * nalm + ob + (long long)cs * nl + base + j;
+            if (d) v = fma(d[l], x[idx], v);
+            y[idx] = v;
+        }
+        __syncthreads();
     }
 }
 
@@ -568,7 +584,9 @@ int launch_pack_t(int lmax, int nrhs, int RC, const double *x, const double *dl,
 
 int launch_unpack_t(int lmax, int nrhs, int RC, int nchunks, const double *P, const double *x,
                     const double *d, const double *bh, double *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_unpack_t, dim3(lmax + 1, nrhs), dim3(256), 0, s, P, nchunks, nrhs, RC, x,
+    if (RC > 8) return fail(MLCR_EINVAL, "unpack supports at most 8 RHS per chunk");
+    const int nrc = (nrhs + RC - 1) / RC;
+    hipLaunchKernelGGL(k_unpack_t, dim3(lmax + 1, nrc), dim3(256), 0, s, P, nchunks, nrhs, RC, x,
                        d, bh, y, lmax);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;

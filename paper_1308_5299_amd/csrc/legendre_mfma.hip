@@ -1,4 +1,4 @@
-// Legendre step on the matrix cores (float32 contraction, float64 recurrence).
+// Legendre step on the matrix cores.
 //
 // Same transforms as legendre.hip (Sec. 2.1 eq. sh-synthesis and its
 // transpose, lambda_lm of Sec. 3.2), written as per-order GEMMs:
@@ -6,12 +6,15 @@
 //     adjoint    V_m[l, c]    = sum_ring Lambda_m[ring, l] G_m[ring, c]
 // with c = (RHS, cos/sin), 16 columns (8 right-hand sides).  The recurrence
 // seeds, the 2^-512 range scaling and the recurrence itself stay in
-// float64 on the vector ALUs; each lambda is rounded once to float32, staged
-// through LDS and fed to v_mfma_f32_16x16x4f32 (float32 products, float32
-// accumulation).  Even and odd l - m are separate GEMMs (mirror-ring parity).
+// float64 on the vector ALUs while the matrix cores contract: each lambda is
+// staged through LDS and fed to v_mfma_f32_16x16x4f32 (T = float: float32
+// products and accumulation, the mixed path) or v_mfma_f64_16x16x4f64
+// (T = double: the float64 path).  Even and odd l - m are separate GEMMs
+// (mirror-ring parity).
 //
 // MFMA 16x16x4 operand layout (lane = 0..63): A[i][k] in lane i + 16 k,
-// B[k][j] in lane j + 16 k, D[i][j] in lane j + 16 (i / 4), element i % 4.
+// B[k][j] in lane j + 16 k.  D[i][j] sits in lane j + 16 (i / 4), element
+// i % 4 for float32, and in lane j + 16 (i % 4), element i / 4 for float64.
 #include <algorithm>
 
 #include "mlcr_internal.h"
@@ -19,6 +22,31 @@
 namespace mlcr {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mma;
+template <>
+struct Mma<float> {
+    typedef f4 acc;
+    static __device__ __forceinline__ acc zero() { return (f4){0.f, 0.f, 0.f, 0.f}; }
+    static __device__ __forceinline__ acc mma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // row i of D held by lane group kq (= lane / 16) in element v
+    static __device__ __forceinline__ int row(int kq, int v) { return 4 * kq + v; }
+    static __device__ __forceinline__ float cvt(double v) { return (float)v; }
+};
+template <>
+struct Mma<double> {
+    typedef d4 acc;
+    static __device__ __forceinline__ acc zero() { return (d4){0.0, 0.0, 0.0, 0.0}; }
+    static __device__ __forceinline__ acc mma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int kq, int v) { return kq + 4 * v; }
+    static __device__ __forceinline__ double cvt(double v) { return v; }
+};
 
 static constexpr int kScaleStepM = 512;
 static constexpr int kSeedMinExpM = -112;
@@ -87,7 +115,7 @@ struct Lane1 {
             sc--;
         }
     }
-    __device__ __forceinline__ float w() const { return sc == 0 ? (float)l1 : 0.0f; }
+    __device__ __forceinline__ double w() const { return sc == 0 ? l1 : 0.0; }
 };
 
 __device__ __forceinline__ int wave_mode1(const Lane1 &L) {
@@ -99,22 +127,24 @@ __device__ __forceinline__ int wave_mode1(const Lane1 &L) {
 // ---------------------------------------------------------------------------
 // synthesis: one wave per (m, 64 ring pairs, 8 RHS)
 // ---------------------------------------------------------------------------
-// U32: float T layout [RHS chunk][m][l - m][8][cos, sin] (16 floats per l)
-__global__ __launch_bounds__(64) void k_lsynth_mfma32(
-    const float *__restrict__ U32, int nrhs, double2 *__restrict__ F, long long fstride, int lmax,
+// U: T layout [RHS chunk][m][l - m][8][cos, sin] (16 values per l)
+template <typename T>
+__global__ __launch_bounds__(64) void k_lsynth_mfma(
+    const T *__restrict__ U, int nrhs, double2 *__restrict__ F, long long fstride, int lmax,
     const double *__restrict__ rz, const double *__restrict__ rs, const double2 *__restrict__ ab,
     const long long *__restrict__ aboff, const double *__restrict__ seedc, int nrings, int npairs,
     int npb, long long total) {
+    typedef Mma<T> M;
     __shared__ double2 sab[kChunkM];
-    __shared__ float su[kChunkM * 16];
-    __shared__ float lam[8][64];
+    __shared__ T su[kChunkM * 16];
+    __shared__ T lam[8][64];
     int m, pb, rc;
     bool ok;
     decode_item_m(total, lmax, npb, m, pb, rc, ok);
     if (!ok) return;
     const int lane = threadIdx.x;
     const long long tri = (long long)(lmax + 1) * (lmax + 2) / 2;
-    const float *Um = U32 + ((long long)rc * tri + tri_off_m(m, lmax)) * 16;
+    const T *Um = U + ((long long)rc * tri + tri_off_m(m, lmax)) * 16;
     const double2 *abm = ab + aboff[m] - (m + 1);
     const int nl = lmax - m + 1;
 
@@ -125,11 +155,27 @@ __global__ __launch_bounds__(64) void k_lsynth_mfma32(
     seed_lambda_m(valid ? rs[kp] : 1.0, m, seedc[m], L.l1, L.sc);
     L.l2 = 0.0;
 
-    f4 CE[4], CO[4];
+    typename M::acc CE[4], CO[4];
 #pragma unroll
-    for (int b = 0; b < 4; b++) CE[b] = CO[b] = (f4){0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < 4; b++) CE[b] = CO[b] = M::zero();
     int mode = wave_mode1(L);
     const int kq = lane >> 4, jc = lane & 15;
+
+    // 8 steps l = m + k*C + j0 + s, s = 0..7 (even s: even l - m): lambda to
+    // LDS, then 4 ring blocks x (even, odd) MFMAs
+    auto mfma_group = [&](int j0) {
+        __syncthreads();
+        const T be = su[(j0 + 2 * kq) * 16 + jc];
+        const T bo = su[(j0 + 2 * kq + 1) * 16 + jc];
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            const T ae = lam[2 * kq][16 * b + jc];
+            const T ao = lam[2 * kq + 1][16 * b + jc];
+            CE[b] = M::mma(ae, be, CE[b]);
+            CO[b] = M::mma(ao, bo, CO[b]);
+        }
+        __syncthreads();
+    };
 
     const int nchunks = (nl + kChunkM - 1) / kChunkM;
     for (int k = 0; k < nchunks; k++) {
@@ -141,43 +187,46 @@ __global__ __launch_bounds__(64) void k_lsynth_mfma32(
         }
         {
             const int base = k * kChunkM;
-            // 32 l x 16 floats = 128 float4: two per lane
-            for (int q = lane; q < kChunkM * 4; q += 64) {
-                const int jl = q >> 2, part = q & 3;
-                const float4 v = (base + jl < nl)
-                                     ? reinterpret_cast<const float4 *>(Um + (long long)(base + jl) * 16)[part]
-                                     : make_float4(0.f, 0.f, 0.f, 0.f);
-                reinterpret_cast<float4 *>(su + jl * 16)[part] = v;
+            // 32 l x 16 values, moved in 16-byte units
+            constexpr int UPL = 16 * (int)sizeof(T) / 16;      // units per l
+            for (int q = lane; q < kChunkM * UPL; q += 64) {
+                const int jl = q / UPL, part = q % UPL;
+                const uint4 v = (base + jl < nl)
+                                    ? reinterpret_cast<const uint4 *>(Um + (long long)(base + jl) * 16)[part]
+                                    : make_uint4(0u, 0u, 0u, 0u);
+                reinterpret_cast<uint4 *>(su + jl * 16)[part] = v;
             }
         }
         __syncthreads();
         const int jend = min(kChunkM, nl - k * kChunkM);
-#pragma unroll 1
-        for (int j0 = 0; j0 < jend; j0 += 8) {
-            // 8 steps l = m + k*C + j0 + s, s = 0..7 (even s: even l - m)
-            if (mode == 0) {
+        int j0 = 0;
+        // every lane still range-scaled: advance only
+        for (; mode == 0 && j0 < jend; j0 += 8) {
 #pragma unroll
-                for (int s = 0; s < 8; s++) L.step_rescale(sab[j0 + s]);
-                mode = wave_mode1(L);
-                continue;
-            }
-            __syncthreads();
+            for (int s = 0; s < 8; s++) L.step_rescale(sab[j0 + s]);
+            mode = wave_mode1(L);
+        }
+        // some lanes scaled: lambda is 0 there until they reach the range
+        for (; mode == 1 && j0 < jend; j0 += 8) {
 #pragma unroll
             for (int s = 0; s < 8; s++) {
-                lam[s][lane] = L.w();
+                lam[s][lane] = M::cvt(L.w());
                 L.step_rescale(sab[j0 + s]);
             }
             mode = wave_mode1(L);
-            __syncthreads();
-            const float be = su[(j0 + 2 * kq) * 16 + jc];
-            const float bo = su[(j0 + 2 * kq + 1) * 16 + jc];
+            mfma_group(j0);
+        }
+        // steady state: plain recurrence, values in range (|lambda| <= O(1))
+        for (; j0 < jend; j0 += 8) {
 #pragma unroll
-            for (int b = 0; b < 4; b++) {
-                const float ae = lam[2 * kq][16 * b + jc];
-                const float ao = lam[2 * kq + 1][16 * b + jc];
-                CE[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ae, be, CE[b], 0, 0, 0);
-                CO[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ao, bo, CO[b], 0, 0, 0);
+            for (int s = 0; s < 8; s++) {
+                lam[s][lane] = M::cvt(L.l1);
+                const double2 c = sab[j0 + s];
+                const double nv = fma(c.x, L.z * L.l1, -c.y * L.l2);
+                L.l2 = L.l1;
+                L.l1 = nv;
             }
+            mfma_group(j0);
         }
     }
     // D[i][j] of block b: ring pair 16 b + 4 kq + v, column j = jc = (rhs, cos/sin)
@@ -189,7 +238,7 @@ __global__ __launch_bounds__(64) void k_lsynth_mfma32(
         for (int b = 0; b < 4; b++)
 #pragma unroll
             for (int v = 0; v < 4; v++) {
-                const int p = pb * 64 + 16 * b + 4 * kq + v;
+                const int p = pb * 64 + 16 * b + M::row(kq, v);
                 if (p >= npairs) continue;
                 const double e = (double)CE[b][v], o = (double)CO[b][v];
                 const int north = p, south = nrings - 1 - p;
@@ -200,25 +249,31 @@ __global__ __launch_bounds__(64) void k_lsynth_mfma32(
 }
 
 // ---------------------------------------------------------------------------
-// adjoint: one wave per (m, chunk of ring-pair blocks, 8 RHS)
+// adjoint: one workgroup of W waves per (m, chunk of W ring-pair blocks, 8 RHS)
 // ---------------------------------------------------------------------------
-// Per tile of 32 l (16 even + 16 odd l - m) and 64 ring pairs:
-// D_even[l_i, c] += sum_{k} Lambda[ring_k, l_2i] g_even[ring_k, c] over 16 MFMAs of
-// 4 ring pairs each; likewise odd.  The tile result is stored (first block
-// of the chunk) or added to the chunk's partial sums P (double, T layout).
-__global__ __launch_bounds__(64) void k_ladj_mfma32(
-    const double2 *__restrict__ G, long long fstride, int nrhs, double *__restrict__ P,
-    int pb_per_chunk, int lmax, const double *__restrict__ rz, const double *__restrict__ rs,
-    const double2 *__restrict__ ab, const long long *__restrict__ aboff,
-    const double *__restrict__ seedc, int nrings, int npairs, int npb, int nchunks,
-    long long total) {
-    __shared__ double2 sab[kChunkM];
-    __shared__ float lam[32][65];
+// Wave w owns ring-pair block chunk * W + w.  Per tile of 32 l (16 even +
+// 16 odd l - m) every wave forms its block's contribution
+//     D_even[l_i, c] = sum_k Lambda[ring_k, l_2i] g_even[ring_k, c]
+// with 16 MFMAs of 4 ring pairs each (likewise odd), the W tiles are summed
+// in LDS, and the chunk's partial sum is stored once (float64, T layout);
+// the chunks are added in the unpack step.
+template <typename T, int W>
+__global__ __launch_bounds__(64 * W) void k_ladj_mfma(
+    const double2 *__restrict__ G, long long fstride, int nrhs, double *__restrict__ P, int lmax,
+    const double *__restrict__ rz, const double *__restrict__ rs, const double2 *__restrict__ ab,
+    const long long *__restrict__ aboff, const double *__restrict__ seedc, int nrings, int npairs,
+    int npb, int nchunks, long long total) {
+    typedef Mma<T> M;
+    constexpr int LS = 32 * 65;                  // lambda tile of one wave, padded rows
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2 *sab = reinterpret_cast<double2 *>(smem);
+    T *lam_all = reinterpret_cast<T *>(smem + kChunkM * sizeof(double2));
     int m, chunk, rc;
     bool ok;
     decode_item_m(total, lmax, nchunks, m, chunk, rc, ok);
     if (!ok) return;
-    const int lane = threadIdx.x;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    T *lam = lam_all + wv * LS;
     const int nl = lmax - m + 1;
     const long long tri = (long long)(lmax + 1) * (lmax + 2) / 2;
     const int nrc = (nrhs + 7) / 8;
@@ -228,105 +283,111 @@ __global__ __launch_bounds__(64) void k_ladj_mfma32(
     double *Pm = P + (((long long)chunk * nrc + rc) * tri + tri_off_m(m, lmax)) * 16;
     const int rB = min(rc * 8 + (jc >> 1), nrhs - 1), csB = jc & 1;
 
-    for (int pbi = 0; pbi < pb_per_chunk; pbi++) {
-        const int pb = chunk * pb_per_chunk + pbi;
-        if (pb >= npb) break;
-        const bool first = (pbi == 0);
-        Lane1 L;
-        const int kp = pb * 64 + lane;
-        const bool valid = kp < npairs;
-        L.z = valid ? rz[kp] : 0.0;
-        seed_lambda_m(valid ? rs[kp] : 1.0, m, seedc[m], L.l1, L.sc);
-        L.l2 = 0.0;
-        // B operands: ring pair 4 g + kq of this block, column jc
-        float ge[16], go[16];
-        {
-            const double *Gr = reinterpret_cast<const double *>(G + (long long)rB * fstride);
+    const int pb = chunk * W + wv;
+    const bool active = pb < npb;                // wave-uniform
+    Lane1 L;
+    const int kp = pb * 64 + lane;
+    const bool valid = active && kp < npairs;
+    L.z = valid ? rz[kp] : 0.0;
+    seed_lambda_m(valid ? rs[kp] : 1.0, m, seedc[m], L.l1, L.sc);
+    L.l2 = 0.0;
+    // B operands: ring pair 4 g + kq of this block, column jc
+    T ge[16], go[16];
+    {
+        const double *Gr = reinterpret_cast<const double *>(G + (long long)rB * fstride);
 #pragma unroll
-            for (int g = 0; g < 16; g++) {
-                const int p = pb * 64 + 4 * g + kq;
-                double gn = 0.0, gs = 0.0;
-                if (p < npairs) {
-                    const int north = p, south = nrings - 1 - p;
-                    gn = Gr[((long long)north * ld + m) * 2 + csB];
-                    if (south != north) gs = Gr[((long long)south * ld + m) * 2 + csB];
-                }
-                ge[g] = (float)(gn + gs);
-                go[g] = (float)(gn - gs);
+        for (int g = 0; g < 16; g++) {
+            const int p = pb * 64 + 4 * g + kq;
+            double gn = 0.0, gs = 0.0;
+            if (active && p < npairs) {
+                const int north = p, south = nrings - 1 - p;
+                gn = Gr[((long long)north * ld + m) * 2 + csB];
+                if (south != north) gs = Gr[((long long)south * ld + m) * 2 + csB];
             }
+            ge[g] = M::cvt(gn + gs);
+            go[g] = M::cvt(gn - gs);
         }
-        int mode = wave_mode1(L);
-        // tiles of 32 l; a tile never spans two coefficient chunks (both 32)
-        const int ntile = (nl + 31) / 32;
-        for (int t = 0; t < ntile; t++) {
-            __syncthreads();
-            if (lane < kChunkM) {
-                const int l = m + t * 32 + lane;
-                sab[lane] = (l + 1 <= lmax) ? abm[l + 1] : make_double2(0.0, 0.0);
-            }
-            __syncthreads();
-            const int lb0 = m + t * 32;
-            if (mode == 0) {
+    }
+    // mode 0 also stands for a block past the last ring pair (no contribution)
+    int mode = active ? wave_mode1(L) : 0;
+    const int ntile = (nl + 31) / 32;
+    for (int t = 0; t < ntile; t++) {
+        __syncthreads();
+        if (threadIdx.x < kChunkM) {
+            const int l = m + t * 32 + threadIdx.x;
+            sab[threadIdx.x] = (l + 1 <= lmax) ? abm[l + 1] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        typename M::acc DE = M::zero(), DO = DE;
+        if (mode == 0) {
+            if (active) {
 #pragma unroll 4
                 for (int s = 0; s < 32; s++) L.step_rescale(sab[s]);
                 mode = wave_mode1(L);
-                if (first) {
-                    // no contribution from this block: store zeros for the tile
-#pragma unroll
-                    for (int v = 0; v < 4; v++) {
-                        const int i = 4 * kq + v;
-                        if (lb0 + 2 * i <= lmax) Pm[(long long)(2 * i + t * 32) * 16 + jc] = 0.0;
-                        if (lb0 + 2 * i + 1 <= lmax) Pm[(long long)(2 * i + 1 + t * 32) * 16 + jc] = 0.0;
-                    }
-                }
-                continue;
             }
+        } else {
+            if (mode == 1) {
 #pragma unroll 4
-            for (int s = 0; s < 32; s++) {
-                lam[s][lane] = L.w();
-                L.step_rescale(sab[s]);
+                for (int s = 0; s < 32; s++) {
+                    lam[s * 65 + lane] = M::cvt(L.w());
+                    L.step_rescale(sab[s]);
+                }
+                mode = wave_mode1(L);
+            } else {
+                // steady state: every lane in range, plain recurrence
+#pragma unroll 8
+                for (int s = 0; s < 32; s++) {
+                    lam[s * 65 + lane] = M::cvt(L.l1);
+                    const double2 c = sab[s];
+                    const double nv = fma(c.x, L.z * L.l1, -c.y * L.l2);
+                    L.l2 = L.l1;
+                    L.l1 = nv;
+                }
             }
-            mode = wave_mode1(L);
-            __syncthreads();
-            f4 DE = (f4){0.f, 0.f, 0.f, 0.f}, DO = DE;
+            __builtin_amdgcn_s_waitcnt(0xc07f);     // this wave's LDS writes landed
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int g = 0; g < 16; g++) {
-                const float ae = lam[2 * jc][4 * g + kq];
-                const float ao = lam[2 * jc + 1][4 * g + kq];
-                DE = __builtin_amdgcn_mfma_f32_16x16x4f32(ae, ge[g], DE, 0, 0, 0);
-                DO = __builtin_amdgcn_mfma_f32_16x16x4f32(ao, go[g], DO, 0, 0, 0);
+                const T ae = lam[(2 * jc) * 65 + 4 * g + kq];
+                const T ao = lam[(2 * jc + 1) * 65 + 4 * g + kq];
+                DE = M::mma(ae, ge[g], DE);
+                DO = M::mma(ao, go[g], DO);
             }
-            // D row i = l index within the parity, column jc = (rhs, cos/sin)
+        }
+        // the wave's tile (32 l x 16 columns) into its own LDS area
+        __syncthreads();
 #pragma unroll
-            for (int v = 0; v < 4; v++) {
-                const int i = 4 * kq + v;
-                const int le = 2 * i, lo = 2 * i + 1;
-                if (lb0 + le <= lmax) {
-                    double *p = Pm + (long long)(le + t * 32) * 16 + jc;
-                    if (first) *p = (double)DE[v];
-                    else *p += (double)DE[v];
-                }
-                if (lb0 + lo <= lmax) {
-                    double *p = Pm + (long long)(lo + t * 32) * 16 + jc;
-                    if (first) *p = (double)DO[v];
-                    else *p += (double)DO[v];
-                }
-            }
+        for (int v = 0; v < 4; v++) {
+            const int i = M::row(kq, v);
+            lam[(2 * i) * 16 + jc] = DE[v];
+            lam[(2 * i + 1) * 16 + jc] = DO[v];
+        }
+        __syncthreads();
+        // sum the W tiles; one store per output
+        const int lb0 = t * 32;
+        for (int o = threadIdx.x; o < 512; o += 64 * W) {
+            const int lr = o >> 4;
+            if (m + lb0 + lr > lmax) continue;
+            double a = 0.0;
+#pragma unroll
+            for (int w = 0; w < W; w++) a += (double)lam_all[w * LS + o];
+            Pm[(long long)(lb0 + lr) * 16 + (o & 15)] = a;
         }
     }
 }
 
-// float T layout: U32[rc][tri_off(m) + l - m][8][cs] = dl[l] x[...]
-__global__ __launch_bounds__(256) void k_pack_t32(const double *__restrict__ x,
-                                                  const double *__restrict__ dl,
-                                                  float *__restrict__ U, int lmax, int nrhs) {
+// T layout: U[rc][tri_off(m) + l - m][8][cs] = dl[l] x[...]
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack_tm(const double *__restrict__ x,
+                                                 const double *__restrict__ dl,
+                                                 T *__restrict__ U, int lmax, int nrhs) {
     const int m = blockIdx.x, rr = blockIdx.y;
     const long long nalm = (long long)(lmax + 1) * (lmax + 1);
     const long long tri = (long long)(lmax + 1) * (lmax + 2) / 2;
     const int nl = lmax - m + 1;
     const int rc = rr / 8, r = rr % 8;
     const long long ob = cos_base(m, lmax);
-    float *Ub = U + ((long long)rc * tri + tri_off_m(m, lmax)) * 16 + 2 * r;
+    T *Ub = U + ((long long)rc * tri + tri_off_m(m, lmax)) * 16 + 2 * r;
     for (int i = threadIdx.x; i < 2 * nl; i += blockDim.x) {
         const int dlm = i >> 1, cs = i & 1;
         double v = 0.0;
@@ -334,64 +395,101 @@ __global__ __launch_bounds__(256) void k_pack_t32(const double *__restrict__ x,
             v = x[(long long)rr * nalm + ob + (cs ? nl : 0) + dlm];
             if (dl) v *= dl[m + dlm];
         }
-        Ub[(long long)dlm * 16 + cs] = (float)v;
+        Ub[(long long)dlm * 16 + cs] = (T)v;
     }
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-long long tlayout32_floats(int lmax, int nrhs) {
+long long tlayout_m_elems(int lmax, int nrhs) {
     const long long tri = (long long)(lmax + 1) * (lmax + 2) / 2;
     return (long long)((nrhs + 7) / 8) * 16 * tri;
 }
 
-int launch_pack_t32(int lmax, int nrhs, const double *x, const double *dl, float *U,
-                    hipStream_t s) {
+int launch_pack_tm(int lmax, int nrhs, const double *x, const double *dl, void *U, bool dbl,
+                   hipStream_t s) {
     const int nrc = (nrhs + 7) / 8;
-    hipLaunchKernelGGL(k_pack_t32, dim3(lmax + 1, nrc * 8), dim3(256), 0, s, x, dl, U, lmax, nrhs);
+    if (dbl)
+        hipLaunchKernelGGL(k_pack_tm<double>, dim3(lmax + 1, nrc * 8), dim3(256), 0, s, x, dl,
+                           (double *)U, lmax, nrhs);
+    else
+        hipLaunchKernelGGL(k_pack_tm<float>, dim3(lmax + 1, nrc * 8), dim3(256), 0, s, x, dl,
+                           (float *)U, lmax, nrhs);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }
 
-int launch_legendre_synth_mfma(const LegendreArgs &a, const float *U32, double2 *F) {
+int launch_legendre_synth_mfma(const LegendreArgs &a, const void *U, double2 *F, bool dbl) {
     const mlcr_geom *g = a.g;
     const int npb = (g->npairs + 63) / 64;
     const int nrc = (a.nrhs + 7) / 8;
     const long long total = (long long)(a.lmax + 1) * npb * nrc;
     const long long grid = ((total + 7) / 8) * 8;
     const long long fstride = (long long)g->nrings * (a.lmax + 1);
-    hipLaunchKernelGGL(k_lsynth_mfma32, dim3((unsigned)grid), dim3(64), 0, a.stream, U32, a.nrhs,
-                       F, fstride, a.lmax, g->ring_z.as<double>(), g->ring_s.as<double>(),
-                       g->ab.as<double2>(), g->aboff.as<long long>(), g->seed.as<double>(),
-                       g->nrings, g->npairs, npb, total);
+#define MLCR_SYNTH_ARGS                                                                        \
+    a.nrhs, F, fstride, a.lmax, g->ring_z.as<double>(), g->ring_s.as<double>(),                 \
+        g->ab.as<double2>(), g->aboff.as<long long>(), g->seed.as<double>(), g->nrings,         \
+        g->npairs, npb, total
+    if (dbl)
+        hipLaunchKernelGGL(k_lsynth_mfma<double>, dim3((unsigned)grid), dim3(64), 0, a.stream,
+                           (const double *)U, MLCR_SYNTH_ARGS);
+    else
+        hipLaunchKernelGGL(k_lsynth_mfma<float>, dim3((unsigned)grid), dim3(64), 0, a.stream,
+                           (const float *)U, MLCR_SYNTH_ARGS);
+#undef MLCR_SYNTH_ARGS
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }
 
+// Waves per adjoint workgroup: one ring-pair block each, up to 8.
+static int adj_waves(int npb) { return npb >= 8 ? 8 : (npb >= 4 ? 4 : (npb >= 2 ? 2 : 1)); }
+
+// Split-K over ring-pair blocks: a workgroup sums W blocks for one order m,
+// the chunks are added in the unpack step.
 int adjoint_chunks_mfma(const mlcr_geom *g, int lmax) {
+    (void)lmax;
     const int npb = (g->npairs + 63) / 64;
-    int want = (8192 + lmax) / (lmax + 1);
-    want = std::max(1, std::min(want, 8));
-    return std::min(want, npb);
+    const int W = adj_waves(npb);
+    return (npb + W - 1) / W;
 }
 
-// P: double T layout with 8 RHS per chunk
-int launch_legendre_adjoint_mfma(const LegendreArgs &a, const double2 *G, double *P,
-                                 int *nchunks_out) {
+template <typename T, int W>
+static int launch_ladj_wg(const LegendreArgs &a, const double2 *G, double *P, int nchunks) {
     const mlcr_geom *g = a.g;
     const int npb = (g->npairs + 63) / 64;
-    const int nchunks = adjoint_chunks_mfma(g, a.lmax);
-    const int per = (npb + nchunks - 1) / nchunks;
     const int nrc = (a.nrhs + 7) / 8;
     const long long total = (long long)(a.lmax + 1) * nchunks * nrc;
     const long long grid = ((total + 7) / 8) * 8;
     const long long fstride = (long long)g->nrings * (a.lmax + 1);
-    hipLaunchKernelGGL(k_ladj_mfma32, dim3((unsigned)grid), dim3(64), 0, a.stream, G, fstride,
-                       a.nrhs, P, per, a.lmax, g->ring_z.as<double>(), g->ring_s.as<double>(),
+    const size_t lds = kChunkM * sizeof(double2) + (size_t)W * 32 * 65 * sizeof(T);
+    int rc = ensure_dynamic_lds((const void *)k_ladj_mfma<T, W>, lds);
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_ladj_mfma<T, W>), dim3((unsigned)grid), dim3(64 * W), lds, a.stream, G,
+                       fstride, a.nrhs, P, a.lmax, g->ring_z.as<double>(), g->ring_s.as<double>(),
                        g->ab.as<double2>(), g->aboff.as<long long>(), g->seed.as<double>(),
                        g->nrings, g->npairs, npb, nchunks, total);
     MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+template <typename T>
+static int launch_ladj_t(const LegendreArgs &a, const double2 *G, double *P, int nchunks) {
+    switch (adj_waves((a.g->npairs + 63) / 64)) {
+    case 8: return launch_ladj_wg<T, 8>(a, G, P, nchunks);
+    case 4: return launch_ladj_wg<T, 4>(a, G, P, nchunks);
+    case 2: return launch_ladj_wg<T, 2>(a, G, P, nchunks);
+    default: return launch_ladj_wg<T, 1>(a, G, P, nchunks);
+    }
+}
+
+// P: double T layout with 8 RHS per chunk
+int launch_legendre_adjoint_mfma(const LegendreArgs &a, const double2 *G, double *P,
+                                 int *nchunks_out, bool dbl) {
+    const int nchunks = adjoint_chunks_mfma(a.g, a.lmax);
+    const int rc = dbl ? launch_ladj_t<double>(a, G, P, nchunks)
+                       : launch_ladj_t<float>(a, G, P, nchunks);
+    if (rc) return rc;
     *nchunks_out = nchunks;
     return MLCR_OK;
 }

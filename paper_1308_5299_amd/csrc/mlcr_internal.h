@@ -125,13 +125,14 @@ int launch_ring_adjoint(const mlcr_geom *g, int lmax, int nrhs, const double *ma
 int launch_ring_apply(const mlcr_geom *g, int lmax, int nrhs, double2 *FG, const double *ninv,
                       hipStream_t s);
 int adjoint_chunks(const mlcr_geom *g, int lmax);
-// matrix-core (float32) Legendre kernels, 8 RHS per wave
-long long tlayout32_floats(int lmax, int nrhs);
-int launch_pack_t32(int lmax, int nrhs, const double *x, const double *dl, float *U,
-                    hipStream_t s);
-int launch_legendre_synth_mfma(const LegendreArgs &a, const float *U32, double2 *F);
+// matrix-core Legendre kernels, 8 RHS per wave; dbl selects float64 MFMA
+// (else float32).  U: T layout with 8 RHS per chunk, elements of that type.
+long long tlayout_m_elems(int lmax, int nrhs);
+int launch_pack_tm(int lmax, int nrhs, const double *x, const double *dl, void *U, bool dbl,
+                   hipStream_t s);
+int launch_legendre_synth_mfma(const LegendreArgs &a, const void *U, double2 *F, bool dbl);
 int launch_legendre_adjoint_mfma(const LegendreArgs &a, const double2 *G, double *P,
-                                 int *nchunks_out);
+                                 int *nchunks_out, bool dbl);
 int adjoint_chunks_mfma(const mlcr_geom *g, int lmax);
 // T layout ([RHS chunk][m][l - m][RC][cos, sin]) of the Legendre kernels
 int synth_rc(int nrhs);
