@@ -223,3 +223,27 @@ def synth_rings(x: np.ndarray, lmax: int, nside: int, rings) -> dict:
         sinm = np.sin(np.outer(ms, phi))
         out[k] = (w * Fc) @ cosm + (w * Fs) @ sinm
     return out
+
+
+def adjoint_orders(y: np.ndarray, lmax: int, nside: int, orders) -> dict:
+    """Adjoint synthesis restricted to selected orders: {m: (cos block, sin block)}.
+
+    Each ring's weighted trigonometric sums at frequency m are evaluated
+    directly from the definition (no FFT, no folding), then contracted with
+    the lambda_lm table of that order over all rings, for grids too large for
+    the full transform."""
+    geom = healpix_rings(nside)
+    y = np.asarray(y, dtype=np.float64)
+    out = {}
+    for m in orders:
+        w = 1.0 if m == 0 else SQRT2
+        gc = np.zeros(y.shape[:-1] + (geom.nrings,))
+        gs = np.zeros_like(gc)
+        for k in range(geom.nrings):
+            phi = geom.ring_phi(k)
+            seg = y[..., geom.start[k]: geom.start[k] + int(geom.nphi[k])]
+            gc[..., k] = w * (seg @ np.cos(m * phi))
+            gs[..., k] = w * (seg @ np.sin(m * phi))
+        lam = lambda_table(m, lmax, geom.z, geom.sint)        # (lmax - m + 1, nrings)
+        out[m] = (gc @ lam.T, gs @ lam.T)
+    return out

@@ -67,13 +67,17 @@ def test_top_diagonal_parity(mlcr):
     assert rel2(got, ref) <= 1e-12, rel2(got, ref)
 
 
-def test_c2_wcycle_manufactured(mlcr):
-    print("case c2 w-cycle manufactured", flush=True)
+@pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
+def test_c2_wcycle_manufactured(mlcr, prec_name):
+    """fp32: the cycle's transforms in float32 (matrix cores), residual and
+    update in float64 -- iterative refinement to the same bar."""
+    print(f"case c2 w-cycle manufactured {prec_name}", flush=True)
+    prec = mlcr.FP64 if prec_name == "fp64" else mlcr.FP32
     cfg, d, g, ninv, op = _problem(mlcr, "c2")
     S = mlcr.Solver(op, max_nrhs=1)
     xt = workloads.prior_sample(cfg, 0)
     b = oop.apply_A(xt, d["cl"], d["bl"], d["ninv"], cfg.nside)
-    x, info = S.solve(dev(b[None]), rtol=1e-8, max_cycles=40)
+    x, info = S.solve(dev(b[None]), rtol=1e-8, max_cycles=40, prec=prec)
     xg = host(x)[0]
     print("c2 info", info[0], flush=True)
     assert info[0]["converged"] == 1 and info[0]["rho"] <= 1e-8

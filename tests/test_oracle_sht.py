@@ -106,3 +106,20 @@ def test_sampled_rings_match_full():
     got = sht.synth_rings(x, lmax, nside, [0, 7, 31, 62])
     for k, v in got.items():
         np.testing.assert_allclose(v, full[g.start[k]: g.start[k] + g.nphi[k]], rtol=0, atol=1e-12)
+
+
+def test_sampled_orders_match_full():
+    """The per-order direct-sum adjoint equals the full FFT-based adjoint,
+    including orders above the rings' Nyquist frequency (m >= N_k / 2)."""
+    nside, lmax = 8, 40
+    y = np.random.default_rng(12).standard_normal((2, 12 * nside * nside))
+    full = sht.adjoint(y, lmax, nside)
+    got = sht.adjoint_orders(y, lmax, nside, [0, 1, 17, 33, 40])
+    for m, (c, s) in got.items():
+        if m == 0:
+            np.testing.assert_allclose(c, full[:, : lmax + 1], rtol=0, atol=1e-12)
+            continue
+        b = sht.block_base(m, lmax)
+        n = lmax - m + 1
+        np.testing.assert_allclose(c, full[:, b: b + n], rtol=0, atol=1e-12)
+        np.testing.assert_allclose(s, full[:, b + n: b + 2 * n], rtol=0, atol=1e-12)
