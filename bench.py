@@ -27,6 +27,20 @@ PEAK_FP32 = 157.3e12          # MI355X FP32 (vector and dense MFMA) FLOP/s
 PEAK_HBM = 8.0e12             # MI355X HBM3E bytes/s
 
 
+# HBM bytes per launch measured with rocprofv3 FETCH_SIZE (x2.0) + WRITE_SIZE
+# (x1.0), the factors from a plain copy of known size; recorded in
+# profiles/apply_A_c5_r8_hbm_traffic.md for the kernels as they are now.
+# Key: (library timer name, Legendre path, workload, RHS per launch).
+MEASURED_TRAFFIC = {
+    ("legendre_adjoint", "fp32", "c5", 8): 34.732e9 + 8.596e9,
+    ("legendre_adjoint", "fp64", "c5", 8): 34.731e9 + 8.596e9,
+    ("legendre_synth", "fp32", "c5", 8): 1.664e9 + 8.637e9,
+    ("legendre_synth", "fp64", "c5", 8): 1.992e9 + 8.611e9,
+    ("ring_apply", "fp32", "c5", 8): 4 * (1.424e9 + 1.074e9),
+    ("ring_apply", "fp64", "c5", 8): 4 * (1.415e9 + 1.074e9),
+}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -52,6 +66,22 @@ def algorithmic_work(name: str, nside: int, lmax: int, R: int):
         return "hbm", 16.0 * nrings * (lmax + 1) * R + 8.0 * npix * R, "byte"
     nalm = (lmax + 1) ** 2
     return "hbm", 3.0 * 8 * nalm * R, "byte"
+
+
+def algorithmic_bytes(name: str, nside: int, lmax: int, R: int):
+    """Bytes a launch must move at least: its inputs read once, outputs written once."""
+    nrings, npix = 4 * nside - 1, 12 * nside * nside
+    fbuf = 16.0 * nrings * (lmax + 1) * R                 # F or G, complex double
+    tri = (lmax + 1) * (lmax + 2) // 2
+    if name == "legendre_synth":
+        return fbuf
+    if name == "legendre_adjoint":
+        npb = (2 * nside + 63) // 64
+        nchunks = (npb + 7) // 8
+        return fbuf + nchunks * 16.0 * tri * 8 * ((R + 7) // 8)
+    if name == "ring_apply":
+        return 2 * fbuf + 8.0 * npix
+    return None
 
 
 def cpu_baseline(cfg, R: int, seed_x, ninv_host, budget_s: float = 20.0):
@@ -140,7 +170,8 @@ def run_path(mlcr, torch, op, x, y, prec, steps, warmup, label):
     return ms_step, kernels
 
 
-def roofline(kernels, cfg, R, mixed: bool):
+def roofline(kernels, cfg, R, path: str):
+    mixed = path != "fp64"
     dom = max(kernels, key=lambda k: kernels[k])
     bound, work, unit = algorithmic_work(dom, cfg.nside, cfg.lmax, R)
     sec = kernels[dom] / 1e3
@@ -155,7 +186,11 @@ def roofline(kernels, cfg, R, mixed: bool):
         roof = {"bound": "hbm", "kernel": dom, "achieved": work / sec / 1e9,
                 "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    t = MEASURED_TRAFFIC.get((dom, path, cfg.name, R))
+    roof["traffic"] = t
+    if t is not None:
+        roof["traffic_unit"] = "bytes per launch (HBM, rocprofv3 counters)"
+        roof["algorithmic_bytes"] = algorithmic_bytes(dom, cfg.nside, cfg.lmax, R)
     roof["kernel_ms"] = {k: round(v, 4) for k, v in kernels.items()}
     return roof
 
@@ -170,6 +205,9 @@ def main():
     ap.add_argument("--paths", default="fp32,fp64",
                     help="Legendre paths to time; the first is the reported value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
+                    help="only run a plain device-to-device copy of this many GiB (a "
+                         "known-size reference for HBM traffic counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design "
@@ -179,6 +217,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy > 0:
+        n = int(args.calibrate_copy * 2 ** 30) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 8 * n, "read": 8 * n, "written": 8 * n}), flush=True)
+        return
 
     import paper_1308_5299_amd as mlcr
     import workloads
@@ -219,7 +267,7 @@ def main():
     head = paths[0]
     ms_step, kernels = res[head]
     value = R / (ms_step / 1e3)
-    roof = roofline(kernels, cfg, R, mixed=(head != "fp64"))
+    roof = roofline(kernels, cfg, R, head)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -228,7 +276,7 @@ def main():
         log(f"[bench] cpu baseline {cpu['value']:.3e} {cpu['unit']}")
 
     others = {p: {"value": R / (res[p][0] / 1e3), "ms_per_step": res[p][0],
-                  "roofline": roofline(res[p][1], cfg, R, mixed=(p != "fp64"))}
+                  "roofline": roofline(res[p][1], cfg, R, p)}
               for p in paths[1:]}
     out = {
         "metric": METRIC,

@@ -181,7 +181,8 @@ int build_geometry(mlcr_geom *g, int nside, int lmax) {
         for (auto &t : th) t.join();
     }
 
-    // ---- ring order for the FFT kernels: most expensive first ----
+    // ---- ring order for the FFT kernels: grouped by LDS need (FFT size M),
+    // each group launched with its own LDS size; most expensive first ----
     std::vector<int> order(nr);
     {
         std::vector<double> cost(nr);
@@ -191,8 +192,25 @@ int build_geometry(mlcr_geom *g, int nside, int lmax) {
             cost[k] = (L.boff >= 0 ? 3.0 : 1.0) * M * std::log2(std::max(2.0, M));
             order[k] = k;
         }
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int a, int b) { return cost[a] > cost[b]; });
+        auto bucket = [&](int k) {
+            const int M = li[ri[k].tab].M;
+            return M <= 1024 ? 0 : (M <= 2048 ? 1 : (M <= 4096 ? 2 : 3));
+        };
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            if (bucket(a) != bucket(b)) return bucket(a) > bucket(b);
+            return cost[a] > cost[b];
+        });
+        g->ring_groups.clear();
+        for (int j = 0; j < nr;) {
+            const int b = bucket(order[j]);
+            RingGroup grp{j, 0, 0};
+            while (j < nr && bucket(order[j]) == b) {
+                grp.mmax = std::max(grp.mmax, li[ri[order[j]].tab].M);
+                grp.count++;
+                j++;
+            }
+            g->ring_groups.push_back(grp);
+        }
     }
 
     // ---- upload ----

@@ -82,6 +82,16 @@ __device__ __forceinline__ void seed_lambda_m(double s, int m, double c, double 
     }
 }
 
+// Work item w = ((rc * (lmax+1)) + mi) * npb + pb: the ring-pair blocks of one
+// order are adjacent, so they run together and share that order's
+// coefficients (and U rows) through L2, while their F/G accesses spread over
+// all rings (all memory channels).  Each XCD (workgroup id mod 8) gets one
+// contiguous run of items; orders are visited 0, lmax, 1, lmax-1, ... so
+// every run holds the same mix of long and short orders.
+__host__ __device__ inline long long mitems(int lmax, int npb, int nrc) {
+    return (long long)(lmax + 1) * npb * nrc;
+}
+
 __device__ __forceinline__ void decode_item_m(long long total, int lmax, int npb, int &m, int &pb,
                                               int &rc, bool &ok) {
     const long long b = blockIdx.x;
@@ -90,10 +100,10 @@ __device__ __forceinline__ void decode_item_m(long long total, int lmax, int npb
     ok = w < total;
     if (!ok) return;
     const int nm = lmax + 1;
-    const int mi = (int)(w % nm);
-    const long long rest = w / nm;
-    pb = (int)(rest % npb);
-    rc = (int)(rest / npb);
+    pb = (int)(w % npb);
+    const long long rest = w / npb;
+    const int mi = (int)(rest % nm);
+    rc = (int)(rest / nm);
     m = (mi & 1) ? (lmax - (mi >> 1)) : (mi >> 1);
 }
 
@@ -376,26 +386,37 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
     }
 }
 
-// T layout: U[rc][tri_off(m) + l - m][8][cs] = dl[l] x[...]
+// T layout: U[rc][tri_off(m) + l - m][8][cs] = dl[l] x[...].  One workgroup
+// per (m, RHS chunk); tiles of 64 l are read along l for each (r, cs) and
+// written as whole 16-value rows after a transpose in LDS.
 template <typename T>
 __global__ __launch_bounds__(256) void k_pack_tm(const double *__restrict__ x,
                                                  const double *__restrict__ dl,
                                                  T *__restrict__ U, int lmax, int nrhs) {
-    const int m = blockIdx.x, rr = blockIdx.y;
+    constexpr int TL = 64;
+    __shared__ T tile[TL * 17];
+    const int m = blockIdx.x, rc = blockIdx.y;
     const long long nalm = (long long)(lmax + 1) * (lmax + 1);
     const long long tri = (long long)(lmax + 1) * (lmax + 2) / 2;
     const int nl = lmax - m + 1;
-    const int rc = rr / 8, r = rr % 8;
     const long long ob = cos_base(m, lmax);
-    T *Ub = U + ((long long)rc * tri + tri_off_m(m, lmax)) * 16 + 2 * r;
-    for (int i = threadIdx.x; i < 2 * nl; i += blockDim.x) {
-        const int dlm = i >> 1, cs = i & 1;
-        double v = 0.0;
-        if (rr < nrhs && !(m == 0 && cs == 1)) {
-            v = x[(long long)rr * nalm + ob + (cs ? nl : 0) + dlm];
-            if (dl) v *= dl[m + dlm];
+    T *Ub = U + ((long long)rc * tri + tri_off_m(m, lmax)) * 16;
+    for (int base = 0; base < nl; base += TL) {
+        const int nt = min(TL, nl - base);
+        for (int e = threadIdx.x; e < 16 * TL; e += blockDim.x) {
+            const int comp = e / TL, j = e % TL;
+            const int r = rc * 8 + (comp >> 1), cs = comp & 1;
+            double v = 0.0;
+            if (j < nt && r < nrhs && !(m == 0 && cs == 1)) {
+                v = x[(long long)r * nalm + ob + (long long)cs * nl + base + j];
+                if (dl) v *= dl[m + base + j];
+            }
+            tile[j * 17 + comp] = (T)v;
         }
-        Ub[(long long)dlm * 16 + cs] = (T)v;
+        __syncthreads();
+        for (int e = threadIdx.x; e < 16 * nt; e += blockDim.x)
+            Ub[(long long)base * 16 + e] = tile[(e >> 4) * 17 + (e & 15)];
+        __syncthreads();
     }
 }
 
@@ -411,10 +432,10 @@ int launch_pack_tm(int lmax, int nrhs, const double *x, const double *dl, void *
                    hipStream_t s) {
     const int nrc = (nrhs + 7) / 8;
     if (dbl)
-        hipLaunchKernelGGL(k_pack_tm<double>, dim3(lmax + 1, nrc * 8), dim3(256), 0, s, x, dl,
+        hipLaunchKernelGGL(k_pack_tm<double>, dim3(lmax + 1, nrc), dim3(256), 0, s, x, dl,
                            (double *)U, lmax, nrhs);
     else
-        hipLaunchKernelGGL(k_pack_tm<float>, dim3(lmax + 1, nrc * 8), dim3(256), 0, s, x, dl,
+        hipLaunchKernelGGL(k_pack_tm<float>, dim3(lmax + 1, nrc), dim3(256), 0, s, x, dl,
                            (float *)U, lmax, nrhs);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
@@ -424,7 +445,7 @@ int launch_legendre_synth_mfma(const LegendreArgs &a, const void *U, double2 *F,
     const mlcr_geom *g = a.g;
     const int npb = (g->npairs + 63) / 64;
     const int nrc = (a.nrhs + 7) / 8;
-    const long long total = (long long)(a.lmax + 1) * npb * nrc;
+    const long long total = mitems(a.lmax, npb, nrc);
     const long long grid = ((total + 7) / 8) * 8;
     const long long fstride = (long long)g->nrings * (a.lmax + 1);
 #define MLCR_SYNTH_ARGS                                                                        \
@@ -459,7 +480,7 @@ static int launch_ladj_wg(const LegendreArgs &a, const double2 *G, double *P, in
     const mlcr_geom *g = a.g;
     const int npb = (g->npairs + 63) / 64;
     const int nrc = (a.nrhs + 7) / 8;
-    const long long total = (long long)(a.lmax + 1) * nchunks * nrc;
+    const long long total = mitems(a.lmax, nchunks, nrc);
     const long long grid = ((total + 7) / 8) * 8;
     const long long fstride = (long long)g->nrings * (a.lmax + 1);
     const size_t lds = kChunkM * sizeof(double2) + (size_t)W * 32 * 65 * sizeof(T);

@@ -59,6 +59,11 @@ struct LenInfo {
     int pad;
 };
 
+// rings order[off .. off+count) share one ring-kernel launch; mmax = largest FFT size
+struct RingGroup {
+    int off, count, mmax;
+};
+
 }  // namespace mlcr
 
 struct mlcr_geom {
@@ -71,7 +76,8 @@ struct mlcr_geom {
     mlcr::DevBuf ring_z, ring_s;        // per ring: cos, sin theta (double)
     mlcr::DevBuf rings;                 // RingInfo[nrings]
     mlcr::DevBuf lens;                  // LenInfo[nside]
-    mlcr::DevBuf order;                 // int[nrings]: rings by decreasing FFT cost
+    mlcr::DevBuf order;                 // int[nrings]: rings by FFT size group, then cost
+    std::vector<mlcr::RingGroup> ring_groups;   // host: launch groups over order
     mlcr::DevBuf T;                     // double2, all twiddle tables
     mlcr::DevBuf Bf;                    // double2, all Bluestein filters
     mlcr::DevBuf W;                     // double2, e^{-2 pi i j / Wmax}, j < Wmax

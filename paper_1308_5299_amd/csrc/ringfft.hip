@@ -18,7 +18,11 @@
 //
 // In the fused operator kernel the map never leaves LDS: F is read, the map
 // is multiplied by N^-1 (0 in the mask, Sec. 2.3), and G is written over F.
-// One workgroup of 512 threads per (ring, right-hand side).
+// One workgroup of 512 threads per (ring, right-hand side).  Rings are
+// launched in groups of similar FFT size, each with the LDS its largest ring
+// needs; within a launch the rings are dealt round-robin to the eight XCDs
+// (workgroup id mod 8) and the right-hand sides of one ring run back to back
+// on the same XCD, so its tables are fetched into that L2 once.
 #include "mlcr_internal.h"
 
 namespace mlcr {
@@ -98,10 +102,14 @@ __global__ __launch_bounds__(kRingThreads) void k_ring(
     double *__restrict__ map_out, const double *__restrict__ ninv,
     const RingInfo *__restrict__ rings, const LenInfo *__restrict__ lens,
     const int *__restrict__ order, const double2 *__restrict__ T, const double2 *__restrict__ Bf,
-    const double2 *__restrict__ W, int Wmax, int lmax, long long fstride, long long npix) {
+    const double2 *__restrict__ W, int Wmax, int lmax, long long fstride, long long npix,
+    int goff, int gcount, int nrhs) {
     extern __shared__ double2 buf[];
-    const int k = order[blockIdx.x];
-    const int r = blockIdx.y;
+    const int xcd = blockIdx.x & 7, seq = blockIdx.x >> 3;
+    const int jr = (seq / nrhs) * 8 + xcd;
+    if (jr >= gcount) return;
+    const int k = order[goff + jr];
+    const int r = seq % nrhs;
     const int tid = threadIdx.x;
     const RingInfo ri = rings[k];
     const LenInfo L = lens[ri.tab];
@@ -209,15 +217,19 @@ template <int MODE>
 static int launch_ring(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, double2 *G,
                        const double *map_in, double *map_out, const double *ninv,
                        hipStream_t s) {
-    const size_t lds = (size_t)g->lds_cplx * sizeof(double2);
-    int rc = ensure_dynamic_lds((const void *)k_ring<MODE>, lds);
-    if (rc) return rc;
     const long long fstride = (long long)g->nrings * (lmax + 1);
-    hipLaunchKernelGGL(k_ring<MODE>, dim3(g->nrings, nrhs), dim3(kRingThreads), lds, s, F, G,
-                       map_in, map_out, ninv, g->rings.as<RingInfo>(), g->lens.as<LenInfo>(),
-                       g->order.as<int>(), g->T.as<double2>(), g->Bf.as<double2>(),
-                       g->W.as<double2>(), g->Wmax, lmax, fstride, g->npix);
-    MLCR_HIP_CHECK(hipGetLastError());
+    for (const RingGroup &grp : g->ring_groups) {
+        const size_t lds = (size_t)grp.mmax * sizeof(double2);
+        int rc = ensure_dynamic_lds((const void *)k_ring<MODE>, lds);
+        if (rc) return rc;
+        const long long nblk = 8LL * ((grp.count + 7) / 8) * nrhs;
+        hipLaunchKernelGGL(k_ring<MODE>, dim3((unsigned)nblk), dim3(kRingThreads), lds, s, F, G,
+                           map_in, map_out, ninv, g->rings.as<RingInfo>(), g->lens.as<LenInfo>(),
+                           g->order.as<int>(), g->T.as<double2>(), g->Bf.as<double2>(),
+                           g->W.as<double2>(), g->Wmax, lmax, fstride, g->npix, grp.off, grp.count,
+                           nrhs);
+        MLCR_HIP_CHECK(hipGetLastError());
+    }
     return MLCR_OK;
 }
 
