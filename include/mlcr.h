@@ -83,9 +83,21 @@ int mlcr_timing_get(int i, char *name, int name_len, double *total_ms, long long
  * grows on demand.  The handle may be used from one host thread at a time.
  * ---------------------------------------------------------------------- */
 int mlcr_geom_create(int nside, int lmax, mlcr_geom **out);
+/* Gauss-Legendre grid (Sec. 3.5): nrings rings at the nodes z_k of the
+ * Legendre polynomial P_nrings, ordered north to south, each with nphi
+ * equispaced pixels from phi = 0 (pixel index k nphi + j).  The quadrature
+ * sum_k W_k sum_j f(theta_k, phi_j) (mlcr_geom_weights) is exact for
+ * polynomials in cos theta of degree < 2 nrings with frequencies |m| < nphi.
+ * nphi: multiple of 4, at most 16384, whose ring FFT fits 8192 points
+ * (nphi/2 a power of two, or nphi <= 4096).  The same transforms apply. */
+int mlcr_geom_create_gl(int lmax, int nrings, int nphi, mlcr_geom **out);
 void mlcr_geom_destroy(mlcr_geom *g);
-/* nside, lmax, pixel count and ring count of a geometry; any out pointer may be NULL. */
+/* nside (0 for a Gauss-Legendre grid), lmax, pixel count and ring count of a
+ * geometry; any out pointer may be NULL. */
 int mlcr_geom_info(const mlcr_geom *g, int *nside, int *lmax, long long *npix, int *nrings);
+/* Quadrature weight of one pixel of each ring, host_w[nrings]: 4 pi / N_pix
+ * for HEALPix (equal area), W_k = w_k 2 pi / nphi for Gauss-Legendre. */
+int mlcr_geom_weights(const mlcr_geom *g, double *host_w);
 
 /* Spherical harmonic synthesis map = Y alm (Sec. 2.1, eq. sh-synthesis),
  * evaluated exactly at the pixel centres (no quadrature, any lmax <= the
@@ -131,6 +143,16 @@ int apply_A(mlcr_op *op, int level, int nrhs, const double *dev_x, double *dev_y
  * B_h = diag(f b_l p_l) (Sec. 3.2, eq. A_h).  1 <= h < 16. */
 int mlcr_op_set_level(mlcr_op *op, int h, int lmax_h, const double *host_fl);
 
+/* Level h like mlcr_op_set_level, with Y^T N^-1 Y evaluated on a
+ * Gauss-Legendre grid (Sec. 3.5, eqs. Ni-rewrite and Xi): xi = Y_obs^T N^-1
+ * truncated at 2 lmax_h is synthesized on 2 lmax_h + 1 Gauss-Legendre rings
+ * of nphi = the smallest power of two >= 4 lmax_h + 1 pixels and weighted
+ * by the quadrature, which reproduces every coupling of Y_obs^T N^-1 Y_obs
+ * between modes l, l' <= lmax_h exactly (up to rounding) at a cost set by
+ * lmax_h rather than by the observation grid.  Needs 2 lmax_h <= the
+ * geometry's lmax.  The operator owns the grid; mlcr_op_set_level on the
+ * same h returns the level to the observation grid. */
+int mlcr_op_set_level_gl(mlcr_op *op, int h, int lmax_h, const double *host_fl);
 /* Band limit of level h (0 = top), or a negative error code. */
 int mlcr_op_level_lmax(const mlcr_op *op, int h);
 

@@ -72,3 +72,45 @@ def pixel_angles(geom: RingGeometry):
     theta = np.repeat(th, geom.nphi)
     phi = np.concatenate([geom.ring_phi(k) for k in range(geom.nrings)])
     return theta, phi
+
+
+def gauss_legendre_rings(nrings: int, nphi: int):
+    """Gauss-Legendre rings (Sec. 3.5): the nodes z_k of P_nrings, north to
+    south, each with nphi equispaced pixels from phi = 0.  Returns the ring
+    geometry and the quadrature weight of one pixel of each ring,
+    W_k = w_k 2 pi / nphi with w_k = 2 / ((1 - z_k^2) P'_n(z_k)^2).
+
+    Nodes by Newton's method on P_n (three-term recurrence) from the
+    Tricomi-type guesses cos(pi (k + 3/4) / (n + 1/2)), in long double; the
+    south half mirrors the north."""
+    n = int(nrings)
+    z = np.empty(n, dtype=np.longdouble)
+    w = np.empty(n, dtype=np.longdouble)
+    half = (n + 1) // 2
+    k = np.arange(half)
+    x = np.cos(np.pi * (k + 0.75) / (n + 0.5)).astype(np.longdouble)
+    for _ in range(100):
+        p0 = np.ones_like(x)
+        p1 = x.copy()
+        for j in range(2, n + 1):
+            p0, p1 = p1, ((2 * j - 1) * x * p1 - (j - 1) * p0) / j
+        dp = n * (x * p1 - p0) / (x * x - 1) if n > 1 else np.ones_like(x)
+        if n == 1:
+            p1 = x
+        dx = p1 / dp
+        x = x - dx
+        if np.max(np.abs(dx)) < 1e-19:
+            break
+    z[:half] = x
+    w[:half] = 2 / ((1 - x * x) * dp * dp)
+    z[n - half:] = -x[::-1]
+    w[n - half:] = w[:half][::-1]
+    if n % 2 == 1:
+        z[n // 2] = 0
+    zf = z.astype(np.float64)
+    st = np.sqrt(((1 - z) * (1 + z)).astype(np.float64))
+    nph = np.full(n, int(nphi), dtype=np.int64)
+    start = (np.arange(n) * int(nphi)).astype(np.int64)
+    geom = RingGeometry(0, zf, st, nph, np.zeros(n), start)
+    W = (w * 2 * np.pi / int(nphi)).astype(np.float64)
+    return geom, W

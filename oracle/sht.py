@@ -161,13 +161,21 @@ def ring_adjoint(y: np.ndarray, lmax: int, geom: RingGeometry):
 # full transforms
 # --------------------------------------------------------------------------
 def synth(x: np.ndarray, lmax: int, nside: int) -> np.ndarray:
-    geom = healpix_rings(nside)
+    return synth_geom(x, lmax, healpix_rings(nside))
+
+
+def adjoint(y: np.ndarray, lmax: int, nside: int) -> np.ndarray:
+    return adjoint_geom(y, lmax, healpix_rings(nside))
+
+
+def synth_geom(x: np.ndarray, lmax: int, geom: RingGeometry) -> np.ndarray:
+    """Synthesis at the pixels of any iso-latitude ring geometry."""
     Fc, Fs = legendre_synth(x, lmax, geom)
     return ring_synth(Fc, Fs, geom)
 
 
-def adjoint(y: np.ndarray, lmax: int, nside: int) -> np.ndarray:
-    geom = healpix_rings(nside)
+def adjoint_geom(y: np.ndarray, lmax: int, geom: RingGeometry) -> np.ndarray:
+    """Adjoint synthesis (plain transpose) for any iso-latitude ring geometry."""
     Gc, Gs = ring_adjoint(y, lmax, geom)
     return legendre_adjoint(Gc, Gs, lmax, geom)
 

@@ -18,6 +18,8 @@ SIGNATURES = {
     "mlcr_last_error": (ctypes.c_char_p, []),
     "mlcr_version": (ctypes.c_char_p, []),
     "mlcr_geom_create": (c_int, [c_int, c_int, ctypes.POINTER(c_void_p)]),
+    "mlcr_geom_create_gl": (c_int, [c_int, c_int, c_int, ctypes.POINTER(c_void_p)]),
+    "mlcr_geom_weights": (c_int, [c_void_p, c_void_p]),
     "mlcr_geom_destroy": (None, [c_void_p]),
     "mlcr_geom_info": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
                                ctypes.POINTER(c_ll), ctypes.POINTER(c_int)]),
@@ -27,6 +29,7 @@ SIGNATURES = {
                                ctypes.POINTER(c_void_p)]),
     "mlcr_op_destroy": (None, [c_void_p]),
     "mlcr_op_set_level": (c_int, [c_void_p, c_int, c_int, c_dbl_p]),
+    "mlcr_op_set_level_gl": (c_int, [c_void_p, c_int, c_int, c_dbl_p]),
     "mlcr_op_level_lmax": (c_int, [c_void_p, c_int]),
     "apply_A": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_int, c_void_p]),
     "mlcr_solver_create": (c_int, [c_void_p, c_int, ctypes.POINTER(c_void_p)]),

@@ -38,16 +38,36 @@ def _batch(t: torch.Tensor, per: int, name: str) -> int:
 
 
 class Geometry:
-    """HEALPix RING grid plus Legendre and FFT tables up to lmax."""
+    """HEALPix RING grid (or, via ``Geometry.gauss_legendre``, a Gauss-Legendre
+    grid) plus Legendre and FFT tables up to lmax."""
 
-    def __init__(self, nside: int, lmax: int):
+    def __init__(self, nside: int, lmax: int, _gl: tuple | None = None):
         lib = load()
         h = ctypes.c_void_p()
-        check(lib.mlcr_geom_create(int(nside), int(lmax), ctypes.byref(h)))
+        if _gl is None:
+            check(lib.mlcr_geom_create(int(nside), int(lmax), ctypes.byref(h)))
+            self.nside = int(nside)
+            self.npix = 12 * self.nside * self.nside
+            self.nrings = 4 * self.nside - 1
+        else:
+            nrings, nphi = _gl
+            check(lib.mlcr_geom_create_gl(int(lmax), int(nrings), int(nphi), ctypes.byref(h)))
+            self.nside = 0
+            self.npix = int(nrings) * int(nphi)
+            self.nrings = int(nrings)
+            self.nphi = int(nphi)
         self._h = h
-        self.nside = int(nside)
         self.lmax = int(lmax)
-        self.npix = 12 * self.nside * self.nside
+
+    @classmethod
+    def gauss_legendre(cls, lmax: int, nrings: int, nphi: int) -> "Geometry":
+        return cls(0, lmax, _gl=(nrings, nphi))
+
+    def weights(self) -> np.ndarray:
+        """Quadrature weight of one pixel of each ring."""
+        w = np.empty(self.nrings, dtype=np.float64)
+        check(load().mlcr_geom_weights(self._h, w.ctypes.data))
+        return w
 
     @property
     def handle(self):
@@ -127,6 +147,13 @@ class Operator:
         fl = np.ascontiguousarray(np.asarray(fl, dtype=np.float64)[: lmax_h + 1])
         check(load().mlcr_op_set_level(self._h, int(h), int(lmax_h),
                                        fl.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        self.level_lmax[int(h)] = int(lmax_h)
+
+    def set_level_gl(self, h: int, lmax_h: int, fl) -> None:
+        """Level h with Y^T N^-1 Y on a Gauss-Legendre grid (downgraded N^-1)."""
+        fl = np.ascontiguousarray(np.asarray(fl, dtype=np.float64)[: lmax_h + 1])
+        check(load().mlcr_op_set_level_gl(self._h, int(h), int(lmax_h),
+                                          fl.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         self.level_lmax[int(h)] = int(lmax_h)
 
     def close(self):

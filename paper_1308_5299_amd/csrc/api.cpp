@@ -58,7 +58,7 @@ int ensure_dynamic_lds(const void *func, size_t bytes) {
 }
 
 static void release_geom(mlcr_geom *g) {
-    DevBuf *bufs[] = {&g->ring_z, &g->ring_s, &g->rings, &g->lens, &g->order, &g->T, &g->Bf,
+    DevBuf *bufs[] = {&g->ring_z, &g->ring_s, &g->ring_w, &g->rings, &g->lens, &g->order, &g->T, &g->Bf,
                       &g->W, &g->ab, &g->aboff, &g->seed, &g->zeros, &g->wsF, &g->wsP, &g->wsU};
     for (DevBuf *b : bufs) b->release();
 }
@@ -199,8 +199,9 @@ int apply_level(mlcr_op *op, int level, int nrhs, const double *x, double *y, in
     if (nrhs < 1) return fail(MLCR_EINVAL, "nrhs must be >= 1");
     int rc;
     if ((rc = check_prec(prec))) return rc;
-    mlcr_geom *g = op->g;
     const mlcr_level &L = op->levels[level];
+    mlcr_geom *g = L.gl ? L.gl : op->g;
+    const double *ninv = L.gl ? L.gninv.as<double>() : op->ninv;
     const int lmax = L.lmax;
     if ((rc = reserve_ws(g, lmax, nrhs))) return rc;
     double2 *F = g->wsF.as<double2>();
@@ -208,7 +209,7 @@ int apply_level(mlcr_op *op, int level, int nrhs, const double *x, double *y, in
     if ((rc = legendre_synth_any(a, x, L.bh.as<double>(), g, F, prec))) return rc;
     {
         KTimer t("ring_apply", s);
-        if ((rc = launch_ring_apply(g, lmax, nrhs, F, op->ninv, s))) return rc;
+        if ((rc = launch_ring_apply(g, lmax, nrhs, F, ninv, s))) return rc;
     }
     if ((rc = legendre_adjoint_any(a, F, g, x, L.d.as<double>(), L.bh.as<double>(), y, prec)))
         return rc;
@@ -271,6 +272,42 @@ int mlcr_geom_create(int nside, int lmax, mlcr_geom **out) {
     return MLCR_OK;
 }
 
+int mlcr_geom_create_gl(int lmax, int nrings, int nphi, mlcr_geom **out) {
+    if (!out) return fail(MLCR_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (lmax < 0 || lmax > 16384) return fail(MLCR_EINVAL, "lmax must be in [0, 16384]");
+    if (nrings < 1 || nrings > 32768) return fail(MLCR_EINVAL, "nrings must be in [1, 32768]");
+    if (nphi < 4 || nphi % 4 || nphi > 8192 * 2)
+        return fail(MLCR_EINVAL, "nphi must be a multiple of 4 in [4, 16384]");
+    {
+        // ring FFT buffers must fit in LDS: n = nphi/2 itself, or Bluestein size
+        int n = nphi / 2, M = 1;
+        while (M < n) M <<= 1;
+        if (M != n) {
+            M = 1;
+            while (M < 2 * n - 1) M <<= 1;
+        }
+        if (M > 8192) return fail(MLCR_EINVAL, "nphi needs an FFT larger than 8192 points");
+    }
+    mlcr_geom *g = new (std::nothrow) mlcr_geom();
+    if (!g) return fail(MLCR_ENOMEM, "host allocation failed");
+    int rc = build_geometry_gl(g, lmax, nrings, nphi);
+    if (rc) {
+        release_geom(g);
+        delete g;
+        return rc;
+    }
+    *out = g;
+    g_err.clear();
+    return MLCR_OK;
+}
+
+int mlcr_geom_weights(const mlcr_geom *g, double *w) {
+    if (!g || !w) return fail(MLCR_EINVAL, "NULL argument");
+    std::copy(g->ring_w_host.begin(), g->ring_w_host.end(), w);
+    return MLCR_OK;
+}
+
 void mlcr_geom_destroy(mlcr_geom *g) {
     if (!g) return;
     (void)hipDeviceSynchronize();
@@ -330,8 +367,18 @@ int sht_adjoint(mlcr_geom *g, int lmax, int nrhs, const double *map, double *alm
 // ---------------------------------------------------------------------------
 // operator
 // ---------------------------------------------------------------------------
+static void drop_gl(mlcr_level &L) {
+    if (L.gl) {
+        (void)hipDeviceSynchronize();
+        mlcr_geom_destroy(L.gl);
+        L.gl = nullptr;
+    }
+    L.gninv.release();
+}
+
 static int upload_level(mlcr_level &L, int lmax_h, const std::vector<double> &cl,
                         const std::vector<double> &bl, const double *fl) {
+    drop_gl(L);
     std::vector<double> d(lmax_h + 1), bh(lmax_h + 1);
     for (int l = 0; l <= lmax_h; l++) {
         const double f = fl ? fl[l] : 1.0;
@@ -391,6 +438,7 @@ void mlcr_op_destroy(mlcr_op *op) {
     if (!op) return;
     (void)hipDeviceSynchronize();
     for (auto &L : op->levels) {
+        drop_gl(L);
         L.d.release();
         L.bh.release();
     }
@@ -404,6 +452,38 @@ int mlcr_op_set_level(mlcr_op *op, int h, int lmax_h, const double *fl) {
     for (int l = 0; l <= lmax_h; l++)
         if (!std::isfinite(fl[l])) return fail(MLCR_EINVAL, "filter must be finite");
     return upload_level(op->levels[h], lmax_h, op->cl, op->bl, fl);
+}
+
+int mlcr_op_set_level_gl(mlcr_op *op, int h, int lmax_h, const double *fl) {
+    if (!op || !fl) return fail(MLCR_EINVAL, "NULL argument");
+    if (h < 1 || h >= 16) return fail(MLCR_EINVAL, "level index must be in [1, 15]");
+    if (lmax_h < 0 || lmax_h > op->lmax) return fail(MLCR_EINVAL, "lmax_h out of range");
+    const int lx = 2 * lmax_h;            // band limit of the downgraded N^-1
+    if (lx > op->g->lmax)
+        return fail(MLCR_EINVAL, "2 lmax_h exceeds the observation geometry's lmax");
+    int nphi = 4;
+    while (nphi < 4 * lmax_h + 1) nphi <<= 1;
+    if (nphi > 16384) return fail(MLCR_EINVAL, "lmax_h too large for a Gauss-Legendre level");
+    int rc = mlcr_op_set_level(op, h, lmax_h, fl);
+    if (rc) return rc;
+    mlcr_level &L = op->levels[h];
+    mlcr_geom *gg = nullptr;
+    if ((rc = mlcr_geom_create_gl(lx, 2 * lmax_h + 1, nphi, &gg))) return rc;
+    L.gl = gg;
+    // xi = Y_obs^T N^-1 (Sec. 3.5): every coupling of Y_obs^T N^-1 Y_obs between
+    // modes l, l' <= lmax_h sees only xi_LM with L <= 2 lmax_h; synthesized on
+    // the Gauss-Legendre grid and weighted by its quadrature, it reproduces
+    // those couplings exactly (up to rounding)
+    DevBuf xi, map;
+    const long long nx = (long long)(lx + 1) * (lx + 1);
+    if (xi.reserve((size_t)nx * sizeof(double)) || map.reserve((size_t)gg->npix * sizeof(double)) ||
+        L.gninv.reserve((size_t)gg->npix * sizeof(double)))
+        return fail(MLCR_ENOMEM, "Gauss-Legendre level allocation failed");
+    if ((rc = sht_adjoint(op->g, lx, 1, op->ninv, xi.as<double>(), MLCR_FP64, nullptr))) return rc;
+    if ((rc = sht_synth(gg, lx, 1, xi.as<double>(), map.as<double>(), MLCR_FP64, nullptr))) return rc;
+    if ((rc = launch_ring_weight(gg, map.as<double>(), L.gninv.as<double>(), nullptr))) return rc;
+    MLCR_HIP_CHECK(hipDeviceSynchronize());
+    return MLCR_OK;
 }
 
 int mlcr_op_level_lmax(const mlcr_op *op, int h) {

@@ -48,14 +48,22 @@ static void fft_ld(std::vector<cld> &x) {
     }
 }
 
+// Tables shared by every ring layout: per length class N = 4 i the twiddles
+// T_N and Bluestein filters, the power-of-two twiddles W, the recurrence
+// coefficients, the ring launch groups; then the upload.  ri[k].tab indexes
+// classes (the ring counts N = 4 i of the layout's length classes).
+static int finish_geometry(mlcr_geom *g, int lmax, const std::vector<double> &z,
+                           const std::vector<double> &s, std::vector<RingInfo> &ri,
+                           const std::vector<int> &classes);
+
 int build_geometry(mlcr_geom *g, int nside, int lmax) {
+    g->kind = 0;
     g->nside = nside;
     g->lmax = lmax;
     g->nrings = 4 * nside - 1;
     g->npairs = 2 * nside;
     g->npix = 12LL * nside * nside;
     const int nr = g->nrings;
-
     // ---- rings (Sec. 2.1; Gorski et al. 2005) ----
     std::vector<double> z(nr), s(nr);
     std::vector<RingInfo> ri(nr);
@@ -88,13 +96,90 @@ int build_geometry(mlcr_geom *g, int nside, int lmax) {
         start += r.nphi;
     }
 
+    std::vector<int> classes(nside);
+    for (int i = 1; i <= nside; i++) classes[i - 1] = i;
+    g->ring_w_host.assign(nr, 4.0 * (double)kPi / (double)g->npix);   // equal-area pixels
+    return finish_geometry(g, lmax, z, s, ri, classes);
+}
+
+// Gauss-Legendre rings: nrings nodes z_k of P_nrings (north to south), nphi
+// equispaced pixels per ring starting at phi = 0.  The quadrature
+// sum_k sum_j W_k f(theta_k, phi_j), W_k = w_k 2 pi / nphi with w_k the
+// Gauss-Legendre weights, integrates f exactly when f is a polynomial of
+// degree < 2 nrings in cos theta and holds frequencies |m| < nphi in phi.
+int build_geometry_gl(mlcr_geom *g, int lmax, int nrings, int nphi) {
+    g->kind = 1;
+    g->nside = 0;
+    g->lmax = lmax;
+    g->nrings = nrings;
+    g->npairs = (nrings + 1) / 2;
+    g->npix = (long long)nrings * nphi;
+    const int nr = nrings;
+    std::vector<long double> zl(nr), wl(nr);
+    // Newton on P_n from the usual cosine guesses; the south half mirrors the north
+    auto node = [&](int k) {
+        long double x = cosl(kPi * ((long double)k + 0.75L) / ((long double)nr + 0.5L));
+        long double dp = 1.0L;
+        for (int it = 0; it < 100; it++) {
+            long double p0 = 1.0L, p1 = x;
+            for (int j = 2; j <= nr; j++) {
+                const long double p2 = ((2.0L * j - 1.0L) * x * p1 - (j - 1.0L) * p0) / (long double)j;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (nr == 1) { p1 = x; p0 = 1.0L; }
+            dp = (long double)nr * (x * p1 - p0) / (x * x - 1.0L);
+            const long double dx = p1 / dp;
+            x -= dx;
+            if (fabsl(dx) < 1e-19L * std::max(1.0L, fabsl(x))) break;
+        }
+        zl[k] = x;
+        wl[k] = 2.0L / ((1.0L - x * x) * dp * dp);
+    };
+    {
+        const int half = (nr + 1) / 2;
+        unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nt; t++)
+            th.emplace_back([&, t] {
+                for (int k = (int)t; k < half; k += (int)nt) node(k);
+            });
+        for (auto &t : th) t.join();
+        for (int k = 0; k < half; k++) {
+            zl[nr - 1 - k] = -zl[k];
+            wl[nr - 1 - k] = wl[k];
+        }
+        if (nr & 1) zl[nr / 2] = 0.0L;
+    }
+    std::vector<double> z(nr), s(nr);
+    std::vector<RingInfo> ri(nr);
+    g->ring_w_host.resize(nr);
+    for (int k = 0; k < nr; k++) {
+        z[k] = (double)zl[k];
+        s[k] = (double)sqrtl((1.0L - zl[k]) * (1.0L + zl[k]));
+        RingInfo &r = ri[k];
+        r.start = (long long)k * nphi;
+        r.nphi = nphi;
+        r.phase = 0;            // phi0 = 0
+        r.tab = 0;
+        r.pad = 0;
+        g->ring_w_host[k] = (double)(wl[k] * 2.0L * kPi / (long double)nphi);
+    }
+    return finish_geometry(g, lmax, z, s, ri, std::vector<int>{nphi / 4});
+}
+
+static int finish_geometry(mlcr_geom *g, int lmax, const std::vector<double> &z,
+                           const std::vector<double> &s, std::vector<RingInfo> &ri,
+                           const std::vector<int> &classes) {
+    const int nr = g->nrings;
+    const int ncls = (int)classes.size();
     // ---- length classes N = 4 i: twiddles T_N and Bluestein filters ----
-    std::vector<LenInfo> li(nside);
+    std::vector<LenInfo> li(ncls);
     long long toff = 0, boff = 0;
     int maxfft = 1;
-    for (int i = 1; i <= nside; i++) {
-        LenInfo &L = li[i - 1];
-        const int N = 4 * i, n = N / 2;
+    for (int c = 0; c < ncls; c++) {
+        LenInfo &L = li[c];
+        const int N = 4 * classes[c], n = N / 2;
         L.toff = toff;
         toff += 2LL * N;
         if (is_pow2(n)) {
@@ -112,9 +197,9 @@ int build_geometry(mlcr_geom *g, int nside, int lmax) {
     g->Wmax = maxfft;
 
     std::vector<double2> T(toff), Bf(std::max<long long>(boff, 1)), W(maxfft);
-    auto fill_class = [&](int i) {
-        const int N = 4 * i, n = N / 2;
-        const LenInfo &L = li[i - 1];
+    auto fill_class = [&](int c) {
+        const int N = 4 * classes[c], n = N / 2;
+        const LenInfo &L = li[c];
         for (int j = 0; j < 2 * N; j++) {
             long double a = kPi * (long double)j / (long double)N;
             T[L.toff + j] = make_double2((double)cosl(a), (double)sinl(a));
@@ -139,7 +224,7 @@ int build_geometry(mlcr_geom *g, int nside, int lmax) {
         std::vector<std::thread> th;
         for (unsigned t = 0; t < nt; t++)
             th.emplace_back([&, t] {
-                for (int i = 1 + (int)t; i <= nside; i += (int)nt) fill_class(i);
+                for (int c = (int)t; c < ncls; c += (int)nt) fill_class(c);
             });
         for (auto &t : th) t.join();
     }
@@ -222,8 +307,9 @@ int build_geometry(mlcr_geom *g, int nside, int lmax) {
     int rc;
     if ((rc = up(g->ring_z, z.data(), nr * sizeof(double)))) return rc;
     if ((rc = up(g->ring_s, s.data(), nr * sizeof(double)))) return rc;
+    if ((rc = up(g->ring_w, g->ring_w_host.data(), nr * sizeof(double)))) return rc;
     if ((rc = up(g->rings, ri.data(), nr * sizeof(RingInfo)))) return rc;
-    if ((rc = up(g->lens, li.data(), nside * sizeof(LenInfo)))) return rc;
+    if ((rc = up(g->lens, li.data(), ncls * sizeof(LenInfo)))) return rc;
     if ((rc = up(g->order, order.data(), nr * sizeof(int)))) return rc;
     if ((rc = up(g->T, T.data(), T.size() * sizeof(double2)))) return rc;
     if ((rc = up(g->Bf, Bf.data(), Bf.size() * sizeof(double2)))) return rc;

@@ -126,6 +126,24 @@ struct Lane1 {
         }
     }
     __device__ __forceinline__ double w() const { return sc == 0 ? l1 : 0.0; }
+    __device__ __forceinline__ void step(double2 c) {
+        const double nv = fma(c.x, z * l1, -c.y * l2);
+        l2 = l1;
+        l1 = nv;
+    }
+    // Range check after a run of 4 plain steps taken while every lane of the
+    // wave is still scaled (contributing nothing).  One step grows |lambda|
+    // by at most 2 max A_lm < 2 sqrt(2 lmax + 2) (< 2^8.5 for lmax <= 16384),
+    // so 4 steps stay far below overflow, and a lane that enters range inside
+    // a run has values below 2^-112 * 2^34 = 2^-78 there, too small to
+    // change any sum.
+    __device__ __forceinline__ void check_range() {
+        if (sc > 0 && fabs(l1) >= 0x1p400) {
+            l1 *= 0x1p-512;
+            l2 *= 0x1p-512;
+            sc--;
+        }
+    }
 };
 
 __device__ __forceinline__ int wave_mode1(const Lane1 &L) {
@@ -146,8 +164,10 @@ __global__ __launch_bounds__(64) void k_lsynth_mfma(
     int npb, long long total) {
     typedef Mma<T> M;
     __shared__ double2 sab[kChunkM];
-    __shared__ T su[kChunkM * 16];
-    __shared__ T lam[8][64];
+    constexpr int SU = 24;       // padded U row: the 4 lane groups hit distinct banks
+    constexpr int SL = 72;       // padded lambda row, likewise
+    __shared__ T su[kChunkM * SU];
+    __shared__ T lam[8][SL];
     int m, pb, rc;
     bool ok;
     decode_item_m(total, lmax, npb, m, pb, rc, ok);
@@ -175,8 +195,8 @@ __global__ __launch_bounds__(64) void k_lsynth_mfma(
     // LDS, then 4 ring blocks x (even, odd) MFMAs
     auto mfma_group = [&](int j0) {
         __syncthreads();
-        const T be = su[(j0 + 2 * kq) * 16 + jc];
-        const T bo = su[(j0 + 2 * kq + 1) * 16 + jc];
+        const T be = su[(j0 + 2 * kq) * SU + jc];
+        const T bo = su[(j0 + 2 * kq + 1) * SU + jc];
 #pragma unroll
         for (int b = 0; b < 4; b++) {
             const T ae = lam[2 * kq][16 * b + jc];
@@ -204,7 +224,7 @@ __global__ __launch_bounds__(64) void k_lsynth_mfma(
                 const uint4 v = (base + jl < nl)
                                     ? reinterpret_cast<const uint4 *>(Um + (long long)(base + jl) * 16)[part]
                                     : make_uint4(0u, 0u, 0u, 0u);
-                reinterpret_cast<uint4 *>(su + jl * 16)[part] = v;
+                reinterpret_cast<uint4 *>(su + jl * SU)[part] = v;
             }
         }
         __syncthreads();
@@ -213,7 +233,10 @@ __global__ __launch_bounds__(64) void k_lsynth_mfma(
         // every lane still range-scaled: advance only
         for (; mode == 0 && j0 < jend; j0 += 8) {
 #pragma unroll
-            for (int s = 0; s < 8; s++) L.step_rescale(sab[j0 + s]);
+            for (int s = 0; s < 8; s++) {
+                L.step(sab[j0 + s]);
+                if ((s & 3) == 3) L.check_range();
+            }
             mode = wave_mode1(L);
         }
         // some lanes scaled: lambda is 0 there until they reach the range
@@ -274,7 +297,8 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
     const long long *__restrict__ aboff, const double *__restrict__ seedc, int nrings, int npairs,
     int npb, int nchunks, long long total) {
     typedef Mma<T> M;
-    constexpr int LS = 32 * 65;                  // lambda tile of one wave, padded rows
+    constexpr int SL = 66;                       // padded lambda row: operand reads hit 64 banks
+    constexpr int LS = 32 * SL;                  // lambda tile of one wave
     extern __shared__ __align__(16) unsigned char smem[];
     double2 *sab = reinterpret_cast<double2 *>(smem);
     T *lam_all = reinterpret_cast<T *>(smem + kChunkM * sizeof(double2));
@@ -331,15 +355,19 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
         typename M::acc DE = M::zero(), DO = DE;
         if (mode == 0) {
             if (active) {
-#pragma unroll 4
-                for (int s = 0; s < 32; s++) L.step_rescale(sab[s]);
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+#pragma unroll
+                    for (int s = 0; s < 4; s++) L.step(sab[4 * q + s]);
+                    L.check_range();
+                }
                 mode = wave_mode1(L);
             }
         } else {
             if (mode == 1) {
 #pragma unroll 4
                 for (int s = 0; s < 32; s++) {
-                    lam[s * 65 + lane] = M::cvt(L.w());
+                    lam[s * SL + lane] = M::cvt(L.w());
                     L.step_rescale(sab[s]);
                 }
                 mode = wave_mode1(L);
@@ -347,7 +375,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
                 // steady state: every lane in range, plain recurrence
 #pragma unroll 8
                 for (int s = 0; s < 32; s++) {
-                    lam[s * 65 + lane] = M::cvt(L.l1);
+                    lam[s * SL + lane] = M::cvt(L.l1);
                     const double2 c = sab[s];
                     const double nv = fma(c.x, L.z * L.l1, -c.y * L.l2);
                     L.l2 = L.l1;
@@ -358,8 +386,8 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int g = 0; g < 16; g++) {
-                const T ae = lam[(2 * jc) * 65 + 4 * g + kq];
-                const T ao = lam[(2 * jc + 1) * 65 + 4 * g + kq];
+                const T ae = lam[(2 * jc) * SL + 4 * g + kq];
+                const T ao = lam[(2 * jc + 1) * SL + 4 * g + kq];
                 DE = M::mma(ae, ge[g], DE);
                 DO = M::mma(ao, go[g], DO);
             }
@@ -483,7 +511,7 @@ static int launch_ladj_wg(const LegendreArgs &a, const double2 *G, double *P, in
     const long long total = mitems(a.lmax, nchunks, nrc);
     const long long grid = ((total + 7) / 8) * 8;
     const long long fstride = (long long)g->nrings * (a.lmax + 1);
-    const size_t lds = kChunkM * sizeof(double2) + (size_t)W * 32 * 65 * sizeof(T);
+    const size_t lds = kChunkM * sizeof(double2) + (size_t)W * 32 * 66 * sizeof(T);
     int rc = ensure_dynamic_lds((const void *)k_ladj_mfma<T, W>, lds);
     if (rc) return rc;
     hipLaunchKernelGGL((k_ladj_mfma<T, W>), dim3((unsigned)grid), dim3(64 * W), lds, a.stream, G,

@@ -67,6 +67,7 @@ struct RingGroup {
 }  // namespace mlcr
 
 struct mlcr_geom {
+    int kind = 0;           // 0: HEALPix RING grid; 1: Gauss-Legendre grid
     int nside = 0, lmax = 0, nrings = 0, npairs = 0;
     long long npix = 0;
     int lds_cplx = 0;       // largest complex FFT buffer of any ring
@@ -74,10 +75,12 @@ struct mlcr_geom {
 
     // device tables
     mlcr::DevBuf ring_z, ring_s;        // per ring: cos, sin theta (double)
+    mlcr::DevBuf ring_w;                // per ring: quadrature weight per pixel (double)
     mlcr::DevBuf rings;                 // RingInfo[nrings]
     mlcr::DevBuf lens;                  // LenInfo[nside]
     mlcr::DevBuf order;                 // int[nrings]: rings by FFT size group, then cost
     std::vector<mlcr::RingGroup> ring_groups;   // host: launch groups over order
+    std::vector<double> ring_w_host;            // host: quadrature weight per pixel of each ring
     mlcr::DevBuf T;                     // double2, all twiddle tables
     mlcr::DevBuf Bf;                    // double2, all Bluestein filters
     mlcr::DevBuf W;                     // double2, e^{-2 pi i j / Wmax}, j < Wmax
@@ -96,6 +99,10 @@ struct mlcr_level {
     int lmax = -1;
     mlcr::DevBuf d;     // double[lmax+1]: f^2 / C_l (0 for excluded modes)
     mlcr::DevBuf bh;    // double[lmax+1]: f b_l p_l (0 for excluded modes)
+    // optional Gauss-Legendre evaluation of Y^T N^-1 Y (owned): the grid and
+    // the quadrature-weighted downgraded inverse noise on it
+    mlcr_geom *gl = nullptr;
+    mlcr::DevBuf gninv;
 };
 
 struct mlcr_op {
@@ -114,6 +121,7 @@ int ensure_dynamic_lds(const void *func, size_t bytes);
 
 // geometry.cpp
 int build_geometry(mlcr_geom *g, int nside, int lmax);
+int build_geometry_gl(mlcr_geom *g, int lmax, int nrings, int nphi);
 
 // launch wrappers (kernels.hip)
 struct LegendreArgs {
@@ -130,6 +138,8 @@ int launch_ring_adjoint(const mlcr_geom *g, int lmax, int nrhs, const double *ma
                         hipStream_t s);
 int launch_ring_apply(const mlcr_geom *g, int lmax, int nrhs, double2 *FG, const double *ninv,
                       hipStream_t s);
+// out[p] = W_ring(p) in[p]: a map times the grid's quadrature weights
+int launch_ring_weight(const mlcr_geom *g, const double *in, double *out, hipStream_t s);
 int adjoint_chunks(const mlcr_geom *g, int lmax);
 // matrix-core Legendre kernels, 8 RHS per wave; dbl selects float64 MFMA
 // (else float32).  U: T layout with 8 RHS per chunk, elements of that type.

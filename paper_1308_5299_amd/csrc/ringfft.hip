@@ -28,7 +28,6 @@
 namespace mlcr {
 
 static constexpr int kRingThreads = 512;
-static constexpr int kMaxBfly = 8;                 // n/2 <= kMaxBfly * kRingThreads
 static constexpr double kSqrt2 = 1.4142135623730950488;
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
@@ -39,40 +38,118 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
-// Unnormalized DFT of size M (power of two) held in LDS, in place, all
-// threads of the block taking part.  Forward: X_k = sum_j x_j e^{-2 pi i jk/M};
-// inverse uses e^{+...}.  W[j] = e^{-2 pi i j / Wmax}, Wmax a multiple of M.
-__device__ void lds_fft(double2 *buf, int M, bool inverse, const double2 *__restrict__ W,
-                        int Wmax) {
-    const int half = M >> 1;
-    const int tid = threadIdx.x;
-    for (int p = 1; p < M; p <<= 1) {
-        const int ts = Wmax / (2 * p);
-        double2 a[kMaxBfly], b[kMaxBfly];
-#pragma unroll
-        for (int c = 0; c < kMaxBfly; c++) {
-            const int i = tid + c * kRingThreads;
-            if (i < half) {
-                a[c] = buf[i];
-                b[c] = buf[i + half];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < kMaxBfly; c++) {
-            const int i = tid + c * kRingThreads;
-            if (i < half) {
-                const int k = i & (p - 1);
-                double2 w = W[(long long)k * ts];
-                if (inverse) w.y = -w.y;
-                const double2 t = cmul(b[c], w);
-                const int j = (i << 1) - k;
-                buf[j] = cadd(a[c], t);
-                buf[j + p] = csub(a[c], t);
-            }
-        }
-        __syncthreads();
+// Small DFTs in registers.  Forward: X_r = sum_j x_j e^{-2 pi i j r / R};
+// INV flips the sign of the exponent.
+template <bool INV>
+__device__ __forceinline__ double2 mul_mi(double2 a) {      // a * (-i), or a * i if INV
+    return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(double2 &x0, double2 &x1, double2 &x2, double2 &x3) {
+    const double2 a = cadd(x0, x2), b = csub(x0, x2), c = cadd(x1, x3);
+    const double2 d = mul_mi<INV>(csub(x1, x3));
+    x0 = cadd(a, c);
+    x2 = csub(a, c);
+    x1 = cadd(b, d);
+    x3 = csub(b, d);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(double2 (&x)[R]) {
+    if constexpr (R == 2) {
+        const double2 a = x[0];
+        x[0] = cadd(a, x[1]);
+        x[1] = csub(a, x[1]);
+    } else if constexpr (R == 4) {
+        dft4<INV>(x[0], x[1], x[2], x[3]);
+    } else {
+        // radix-2 split into even and odd 4-point DFTs, then w^r = e^{-2 pi i r / 8}
+        double2 e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
+        double2 o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
+        dft4<INV>(e0, e1, e2, e3);
+        dft4<INV>(o0, o1, o2, o3);
+        constexpr double h = 0.70710678118654752440;
+        const double2 w1o = INV ? make_double2(h * (o1.x - o1.y), h * (o1.x + o1.y))
+                                : make_double2(h * (o1.x + o1.y), h * (o1.y - o1.x));
+        const double2 w2o = mul_mi<INV>(o2);
+        const double2 w3o = INV ? make_double2(-h * (o3.x + o3.y), h * (o3.x - o3.y))
+                                : make_double2(h * (o3.y - o3.x), -h * (o3.x + o3.y));
+        x[0] = cadd(e0, o0);
+        x[4] = csub(e0, o0);
+        x[1] = cadd(e1, w1o);
+        x[5] = csub(e1, w1o);
+        x[2] = cadd(e2, w2o);
+        x[6] = csub(e2, w2o);
+        x[3] = cadd(e3, w3o);
+        x[7] = csub(e3, w3o);
     }
+}
+
+// One radix-R Stockham pass over the M values in LDS (stride p so far):
+// butterfly i (k = i mod p) reads x[i + j M/R], scales input j by
+// w^{j k} with w = e^{-2 pi i / (p R)}, does an R-point DFT and writes
+// output r to x[(i - k) R + k + r p].  W[j] = e^{-2 pi i j / Wmax}.
+template <int R, bool INV>
+__device__ __forceinline__ void fft_pass(double2 *buf, int M, int p, const double2 *__restrict__ W,
+                                         int Wmax) {
+    constexpr int CMAX = 8192 / (R * kRingThreads);
+    const int T = M / R;
+    const int ts = Wmax / (p * R);
+    double2 v[CMAX][R];
+#pragma unroll
+    for (int c = 0; c < CMAX; c++) {
+        const int i = threadIdx.x + c * kRingThreads;
+        if (i < T) {
+            const int k = i & (p - 1);
+#pragma unroll
+            for (int j = 0; j < R; j++) v[c][j] = buf[i + j * T];
+            if (p > 1) {
+#pragma unroll
+                for (int j = 1; j < R; j++) {
+                    double2 w = W[j * k * ts];
+                    if (INV) w.y = -w.y;
+                    v[c][j] = cmul(v[c][j], w);
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CMAX; c++) {
+        const int i = threadIdx.x + c * kRingThreads;
+        if (i < T) {
+            const int k = i & (p - 1);
+            dft<R, INV>(v[c]);
+            const int jo = (i - k) * R + k;
+#pragma unroll
+            for (int j = 0; j < R; j++) buf[jo + j * p] = v[c][j];
+        }
+    }
+    __syncthreads();
+}
+
+// Unnormalized DFT of size M (a power of two, M <= 8192) held in LDS, in
+// place, all threads of the block taking part: one radix-2 or radix-4 pass
+// when log2 M is not a multiple of 3, then radix-8 passes.
+template <bool INV>
+__device__ void lds_fft_t(double2 *buf, int M, const double2 *__restrict__ W, int Wmax) {
+    const int lg = 31 - __clz(M);
+    int p = 1;
+    if (lg % 3 == 1) {
+        fft_pass<2, INV>(buf, M, p, W, Wmax);
+        p = 2;
+    } else if (lg % 3 == 2) {
+        fft_pass<4, INV>(buf, M, p, W, Wmax);
+        p = 4;
+    }
+    for (; p < M; p *= 8) fft_pass<8, INV>(buf, M, p, W, Wmax);
+}
+
+__device__ __forceinline__ void lds_fft(double2 *buf, int M, bool inverse,
+                                        const double2 *__restrict__ W, int Wmax) {
+    if (inverse) lds_fft_t<true>(buf, M, W, Wmax);
+    else lds_fft_t<false>(buf, M, W, Wmax);
 }
 
 // Folded, phased coefficient  Hhat_q = sum_{m = q mod N} H_m  for 0 <= q < N.
@@ -241,6 +318,23 @@ int launch_ring_adjoint(const mlcr_geom *g, int lmax, int nrhs, const double *ma
                         hipStream_t s) {
     return launch_ring<1>(g, lmax, nrhs, nullptr, G, map, nullptr, nullptr, s);
 }
+// one workgroup per ring
+__global__ __launch_bounds__(256) void k_ring_weight(const double *__restrict__ in,
+                                                     double *__restrict__ out,
+                                                     const RingInfo *__restrict__ rings,
+                                                     const double *__restrict__ w) {
+    const RingInfo ri = rings[blockIdx.x];
+    const double wk = w[blockIdx.x];
+    for (int j = threadIdx.x; j < ri.nphi; j += blockDim.x) out[ri.start + j] = wk * in[ri.start + j];
+}
+
+int launch_ring_weight(const mlcr_geom *g, const double *in, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_ring_weight, dim3(g->nrings), dim3(256), 0, s, in, out,
+                       g->rings.as<RingInfo>(), g->ring_w.as<double>());
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
 int launch_ring_apply(const mlcr_geom *g, int lmax, int nrhs, double2 *FG, const double *ninv,
                       hipStream_t s) {
     return launch_ring<2>(g, lmax, nrhs, FG, FG, nullptr, nullptr, ninv, s);

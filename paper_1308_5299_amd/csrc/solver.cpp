@@ -553,6 +553,20 @@ static int setup_bottom(mlcr_solver *S, hipStream_t s) {
     return MLCR_OK;
 }
 
+// A coarse level evaluates Y^T N^-1 Y on a Gauss-Legendre grid (Sec. 3.5)
+// when that grid -- 2 lmax_h + 1 rings of the smallest power of two >=
+// 4 lmax_h + 1 pixels -- is smaller than the observation grid; otherwise on
+// the observation grid itself.  Both give the same operator (exactly, up to
+// rounding); only the cost differs.
+static int set_level_best(mlcr_op *op, int h, int lmax_h, const double *fl) {
+    long long nphi = 4;
+    while (nphi < 4LL * lmax_h + 1) nphi <<= 1;
+    const long long gl_pix = (2LL * lmax_h + 1) * nphi;
+    if (2 * lmax_h <= op->g->lmax && nphi <= 16384 && gl_pix < op->g->npix)
+        return mlcr_op_set_level_gl(op, h, lmax_h, fl);
+    return mlcr_op_set_level(op, h, lmax_h, fl);
+}
+
 static int solver_build(mlcr_solver *S, const Plan &p, hipStream_t s) {
     mlcr_op *op = S->op;
     const int R = S->max_nrhs;
@@ -597,7 +611,7 @@ static int solver_build(mlcr_solver *S, const Plan &p, hipStream_t s) {
         L->lmax = p.lmax[h];
         L->opl = h + 1;
         if ((rc = mlcr_geom_create(L->nside, L->lmax, &L->geom))) return rc;
-        if ((rc = mlcr_op_set_level(op, L->opl, L->lmax, p.fl[h].data()))) return rc;
+        if ((rc = set_level_best(op, L->opl, L->lmax, p.fl[h].data()))) return rc;
         std::vector<double> act(L->lmax + 1), one(L->lmax + 1);
         for (int l = 0; l <= L->lmax; l++) {
             act[l] = op->cl[l] > 0 ? 1.0 : 0.0;
@@ -639,7 +653,7 @@ static int solver_build(mlcr_solver *S, const Plan &p, hipStream_t s) {
     S->opl_b = p.H + 1;
     {
         std::vector<double> fb(p.fl[p.H - 1].begin(), p.fl[p.H - 1].begin() + p.lmax_b + 1);
-        if ((rc = mlcr_op_set_level(op, S->opl_b, S->lmax_b, fb.data()))) return rc;
+        if ((rc = set_level_best(op, S->opl_b, S->lmax_b, fb.data()))) return rc;
     }
     const size_t bbytes = (size_t)R * nalm_l(S->lmax_b) * sizeof(double);
     if ((rc = alloc(S->xb, bbytes)) || (rc = alloc(S->bb, bbytes))) return rc;

@@ -123,3 +123,44 @@ def test_sampled_orders_match_full():
         n = lmax - m + 1
         np.testing.assert_allclose(c, full[:, b: b + n], rtol=0, atol=1e-12)
         np.testing.assert_allclose(s, full[:, b + n: b + 2 * n], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 64, 100])
+def test_gauss_legendre_rings(n):
+    """Nodes match numpy's Gauss-Legendre rule; weights integrate z^k exactly
+    for k < 2n (sum over rings of W_k nphi / (2 pi) = Gauss-Legendre weights)."""
+    g, W = geometry.gauss_legendre_rings(n, 8)
+    x, w = np.polynomial.legendre.leggauss(n)
+    np.testing.assert_allclose(np.sort(g.z), np.sort(x), rtol=0, atol=1e-14)
+    wl = W * 8 / (2 * np.pi)
+    for k in range(0, 2 * n, max(1, n // 8)):
+        exact = 0.0 if k % 2 else 2.0 / (k + 1)
+        assert abs(np.sum(wl * g.z ** k) - exact) < 1e-13, k
+    np.testing.assert_allclose(g.z, -g.z[::-1], rtol=0, atol=0)
+
+
+def test_gauss_legendre_quadrature_is_exact():
+    """Y^T W Y = I on a Gauss-Legendre grid with lmax + 1 rings and
+    nphi > 2 lmax (the exact quadrature the coarse levels rely on, Sec. 3.5)."""
+    lmax = 24
+    g, W = geometry.gauss_legendre_rings(lmax + 1, 52)
+    x = np.random.default_rng(21).standard_normal(sht.nalm(lmax))
+    m = sht.synth_geom(x, lmax, g)
+    y = sht.adjoint_geom(m * np.repeat(W, g.nphi), lmax, g)
+    np.testing.assert_allclose(y, x, rtol=0, atol=1e-13)
+
+
+def test_downgraded_inverse_noise_identity():
+    """Sec. 3.5: for modes l, l' <= lh, Y_obs^T N^-1 Y_obs equals
+    Y_GL^T W Ntilde Y_GL with Ntilde the synthesis of xi = Y_obs^T N^-1
+    truncated at 2 lh on 2 lh + 1 Gauss-Legendre rings of > 4 lh pixels."""
+    nside, lh = 8, 9
+    cfg = workloads.WorkloadConfig("t", nside, 2 * lh, -1.0, 10.0, 20.0, 3, 8.0, 1)
+    ninv, _, _ = workloads.inverse_noise_map(cfg)
+    x = np.random.default_rng(22).standard_normal(sht.nalm(lh))
+    ref = sht.adjoint(ninv * sht.synth(x, lh, nside), lh, nside)
+    xi = sht.adjoint(ninv, 2 * lh, nside)
+    g, W = geometry.gauss_legendre_rings(2 * lh + 1, 64)
+    nt = sht.synth_geom(xi, 2 * lh, g) * np.repeat(W, g.nphi)
+    got = sht.adjoint_geom(nt * sht.synth_geom(x, lh, g), lh, g)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
