@@ -561,11 +561,21 @@ int synth_rc(int nrhs) { return nrhs >= 5 ? 8 : (nrhs >= 2 ? 4 : 1); }
 int adj_rc(int nrhs) { return nrhs >= 2 ? 4 : 1; }
 static constexpr int kAdjNR = 2;
 
-int adjoint_chunks(const mlcr_geom *g, int lmax) {
+// Split-K over ring-pair blocks: `per` consecutive blocks per chunk, and as
+// many chunks as that takes, so that every chunk holds at least one block
+// (each chunk's partial sums are stored by its first block; an empty chunk
+// would leave its slice of P unwritten for the unpack step to add).
+static int adjoint_per(const mlcr_geom *g, int lmax) {
     const int npb = (g->npairs + 64 * kAdjNR - 1) / (64 * kAdjNR);
     int want = (8192 + lmax) / (lmax + 1);
-    want = std::max(1, std::min(want, 8));
-    return std::min(want, npb);
+    want = std::max(1, std::min(std::min(want, 8), npb));
+    return (npb + want - 1) / want;
+}
+
+int adjoint_chunks(const mlcr_geom *g, int lmax) {
+    const int npb = (g->npairs + 64 * kAdjNR - 1) / (64 * kAdjNR);
+    const int per = adjoint_per(g, lmax);
+    return (npb + per - 1) / per;
 }
 
 long long tlayout_doubles(int lmax, int nrhs, int rc) {
@@ -622,7 +632,7 @@ static int launch_ladj(const LegendreArgs &a, const double2 *G, double *P, int *
     const mlcr_geom *g = a.g;
     const int npb = (g->npairs + 64 * kAdjNR - 1) / (64 * kAdjNR);
     const int nchunks = adjoint_chunks(g, a.lmax);
-    const int per = (npb + nchunks - 1) / nchunks;
+    const int per = adjoint_per(g, a.lmax);
     const int nrc = (a.nrhs + RC - 1) / RC;
     const long long total = (long long)(a.lmax + 1) * nchunks * nrc;
     const long long grid = ((total + 7) / 8) * 8;

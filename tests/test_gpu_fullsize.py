@@ -152,3 +152,31 @@ def test_c3_solve_to_1e3_uK(mlcr, prec_name):
           flush=True)
     assert info[0]["converged"] == 1
     assert err <= 1e-3
+
+
+@pytest.mark.parametrize("nrhs", [1, 2])
+def test_adjoint_ignores_stale_workspace(mlcr, nrhs):
+    """Regression: the vector adjoint's split-K chunks each store their
+    partial sums; no chunk may be left empty (its slice would be stale when a
+    larger transform used the workspace before).  N_side 300 / lmax 2048 has 5
+    ring-pair blocks, the shape that once produced an empty chunk."""
+    print(f"case stale workspace nrhs={nrhs}", flush=True)
+    nside, lmax = 300, 2048
+    g = mlcr.Geometry(nside, lmax)
+    y = dev(np.random.default_rng(88).standard_normal((nrhs, 12 * nside * nside)))
+    a1 = mlcr.sht_adjoint(g, y).clone()
+    big = dev(np.random.default_rng(89).standard_normal((16, 12 * nside * nside)))
+    mlcr.sht_adjoint(g, big)                 # fills the workspaces with other data
+    del big
+    a2 = mlcr.sht_adjoint(g, y)
+    assert torch.equal(a1, a2)
+    # and against the oracle on a few whole orders
+    ref = osht.adjoint_orders(host(y), lmax, nside, [0, 700, 2048])
+    got = [host(a2[:, : lmax + 1])]
+    want = [ref[0][0]]
+    for m in (700, 2048):
+        b = osht.block_base(m, lmax)
+        n = lmax - m + 1
+        got += [host(a2[:, b: b + n]), host(a2[:, b + n: b + 2 * n])]
+        want += [ref[m][0], ref[m][1]]
+    assert _rel(np.concatenate(got, axis=1), np.concatenate(want, axis=1)) <= TOL
