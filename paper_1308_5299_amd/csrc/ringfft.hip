@@ -90,16 +90,16 @@ __device__ __forceinline__ void dft(double2 (&x)[R]) {
 // butterfly i (k = i mod p) reads x[i + j M/R], scales input j by
 // w^{j k} with w = e^{-2 pi i / (p R)}, does an R-point DFT and writes
 // output r to x[(i - k) R + k + r p].  W[j] = e^{-2 pi i j / Wmax}.
-template <int R, bool INV>
+template <int R, bool INV, int NT>
 __device__ __forceinline__ void fft_pass(double2 *buf, int M, int p, const double2 *__restrict__ W,
                                          int Wmax) {
-    constexpr int CMAX = 8192 / (R * kRingThreads);
+    constexpr int CMAX = 8192 / (R * NT) > 0 ? 8192 / (R * NT) : 1;
     const int T = M / R;
     const int ts = Wmax / (p * R);
     double2 v[CMAX][R];
 #pragma unroll
     for (int c = 0; c < CMAX; c++) {
-        const int i = threadIdx.x + c * kRingThreads;
+        const int i = threadIdx.x + c * NT;
         if (i < T) {
             const int k = i & (p - 1);
 #pragma unroll
@@ -117,7 +117,7 @@ __device__ __forceinline__ void fft_pass(double2 *buf, int M, int p, const doubl
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < CMAX; c++) {
-        const int i = threadIdx.x + c * kRingThreads;
+        const int i = threadIdx.x + c * NT;
         if (i < T) {
             const int k = i & (p - 1);
             dft<R, INV>(v[c]);
@@ -132,24 +132,25 @@ __device__ __forceinline__ void fft_pass(double2 *buf, int M, int p, const doubl
 // Unnormalized DFT of size M (a power of two, M <= 8192) held in LDS, in
 // place, all threads of the block taking part: one radix-2 or radix-4 pass
 // when log2 M is not a multiple of 3, then radix-8 passes.
-template <bool INV>
+template <bool INV, int NT>
 __device__ void lds_fft_t(double2 *buf, int M, const double2 *__restrict__ W, int Wmax) {
     const int lg = 31 - __clz(M);
     int p = 1;
     if (lg % 3 == 1) {
-        fft_pass<2, INV>(buf, M, p, W, Wmax);
+        fft_pass<2, INV, NT>(buf, M, p, W, Wmax);
         p = 2;
     } else if (lg % 3 == 2) {
-        fft_pass<4, INV>(buf, M, p, W, Wmax);
+        fft_pass<4, INV, NT>(buf, M, p, W, Wmax);
         p = 4;
     }
-    for (; p < M; p *= 8) fft_pass<8, INV>(buf, M, p, W, Wmax);
+    for (; p < M; p *= 8) fft_pass<8, INV, NT>(buf, M, p, W, Wmax);
 }
 
+template <int NT>
 __device__ __forceinline__ void lds_fft(double2 *buf, int M, bool inverse,
                                         const double2 *__restrict__ W, int Wmax) {
-    if (inverse) lds_fft_t<true>(buf, M, W, Wmax);
-    else lds_fft_t<false>(buf, M, W, Wmax);
+    if (inverse) lds_fft_t<true, NT>(buf, M, W, Wmax);
+    else lds_fft_t<false, NT>(buf, M, W, Wmax);
 }
 
 // Folded, phased coefficient  Hhat_q = sum_{m = q mod N} H_m  for 0 <= q < N.
@@ -173,8 +174,8 @@ __device__ __forceinline__ double2 chirp(const double2 *__restrict__ TN, int t, 
 }
 
 // MODE 0: F -> map.  MODE 1: map -> G.  MODE 2: F -> N^-1 map -> G (G over F).
-template <int MODE>
-__global__ __launch_bounds__(kRingThreads) void k_ring(
+template <int MODE, int NT>
+__global__ __launch_bounds__(NT) void k_ring(
     const double2 *Fin, double2 *Gout, const double *__restrict__ map_in,
     double *__restrict__ map_out, const double *__restrict__ ninv,
     const RingInfo *__restrict__ rings, const LenInfo *__restrict__ lens,
@@ -202,10 +203,10 @@ __global__ __launch_bounds__(kRingThreads) void k_ring(
     if (MODE != 1) {
         const double2 *Fk = Fin + (long long)r * fstride + (long long)k * ld;
         if (blue)
-            for (int t = n + tid; t < M; t += kRingThreads) buf[t] = make_double2(0.0, 0.0);
+            for (int t = n + tid; t < M; t += NT) buf[t] = make_double2(0.0, 0.0);
         // Z_k = (G_k + G_{k+n}) + i w^k (G_k - G_{k+n}),  G_q = (Hhat_q + conj Hhat_{N-q}) / 2,
         // w = e^{2 pi i / N}: the length-n DFT input whose inverse is z_t = f_2t + i f_2t+1.
-        for (int kk = tid; 2 * kk <= n; kk += kRingThreads) {
+        for (int kk = tid; 2 * kk <= n; kk += NT) {
             const int i1 = kk == 0 ? 0 : N - kk;
             const double2 H0 = hhat(Fk, kk, N, p, lmax, TN);
             const double2 H1 = hhat(Fk, i1, N, p, lmax, TN);
@@ -231,50 +232,50 @@ __global__ __launch_bounds__(kRingThreads) void k_ring(
         }
         __syncthreads();
         if (!blue) {
-            lds_fft(buf, n, true, W, Wmax);
+            lds_fft<NT>(buf, n, true, W, Wmax);
         } else {
-            lds_fft(buf, M, false, W, Wmax);
-            for (int t = tid; t < M; t += kRingThreads) buf[t] = cmul(buf[t], Bk[t]);
+            lds_fft<NT>(buf, M, false, W, Wmax);
+            for (int t = tid; t < M; t += NT) buf[t] = cmul(buf[t], Bk[t]);
             __syncthreads();
-            lds_fft(buf, M, true, W, Wmax);
-            for (int t = tid; t < n; t += kRingThreads)
+            lds_fft<NT>(buf, M, true, W, Wmax);
+            for (int t = tid; t < n; t += NT)
                 buf[t] = cscale(cmul(buf[t], chirp(TN, t, N)), invM);
             __syncthreads();
         }
         if (MODE == 0) {
             double2 *out = reinterpret_cast<double2 *>(map_out + pix0);
-            for (int t = tid; t < n; t += kRingThreads) out[t] = buf[t];
+            for (int t = tid; t < n; t += NT) out[t] = buf[t];
             return;
         }
         const double2 *ni = reinterpret_cast<const double2 *>(ninv + ri.start);
-        for (int t = tid; t < n; t += kRingThreads) {
+        for (int t = tid; t < n; t += NT) {
             const double2 w = ni[t];
             const double2 v = buf[t];
             buf[t] = make_double2(v.x * w.x, v.y * w.y);
         }
     } else {
         const double2 *in = reinterpret_cast<const double2 *>(map_in + pix0);
-        for (int t = tid; t < n; t += kRingThreads) buf[t] = in[t];
+        for (int t = tid; t < n; t += NT) buf[t] = in[t];
     }
     // forward DFT of z (adjoint direction)
     if (!blue) {
         __syncthreads();
-        lds_fft(buf, n, false, W, Wmax);
+        lds_fft<NT>(buf, n, false, W, Wmax);
     } else {
-        for (int t = tid; t < M; t += kRingThreads)
+        for (int t = tid; t < M; t += NT)
             buf[t] = (t < n) ? cmul(buf[t], cconj(chirp(TN, t, N))) : make_double2(0.0, 0.0);
         __syncthreads();
-        lds_fft(buf, M, false, W, Wmax);
-        for (int t = tid; t < M; t += kRingThreads) buf[t] = cmul(buf[t], cconj(Bk[t]));
+        lds_fft<NT>(buf, M, false, W, Wmax);
+        for (int t = tid; t < M; t += NT) buf[t] = cmul(buf[t], cconj(Bk[t]));
         __syncthreads();
-        lds_fft(buf, M, true, W, Wmax);
-        for (int t = tid; t < n; t += kRingThreads)
+        lds_fft<NT>(buf, M, true, W, Wmax);
+        for (int t = tid; t < n; t += NT)
             buf[t] = cscale(cmul(buf[t], cconj(chirp(TN, t, N))), invM);
         __syncthreads();
     }
     // unfold: Y_q from the half-length transform, then G_m for m = 0..lmax
     double2 *Gk = Gout + (long long)r * fstride + (long long)k * ld;
-    for (int m = tid; m <= lmax; m += kRingThreads) {
+    for (int m = tid; m <= lmax; m += NT) {
         const int q = m % N;
         const int kq = q % n;
         const int kc = kq == 0 ? 0 : n - kq;
@@ -290,22 +291,38 @@ __global__ __launch_bounds__(kRingThreads) void k_ring(
     }
 }
 
+template <int MODE, int NT>
+static int launch_group(const mlcr_geom *g, const RingGroup &grp, int lmax, int nrhs,
+                        const double2 *F, double2 *G, const double *map_in, double *map_out,
+                        const double *ninv, long long fstride, hipStream_t s) {
+    const size_t lds = (size_t)grp.mmax * sizeof(double2);
+    int rc = ensure_dynamic_lds((const void *)k_ring<MODE, NT>, lds);
+    if (rc) return rc;
+    const long long nblk = 8LL * ((grp.count + 7) / 8) * nrhs;
+    hipLaunchKernelGGL((k_ring<MODE, NT>), dim3((unsigned)nblk), dim3(NT), lds, s, F, G, map_in,
+                       map_out, ninv, g->rings.as<RingInfo>(), g->lens.as<LenInfo>(),
+                       g->order.as<int>(), g->T.as<double2>(), g->Bf.as<double2>(),
+                       g->W.as<double2>(), g->Wmax, lmax, fstride, g->npix, grp.off, grp.count,
+                       nrhs);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+// Groups whose FFT fills 128 KiB of LDS run one workgroup per CU: they get
+// 1024 threads (one butterfly per thread and radix-8 pass) so the CU still
+// holds 16 waves; the others use 512.
 template <int MODE>
 static int launch_ring(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, double2 *G,
                        const double *map_in, double *map_out, const double *ninv,
                        hipStream_t s) {
     const long long fstride = (long long)g->nrings * (lmax + 1);
     for (const RingGroup &grp : g->ring_groups) {
-        const size_t lds = (size_t)grp.mmax * sizeof(double2);
-        int rc = ensure_dynamic_lds((const void *)k_ring<MODE>, lds);
+        const int rc = grp.mmax > 4096
+                           ? launch_group<MODE, 1024>(g, grp, lmax, nrhs, F, G, map_in, map_out,
+                                                      ninv, fstride, s)
+                           : launch_group<MODE, kRingThreads>(g, grp, lmax, nrhs, F, G, map_in,
+                                                              map_out, ninv, fstride, s);
         if (rc) return rc;
-        const long long nblk = 8LL * ((grp.count + 7) / 8) * nrhs;
-        hipLaunchKernelGGL(k_ring<MODE>, dim3((unsigned)nblk), dim3(kRingThreads), lds, s, F, G,
-                           map_in, map_out, ninv, g->rings.as<RingInfo>(), g->lens.as<LenInfo>(),
-                           g->order.as<int>(), g->T.as<double2>(), g->Bf.as<double2>(),
-                           g->W.as<double2>(), g->Wmax, lmax, fstride, g->npix, grp.off, grp.count,
-                           nrhs);
-        MLCR_HIP_CHECK(hipGetLastError());
     }
     return MLCR_OK;
 }
