@@ -9,6 +9,8 @@ from ._lib import MLCRError, load as load_library  # noqa: F401
 from .api import (FP32, FP64, Geometry, KernelTimer, Operator, Solver, apply_A,  # noqa: F401
                   cycle_counts, ladder_plan, nest2ring, sht_adjoint, sht_synth, tile_graph)
 
-__all__ = ["MLCRError", "load_library", "FP32", "FP64", "Geometry", "Operator",
+from . import autograd  # noqa: F401,E402
+
+__all__ = ["autograd", "MLCRError", "load_library", "FP32", "FP64", "Geometry", "Operator",
            "apply_A", "sht_adjoint", "sht_synth", "KernelTimer", "Solver", "nest2ring", "tile_graph",
            "ladder_plan", "cycle_counts"]

@@ -85,6 +85,16 @@ class Geometry:
             pass
 
 
+def packed_ell(lmax: int) -> np.ndarray:
+    """Multipole l of every entry of a real packed harmonic vector (m = 0 block,
+    then a cosine and a sine block per m >= 1, l = m .. lmax)."""
+    parts = [np.arange(lmax + 1)]
+    for m in range(1, lmax + 1):
+        ls = np.arange(m, lmax + 1)
+        parts += [ls, ls]
+    return np.concatenate(parts).astype(np.int64)
+
+
 def nalm(lmax: int) -> int:
     return (lmax + 1) ** 2
 
