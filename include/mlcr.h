@@ -52,7 +52,15 @@ enum {
     MLCR_EUNSUPPORTED = -6  /* valid request this build does not implement        */
 };
 
-enum { MLCR_FP64 = 0, MLCR_FP32 = 1 };
+/* Arithmetic of the Legendre contraction (the rest of every call is float64):
+ *   MLCR_FP64   float64 throughout;
+ *   MLCR_FP32   lambda and coefficients rounded to float32, float32 products
+ *               and accumulation on the matrix cores;
+ *   MLCR_BF16X3 each float32 operand split into bfloat16 hi + lo, products
+ *               hi*hi + hi*lo + lo*hi with float32 accumulation (about
+ *               3 * 2^-18 relative per product).
+ * The recurrence, its seeds and range scaling are float64 in every mode. */
+enum { MLCR_FP64 = 0, MLCR_FP32 = 1, MLCR_BF16X3 = 2 };
 
 typedef struct mlcr_geom mlcr_geom;
 typedef struct mlcr_op mlcr_op;

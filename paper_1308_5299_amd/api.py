@@ -15,6 +15,7 @@ from ._lib import check, load
 
 FP64 = 0
 FP32 = 1
+BF16X3 = 2
 
 
 def _stream() -> ctypes.c_void_p:

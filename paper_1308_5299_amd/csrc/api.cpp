@@ -76,8 +76,9 @@ static int reserve_ws(mlcr_geom *g, int lmax, int nrhs) {
                  (size_t)adjoint_chunks_mfma(g, lmax) * tlayout_doubles(lmax, nrhs, 8)) *
         sizeof(double);
     const size_t ubytes =
-        std::max((size_t)tlayout_doubles(lmax, nrhs, synth_rc(nrhs)) * sizeof(double),
-                 (size_t)tlayout_m_elems(lmax, nrhs) * sizeof(double));
+        std::max({(size_t)tlayout_doubles(lmax, nrhs, synth_rc(nrhs)) * sizeof(double),
+                  (size_t)tlayout_m_elems(lmax, nrhs) * sizeof(double),
+                  (size_t)b3_u_bytes(lmax, nrhs)});
     if (g->wsF.reserve(fbytes)) return fail(MLCR_ENOMEM, "workspace allocation failed (F)");
     if (g->wsP.reserve(pbytes)) return fail(MLCR_ENOMEM, "workspace allocation failed (P)");
     if (g->wsU.reserve(ubytes)) return fail(MLCR_ENOMEM, "workspace allocation failed (U)");
@@ -134,7 +135,7 @@ static void drain_timing() {
 }
 
 static int check_prec(int prec) {
-    if (prec == MLCR_FP64 || prec == MLCR_FP32) return MLCR_OK;
+    if (prec == MLCR_FP64 || prec == MLCR_FP32 || prec == MLCR_BF16X3) return MLCR_OK;
     return fail(MLCR_EINVAL, "unknown precision");
 }
 
@@ -145,12 +146,21 @@ static int check_prec(int prec) {
 static constexpr int kMfmaF64MinRhs = 4;
 
 static bool use_mfma(int prec, int nrhs) {
-    return prec == MLCR_FP32 || nrhs >= kMfmaF64MinRhs;
+    return prec != MLCR_FP64 || nrhs >= kMfmaF64MinRhs;
 }
 
 static int legendre_synth_any(const LegendreArgs &a, const double *x, const double *dl, mlcr_geom *g,
                               double2 *F, int prec) {
     int rc;
+    if (prec == MLCR_BF16X3) {
+        void *U = g->wsU.ptr;
+        {
+            KTimer t("pack", a.stream);
+            if ((rc = launch_pack_b3(a.lmax, a.nrhs, x, dl, U, a.stream))) return rc;
+        }
+        KTimer t("legendre_synth", a.stream);
+        return launch_legendre_synth_b3(a, U, F);
+    }
     if (use_mfma(prec, a.nrhs)) {
         const bool dbl = prec == MLCR_FP64;
         void *U = g->wsU.ptr;
@@ -178,7 +188,8 @@ static int legendre_adjoint_any(const LegendreArgs &a, const double2 *G, mlcr_ge
     const bool mm = use_mfma(prec, a.nrhs);
     {
         KTimer t("legendre_adjoint", a.stream);
-        if (mm) rc = launch_legendre_adjoint_mfma(a, G, P, &nch, prec == MLCR_FP64);
+        if (prec == MLCR_BF16X3) rc = launch_legendre_adjoint_b3(a, G, P, &nch);
+        else if (mm) rc = launch_legendre_adjoint_mfma(a, G, P, &nch, prec == MLCR_FP64);
         else rc = launch_legendre_adjoint(a, G, P, &nch);
         if (rc) return rc;
     }

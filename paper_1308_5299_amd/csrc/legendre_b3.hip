@@ -1,0 +1,453 @@
+// Legendre step with split-bfloat16 products on the matrix cores.
+//
+// The same per-order GEMMs as legendre_mfma.hip (Sec. 2.1 eq. sh-synthesis
+// and its transpose, lambda_lm by the recurrence of Sec. 3.2), but each
+// float32 operand f is carried as two bfloat16 numbers, hi = bf16(f) and
+// lo = bf16(f - hi), and a product as hi*hi + hi*lo + lo*hi, three
+// v_mfma_f32_16x16x32_bf16 with float32 accumulation.  |f - hi - lo| is at
+// most 2^-18 |f| and the dropped lo*lo term at most 2^-18 of the product, so
+// one product is good to about 3 * 2^-18 (1.1e-5) relative.  The recurrence,
+// its seeds and its range scaling stay in float64 exactly as in the float32
+// path; the split costs a few vector instructions per lambda, the contraction
+// runs at the bfloat16 rate.
+//
+// v_mfma_f32_16x16x32_bf16 operands (lane = 0..63): A[i][k] in lane
+// i + 16 (k / 8), element k % 8; B[k][j] in lane j + 16 (k / 8), element
+// k % 8; D[i][j] in lane j + 16 (i / 4), element i % 4.  Even and odd l - m
+// are separate GEMMs (mirror-ring parity); the contraction index k runs over
+// 32 values of one parity.
+#include <algorithm>
+
+#include "legendre_dev.h"
+
+namespace mlcr {
+
+typedef float f4b __attribute__((ext_vector_type(4)));
+typedef float f2b __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// hi/lo bfloat16 pair of two float32 numbers a (low half) and b (high half)
+__device__ __forceinline__ void split2(float a, float b, unsigned &h, unsigned &l) {
+    h = __builtin_bit_cast(unsigned, __builtin_convertvector((f2b){a, b}, bf2));
+    const float ah = __uint_as_float(h << 16), bh = __uint_as_float(h & 0xffff0000u);
+    l = __builtin_bit_cast(unsigned, __builtin_convertvector((f2b){a - ah, b - bh}, bf2));
+}
+
+__device__ __forceinline__ f4b mma_b3(uint4 a, uint4 b, f4b c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a),
+                                                   __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
+
+// U layout: per RHS chunk of 8 and order m, blocks of 16 l-steps; block q of
+// order m holds [p][hl][column j][8 bf16], element e at l = m + 16 q + 2 e + p
+// (1 KiB per block).  Order m has ceil((lmax - m + 1) / 16) blocks.
+__host__ __device__ inline long long b3_ceil16_sum(long long n) {   // sum_{k=1..n} ceil(k / 16)
+    const long long q = n / 16, r = n % 16;
+    return 8 * q * (q + 1) + r * (q + 1);
+}
+__host__ __device__ inline long long b3_qoff(int m, int lmax) {
+    return b3_ceil16_sum(lmax + 1) - b3_ceil16_sum(lmax + 1 - m);
+}
+
+long long b3_u_bytes(int lmax, int nrhs) {
+    return (long long)((nrhs + 7) / 8) * b3_qoff(lmax + 1, lmax) * 1024;
+}
+
+// One thread per (block q, column j): 16 consecutive l of one RHS component.
+__global__ __launch_bounds__(256) void k_pack_b3(const double *__restrict__ x,
+                                                 const double *__restrict__ dl,
+                                                 uint4 *__restrict__ U, int lmax, int nrhs) {
+    const int m = blockIdx.x, rc = blockIdx.y;
+    const long long nalm = (long long)(lmax + 1) * (lmax + 1);
+    const int nl = lmax - m + 1, nq = (nl + 15) / 16;
+    const long long ob = cos_base(m, lmax);
+    uint4 *Ub = U + ((long long)rc * b3_qoff(lmax + 1, lmax) + b3_qoff(m, lmax)) * 64;
+    for (int t = threadIdx.x; t < nq * 16; t += blockDim.x) {
+        const int q = t >> 4, j = t & 15;
+        const int r = rc * 8 + (j >> 1), cs = j & 1;
+        const bool live = r < nrhs && !(m == 0 && cs == 1);
+        float f[16];
+#pragma unroll
+        for (int s = 0; s < 16; s++) {
+            const int lo = 16 * q + s;
+            double v = 0.0;
+            if (live && lo < nl) {
+                v = x[(long long)r * nalm + ob + (long long)cs * nl + lo];
+                if (dl) v *= dl[m + lo];
+            }
+            f[s] = (float)v;
+        }
+#pragma unroll
+        for (int p = 0; p < 2; p++) {
+            uint4 h, l;
+            split2(f[p], f[2 + p], h.x, l.x);
+            split2(f[4 + p], f[6 + p], h.y, l.y);
+            split2(f[8 + p], f[10 + p], h.z, l.z);
+            split2(f[12 + p], f[14 + p], h.w, l.w);
+            Ub[(long long)q * 64 + (2 * p) * 16 + j] = h;
+            Ub[(long long)q * 64 + (2 * p + 1) * 16 + j] = l;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// synthesis: one wave per (m, 64 ring pairs, 8 RHS), groups of 64 l-steps
+// ---------------------------------------------------------------------------
+// Lane r runs the recurrence of ring pair r and writes its 64 lambdas of a
+// group, split and sorted by parity, as one row per ring; lane i + 16 kg then
+// reads the 8 values of sub-block kg of ring 16 b + i as its A operand, and
+// the B operand (the U block) comes straight from global memory.
+__global__ __launch_bounds__(64) void k_lsynth_b3(
+    const uint4 *__restrict__ U, int nrhs, double2 *__restrict__ F, long long fstride, int lmax,
+    const double *__restrict__ rz, const double *__restrict__ rs, const double2 *__restrict__ ab,
+    const long long *__restrict__ aboff, const double *__restrict__ seedc, int nrings, int npairs,
+    int npb, long long total) {
+    constexpr int RS = 5;                       // uint4 per ring row: 4 sub-blocks + 1 pad
+    __shared__ double2 sab[64];
+    __shared__ uint4 lamb[4][64 * RS];          // [2 p + hl][ring * RS + sub-block]
+    int m, pb, rc;
+    bool ok;
+    decode_item_m(total, lmax, npb, m, pb, rc, ok);
+    if (!ok) return;
+    const int lane = threadIdx.x;
+    const uint4 *Um = U + ((long long)rc * b3_qoff(lmax + 1, lmax) + b3_qoff(m, lmax)) * 64;
+    const double2 *abm = ab + aboff[m] - (m + 1);
+    const int nl = lmax - m + 1, nq = (nl + 15) / 16;
+
+    Lane1 L;
+    const int kp = pb * 64 + lane;
+    const bool valid = kp < npairs;
+    L.z = valid ? rz[kp] : 0.0;
+    seed_lambda_m(valid ? rs[kp] : 1.0, m, seedc[m], L.l1, L.sc);
+    L.l2 = 0.0;
+
+    f4b acc[4][2];
+#pragma unroll
+    for (int b = 0; b < 4; b++) acc[b][0] = acc[b][1] = (f4b){0.f, 0.f, 0.f, 0.f};
+    int mode = wave_mode1(L);
+    const int kg = lane >> 4, jc = lane & 15;
+
+    int q = 0;
+    // every lane still range-scaled: advance only, 16 steps at a time
+    while (mode == 0 && q < nq) {
+#pragma unroll
+        for (int s = 0; s < 16; s++) {
+            const int l = m + 16 * q + s;
+            L.step(l + 1 <= lmax ? abm[l + 1] : make_double2(0.0, 0.0));
+            if ((s & 3) == 3) L.check_range();
+        }
+        mode = wave_mode1(L);
+        q++;
+    }
+    for (; q < nq; q += 4) {
+        __syncthreads();
+        {
+            const int l = m + 16 * q + lane;
+            sab[lane] = (l + 1 <= lmax) ? abm[l + 1] : make_double2(0.0, 0.0);
+        }
+        uint4 bu[4];
+        {
+            const int qb = q + kg;
+#pragma unroll
+            for (int ph = 0; ph < 4; ph++)
+                bu[ph] = qb < nq ? Um[(long long)qb * 64 + ph * 16 + jc] : make_uint4(0u, 0u, 0u, 0u);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int qq = 0; qq < 4; qq++) {
+            float f[16];
+            if (mode == 1) {
+#pragma unroll
+                for (int s = 0; s < 16; s++) {
+                    f[s] = (float)L.w();
+                    L.step_rescale(sab[16 * qq + s]);
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < 16; s++) {
+                    f[s] = (float)L.l1;
+                    const double2 c = sab[16 * qq + s];
+                    const double nv = fma(c.x, L.z * L.l1, -c.y * L.l2);
+                    L.l2 = L.l1;
+                    L.l1 = nv;
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < 2; p++) {
+                uint4 h, l;
+                split2(f[p], f[2 + p], h.x, l.x);
+                split2(f[4 + p], f[6 + p], h.y, l.y);
+                split2(f[8 + p], f[10 + p], h.z, l.z);
+                split2(f[12 + p], f[14 + p], h.w, l.w);
+                lamb[2 * p][lane * RS + qq] = h;
+                lamb[2 * p + 1][lane * RS + qq] = l;
+            }
+        }
+        if (mode == 1) mode = wave_mode1(L);
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            const int row = (16 * b + jc) * RS + kg;
+            const uint4 a0h = lamb[0][row], a0l = lamb[1][row];
+            const uint4 a1h = lamb[2][row], a1l = lamb[3][row];
+            acc[b][0] = mma_b3(a0h, bu[0], acc[b][0]);
+            acc[b][1] = mma_b3(a1h, bu[2], acc[b][1]);
+            acc[b][0] = mma_b3(a0h, bu[1], acc[b][0]);
+            acc[b][1] = mma_b3(a1h, bu[3], acc[b][1]);
+            acc[b][0] = mma_b3(a0l, bu[0], acc[b][0]);
+            acc[b][1] = mma_b3(a1l, bu[2], acc[b][1]);
+        }
+    }
+    // D[i][j] of block b: ring pair 16 b + 4 kg + v, column j = jc = (rhs, cos/sin)
+    const int r = rc * 8 + (jc >> 1), cs = jc & 1;
+    const int ld = lmax + 1;
+    if (r < nrhs) {
+        double *Fr = reinterpret_cast<double *>(F + (long long)r * fstride);
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int p = pb * 64 + 16 * b + 4 * kg + v;
+                if (p >= npairs) continue;
+                const double e = (double)acc[b][0][v], o = (double)acc[b][1][v];
+                const int north = p, south = nrings - 1 - p;
+                Fr[((long long)north * ld + m) * 2 + cs] = e + o;
+                if (south != north) Fr[((long long)south * ld + m) * 2 + cs] = e - o;
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint: one workgroup of W waves per (m, chunk of W ring-pair blocks, 8 RHS)
+// ---------------------------------------------------------------------------
+// Wave w owns ring-pair block chunk * W + w.  Per tile of 32 l-steps each lane
+// writes its ring's lambdas (hi and lo planes, row = (parity, l index), column
+// = ring); lane i + 16 kg reads rings 32 c + 8 kg .. + 7 of row i as its A
+// operand, the B operand holds the split even/odd ring sums of G for the same
+// rings.  The W tiles are summed in LDS and the chunk's partial sum stored
+// once (float64, T layout), exactly as the float32 adjoint does.
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_ladj_b3(
+    const double2 *__restrict__ G, long long fstride, int nrhs, double *__restrict__ P, int lmax,
+    const double *__restrict__ rz, const double *__restrict__ rs, const double2 *__restrict__ ab,
+    const long long *__restrict__ aboff, const double *__restrict__ seedc, int nrings, int npairs,
+    int npb, int nchunks, long long total) {
+    constexpr int RW = 72;                      // bf16 per row: 64 rings + 8 pad (144 B)
+    constexpr int LSB = 2 * 32 * RW * 2;        // bytes per wave: [hl][p * 16 + i][RW]
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2 *sab = reinterpret_cast<double2 *>(smem);
+    unsigned char *lam_all = smem + kChunkM * sizeof(double2);
+    int m, chunk, rc;
+    bool ok;
+    decode_item_m(total, lmax, nchunks, m, chunk, rc, ok);
+    if (!ok) return;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    unsigned short *lamh = reinterpret_cast<unsigned short *>(lam_all + wv * LSB);
+    unsigned short *laml = lamh + 32 * RW;
+    float *tile = reinterpret_cast<float *>(lam_all + wv * LSB);
+    const int nl = lmax - m + 1;
+    const long long tri = (long long)(lmax + 1) * (lmax + 2) / 2;
+    const int nrc = (nrhs + 7) / 8;
+    const double2 *abm = ab + aboff[m] - (m + 1);
+    const int ld = lmax + 1;
+    const int kg = lane >> 4, jc = lane & 15;
+    double *Pm = P + (((long long)chunk * nrc + rc) * tri + tri_off_m(m, lmax)) * 16;
+    const int rB = min(rc * 8 + (jc >> 1), nrhs - 1), csB = jc & 1;
+
+    const int pb = chunk * W + wv;
+    const bool active = pb < npb;               // wave-uniform
+    Lane1 L;
+    const int kp = pb * 64 + lane;
+    const bool valid = active && kp < npairs;
+    L.z = valid ? rz[kp] : 0.0;
+    seed_lambda_m(valid ? rs[kp] : 1.0, m, seedc[m], L.l1, L.sc);
+    L.l2 = 0.0;
+    // B operands [c][parity]: ring pairs 32 c + 8 kg + e of this block, column jc
+    uint4 bh[2][2], bl[2][2];
+    {
+        const double *Gr = reinterpret_cast<const double *>(G + (long long)rB * fstride);
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            float ev[8], od[8];
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const int p = pb * 64 + 32 * c + 8 * kg + e;
+                double gn = 0.0, gs = 0.0;
+                if (active && p < npairs) {
+                    const int north = p, south = nrings - 1 - p;
+                    gn = Gr[((long long)north * ld + m) * 2 + csB];
+                    if (south != north) gs = Gr[((long long)south * ld + m) * 2 + csB];
+                }
+                ev[e] = (float)(gn + gs);
+                od[e] = (float)(gn - gs);
+            }
+            split2(ev[0], ev[1], bh[c][0].x, bl[c][0].x);
+            split2(ev[2], ev[3], bh[c][0].y, bl[c][0].y);
+            split2(ev[4], ev[5], bh[c][0].z, bl[c][0].z);
+            split2(ev[6], ev[7], bh[c][0].w, bl[c][0].w);
+            split2(od[0], od[1], bh[c][1].x, bl[c][1].x);
+            split2(od[2], od[3], bh[c][1].y, bl[c][1].y);
+            split2(od[4], od[5], bh[c][1].z, bl[c][1].z);
+            split2(od[6], od[7], bh[c][1].w, bl[c][1].w);
+        }
+    }
+    int mode = active ? wave_mode1(L) : 0;
+    const int ntile = (nl + 31) / 32;
+    for (int t = 0; t < ntile; t++) {
+        __syncthreads();
+        if (threadIdx.x < kChunkM) {
+            const int l = m + t * 32 + threadIdx.x;
+            sab[threadIdx.x] = (l + 1 <= lmax) ? abm[l + 1] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        f4b D[2][2];
+#pragma unroll
+        for (int p = 0; p < 2; p++) D[p][0] = D[p][1] = (f4b){0.f, 0.f, 0.f, 0.f};
+        if (mode == 0) {
+            if (active) {
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+#pragma unroll
+                    for (int s = 0; s < 4; s++) L.step(sab[4 * q + s]);
+                    L.check_range();
+                }
+                mode = wave_mode1(L);
+            }
+        } else {
+            // steps 2 i (even l - m, row i) and 2 i + 1 (odd, row 16 + i)
+            if (mode == 1) {
+#pragma unroll 4
+                for (int i = 0; i < 16; i++) {
+                    const float fe = (float)L.w();
+                    L.step_rescale(sab[2 * i]);
+                    const float fo = (float)L.w();
+                    L.step_rescale(sab[2 * i + 1]);
+                    unsigned h, l;
+                    split2(fe, fo, h, l);
+                    lamh[i * RW + lane] = (unsigned short)h;
+                    lamh[(16 + i) * RW + lane] = (unsigned short)(h >> 16);
+                    laml[i * RW + lane] = (unsigned short)l;
+                    laml[(16 + i) * RW + lane] = (unsigned short)(l >> 16);
+                }
+                mode = wave_mode1(L);
+            } else {
+#pragma unroll 8
+                for (int i = 0; i < 16; i++) {
+                    const float fe = (float)L.l1;
+                    double2 c = sab[2 * i];
+                    double nv = fma(c.x, L.z * L.l1, -c.y * L.l2);
+                    L.l2 = L.l1;
+                    L.l1 = nv;
+                    const float fo = (float)L.l1;
+                    c = sab[2 * i + 1];
+                    nv = fma(c.x, L.z * L.l1, -c.y * L.l2);
+                    L.l2 = L.l1;
+                    L.l1 = nv;
+                    unsigned h, l;
+                    split2(fe, fo, h, l);
+                    lamh[i * RW + lane] = (unsigned short)h;
+                    lamh[(16 + i) * RW + lane] = (unsigned short)(h >> 16);
+                    laml[i * RW + lane] = (unsigned short)l;
+                    laml[(16 + i) * RW + lane] = (unsigned short)(l >> 16);
+                }
+            }
+            __builtin_amdgcn_s_waitcnt(0xc07f);     // this wave's LDS writes landed
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int p = 0; p < 2; p++)
+#pragma unroll
+                for (int c = 0; c < 2; c++) {
+                    const int off = (16 * p + jc) * RW + 32 * c + 8 * kg;
+                    const uint4 ah = *reinterpret_cast<const uint4 *>(lamh + off);
+                    const uint4 al = *reinterpret_cast<const uint4 *>(laml + off);
+                    D[p][c] = mma_b3(ah, bh[c][p], D[p][c]);
+                    D[p][c] = mma_b3(ah, bl[c][p], D[p][c]);
+                    D[p][c] = mma_b3(al, bh[c][p], D[p][c]);
+                }
+        }
+        // the wave's tile (32 l x 16 columns) into its own LDS area
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int i = 4 * kg + v;
+            tile[(2 * i) * 16 + jc] = D[0][0][v] + D[0][1][v];
+            tile[(2 * i + 1) * 16 + jc] = D[1][0][v] + D[1][1][v];
+        }
+        __syncthreads();
+        // sum the W tiles; one store per output
+        const int lb0 = t * 32;
+        for (int o = threadIdx.x; o < 512; o += 64 * W) {
+            const int lr = o >> 4;
+            if (m + lb0 + lr > lmax) continue;
+            double a = 0.0;
+#pragma unroll
+            for (int w = 0; w < W; w++)
+                a += (double)reinterpret_cast<const float *>(lam_all + w * LSB)[o];
+            Pm[(long long)(lb0 + lr) * 16 + (o & 15)] = a;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+int launch_pack_b3(int lmax, int nrhs, const double *x, const double *dl, void *U, hipStream_t s) {
+    const int nrc = (nrhs + 7) / 8;
+    hipLaunchKernelGGL(k_pack_b3, dim3(lmax + 1, nrc), dim3(256), 0, s, x, dl, (uint4 *)U, lmax,
+                       nrhs);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_legendre_synth_b3(const LegendreArgs &a, const void *U, double2 *F) {
+    const mlcr_geom *g = a.g;
+    const int npb = (g->npairs + 63) / 64;
+    const int nrc = (a.nrhs + 7) / 8;
+    const long long total = mitems(a.lmax, npb, nrc);
+    const long long grid = ((total + 7) / 8) * 8;
+    const long long fstride = (long long)g->nrings * (a.lmax + 1);
+    hipLaunchKernelGGL(k_lsynth_b3, dim3((unsigned)grid), dim3(64), 0, a.stream,
+                       (const uint4 *)U, a.nrhs, F, fstride, a.lmax, g->ring_z.as<double>(),
+                       g->ring_s.as<double>(), g->ab.as<double2>(), g->aboff.as<long long>(),
+                       g->seed.as<double>(), g->nrings, g->npairs, npb, total);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+template <int W>
+static int launch_ladj_b3_w(const LegendreArgs &a, const double2 *G, double *P, int nchunks) {
+    const mlcr_geom *g = a.g;
+    const int npb = (g->npairs + 63) / 64;
+    const int nrc = (a.nrhs + 7) / 8;
+    const long long total = mitems(a.lmax, nchunks, nrc);
+    const long long grid = ((total + 7) / 8) * 8;
+    const long long fstride = (long long)g->nrings * (a.lmax + 1);
+    const size_t lds = kChunkM * sizeof(double2) + (size_t)W * (2 * 32 * 72 * 2);
+    int rc = ensure_dynamic_lds((const void *)k_ladj_b3<W>, lds);
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_ladj_b3<W>), dim3((unsigned)grid), dim3(64 * W), lds, a.stream, G,
+                       fstride, a.nrhs, P, a.lmax, g->ring_z.as<double>(), g->ring_s.as<double>(),
+                       g->ab.as<double2>(), g->aboff.as<long long>(), g->seed.as<double>(),
+                       g->nrings, g->npairs, npb, nchunks, total);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+// Same split-K chunking and P layout as the float32 adjoint (adjoint_chunks_mfma).
+int launch_legendre_adjoint_b3(const LegendreArgs &a, const double2 *G, double *P,
+                               int *nchunks_out) {
+    const int npb = (a.g->npairs + 63) / 64;
+    const int nchunks = adjoint_chunks_mfma(a.g, a.lmax);
+    const int W = (npb + nchunks - 1) / nchunks;
+    int rc;
+    if (W > 4) rc = launch_ladj_b3_w<8>(a, G, P, nchunks);
+    else if (W > 2) rc = launch_ladj_b3_w<4>(a, G, P, nchunks);
+    else if (W > 1) rc = launch_ladj_b3_w<2>(a, G, P, nchunks);
+    else rc = launch_ladj_b3_w<1>(a, G, P, nchunks);
+    if (rc) return rc;
+    *nchunks_out = nchunks;
+    return MLCR_OK;
+}
+
+}  // namespace mlcr

@@ -150,6 +150,13 @@ int launch_legendre_synth_mfma(const LegendreArgs &a, const void *U, double2 *F,
 int launch_legendre_adjoint_mfma(const LegendreArgs &a, const double2 *G, double *P,
                                  int *nchunks_out, bool dbl);
 int adjoint_chunks_mfma(const mlcr_geom *g, int lmax);
+// split-bfloat16 matrix-core Legendre kernels (legendre_b3.hip): U in blocks
+// of 16 l-steps per order, hi/lo bf16 planes; P as for the float32 adjoint.
+long long b3_u_bytes(int lmax, int nrhs);
+int launch_pack_b3(int lmax, int nrhs, const double *x, const double *dl, void *U, hipStream_t s);
+int launch_legendre_synth_b3(const LegendreArgs &a, const void *U, double2 *F);
+int launch_legendre_adjoint_b3(const LegendreArgs &a, const double2 *G, double *P,
+                               int *nchunks_out);
 // T layout ([RHS chunk][m][l - m][RC][cos, sin]) of the Legendre kernels
 int synth_rc(int nrhs);
 int adj_rc(int nrhs);

@@ -780,7 +780,8 @@ int wcycle_solve(mlcr_solver *S, int nrhs, const double *b, double *x, double rt
     if (nrhs < 1 || nrhs > S->max_nrhs) return fail(MLCR_EINVAL, "nrhs out of [1, max_nrhs]");
     if (max_cycles < 1) return fail(MLCR_EINVAL, "max_cycles must be >= 1");
     if (!(rtol >= 0.0)) return fail(MLCR_EINVAL, "rtol must be >= 0");
-    if (prec != MLCR_FP64 && prec != MLCR_FP32) return fail(MLCR_EINVAL, "unknown precision");
+    if (prec != MLCR_FP64 && prec != MLCR_FP32 && prec != MLCR_BF16X3)
+        return fail(MLCR_EINVAL, "unknown precision");
     hipStream_t s = (hipStream_t)stream;
     mlcr_op *op = S->op;
     const int lmax = op->lmax;

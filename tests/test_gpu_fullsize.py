@@ -29,6 +29,7 @@ pytestmark = pytest.mark.gpu
 R = 8
 TOL = 1e-12
 TOL32 = 2e-5          # float32 contraction: ~2^-24 sqrt(lmax) relative
+TOLB3 = 1e-4          # split-bfloat16 contraction: 3 * 2^-18 per product, 9x margin
 
 
 @pytest.fixture(scope="module")
@@ -59,7 +60,7 @@ def test_c5_synthesis_sampled_rings(mlcr, c5):
     ref = osht.synth_rings(x, cfg.lmax, cfg.nside, rings)
     # the relative 2-norm bar applies to the sampled output as a whole; a
     # single ring near a pole holds only a few pixels, so it gets 4x slack
-    for prec, tol in [(mlcr.FP64, TOL), (mlcr.FP32, TOL32)]:
+    for prec, tol in [(mlcr.FP64, TOL), (mlcr.FP32, TOL32), (mlcr.BF16X3, TOLB3)]:
         f = mlcr.sht_synth(g, dev(x), prec=prec)
         got = {k: host(f[:, geo.start[k]: geo.start[k] + geo.nphi[k]]) for k in rings}
         del f
@@ -78,7 +79,7 @@ def test_c5_adjoint_sampled_orders(mlcr, c5):
     y = np.random.default_rng(77).standard_normal((R, cfg.npix))
     orders = [0, 1, 2048, 4096]
     ref = osht.adjoint_orders(y, cfg.lmax, cfg.nside, orders)
-    for prec, tol in [(mlcr.FP64, TOL), (mlcr.FP32, TOL32)]:
+    for prec, tol in [(mlcr.FP64, TOL), (mlcr.FP32, TOL32), (mlcr.BF16X3, TOLB3)]:
         a = mlcr.sht_adjoint(g, dev(y), prec=prec)
         got, want = [], []
         for m in orders:
@@ -126,9 +127,13 @@ def test_c5_apply_properties(mlcr, c5):
     # float32 contraction within its rounding bound of the float64 path
     Au32 = mlcr.apply_A(op, u, prec=mlcr.FP32)
     assert float((Au32 - Au).norm() / Au.norm()) <= TOL32
+    Aub3 = mlcr.apply_A(op, u, prec=mlcr.BF16X3)
+    print(f"apply rel vs float64: fp32 {float((Au32 - Au).norm() / Au.norm()):.2e}, "
+          f"bf16x3 {float((Aub3 - Au).norm() / Au.norm()):.2e}", flush=True)
+    assert float((Aub3 - Au).norm() / Au.norm()) <= TOLB3
 
 
-@pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec_name", ["fp64", "fp32", "bf16x3"])
 def test_c3_solve_to_1e3_uK(mlcr, prec_name):
     """W-cycles reach 1e-3 uK max pixel error on a manufactured solution at
     N_side 1024 / lmax 2048; fp32 runs the cycle's transforms in float32 with
@@ -136,7 +141,7 @@ def test_c3_solve_to_1e3_uK(mlcr, prec_name):
     cfg = workloads.get_config("c3")
     d = workloads.workload_inputs(cfg)
     print(f"case c3 solve {prec_name}", flush=True)
-    prec = mlcr.FP64 if prec_name == "fp64" else mlcr.FP32
+    prec = {"fp64": mlcr.FP64, "fp32": mlcr.FP32, "bf16x3": mlcr.BF16X3}[prec_name]
     g = mlcr.Geometry(cfg.nside, cfg.lmax)
     op = mlcr.Operator(g, d["cl"], d["bl"], dev(d["ninv"]), max_nrhs=1)
     S = mlcr.Solver(op, max_nrhs=1)

@@ -165,3 +165,37 @@ def test_fp32_apply_parity(mlcr):
     y = host(mlcr.apply_A(op, dev(x), prec=mlcr.FP32))
     yr = oop.apply_A(x, d["cl"], d["bl"], d["ninv"], cfg.nside)
     assert rel2(y, yr) <= TOL32, rel2(y, yr)
+
+
+# Split-bfloat16 contraction: each float32 operand is carried as hi + lo
+# bfloat16 to 2^-18 relative and the dropped lo*lo term is below 2^-18 of the
+# product, so a product is good to 3 * 2^-18 = 1.1e-5; sums of terms of
+# random sign keep that relative 2-norm error.  The bar is 9x that.
+TOLB3 = 1e-4
+
+
+@pytest.mark.parametrize("nside,lmax,nrhs", [(1, 3, 1), (4, 12, 1), (16, 32, 3), (32, 100, 8),
+                                             (64, 128, 9), (256, 512, 2), (64, 255, 17)])
+def test_bf16x3_synth_adjoint_parity(mlcr, nside, lmax, nrhs):
+    print(f"case bf16x3 nside={nside} lmax={lmax} nrhs={nrhs}", flush=True)
+    g = mlcr.Geometry(nside, lmax)
+    rng = np.random.default_rng(700 + lmax)
+    x = rng.standard_normal((nrhs, osht.nalm(lmax)))
+    y = rng.standard_normal((nrhs, 12 * nside * nside))
+    f = host(mlcr.sht_synth(g, dev(x), prec=mlcr.BF16X3))
+    a = host(mlcr.sht_adjoint(g, dev(y), prec=mlcr.BF16X3))
+    ef, ea = rel2(f, osht.synth(x, lmax, nside)), rel2(a, osht.adjoint(y, lmax, nside))
+    print(f"bf16x3 synth rel {ef:.2e} adjoint rel {ea:.2e}", flush=True)
+    assert ef <= TOLB3 and ea <= TOLB3, (ef, ea)
+
+
+def test_bf16x3_apply_parity(mlcr):
+    cfg = workloads.get_config("c2")
+    d = workloads.workload_inputs(cfg)
+    g = mlcr.Geometry(cfg.nside, cfg.lmax)
+    op = mlcr.Operator(g, d["cl"], d["bl"], dev(d["ninv"]), max_nrhs=1)
+    x = workloads.prior_sample(cfg, 0)[None, :]
+    y = host(mlcr.apply_A(op, dev(x), prec=mlcr.BF16X3))
+    yr = oop.apply_A(x, d["cl"], d["bl"], d["ninv"], cfg.nside)
+    print(f"bf16x3 apply rel {rel2(y, yr):.2e}", flush=True)
+    assert rel2(y, yr) <= TOLB3, rel2(y, yr)

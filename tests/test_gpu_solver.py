@@ -67,12 +67,13 @@ def test_top_diagonal_parity(mlcr):
     assert rel2(got, ref) <= 1e-12, rel2(got, ref)
 
 
-@pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec_name", ["fp64", "fp32", "bf16x3"])
 def test_c2_wcycle_manufactured(mlcr, prec_name):
-    """fp32: the cycle's transforms in float32 (matrix cores), residual and
-    update in float64 -- iterative refinement to the same bar."""
+    """fp32 / bf16x3: the cycle's transforms with that contraction (matrix
+    cores), residual and update in float64 -- iterative refinement to the
+    same bar."""
     print(f"case c2 w-cycle manufactured {prec_name}", flush=True)
-    prec = mlcr.FP64 if prec_name == "fp64" else mlcr.FP32
+    prec = {"fp64": mlcr.FP64, "fp32": mlcr.FP32, "bf16x3": mlcr.BF16X3}[prec_name]
     cfg, d, g, ninv, op = _problem(mlcr, "c2")
     S = mlcr.Solver(op, max_nrhs=1)
     xt = workloads.prior_sample(cfg, 0)
