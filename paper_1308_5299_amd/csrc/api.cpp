@@ -61,6 +61,12 @@ static void release_geom(mlcr_geom *g) {
     DevBuf *bufs[] = {&g->ring_z, &g->ring_s, &g->ring_w, &g->rings, &g->lens, &g->order, &g->T, &g->Bf,
                       &g->W, &g->ab, &g->aboff, &g->seed, &g->zeros, &g->wsF, &g->wsP, &g->wsU};
     for (DevBuf *b : bufs) b->release();
+    for (SegTable &t : g->seg) {
+        t.st.release();
+        t.sc.release();
+        t.ls.release();
+    }
+    g->seg.clear();
 }
 
 // Pixel kernels read maps and N^-1 ring by ring as 16-byte pairs.
@@ -78,7 +84,7 @@ static int reserve_ws(mlcr_geom *g, int lmax, int nrhs) {
     const size_t ubytes =
         std::max({(size_t)tlayout_doubles(lmax, nrhs, synth_rc(nrhs)) * sizeof(double),
                   (size_t)tlayout_m_elems(lmax, nrhs) * sizeof(double),
-                  (size_t)b3_u_bytes(lmax, nrhs)});
+                  (size_t)b3_u_bytes(lmax, nrhs), (size_t)seg_u_bytes(lmax, nrhs, MLCR_FP64)});
     if (g->wsF.reserve(fbytes)) return fail(MLCR_ENOMEM, "workspace allocation failed (F)");
     if (g->wsP.reserve(pbytes)) return fail(MLCR_ENOMEM, "workspace allocation failed (P)");
     if (g->wsU.reserve(ubytes)) return fail(MLCR_ENOMEM, "workspace allocation failed (U)");
@@ -152,24 +158,16 @@ static bool use_mfma(int prec, int nrhs) {
 static int legendre_synth_any(const LegendreArgs &a, const double *x, const double *dl, mlcr_geom *g,
                               double2 *F, int prec) {
     int rc;
-    if (prec == MLCR_BF16X3) {
-        void *U = g->wsU.ptr;
-        {
-            KTimer t("pack", a.stream);
-            if ((rc = launch_pack_b3(a.lmax, a.nrhs, x, dl, U, a.stream))) return rc;
-        }
-        KTimer t("legendre_synth", a.stream);
-        return launch_legendre_synth_b3(a, U, F);
-    }
     if (use_mfma(prec, a.nrhs)) {
-        const bool dbl = prec == MLCR_FP64;
+        const SegTable *st = nullptr;
+        if ((rc = seg_table(g, a.lmax, a.stream, &st))) return rc;
         void *U = g->wsU.ptr;
         {
             KTimer t("pack", a.stream);
-            if ((rc = launch_pack_tm(a.lmax, a.nrhs, x, dl, U, dbl, a.stream))) return rc;
+            if ((rc = launch_pack_seg(a.lmax, a.nrhs, x, dl, U, prec, a.stream))) return rc;
         }
         KTimer t("legendre_synth", a.stream);
-        return launch_legendre_synth_mfma(a, U, F, dbl);
+        return launch_legendre_synth_seg(a, st, U, F, prec);
     }
     double *U = g->wsU.as<double>();
     {

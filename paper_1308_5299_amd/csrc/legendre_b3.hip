@@ -22,34 +22,6 @@
 
 namespace mlcr {
 
-typedef float f4b __attribute__((ext_vector_type(4)));
-typedef float f2b __attribute__((ext_vector_type(2)));
-typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-
-// hi/lo bfloat16 pair of two float32 numbers a (low half) and b (high half)
-__device__ __forceinline__ void split2(float a, float b, unsigned &h, unsigned &l) {
-    h = __builtin_bit_cast(unsigned, __builtin_convertvector((f2b){a, b}, bf2));
-    const float ah = __uint_as_float(h << 16), bh = __uint_as_float(h & 0xffff0000u);
-    l = __builtin_bit_cast(unsigned, __builtin_convertvector((f2b){a - ah, b - bh}, bf2));
-}
-
-__device__ __forceinline__ f4b mma_b3(uint4 a, uint4 b, f4b c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a),
-                                                   __builtin_bit_cast(bf8, b), c, 0, 0, 0);
-}
-
-// U layout: per RHS chunk of 8 and order m, blocks of 16 l-steps; block q of
-// order m holds [p][hl][column j][8 bf16], element e at l = m + 16 q + 2 e + p
-// (1 KiB per block).  Order m has ceil((lmax - m + 1) / 16) blocks.
-__host__ __device__ inline long long b3_ceil16_sum(long long n) {   // sum_{k=1..n} ceil(k / 16)
-    const long long q = n / 16, r = n % 16;
-    return 8 * q * (q + 1) + r * (q + 1);
-}
-__host__ __device__ inline long long b3_qoff(int m, int lmax) {
-    return b3_ceil16_sum(lmax + 1) - b3_ceil16_sum(lmax + 1 - m);
-}
-
 long long b3_u_bytes(int lmax, int nrhs) {
     return (long long)((nrhs + 7) / 8) * b3_qoff(lmax + 1, lmax) * 1024;
 }
@@ -63,6 +35,10 @@ __global__ __launch_bounds__(256) void k_pack_b3(const double *__restrict__ x,
     const int nl = lmax - m + 1, nq = (nl + 15) / 16;
     const long long ob = cos_base(m, lmax);
     uint4 *Ub = U + ((long long)rc * b3_qoff(lmax + 1, lmax) + b3_qoff(m, lmax)) * 64;
+    if (m == 0 && rc == 0) {
+        uint4 *pad = U + (long long)gridDim.y * b3_qoff(lmax + 1, lmax) * 64;
+        for (int i = threadIdx.x; i < kSegPadBlocks * 64; i += blockDim.x) pad[i] = make_uint4(0u, 0u, 0u, 0u);
+    }
     for (int t = threadIdx.x; t < nq * 16; t += blockDim.x) {
         const int q = t >> 4, j = t & 15;
         const int r = rc * 8 + (j >> 1), cs = j & 1;

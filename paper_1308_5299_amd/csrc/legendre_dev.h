@@ -112,4 +112,36 @@ __device__ __forceinline__ int wave_mode1(const Lane1 &L) {
     return 1;
 }
 
+// U layout: per RHS chunk of 8 and order m, blocks of 16 l-steps; block q of
+// order m holds [p][hl][column j][8 bf16], element e at l = m + 16 q + 2 e + p
+// (1 KiB per block).  Order m has ceil((lmax - m + 1) / 16) blocks.
+__host__ __device__ inline long long b3_ceil16_sum(long long n) {   // sum_{k=1..n} ceil(k / 16)
+    const long long q = n / 16, r = n % 16;
+    return 8 * q * (q + 1) + r * (q + 1);
+}
+__host__ __device__ inline long long b3_qoff(int m, int lmax) {
+    return b3_ceil16_sum(lmax + 1) - b3_ceil16_sum(lmax + 1 - m);
+}
+
+// zeroed blocks after the last U block of the segment-parallel synthesis
+constexpr int kSegPadBlocks = 4;
+
+// split-bfloat16 operands (v_mfma_f32_16x16x32_bf16)
+typedef float f4b __attribute__((ext_vector_type(4)));
+typedef float f2b __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// hi/lo bfloat16 pair of two float32 numbers a (low half) and b (high half)
+__device__ __forceinline__ void split2(float a, float b, unsigned &h, unsigned &l) {
+    h = __builtin_bit_cast(unsigned, __builtin_convertvector((f2b){a, b}, bf2));
+    const float ah = __uint_as_float(h << 16), bh = __uint_as_float(h & 0xffff0000u);
+    l = __builtin_bit_cast(unsigned, __builtin_convertvector((f2b){a - ah, b - bh}, bf2));
+}
+
+__device__ __forceinline__ f4b mma_b3(uint4 a, uint4 b, f4b c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a),
+                                                   __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
+
 }  // namespace mlcr

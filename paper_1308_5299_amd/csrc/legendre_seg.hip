@@ -1,0 +1,414 @@
+// Segment-parallel Legendre synthesis on the matrix cores.
+//
+// Synthesis contracts over l (Sec. 2.1 eq. sh-synthesis): for each order m,
+//     F_m[ring, c] = sum_l lambda_lm(ring) U_m[l, c].
+// On the matrix cores a lane supplies the A operand of one row (ring pair) and
+// a slice of the contraction index; here that slice is a contiguous
+// l-segment, so a lane runs the float64 recurrence (Sec. 3.2) of its ring
+// pairs over its own segment and its lambdas go straight into its A-operand
+// registers, with no exchange between lanes.  A wave covers 64 ring pairs and
+// 4 segments (kg = lane / 16) of [m + ls, lmax]: lane i + 16 kg runs 4 chains,
+// ring pairs 16 nb + i (nb = 0..3), which share the segment, the recurrence
+// coefficients and the B operand.  The recurrence state at each segment start
+// comes from a table made once per grid and band limit (k_seg_init), which
+// also records ls: below m + ls every lambda of the 64 ring pairs is below
+// 2^-112 (all lanes range-scaled) and contributes nothing, so those steps are
+// skipped.
+//
+// Contraction arithmetic: float32 (v_mfma_f32_16x16x4f32), float64
+// (v_mfma_f64_16x16x4f64) or split bfloat16 hi*hi + hi*lo + lo*hi
+// (v_mfma_f32_16x16x32_bf16); K index = segment (16x16x4) or 8 values of one
+// parity of the segment (16x16x32).
+#include <algorithm>
+#include <type_traits>
+
+#include "legendre_dev.h"
+
+namespace mlcr {
+
+typedef double d4s __attribute__((ext_vector_type(4)));
+
+constexpr int kSegP32 = 0, kSegP64 = 1, kSegPB3 = 2;
+
+// ---------------------------------------------------------------------------
+// start states: one wave per (m, 64 ring pairs) = 4 blocks of 16
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_seg_init(int lmax, const double *__restrict__ rz,
+                                                 const double *__restrict__ rs,
+                                                 const double2 *__restrict__ ab,
+                                                 const long long *__restrict__ aboff,
+                                                 const double *__restrict__ seedc, int npairs,
+                                                 int npb, int nb16, long long total,
+                                                 double2 *__restrict__ st, int *__restrict__ sc,
+                                                 int *__restrict__ lstab) {
+    int m, pb, rc;
+    bool ok;
+    decode_item_m(total, lmax, npb, m, pb, rc, ok);
+    if (!ok) return;
+    const int lane = threadIdx.x;
+    const int b16 = pb * 4 + (lane >> 4);
+    const int kp = pb * 64 + lane;
+    const bool valid = kp < npairs;
+    const double2 *abm = ab + aboff[m] - (m + 1);
+    const int nl = lmax - m + 1;
+    const int nu = (nl + 15) / 16;
+    Lane1 L;
+    L.z = valid ? rz[kp] : 0.0;
+    seed_lambda_m(valid ? rs[kp] : 1.0, m, seedc[m], L.l1, L.sc);
+    L.l2 = 0.0;
+    const double l1s = L.l1;
+    const int scs = L.sc;
+    auto unit = [&](int u) {            // 16 steps from offset 16 u, range check every 4
+#pragma unroll
+        for (int s = 0; s < 16; s++) {
+            const int l = m + 16 * u + s;
+            L.step(l + 1 <= lmax ? abm[l + 1] : make_double2(0.0, 0.0));
+            if ((s & 3) == 3) L.check_range();
+        }
+    };
+    // first unit boundary u (0..nu) at which the lane is in range; nu + 1: never
+    int eu = nu + 1;
+    for (int u = 0; u <= nu; u++) {
+        if (eu > nu && L.sc == 0) eu = u;
+        if (u == nu || __all(eu <= nu)) break;
+        unit(u);
+    }
+    int mn = eu;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mn = min(mn, __shfl_xor(mn, o));
+    // all 64 lanes range-scaled at boundary mn - 1 and at every check before it
+    const int ls = mn > nu ? 16 * nu : 16 * max(mn - 1, 0);
+    const int nlive = nl - ls;
+    const int n4 = nlive > 0 ? 16 * ((nlive + 63) / 64) : 0;
+    // states at the segment starts ls + k n4, k = 0..3
+    L.l1 = l1s;
+    L.l2 = 0.0;
+    L.sc = scs;
+    const long long tb = ((long long)m * nb16 + b16) * 64 + (lane & 15);
+    int k = 0;
+    for (int u = 0;; u++) {
+        while (k < 4 && ls + k * n4 == 16 * u) {
+            st[tb + 16 * k] = make_double2(L.l1, L.l2);
+            sc[tb + 16 * k] = L.sc;
+            k++;
+        }
+        if (k >= 4) break;
+        unit(u);
+    }
+    if ((lane & 15) == 0) lstab[(long long)m * nb16 + b16] = ls;
+}
+
+// ---------------------------------------------------------------------------
+// synthesis: one wave per (m, 64 ring pairs, 8 RHS)
+// ---------------------------------------------------------------------------
+// Lane i + 16 kg runs 4 recurrence chains, ring pairs 16 nb + i of the wave's
+// 64 (nb = 0..3), over segment kg; the 4 chains share the segment, the
+// coefficients and the B operand, and feed 4 MFMAs (one per 16 ring pairs).
+// U (per RHS chunk, order m, block q of 16 l-steps from m):
+//   float32 / float64: [j][16] values, element s at l = m + 16 q + s;
+//   split bf16: [p][hl][j][8], element e at l = m + 16 q + 2 e + p.
+template <int P>
+__global__ __launch_bounds__(64) void k_lsynth_seg(
+    const void *__restrict__ Uv, int nrhs, double2 *__restrict__ F, long long fstride, int lmax,
+    const double *__restrict__ rz, const double2 *__restrict__ ab,
+    const long long *__restrict__ aboff, const double2 *__restrict__ st,
+    const int *__restrict__ stsc, const int *__restrict__ lstab, int nrings, int npairs, int nb16,
+    int npb, long long total) {
+    typedef typename std::conditional<P == kSegP64, double, float>::type T;
+    typedef typename std::conditional<P == kSegP64, d4s, f4b>::type acc_t;
+    constexpr int NB = 4;
+    constexpr int CS = 17;                      // padded coefficient row per segment
+    __shared__ double2 sab[4 * CS];
+    int m, pb, rc;
+    bool ok;
+    decode_item_m(total, lmax, npb, m, pb, rc, ok);
+    if (!ok) return;
+    const int lane = threadIdx.x, kg = lane >> 4, jc = lane & 15;
+    const int nl = lmax - m + 1;
+    const int ls = lstab[(long long)m * nb16 + 4 * pb];
+    const int nlive = nl - ls;
+    const int n4 = nlive > 0 ? 16 * ((nlive + 63) / 64) : 0;
+    const int nt = n4 / 16;
+    // acc[nb][parity]
+    acc_t acc[NB][2];
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) acc[nb][0] = acc[nb][1] = (acc_t){0, 0, 0, 0};
+    if (nt > 0) {
+        Lane1 L[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; nb++) {
+            const int kp = pb * 64 + 16 * nb + jc;
+            L[nb].z = kp < npairs ? rz[kp] : 0.0;
+            const long long tix = ((long long)m * nb16 + 4 * pb + nb) * 64 + lane;
+            const double2 s0 = st[tix];
+            L[nb].l1 = s0.x;
+            L[nb].l2 = s0.y;
+            L[nb].sc = stsc[tix];
+        }
+        const int seg0 = ls + kg * n4;                  // this lane's segment, offset from m
+        const long long ub = (long long)rc * b3_qoff(lmax + 1, lmax) + b3_qoff(m, lmax);
+        const double2 *abm = ab + aboff[m] - (m + 1);
+        // U block of step t: seg0 / 16 + t.  Past the order's last block the
+        // reads land in the next order's blocks or in the zeroed pad after the
+        // last one; lambda is exactly 0 there (zero coefficients past lmax).
+        const int q0 = seg0 / 16;
+        auto stage = [&](int t) {
+            __syncthreads();
+            const int l = m + seg0 + 16 * t + jc;
+            sab[kg * CS + jc] = (l + 1 <= lmax) ? abm[l + 1] : make_double2(0.0, 0.0);
+            __syncthreads();
+        };
+        auto all_in_range = [&]() {
+            bool in = true;
+#pragma unroll
+            for (int nb = 0; nb < NB; nb++) in = in && L[nb].sc == 0;
+            return __all(in);
+        };
+        // lambda of chain nb at the current step (0 while range-scaled), then one step
+        auto advance = [&](Lane1 &C, double2 c, int s, auto checked) -> double {
+            double v;
+            if constexpr (decltype(checked)::value) {
+                v = C.sc == 0 ? C.l1 : 0.0;
+                C.step(c);
+                if ((s & 3) == 3) C.check_range();
+            } else {
+                v = C.l1;
+                const double nv = fma(c.x, C.z * C.l1, -c.y * C.l2);
+                C.l2 = C.l1;
+                C.l1 = nv;
+            }
+            return v;
+        };
+        if constexpr (P == kSegPB3) {
+            const uint4 *Ub = reinterpret_cast<const uint4 *>(Uv) + (ub + q0) * 64 + jc;
+            auto body = [&](int t, auto checked) {
+                uint4 bu[4];
+#pragma unroll
+                for (int ph = 0; ph < 4; ph++) bu[ph] = Ub[(long long)t * 64 + ph * 16];
+                uint4 ah[NB][2], al[NB][2];
+#pragma unroll
+                for (int d = 0; d < 4; d++) {           // steps 4 d .. 4 d + 3
+                    float f[NB][4];
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; s4++) {
+                        const int s = 4 * d + s4;
+                        const double2 c = sab[kg * CS + s];
+#pragma unroll
+                        for (int nb = 0; nb < NB; nb++) f[nb][s4] = (float)advance(L[nb], c, s, checked);
+                    }
+                    // element 2 d (step 4 d + p) and 2 d + 1 (step 4 d + 2 + p) of parity p
+#pragma unroll
+                    for (int nb = 0; nb < NB; nb++)
+#pragma unroll
+                        for (int p = 0; p < 2; p++) {
+                            unsigned h, l;
+                            split2(f[nb][p], f[nb][2 + p], h, l);
+                            reinterpret_cast<unsigned *>(&ah[nb][p])[d] = h;
+                            reinterpret_cast<unsigned *>(&al[nb][p])[d] = l;
+                        }
+                }
+#pragma unroll
+                for (int nb = 0; nb < NB; nb++) {
+                    acc[nb][0] = mma_b3(ah[nb][0], bu[0], acc[nb][0]);
+                    acc[nb][1] = mma_b3(ah[nb][1], bu[2], acc[nb][1]);
+                }
+#pragma unroll
+                for (int nb = 0; nb < NB; nb++) {
+                    acc[nb][0] = mma_b3(ah[nb][0], bu[1], acc[nb][0]);
+                    acc[nb][1] = mma_b3(ah[nb][1], bu[3], acc[nb][1]);
+                }
+#pragma unroll
+                for (int nb = 0; nb < NB; nb++) {
+                    acc[nb][0] = mma_b3(al[nb][0], bu[0], acc[nb][0]);
+                    acc[nb][1] = mma_b3(al[nb][1], bu[2], acc[nb][1]);
+                }
+            };
+            int t = 0;
+            for (; t < nt && !all_in_range(); t++) {
+                stage(t);
+                body(t, std::true_type{});
+            }
+            for (; t < nt; t++) {
+                stage(t);
+                body(t, std::false_type{});
+            }
+        } else {
+            constexpr int NV = 16 * (int)sizeof(T) / 16;     // uint4 per lane per block
+            const uint4 *Ub = reinterpret_cast<const uint4 *>(reinterpret_cast<const T *>(Uv) +
+                                                              ((ub + q0) * 16 + jc) * 16);
+            auto body = [&](int t, auto checked) {
+                uint4 raw[NV];
+#pragma unroll
+                for (int v = 0; v < NV; v++) raw[v] = Ub[(long long)t * 16 * NV + v];
+#pragma unroll
+                for (int s = 0; s < 16; s++) {
+                    const double2 c = sab[kg * CS + s];
+                    const T u = reinterpret_cast<const T *>(raw)[s];
+#pragma unroll
+                    for (int nb = 0; nb < NB; nb++) {
+                        const T a = (T)advance(L[nb], c, s, checked);
+                        if constexpr (P == kSegP64)
+                            acc[nb][s & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, u, acc[nb][s & 1], 0, 0, 0);
+                        else
+                            acc[nb][s & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, u, acc[nb][s & 1], 0, 0, 0);
+                    }
+                }
+            };
+            int t = 0;
+            for (; t < nt && !all_in_range(); t++) {
+                stage(t);
+                body(t, std::true_type{});
+            }
+            for (; t < nt; t++) {
+                stage(t);
+                body(t, std::false_type{});
+            }
+        }
+    }
+    // D[i][j] of chain nb: ring pair 64 pb + 16 nb + i, column j = jc = (rhs,
+    // cos/sin); element v of lane j + 16 kg holds row i = 4 kg + v (float32
+    // result) or kg + 4 v (float64)
+    const int r = rc * 8 + (jc >> 1), cs = jc & 1;
+    const int ld = lmax + 1;
+    if (r < nrhs) {
+        double *Fr = reinterpret_cast<double *>(F + (long long)r * fstride);
+#pragma unroll
+        for (int nb = 0; nb < NB; nb++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int i = P == kSegP64 ? kg + 4 * v : 4 * kg + v;
+                const int p = pb * 64 + 16 * nb + i;
+                if (p >= npairs) continue;
+                const double e = (double)acc[nb][0][v], o = (double)acc[nb][1][v];
+                const int north = p, south = nrings - 1 - p;
+                Fr[((long long)north * ld + m) * 2 + cs] = e + o;
+                if (south != north) Fr[((long long)south * ld + m) * 2 + cs] = e - o;
+            }
+    }
+}
+
+// float32 / float64 U: one thread per (block q, column j), 16 consecutive l
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack_seg(const double *__restrict__ x,
+                                                  const double *__restrict__ dl,
+                                                  T *__restrict__ U, int lmax, int nrhs) {
+    const int m = blockIdx.x, rc = blockIdx.y;
+    const long long nalm = (long long)(lmax + 1) * (lmax + 1);
+    const int nl = lmax - m + 1, nq = (nl + 15) / 16;
+    const long long ob = cos_base(m, lmax);
+    T *Ub = U + ((long long)rc * b3_qoff(lmax + 1, lmax) + b3_qoff(m, lmax)) * 256;
+    if (m == 0 && rc == 0) {
+        T *pad = U + (long long)gridDim.y * b3_qoff(lmax + 1, lmax) * 256;
+        for (int i = threadIdx.x; i < kSegPadBlocks * 256; i += blockDim.x) pad[i] = (T)0;
+    }
+    for (int t = threadIdx.x; t < nq * 16; t += blockDim.x) {
+        const int q = t >> 4, j = t & 15;
+        const int r = rc * 8 + (j >> 1), cs = j & 1;
+        const bool live = r < nrhs && !(m == 0 && cs == 1);
+        T f[16];
+#pragma unroll
+        for (int s = 0; s < 16; s++) {
+            const int lo = 16 * q + s;
+            double v = 0.0;
+            if (live && lo < nl) {
+                v = x[(long long)r * nalm + ob + (long long)cs * nl + lo];
+                if (dl) v *= dl[m + lo];
+            }
+            f[s] = (T)v;
+        }
+        uint4 *dst = reinterpret_cast<uint4 *>(Ub + ((long long)q * 16 + j) * 16);
+        constexpr int NV = 16 * (int)sizeof(T) / 16;
+#pragma unroll
+        for (int v = 0; v < NV; v++) dst[v] = reinterpret_cast<const uint4 *>(f)[v];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+// 4 zeroed pad blocks follow the last block (reads of the last order's
+// trailing segments).
+long long seg_u_bytes(int lmax, int nrhs, int prec) {
+    return ((long long)((nrhs + 7) / 8) * b3_qoff(lmax + 1, lmax) + kSegPadBlocks) *
+           (prec == MLCR_FP64 ? 2048 : 1024);
+}
+
+int seg_table(mlcr_geom *g, int lmax, hipStream_t s, const SegTable **out) {
+    for (const SegTable &t : g->seg)
+        if (t.lmax == lmax) {
+            *out = &t;
+            return MLCR_OK;
+        }
+    const int npb = (g->npairs + 63) / 64;
+    const int nb16 = 4 * npb;
+    const size_t n = (size_t)(lmax + 1) * nb16 * 64;
+    SegTable t;
+    t.lmax = lmax;
+    if (t.st.reserve(n * sizeof(double2)) || t.sc.reserve(n * sizeof(int)) ||
+        t.ls.reserve((size_t)(lmax + 1) * nb16 * sizeof(int))) {
+        t.st.release();
+        t.sc.release();
+        t.ls.release();
+        return fail(MLCR_ENOMEM, "segment start-state table allocation failed");
+    }
+    const long long total = mitems(lmax, npb, 1);
+    const long long grid = ((total + 7) / 8) * 8;
+    hipLaunchKernelGGL(k_seg_init, dim3((unsigned)grid), dim3(64), 0, s, lmax, g->ring_z.as<double>(),
+                       g->ring_s.as<double>(), g->ab.as<double2>(), g->aboff.as<long long>(),
+                       g->seed.as<double>(), g->npairs, npb, nb16, total, t.st.as<double2>(),
+                       t.sc.as<int>(), t.ls.as<int>());
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        t.st.release();
+        t.sc.release();
+        t.ls.release();
+        return fail(MLCR_EHIP, std::string("k_seg_init: ") + hipGetErrorString(e));
+    }
+    g->seg.push_back(t);
+    *out = &g->seg.back();
+    return MLCR_OK;
+}
+
+int launch_pack_seg(int lmax, int nrhs, const double *x, const double *dl, void *U, int prec,
+                    hipStream_t s) {
+    const int nrc = (nrhs + 7) / 8;
+    if (prec == MLCR_BF16X3) return launch_pack_b3(lmax, nrhs, x, dl, U, s);
+    if (prec == MLCR_FP64)
+        hipLaunchKernelGGL(k_pack_seg<double>, dim3(lmax + 1, nrc), dim3(256), 0, s, x, dl,
+                           (double *)U, lmax, nrhs);
+    else
+        hipLaunchKernelGGL(k_pack_seg<float>, dim3(lmax + 1, nrc), dim3(256), 0, s, x, dl,
+                           (float *)U, lmax, nrhs);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_legendre_synth_seg(const LegendreArgs &a, const SegTable *t, const void *U, double2 *F,
+                              int prec) {
+    const mlcr_geom *g = a.g;
+    if (t->lmax != a.lmax) return fail(MLCR_EINVAL, "segment table of another band limit");
+    const int nb16 = 4 * ((g->npairs + 63) / 64);
+    const int npb = (g->npairs + 63) / 64;
+    const int nrc = (a.nrhs + 7) / 8;
+    const long long total = mitems(a.lmax, npb, nrc);
+    const long long grid = ((total + 7) / 8) * 8;
+    const long long fstride = (long long)g->nrings * (a.lmax + 1);
+#define MLCR_SEG_ARGS                                                                           \
+    U, a.nrhs, F, fstride, a.lmax, g->ring_z.as<double>(), g->ab.as<double2>(),                 \
+        g->aboff.as<long long>(), t->st.as<double2>(), t->sc.as<int>(), t->ls.as<int>(),         \
+        g->nrings, g->npairs, nb16, npb, total
+    if (prec == MLCR_BF16X3)
+        hipLaunchKernelGGL(k_lsynth_seg<kSegPB3>, dim3((unsigned)grid), dim3(64), 0, a.stream,
+                           MLCR_SEG_ARGS);
+    else if (prec == MLCR_FP64)
+        hipLaunchKernelGGL(k_lsynth_seg<kSegP64>, dim3((unsigned)grid), dim3(64), 0, a.stream,
+                           MLCR_SEG_ARGS);
+    else
+        hipLaunchKernelGGL(k_lsynth_seg<kSegP32>, dim3((unsigned)grid), dim3(64), 0, a.stream,
+                           MLCR_SEG_ARGS);
+#undef MLCR_SEG_ARGS
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+}  // namespace mlcr

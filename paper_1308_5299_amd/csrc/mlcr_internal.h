@@ -64,6 +64,18 @@ struct RingGroup {
     int off, count, mmax;
 };
 
+// Start states of the segment-parallel synthesis at one band limit: per
+// order m and block of 16 ring pairs, the offset ls (from m, a multiple of 16)
+// below which every lambda of the block is negligible, and for each of the 4
+// l-segments of [m + ls, lmax] the recurrence state (l1, l2, scale count) of
+// each ring pair at the segment start.
+struct SegTable {
+    int lmax = -1;
+    DevBuf st;          // double2 [(lmax+1) * nb16 * 64]
+    DevBuf sc;          // int     [(lmax+1) * nb16 * 64]
+    DevBuf ls;          // int     [(lmax+1) * nb16]
+};
+
 }  // namespace mlcr
 
 struct mlcr_geom {
@@ -93,6 +105,7 @@ struct mlcr_geom {
     mlcr::DevBuf wsF;                   // ring-major Fourier coefficients
     mlcr::DevBuf wsP;                   // partial adjoint sums
     mlcr::DevBuf wsU;                   // beam-weighted input
+    std::vector<mlcr::SegTable> seg;    // synthesis start states, one per band limit used
 };
 
 struct mlcr_level {
@@ -153,6 +166,13 @@ int adjoint_chunks_mfma(const mlcr_geom *g, int lmax);
 // split-bfloat16 matrix-core Legendre kernels (legendre_b3.hip): U in blocks
 // of 16 l-steps per order, hi/lo bf16 planes; P as for the float32 adjoint.
 long long b3_u_bytes(int lmax, int nrhs);
+// segment-parallel synthesis (legendre_seg.hip); prec: MLCR_FP32 / FP64 / BF16X3
+long long seg_u_bytes(int lmax, int nrhs, int prec);
+int seg_table(mlcr_geom *g, int lmax, hipStream_t s, const SegTable **out);
+int launch_pack_seg(int lmax, int nrhs, const double *x, const double *dl, void *U, int prec,
+                    hipStream_t s);
+int launch_legendre_synth_seg(const LegendreArgs &a, const SegTable *t, const void *U, double2 *F,
+                              int prec);
 int launch_pack_b3(int lmax, int nrhs, const double *x, const double *dl, void *U, hipStream_t s);
 int launch_legendre_synth_b3(const LegendreArgs &a, const void *U, double2 *F);
 int launch_legendre_adjoint_b3(const LegendreArgs &a, const double2 *G, double *P,
