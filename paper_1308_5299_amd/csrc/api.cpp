@@ -82,9 +82,8 @@ static int reserve_ws(mlcr_geom *g, int lmax, int nrhs) {
                  (size_t)adjoint_chunks_mfma(g, lmax) * tlayout_doubles(lmax, nrhs, 8)) *
         sizeof(double);
     const size_t ubytes =
-        std::max({(size_t)tlayout_doubles(lmax, nrhs, synth_rc(nrhs)) * sizeof(double),
-                  (size_t)tlayout_m_elems(lmax, nrhs) * sizeof(double),
-                  (size_t)b3_u_bytes(lmax, nrhs), (size_t)seg_u_bytes(lmax, nrhs, MLCR_FP64)});
+        std::max((size_t)tlayout_doubles(lmax, nrhs, synth_rc(nrhs)) * sizeof(double),
+                 (size_t)seg_u_bytes(lmax, nrhs, MLCR_FP64));
     if (g->wsF.reserve(fbytes)) return fail(MLCR_ENOMEM, "workspace allocation failed (F)");
     if (g->wsP.reserve(pbytes)) return fail(MLCR_ENOMEM, "workspace allocation failed (P)");
     if (g->wsU.reserve(ubytes)) return fail(MLCR_ENOMEM, "workspace allocation failed (U)");

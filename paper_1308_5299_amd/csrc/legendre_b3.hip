@@ -1,7 +1,7 @@
-// Legendre step with split-bfloat16 products on the matrix cores.
+// Legendre adjoint with split-bfloat16 products on the matrix cores.
 //
-// The same per-order GEMMs as legendre_mfma.hip (Sec. 2.1 eq. sh-synthesis
-// and its transpose, lambda_lm by the recurrence of Sec. 3.2), but each
+// The same per-order GEMMs as the adjoint of legendre_mfma.hip (transpose of
+// Sec. 2.1 eq. sh-synthesis, lambda_lm by the recurrence of Sec. 3.2), but each
 // float32 operand f is carried as two bfloat16 numbers, hi = bf16(f) and
 // lo = bf16(f - hi), and a product as hi*hi + hi*lo + lo*hi, three
 // v_mfma_f32_16x16x32_bf16 with float32 accumulation.  |f - hi - lo| is at
@@ -21,178 +21,6 @@
 #include "legendre_dev.h"
 
 namespace mlcr {
-
-long long b3_u_bytes(int lmax, int nrhs) {
-    return (long long)((nrhs + 7) / 8) * b3_qoff(lmax + 1, lmax) * 1024;
-}
-
-// One thread per (block q, column j): 16 consecutive l of one RHS component.
-__global__ __launch_bounds__(256) void k_pack_b3(const double *__restrict__ x,
-                                                 const double *__restrict__ dl,
-                                                 uint4 *__restrict__ U, int lmax, int nrhs) {
-    const int m = blockIdx.x, rc = blockIdx.y;
-    const long long nalm = (long long)(lmax + 1) * (lmax + 1);
-    const int nl = lmax - m + 1, nq = (nl + 15) / 16;
-    const long long ob = cos_base(m, lmax);
-    uint4 *Ub = U + ((long long)rc * b3_qoff(lmax + 1, lmax) + b3_qoff(m, lmax)) * 64;
-    if (m == 0 && rc == 0) {
-        uint4 *pad = U + (long long)gridDim.y * b3_qoff(lmax + 1, lmax) * 64;
-        for (int i = threadIdx.x; i < kSegPadBlocks * 64; i += blockDim.x) pad[i] = make_uint4(0u, 0u, 0u, 0u);
-    }
-    for (int t = threadIdx.x; t < nq * 16; t += blockDim.x) {
-        const int q = t >> 4, j = t & 15;
-        const int r = rc * 8 + (j >> 1), cs = j & 1;
-        const bool live = r < nrhs && !(m == 0 && cs == 1);
-        float f[16];
-#pragma unroll
-        for (int s = 0; s < 16; s++) {
-            const int lo = 16 * q + s;
-            double v = 0.0;
-            if (live && lo < nl) {
-                v = x[(long long)r * nalm + ob + (long long)cs * nl + lo];
-                if (dl) v *= dl[m + lo];
-            }
-            f[s] = (float)v;
-        }
-#pragma unroll
-        for (int p = 0; p < 2; p++) {
-            uint4 h, l;
-            split2(f[p], f[2 + p], h.x, l.x);
-            split2(f[4 + p], f[6 + p], h.y, l.y);
-            split2(f[8 + p], f[10 + p], h.z, l.z);
-            split2(f[12 + p], f[14 + p], h.w, l.w);
-            Ub[(long long)q * 64 + (2 * p) * 16 + j] = h;
-            Ub[(long long)q * 64 + (2 * p + 1) * 16 + j] = l;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// synthesis: one wave per (m, 64 ring pairs, 8 RHS), groups of 64 l-steps
-// ---------------------------------------------------------------------------
-// Lane r runs the recurrence of ring pair r and writes its 64 lambdas of a
-// group, split and sorted by parity, as one row per ring; lane i + 16 kg then
-// reads the 8 values of sub-block kg of ring 16 b + i as its A operand, and
-// the B operand (the U block) comes straight from global memory.
-__global__ __launch_bounds__(64) void k_lsynth_b3(
-    const uint4 *__restrict__ U, int nrhs, double2 *__restrict__ F, long long fstride, int lmax,
-    const double *__restrict__ rz, const double *__restrict__ rs, const double2 *__restrict__ ab,
-    const long long *__restrict__ aboff, const double *__restrict__ seedc, int nrings, int npairs,
-    int npb, long long total) {
-    constexpr int RS = 5;                       // uint4 per ring row: 4 sub-blocks + 1 pad
-    __shared__ double2 sab[64];
-    __shared__ uint4 lamb[4][64 * RS];          // [2 p + hl][ring * RS + sub-block]
-    int m, pb, rc;
-    bool ok;
-    decode_item_m(total, lmax, npb, m, pb, rc, ok);
-    if (!ok) return;
-    const int lane = threadIdx.x;
-    const uint4 *Um = U + ((long long)rc * b3_qoff(lmax + 1, lmax) + b3_qoff(m, lmax)) * 64;
-    const double2 *abm = ab + aboff[m] - (m + 1);
-    const int nl = lmax - m + 1, nq = (nl + 15) / 16;
-
-    Lane1 L;
-    const int kp = pb * 64 + lane;
-    const bool valid = kp < npairs;
-    L.z = valid ? rz[kp] : 0.0;
-    seed_lambda_m(valid ? rs[kp] : 1.0, m, seedc[m], L.l1, L.sc);
-    L.l2 = 0.0;
-
-    f4b acc[4][2];
-#pragma unroll
-    for (int b = 0; b < 4; b++) acc[b][0] = acc[b][1] = (f4b){0.f, 0.f, 0.f, 0.f};
-    int mode = wave_mode1(L);
-    const int kg = lane >> 4, jc = lane & 15;
-
-    int q = 0;
-    // every lane still range-scaled: advance only, 16 steps at a time
-    while (mode == 0 && q < nq) {
-#pragma unroll
-        for (int s = 0; s < 16; s++) {
-            const int l = m + 16 * q + s;
-            L.step(l + 1 <= lmax ? abm[l + 1] : make_double2(0.0, 0.0));
-            if ((s & 3) == 3) L.check_range();
-        }
-        mode = wave_mode1(L);
-        q++;
-    }
-    for (; q < nq; q += 4) {
-        __syncthreads();
-        {
-            const int l = m + 16 * q + lane;
-            sab[lane] = (l + 1 <= lmax) ? abm[l + 1] : make_double2(0.0, 0.0);
-        }
-        uint4 bu[4];
-        {
-            const int qb = q + kg;
-#pragma unroll
-            for (int ph = 0; ph < 4; ph++)
-                bu[ph] = qb < nq ? Um[(long long)qb * 64 + ph * 16 + jc] : make_uint4(0u, 0u, 0u, 0u);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int qq = 0; qq < 4; qq++) {
-            float f[16];
-            if (mode == 1) {
-#pragma unroll
-                for (int s = 0; s < 16; s++) {
-                    f[s] = (float)L.w();
-                    L.step_rescale(sab[16 * qq + s]);
-                }
-            } else {
-#pragma unroll
-                for (int s = 0; s < 16; s++) {
-                    f[s] = (float)L.l1;
-                    const double2 c = sab[16 * qq + s];
-                    const double nv = fma(c.x, L.z * L.l1, -c.y * L.l2);
-                    L.l2 = L.l1;
-                    L.l1 = nv;
-                }
-            }
-#pragma unroll
-            for (int p = 0; p < 2; p++) {
-                uint4 h, l;
-                split2(f[p], f[2 + p], h.x, l.x);
-                split2(f[4 + p], f[6 + p], h.y, l.y);
-                split2(f[8 + p], f[10 + p], h.z, l.z);
-                split2(f[12 + p], f[14 + p], h.w, l.w);
-                lamb[2 * p][lane * RS + qq] = h;
-                lamb[2 * p + 1][lane * RS + qq] = l;
-            }
-        }
-        if (mode == 1) mode = wave_mode1(L);
-        __syncthreads();
-#pragma unroll
-        for (int b = 0; b < 4; b++) {
-            const int row = (16 * b + jc) * RS + kg;
-            const uint4 a0h = lamb[0][row], a0l = lamb[1][row];
-            const uint4 a1h = lamb[2][row], a1l = lamb[3][row];
-            acc[b][0] = mma_b3(a0h, bu[0], acc[b][0]);
-            acc[b][1] = mma_b3(a1h, bu[2], acc[b][1]);
-            acc[b][0] = mma_b3(a0h, bu[1], acc[b][0]);
-            acc[b][1] = mma_b3(a1h, bu[3], acc[b][1]);
-            acc[b][0] = mma_b3(a0l, bu[0], acc[b][0]);
-            acc[b][1] = mma_b3(a1l, bu[2], acc[b][1]);
-        }
-    }
-    // D[i][j] of block b: ring pair 16 b + 4 kg + v, column j = jc = (rhs, cos/sin)
-    const int r = rc * 8 + (jc >> 1), cs = jc & 1;
-    const int ld = lmax + 1;
-    if (r < nrhs) {
-        double *Fr = reinterpret_cast<double *>(F + (long long)r * fstride);
-#pragma unroll
-        for (int b = 0; b < 4; b++)
-#pragma unroll
-            for (int v = 0; v < 4; v++) {
-                const int p = pb * 64 + 16 * b + 4 * kg + v;
-                if (p >= npairs) continue;
-                const double e = (double)acc[b][0][v], o = (double)acc[b][1][v];
-                const int north = p, south = nrings - 1 - p;
-                Fr[((long long)north * ld + m) * 2 + cs] = e + o;
-                if (south != north) Fr[((long long)south * ld + m) * 2 + cs] = e - o;
-            }
-    }
-}
 
 // ---------------------------------------------------------------------------
 // adjoint: one workgroup of W waves per (m, chunk of W ring-pair blocks, 8 RHS)
@@ -368,29 +196,6 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-int launch_pack_b3(int lmax, int nrhs, const double *x, const double *dl, void *U, hipStream_t s) {
-    const int nrc = (nrhs + 7) / 8;
-    hipLaunchKernelGGL(k_pack_b3, dim3(lmax + 1, nrc), dim3(256), 0, s, x, dl, (uint4 *)U, lmax,
-                       nrhs);
-    MLCR_HIP_CHECK(hipGetLastError());
-    return MLCR_OK;
-}
-
-int launch_legendre_synth_b3(const LegendreArgs &a, const void *U, double2 *F) {
-    const mlcr_geom *g = a.g;
-    const int npb = (g->npairs + 63) / 64;
-    const int nrc = (a.nrhs + 7) / 8;
-    const long long total = mitems(a.lmax, npb, nrc);
-    const long long grid = ((total + 7) / 8) * 8;
-    const long long fstride = (long long)g->nrings * (a.lmax + 1);
-    hipLaunchKernelGGL(k_lsynth_b3, dim3((unsigned)grid), dim3(64), 0, a.stream,
-                       (const uint4 *)U, a.nrhs, F, fstride, a.lmax, g->ring_z.as<double>(),
-                       g->ring_s.as<double>(), g->ab.as<double2>(), g->aboff.as<long long>(),
-                       g->seed.as<double>(), g->nrings, g->npairs, npb, total);
-    MLCR_HIP_CHECK(hipGetLastError());
-    return MLCR_OK;
-}
-
 template <int W>
 static int launch_ladj_b3_w(const LegendreArgs &a, const double2 *G, double *P, int nchunks) {
     const mlcr_geom *g = a.g;

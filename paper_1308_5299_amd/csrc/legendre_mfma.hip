@@ -1,10 +1,10 @@
-// Legendre step on the matrix cores.
+// Legendre adjoint on the matrix cores.
 //
-// Same transforms as legendre.hip (Sec. 2.1 eq. sh-synthesis and its
-// transpose, lambda_lm of Sec. 3.2), written as per-order GEMMs:
-//     synthesis  F_m[ring, c] = sum_l Lambda_m[ring, l] U_m[l, c]
-//     adjoint    V_m[l, c]    = sum_ring Lambda_m[ring, l] G_m[ring, c]
-// with c = (RHS, cos/sin), 16 columns (8 right-hand sides).  The recurrence
+// The transpose of the synthesis of Sec. 2.1 (eq. sh-synthesis), lambda_lm
+// by the recurrence of Sec. 3.2, as per-order GEMMs contracting over rings:
+//     V_m[l, c] = sum_ring Lambda_m[ring, l] G_m[ring, c]
+// with c = (RHS, cos/sin), 16 columns (8 right-hand sides).  (The synthesis
+// direction is in legendre_seg.hip.)  The recurrence
 // seeds, the 2^-512 range scaling and the recurrence itself stay in
 // float64 on the vector ALUs while the matrix cores contract: each lambda is
 // staged through LDS and fed to v_mfma_f32_16x16x4f32 (T = float: float32
@@ -47,135 +47,6 @@ struct Mma<double> {
     static __device__ __forceinline__ int row(int kq, int v) { return kq + 4 * v; }
     static __device__ __forceinline__ double cvt(double v) { return v; }
 };
-
-// ---------------------------------------------------------------------------
-// synthesis: one wave per (m, 64 ring pairs, 8 RHS)
-// ---------------------------------------------------------------------------
-// U: T layout [RHS chunk][m][l - m][8][cos, sin] (16 values per l)
-template <typename T>
-__global__ __launch_bounds__(64) void k_lsynth_mfma(
-    const T *__restrict__ U, int nrhs, double2 *__restrict__ F, long long fstride, int lmax,
-    const double *__restrict__ rz, const double *__restrict__ rs, const double2 *__restrict__ ab,
-    const long long *__restrict__ aboff, const double *__restrict__ seedc, int nrings, int npairs,
-    int npb, long long total) {
-    typedef Mma<T> M;
-    __shared__ double2 sab[kChunkM];
-    constexpr int SU = 24;       // padded U row: the 4 lane groups hit distinct banks
-    constexpr int SL = 72;       // padded lambda row, likewise
-    __shared__ T su[kChunkM * SU];
-    __shared__ T lam[8][SL];
-    int m, pb, rc;
-    bool ok;
-    decode_item_m(total, lmax, npb, m, pb, rc, ok);
-    if (!ok) return;
-    const int lane = threadIdx.x;
-    const long long tri = (long long)(lmax + 1) * (lmax + 2) / 2;
-    const T *Um = U + ((long long)rc * tri + tri_off_m(m, lmax)) * 16;
-    const double2 *abm = ab + aboff[m] - (m + 1);
-    const int nl = lmax - m + 1;
-
-    Lane1 L;
-    const int kp = pb * 64 + lane;
-    const bool valid = kp < npairs;
-    L.z = valid ? rz[kp] : 0.0;
-    seed_lambda_m(valid ? rs[kp] : 1.0, m, seedc[m], L.l1, L.sc);
-    L.l2 = 0.0;
-
-    typename M::acc CE[4], CO[4];
-#pragma unroll
-    for (int b = 0; b < 4; b++) CE[b] = CO[b] = M::zero();
-    int mode = wave_mode1(L);
-    const int kq = lane >> 4, jc = lane & 15;
-
-    // 8 steps l = m + k*C + j0 + s, s = 0..7 (even s: even l - m): lambda to
-    // LDS, then 4 ring blocks x (even, odd) MFMAs
-    auto mfma_group = [&](int j0) {
-        __syncthreads();
-        const T be = su[(j0 + 2 * kq) * SU + jc];
-        const T bo = su[(j0 + 2 * kq + 1) * SU + jc];
-#pragma unroll
-        for (int b = 0; b < 4; b++) {
-            const T ae = lam[2 * kq][16 * b + jc];
-            const T ao = lam[2 * kq + 1][16 * b + jc];
-            CE[b] = M::mma(ae, be, CE[b]);
-            CO[b] = M::mma(ao, bo, CO[b]);
-        }
-        __syncthreads();
-    };
-
-    const int nchunks = (nl + kChunkM - 1) / kChunkM;
-    for (int k = 0; k < nchunks; k++) {
-        // stage the chunk's coefficients (A, B of l -> l+1; U at l)
-        __syncthreads();
-        if (lane < kChunkM) {
-            const int l = m + k * kChunkM + lane;
-            sab[lane] = (l + 1 <= lmax) ? abm[l + 1] : make_double2(0.0, 0.0);
-        }
-        {
-            const int base = k * kChunkM;
-            // 32 l x 16 values, moved in 16-byte units
-            constexpr int UPL = 16 * (int)sizeof(T) / 16;      // units per l
-            for (int q = lane; q < kChunkM * UPL; q += 64) {
-                const int jl = q / UPL, part = q % UPL;
-                const uint4 v = (base + jl < nl)
-                                    ? reinterpret_cast<const uint4 *>(Um + (long long)(base + jl) * 16)[part]
-                                    : make_uint4(0u, 0u, 0u, 0u);
-                reinterpret_cast<uint4 *>(su + jl * SU)[part] = v;
-            }
-        }
-        __syncthreads();
-        const int jend = min(kChunkM, nl - k * kChunkM);
-        int j0 = 0;
-        // every lane still range-scaled: advance only
-        for (; mode == 0 && j0 < jend; j0 += 8) {
-#pragma unroll
-            for (int s = 0; s < 8; s++) {
-                L.step(sab[j0 + s]);
-                if ((s & 3) == 3) L.check_range();
-            }
-            mode = wave_mode1(L);
-        }
-        // some lanes scaled: lambda is 0 there until they reach the range
-        for (; mode == 1 && j0 < jend; j0 += 8) {
-#pragma unroll
-            for (int s = 0; s < 8; s++) {
-                lam[s][lane] = M::cvt(L.w());
-                L.step_rescale(sab[j0 + s]);
-            }
-            mode = wave_mode1(L);
-            mfma_group(j0);
-        }
-        // steady state: plain recurrence, values in range (|lambda| <= O(1))
-        for (; j0 < jend; j0 += 8) {
-#pragma unroll
-            for (int s = 0; s < 8; s++) {
-                lam[s][lane] = M::cvt(L.l1);
-                const double2 c = sab[j0 + s];
-                const double nv = fma(c.x, L.z * L.l1, -c.y * L.l2);
-                L.l2 = L.l1;
-                L.l1 = nv;
-            }
-            mfma_group(j0);
-        }
-    }
-    // D[i][j] of block b: ring pair 16 b + 4 kq + v, column j = jc = (rhs, cos/sin)
-    const int r = rc * 8 + (jc >> 1), cs = jc & 1;
-    const int ld = lmax + 1;
-    if (r < nrhs) {
-        double *Fr = reinterpret_cast<double *>(F + (long long)r * fstride);
-#pragma unroll
-        for (int b = 0; b < 4; b++)
-#pragma unroll
-            for (int v = 0; v < 4; v++) {
-                const int p = pb * 64 + 16 * b + M::row(kq, v);
-                if (p >= npairs) continue;
-                const double e = (double)CE[b][v], o = (double)CO[b][v];
-                const int north = p, south = nrings - 1 - p;
-                Fr[((long long)north * ld + m) * 2 + cs] = e + o;
-                if (south != north) Fr[((long long)south * ld + m) * 2 + cs] = e - o;
-            }
-    }
-}
 
 // ---------------------------------------------------------------------------
 // adjoint: one workgroup of W waves per (m, chunk of W ring-pair blocks, 8 RHS)
@@ -310,83 +181,9 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
     }
 }
 
-// T layout: U[rc][tri_off(m) + l - m][8][cs] = dl[l] x[...].  One workgroup
-// per (m, RHS chunk); tiles of 64 l are read along l for each (r, cs) and
-// written as whole 16-value rows after a transpose in LDS.
-template <typename T>
-__global__ __launch_bounds__(256) void k_pack_tm(const double *__restrict__ x,
-                                                 const double *__restrict__ dl,
-                                                 T *__restrict__ U, int lmax, int nrhs) {
-    constexpr int TL = 64;
-    __shared__ T tile[TL * 17];
-    const int m = blockIdx.x, rc = blockIdx.y;
-    const long long nalm = (long long)(lmax + 1) * (lmax + 1);
-    const long long tri = (long long)(lmax + 1) * (lmax + 2) / 2;
-    const int nl = lmax - m + 1;
-    const long long ob = cos_base(m, lmax);
-    T *Ub = U + ((long long)rc * tri + tri_off_m(m, lmax)) * 16;
-    for (int base = 0; base < nl; base += TL) {
-        const int nt = min(TL, nl - base);
-        for (int e = threadIdx.x; e < 16 * TL; e += blockDim.x) {
-            const int comp = e / TL, j = e % TL;
-            const int r = rc * 8 + (comp >> 1), cs = comp & 1;
-            double v = 0.0;
-            if (j < nt && r < nrhs && !(m == 0 && cs == 1)) {
-                v = x[(long long)r * nalm + ob + (long long)cs * nl + base + j];
-                if (dl) v *= dl[m + base + j];
-            }
-            tile[j * 17 + comp] = (T)v;
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < 16 * nt; e += blockDim.x)
-            Ub[(long long)base * 16 + e] = tile[(e >> 4) * 17 + (e & 15)];
-        __syncthreads();
-    }
-}
-
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-long long tlayout_m_elems(int lmax, int nrhs) {
-    const long long tri = (long long)(lmax + 1) * (lmax + 2) / 2;
-    return (long long)((nrhs + 7) / 8) * 16 * tri;
-}
-
-int launch_pack_tm(int lmax, int nrhs, const double *x, const double *dl, void *U, bool dbl,
-                   hipStream_t s) {
-    const int nrc = (nrhs + 7) / 8;
-    if (dbl)
-        hipLaunchKernelGGL(k_pack_tm<double>, dim3(lmax + 1, nrc), dim3(256), 0, s, x, dl,
-                           (double *)U, lmax, nrhs);
-    else
-        hipLaunchKernelGGL(k_pack_tm<float>, dim3(lmax + 1, nrc), dim3(256), 0, s, x, dl,
-                           (float *)U, lmax, nrhs);
-    MLCR_HIP_CHECK(hipGetLastError());
-    return MLCR_OK;
-}
-
-int launch_legendre_synth_mfma(const LegendreArgs &a, const void *U, double2 *F, bool dbl) {
-    const mlcr_geom *g = a.g;
-    const int npb = (g->npairs + 63) / 64;
-    const int nrc = (a.nrhs + 7) / 8;
-    const long long total = mitems(a.lmax, npb, nrc);
-    const long long grid = ((total + 7) / 8) * 8;
-    const long long fstride = (long long)g->nrings * (a.lmax + 1);
-#define MLCR_SYNTH_ARGS                                                                        \
-    a.nrhs, F, fstride, a.lmax, g->ring_z.as<double>(), g->ring_s.as<double>(),                 \
-        g->ab.as<double2>(), g->aboff.as<long long>(), g->seed.as<double>(), g->nrings,         \
-        g->npairs, npb, total
-    if (dbl)
-        hipLaunchKernelGGL(k_lsynth_mfma<double>, dim3((unsigned)grid), dim3(64), 0, a.stream,
-                           (const double *)U, MLCR_SYNTH_ARGS);
-    else
-        hipLaunchKernelGGL(k_lsynth_mfma<float>, dim3((unsigned)grid), dim3(64), 0, a.stream,
-                           (const float *)U, MLCR_SYNTH_ARGS);
-#undef MLCR_SYNTH_ARGS
-    MLCR_HIP_CHECK(hipGetLastError());
-    return MLCR_OK;
-}
-
 // Waves per adjoint workgroup: one ring-pair block each, up to 8.
 static int adj_waves(int npb) { return npb >= 8 ? 8 : (npb >= 4 ? 4 : (npb >= 2 ? 2 : 1)); }
 

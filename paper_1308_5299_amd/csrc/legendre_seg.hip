@@ -287,39 +287,73 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
     }
 }
 
-// float32 / float64 U: one thread per (block q, column j), 16 consecutive l
-template <typename T>
+// U from x (and the per-l weights dl, e.g. the beam): one workgroup per
+// (m, RHS chunk); tiles of 64 l are read along l for each of the 16 columns
+// (j = 2 r + cos/sin) into LDS and written as whole 16-step blocks.
+template <int P>
 __global__ __launch_bounds__(256) void k_pack_seg(const double *__restrict__ x,
                                                   const double *__restrict__ dl,
-                                                  T *__restrict__ U, int lmax, int nrhs) {
+                                                  void *__restrict__ Uv, int lmax, int nrhs) {
+    constexpr int TL = 64;
+    __shared__ double tile[16][TL + 1];
     const int m = blockIdx.x, rc = blockIdx.y;
     const long long nalm = (long long)(lmax + 1) * (lmax + 1);
-    const int nl = lmax - m + 1, nq = (nl + 15) / 16;
+    const int nl = lmax - m + 1;
     const long long ob = cos_base(m, lmax);
-    T *Ub = U + ((long long)rc * b3_qoff(lmax + 1, lmax) + b3_qoff(m, lmax)) * 256;
-    if (m == 0 && rc == 0) {
-        T *pad = U + (long long)gridDim.y * b3_qoff(lmax + 1, lmax) * 256;
-        for (int i = threadIdx.x; i < kSegPadBlocks * 256; i += blockDim.x) pad[i] = (T)0;
+    const long long qb = (long long)rc * b3_qoff(lmax + 1, lmax) + b3_qoff(m, lmax);
+    constexpr int BU = P == kSegP64 ? 128 : 64;          // uint4 per 16-step block
+    uint4 *U = reinterpret_cast<uint4 *>(Uv);
+    if (m == 0 && rc == 0) {                             // zeroed pad after the last block
+        uint4 *pad = U + (long long)gridDim.y * b3_qoff(lmax + 1, lmax) * BU;
+        for (int i = threadIdx.x; i < kSegPadBlocks * BU; i += blockDim.x)
+            pad[i] = make_uint4(0u, 0u, 0u, 0u);
     }
-    for (int t = threadIdx.x; t < nq * 16; t += blockDim.x) {
-        const int q = t >> 4, j = t & 15;
-        const int r = rc * 8 + (j >> 1), cs = j & 1;
-        const bool live = r < nrhs && !(m == 0 && cs == 1);
-        T f[16];
-#pragma unroll
-        for (int s = 0; s < 16; s++) {
-            const int lo = 16 * q + s;
+    for (int base = 0; base < nl; base += TL) {
+        for (int e = threadIdx.x; e < 16 * TL; e += blockDim.x) {
+            const int j = e / TL, o = e % TL;
+            const int r = rc * 8 + (j >> 1), cs = j & 1;
             double v = 0.0;
-            if (live && lo < nl) {
-                v = x[(long long)r * nalm + ob + (long long)cs * nl + lo];
-                if (dl) v *= dl[m + lo];
+            if (base + o < nl && r < nrhs && !(m == 0 && cs == 1)) {
+                v = x[(long long)r * nalm + ob + (long long)cs * nl + base + o];
+                if (dl) v *= dl[m + base + o];
             }
-            f[s] = (T)v;
+            tile[j][o] = v;
         }
-        uint4 *dst = reinterpret_cast<uint4 *>(Ub + ((long long)q * 16 + j) * 16);
-        constexpr int NV = 16 * (int)sizeof(T) / 16;
-#pragma unroll
-        for (int v = 0; v < NV; v++) dst[v] = reinterpret_cast<const uint4 *>(f)[v];
+        __syncthreads();
+        const int nqt = min(TL, nl - base + 15) / 16;    // blocks of this tile
+        uint4 *Ut = U + (qb + base / 16) * BU;
+        if constexpr (P == kSegPB3) {
+            // [p][hl][j][8]: element e of parity p at step 2 e + p
+            for (int w = threadIdx.x; w < nqt * 2 * 16; w += blockDim.x) {
+                const int qq = w / 32, p = (w / 16) & 1, j = w & 15;
+                uint4 h, l;
+                const double *t = &tile[j][16 * qq + p];
+                split2((float)t[0], (float)t[2], h.x, l.x);
+                split2((float)t[4], (float)t[6], h.y, l.y);
+                split2((float)t[8], (float)t[10], h.z, l.z);
+                split2((float)t[12], (float)t[14], h.w, l.w);
+                Ut[qq * 64 + (2 * p) * 16 + j] = h;
+                Ut[qq * 64 + (2 * p + 1) * 16 + j] = l;
+            }
+        } else {
+            // [j][16]: element s at step s, 4 (float32) or 2 (float64) per uint4
+            constexpr int PER = P == kSegP64 ? 2 : 4;
+            for (int w = threadIdx.x; w < nqt * BU; w += blockDim.x) {
+                const int qq = w / BU, rem = w % BU;
+                const int j = rem / (16 / PER), s0 = (rem % (16 / PER)) * PER;
+                const double *t = &tile[j][16 * qq + s0];
+                uint4 o;
+                if constexpr (P == kSegP64) {
+                    const double2 d = make_double2(t[0], t[1]);
+                    o = *reinterpret_cast<const uint4 *>(&d);
+                } else {
+                    o = make_uint4(__float_as_uint((float)t[0]), __float_as_uint((float)t[1]),
+                                   __float_as_uint((float)t[2]), __float_as_uint((float)t[3]));
+                }
+                Ut[w] = o;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -372,13 +406,15 @@ int seg_table(mlcr_geom *g, int lmax, hipStream_t s, const SegTable **out) {
 int launch_pack_seg(int lmax, int nrhs, const double *x, const double *dl, void *U, int prec,
                     hipStream_t s) {
     const int nrc = (nrhs + 7) / 8;
-    if (prec == MLCR_BF16X3) return launch_pack_b3(lmax, nrhs, x, dl, U, s);
-    if (prec == MLCR_FP64)
-        hipLaunchKernelGGL(k_pack_seg<double>, dim3(lmax + 1, nrc), dim3(256), 0, s, x, dl,
-                           (double *)U, lmax, nrhs);
+    if (prec == MLCR_BF16X3)
+        hipLaunchKernelGGL(k_pack_seg<kSegPB3>, dim3(lmax + 1, nrc), dim3(256), 0, s, x, dl, U,
+                           lmax, nrhs);
+    else if (prec == MLCR_FP64)
+        hipLaunchKernelGGL(k_pack_seg<kSegP64>, dim3(lmax + 1, nrc), dim3(256), 0, s, x, dl, U,
+                           lmax, nrhs);
     else
-        hipLaunchKernelGGL(k_pack_seg<float>, dim3(lmax + 1, nrc), dim3(256), 0, s, x, dl,
-                           (float *)U, lmax, nrhs);
+        hipLaunchKernelGGL(k_pack_seg<kSegP32>, dim3(lmax + 1, nrc), dim3(256), 0, s, x, dl, U,
+                           lmax, nrhs);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }

@@ -154,12 +154,8 @@ int launch_ring_apply(const mlcr_geom *g, int lmax, int nrhs, double2 *FG, const
 // out[p] = W_ring(p) in[p]: a map times the grid's quadrature weights
 int launch_ring_weight(const mlcr_geom *g, const double *in, double *out, hipStream_t s);
 int adjoint_chunks(const mlcr_geom *g, int lmax);
-// matrix-core Legendre kernels, 8 RHS per wave; dbl selects float64 MFMA
-// (else float32).  U: T layout with 8 RHS per chunk, elements of that type.
-long long tlayout_m_elems(int lmax, int nrhs);
-int launch_pack_tm(int lmax, int nrhs, const double *x, const double *dl, void *U, bool dbl,
-                   hipStream_t s);
-int launch_legendre_synth_mfma(const LegendreArgs &a, const void *U, double2 *F, bool dbl);
+// matrix-core Legendre adjoint, 8 RHS per wave; dbl selects float64 MFMA
+// (else float32).
 int launch_legendre_adjoint_mfma(const LegendreArgs &a, const double2 *G, double *P,
                                  int *nchunks_out, bool dbl);
 int adjoint_chunks_mfma(const mlcr_geom *g, int lmax);
