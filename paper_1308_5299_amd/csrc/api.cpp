@@ -183,10 +183,12 @@ static int legendre_adjoint_any(const LegendreArgs &a, const double2 *G, mlcr_ge
     int rc, nch = 0;
     double *P = g->wsP.as<double>();
     const bool mm = use_mfma(prec, a.nrhs);
+    const SegTable *st = nullptr;
+    if (mm && (rc = seg_table(g, a.lmax, a.stream, &st))) return rc;
     {
         KTimer t("legendre_adjoint", a.stream);
-        if (prec == MLCR_BF16X3) rc = launch_legendre_adjoint_b3(a, G, P, &nch);
-        else if (mm) rc = launch_legendre_adjoint_mfma(a, G, P, &nch, prec == MLCR_FP64);
+        if (prec == MLCR_BF16X3) rc = launch_legendre_adjoint_b3(a, st, G, P, &nch);
+        else if (mm) rc = launch_legendre_adjoint_mfma(a, st, G, P, &nch, prec == MLCR_FP64);
         else rc = launch_legendre_adjoint(a, G, P, &nch);
         if (rc) return rc;
     }

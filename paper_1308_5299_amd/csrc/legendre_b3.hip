@@ -34,8 +34,9 @@ namespace mlcr {
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_ladj_b3(
     const double2 *__restrict__ G, long long fstride, int nrhs, double *__restrict__ P, int lmax,
-    const double *__restrict__ rz, const double *__restrict__ rs, const double2 *__restrict__ ab,
-    const long long *__restrict__ aboff, const double *__restrict__ seedc, int nrings, int npairs,
+    const double *__restrict__ rz, const double2 *__restrict__ ab,
+    const long long *__restrict__ aboff, const double2 *__restrict__ st,
+    const int *__restrict__ stsc, const int *__restrict__ lstab, int nb16, int nrings, int npairs,
     int npb, int nchunks, long long total) {
     constexpr int RW = 72;                      // bf16 per row: 64 rings + 8 pad (144 B)
     constexpr int LSB = 2 * 32 * RW * 2;        // bytes per wave: [hl][p * 16 + i][RW]
@@ -61,12 +62,21 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
 
     const int pb = chunk * W + wv;
     const bool active = pb < npb;               // wave-uniform
+    // The recurrence starts at tile tw: the 32-aligned offset (start-state
+    // table of the segment synthesis) below which every lambda of this block
+    // is negligible, with the table's state there.  Tiles below t0 (the
+    // workgroup's first) hold no contribution of any wave.
     Lane1 L;
     const int kp = pb * 64 + lane;
     const bool valid = active && kp < npairs;
     L.z = valid ? rz[kp] : 0.0;
-    seed_lambda_m(valid ? rs[kp] : 1.0, m, seedc[m], L.l1, L.sc);
-    L.l2 = 0.0;
+    L.l1 = L.l2 = 0.0;
+    L.sc = 1;
+    const int ntile = (nl + 31) / 32;
+    const int tw = active ? lstab[(long long)m * nb16 + 4 * pb] / 32 : ntile;
+    int t0 = ntile;
+    for (int w = 0; w < W; w++)
+        if (chunk * W + w < npb) t0 = min(t0, lstab[(long long)m * nb16 + 4 * (chunk * W + w)] / 32);
     // B operands [c][parity]: ring pairs 32 c + 8 kg + e of this block, column jc
     uint4 bh[2][2], bl[2][2];
     {
@@ -96,20 +106,29 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
             split2(od[6], od[7], bh[c][1].w, bl[c][1].w);
         }
     }
-    int mode = active ? wave_mode1(L) : 0;
-    const int ntile = (nl + 31) / 32;
-    for (int t = 0; t < ntile; t++) {
+    // mode -1: before tw (or no block), 0: all lanes range-scaled, 1: some, 2: none
+    int mode = -1;
+    for (int o = threadIdx.x; o < min(32 * t0, nl) * 16; o += 64 * W) Pm[o] = 0.0;
+    for (int t = t0; t < ntile; t++) {
         __syncthreads();
         if (threadIdx.x < kChunkM) {
             const int l = m + t * 32 + threadIdx.x;
             sab[threadIdx.x] = (l + 1 <= lmax) ? abm[l + 1] : make_double2(0.0, 0.0);
         }
         __syncthreads();
+        if (t == tw) {
+            const long long tix = ((long long)m * nb16 + 4 * pb + (lane >> 4)) * 64 + (lane & 15);
+            const double2 s0 = st[tix];
+            L.l1 = s0.x;
+            L.l2 = s0.y;
+            L.sc = stsc[tix];
+            mode = wave_mode1(L);
+        }
         f4b D[2][2];
 #pragma unroll
         for (int p = 0; p < 2; p++) D[p][0] = D[p][1] = (f4b){0.f, 0.f, 0.f, 0.f};
-        if (mode == 0) {
-            if (active) {
+        if (mode <= 0) {
+            if (mode == 0) {
 #pragma unroll
                 for (int q = 0; q < 8; q++) {
 #pragma unroll
@@ -197,7 +216,8 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
 // launchers
 // ---------------------------------------------------------------------------
 template <int W>
-static int launch_ladj_b3_w(const LegendreArgs &a, const double2 *G, double *P, int nchunks) {
+static int launch_ladj_b3_w(const LegendreArgs &a, const SegTable *st, const double2 *G, double *P,
+                            int nchunks) {
     const mlcr_geom *g = a.g;
     const int npb = (g->npairs + 63) / 64;
     const int nrc = (a.nrhs + 7) / 8;
@@ -208,24 +228,25 @@ static int launch_ladj_b3_w(const LegendreArgs &a, const double2 *G, double *P, 
     int rc = ensure_dynamic_lds((const void *)k_ladj_b3<W>, lds);
     if (rc) return rc;
     hipLaunchKernelGGL((k_ladj_b3<W>), dim3((unsigned)grid), dim3(64 * W), lds, a.stream, G,
-                       fstride, a.nrhs, P, a.lmax, g->ring_z.as<double>(), g->ring_s.as<double>(),
-                       g->ab.as<double2>(), g->aboff.as<long long>(), g->seed.as<double>(),
-                       g->nrings, g->npairs, npb, nchunks, total);
+                       fstride, a.nrhs, P, a.lmax, g->ring_z.as<double>(), g->ab.as<double2>(),
+                       g->aboff.as<long long>(), st->st.as<double2>(), st->sc.as<int>(),
+                       st->ls.as<int>(), 4 * npb, g->nrings, g->npairs, npb, nchunks, total);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }
 
 // Same split-K chunking and P layout as the float32 adjoint (adjoint_chunks_mfma).
-int launch_legendre_adjoint_b3(const LegendreArgs &a, const double2 *G, double *P,
-                               int *nchunks_out) {
+int launch_legendre_adjoint_b3(const LegendreArgs &a, const SegTable *st, const double2 *G,
+                               double *P, int *nchunks_out) {
+    if (st->lmax != a.lmax) return fail(MLCR_EINVAL, "start-state table of another band limit");
     const int npb = (a.g->npairs + 63) / 64;
     const int nchunks = adjoint_chunks_mfma(a.g, a.lmax);
     const int W = (npb + nchunks - 1) / nchunks;
     int rc;
-    if (W > 4) rc = launch_ladj_b3_w<8>(a, G, P, nchunks);
-    else if (W > 2) rc = launch_ladj_b3_w<4>(a, G, P, nchunks);
-    else if (W > 1) rc = launch_ladj_b3_w<2>(a, G, P, nchunks);
-    else rc = launch_ladj_b3_w<1>(a, G, P, nchunks);
+    if (W > 4) rc = launch_ladj_b3_w<8>(a, st, G, P, nchunks);
+    else if (W > 2) rc = launch_ladj_b3_w<4>(a, st, G, P, nchunks);
+    else if (W > 1) rc = launch_ladj_b3_w<2>(a, st, G, P, nchunks);
+    else rc = launch_ladj_b3_w<1>(a, st, G, P, nchunks);
     if (rc) return rc;
     *nchunks_out = nchunks;
     return MLCR_OK;

@@ -60,8 +60,9 @@ struct Mma<double> {
 template <typename T, int W>
 __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
     const double2 *__restrict__ G, long long fstride, int nrhs, double *__restrict__ P, int lmax,
-    const double *__restrict__ rz, const double *__restrict__ rs, const double2 *__restrict__ ab,
-    const long long *__restrict__ aboff, const double *__restrict__ seedc, int nrings, int npairs,
+    const double *__restrict__ rz, const double2 *__restrict__ ab,
+    const long long *__restrict__ aboff, const double2 *__restrict__ st,
+    const int *__restrict__ stsc, const int *__restrict__ lstab, int nb16, int nrings, int npairs,
     int npb, int nchunks, long long total) {
     typedef Mma<T> M;
     constexpr int SL = 66;                       // padded lambda row: operand reads hit 64 banks
@@ -86,12 +87,21 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
 
     const int pb = chunk * W + wv;
     const bool active = pb < npb;                // wave-uniform
+    // The recurrence starts at tile tw: the 32-aligned offset (start-state
+    // table of the segment synthesis) below which every lambda of this block
+    // is negligible, with the table's state there.  Tiles below t0 (the
+    // workgroup's first) hold no contribution of any wave.
     Lane1 L;
     const int kp = pb * 64 + lane;
     const bool valid = active && kp < npairs;
     L.z = valid ? rz[kp] : 0.0;
-    seed_lambda_m(valid ? rs[kp] : 1.0, m, seedc[m], L.l1, L.sc);
-    L.l2 = 0.0;
+    L.l1 = L.l2 = 0.0;
+    L.sc = 1;
+    const int ntile = (nl + 31) / 32;
+    const int tw = active ? lstab[(long long)m * nb16 + 4 * pb] / 32 : ntile;
+    int t0 = ntile;
+    for (int w = 0; w < W; w++)
+        if (chunk * W + w < npb) t0 = min(t0, lstab[(long long)m * nb16 + 4 * (chunk * W + w)] / 32);
     // B operands: ring pair 4 g + kq of this block, column jc
     T ge[16], go[16];
     {
@@ -109,19 +119,27 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
             go[g] = M::cvt(gn - gs);
         }
     }
-    // mode 0 also stands for a block past the last ring pair (no contribution)
-    int mode = active ? wave_mode1(L) : 0;
-    const int ntile = (nl + 31) / 32;
-    for (int t = 0; t < ntile; t++) {
+    // mode -1: before tw (or no block), 0: all lanes range-scaled, 1: some, 2: none
+    int mode = -1;
+    for (int o = threadIdx.x; o < min(32 * t0, nl) * 16; o += 64 * W) Pm[o] = 0.0;
+    for (int t = t0; t < ntile; t++) {
         __syncthreads();
         if (threadIdx.x < kChunkM) {
             const int l = m + t * 32 + threadIdx.x;
             sab[threadIdx.x] = (l + 1 <= lmax) ? abm[l + 1] : make_double2(0.0, 0.0);
         }
         __syncthreads();
+        if (t == tw) {
+            const long long tix = ((long long)m * nb16 + 4 * pb + (lane >> 4)) * 64 + (lane & 15);
+            const double2 s0 = st[tix];
+            L.l1 = s0.x;
+            L.l2 = s0.y;
+            L.sc = stsc[tix];
+            mode = wave_mode1(L);
+        }
         typename M::acc DE = M::zero(), DO = DE;
-        if (mode == 0) {
-            if (active) {
+        if (mode <= 0) {
+            if (mode == 0) {
 #pragma unroll
                 for (int q = 0; q < 8; q++) {
 #pragma unroll
@@ -197,7 +215,8 @@ int adjoint_chunks_mfma(const mlcr_geom *g, int lmax) {
 }
 
 template <typename T, int W>
-static int launch_ladj_wg(const LegendreArgs &a, const double2 *G, double *P, int nchunks) {
+static int launch_ladj_wg(const LegendreArgs &a, const SegTable *st, const double2 *G, double *P,
+                          int nchunks) {
     const mlcr_geom *g = a.g;
     const int npb = (g->npairs + 63) / 64;
     const int nrc = (a.nrhs + 7) / 8;
@@ -208,29 +227,31 @@ static int launch_ladj_wg(const LegendreArgs &a, const double2 *G, double *P, in
     int rc = ensure_dynamic_lds((const void *)k_ladj_mfma<T, W>, lds);
     if (rc) return rc;
     hipLaunchKernelGGL((k_ladj_mfma<T, W>), dim3((unsigned)grid), dim3(64 * W), lds, a.stream, G,
-                       fstride, a.nrhs, P, a.lmax, g->ring_z.as<double>(), g->ring_s.as<double>(),
-                       g->ab.as<double2>(), g->aboff.as<long long>(), g->seed.as<double>(),
-                       g->nrings, g->npairs, npb, nchunks, total);
+                       fstride, a.nrhs, P, a.lmax, g->ring_z.as<double>(), g->ab.as<double2>(),
+                       g->aboff.as<long long>(), st->st.as<double2>(), st->sc.as<int>(),
+                       st->ls.as<int>(), 4 * npb, g->nrings, g->npairs, npb, nchunks, total);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }
 
 template <typename T>
-static int launch_ladj_t(const LegendreArgs &a, const double2 *G, double *P, int nchunks) {
+static int launch_ladj_t(const LegendreArgs &a, const SegTable *st, const double2 *G, double *P,
+                         int nchunks) {
     switch (adj_waves((a.g->npairs + 63) / 64)) {
-    case 8: return launch_ladj_wg<T, 8>(a, G, P, nchunks);
-    case 4: return launch_ladj_wg<T, 4>(a, G, P, nchunks);
-    case 2: return launch_ladj_wg<T, 2>(a, G, P, nchunks);
-    default: return launch_ladj_wg<T, 1>(a, G, P, nchunks);
+    case 8: return launch_ladj_wg<T, 8>(a, st, G, P, nchunks);
+    case 4: return launch_ladj_wg<T, 4>(a, st, G, P, nchunks);
+    case 2: return launch_ladj_wg<T, 2>(a, st, G, P, nchunks);
+    default: return launch_ladj_wg<T, 1>(a, st, G, P, nchunks);
     }
 }
 
 // P: double T layout with 8 RHS per chunk
-int launch_legendre_adjoint_mfma(const LegendreArgs &a, const double2 *G, double *P,
-                                 int *nchunks_out, bool dbl) {
+int launch_legendre_adjoint_mfma(const LegendreArgs &a, const SegTable *st, const double2 *G,
+                                 double *P, int *nchunks_out, bool dbl) {
+    if (st->lmax != a.lmax) return fail(MLCR_EINVAL, "start-state table of another band limit");
     const int nchunks = adjoint_chunks_mfma(a.g, a.lmax);
-    const int rc = dbl ? launch_ladj_t<double>(a, G, P, nchunks)
-                       : launch_ladj_t<float>(a, G, P, nchunks);
+    const int rc = dbl ? launch_ladj_t<double>(a, st, G, P, nchunks)
+                       : launch_ladj_t<float>(a, st, G, P, nchunks);
     if (rc) return rc;
     *nchunks_out = nchunks;
     return MLCR_OK;

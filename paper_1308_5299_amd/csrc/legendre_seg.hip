@@ -77,7 +77,8 @@ __global__ __launch_bounds__(64) void k_seg_init(int lmax, const double *__restr
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) mn = min(mn, __shfl_xor(mn, o));
     // all 64 lanes range-scaled at boundary mn - 1 and at every check before it
-    const int ls = mn > nu ? 16 * nu : 16 * max(mn - 1, 0);
+    // (32-aligned: the adjoint's tiles start there too; dead blocks past nl)
+    const int ls = mn > nu ? 32 * ((nl + 31) / 32) : 32 * ((16 * max(mn - 1, 0)) / 32);
     const int nlive = nl - ls;
     const int n4 = nlive > 0 ? 16 * ((nlive + 63) / 64) : 0;
     // states at the segment starts ls + k n4, k = 0..3

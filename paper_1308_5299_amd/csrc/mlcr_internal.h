@@ -64,11 +64,12 @@ struct RingGroup {
     int off, count, mmax;
 };
 
-// Start states of the segment-parallel synthesis at one band limit: per
-// order m and block of 16 ring pairs, the offset ls (from m, a multiple of 16)
-// below which every lambda of the block is negligible, and for each of the 4
-// l-segments of [m + ls, lmax] the recurrence state (l1, l2, scale count) of
-// each ring pair at the segment start.
+// Recurrence start states of the matrix-core Legendre kernels at one band
+// limit: per order m and block of 16 ring pairs, the offset ls (from m, a
+// multiple of 32, the same for the 64 ring pairs of a wave) below which every
+// lambda of those ring pairs is negligible, and for each of the 4 l-segments
+// of [m + ls, lmax] the recurrence state (l1, l2, scale count) of each ring
+// pair at the segment start (segment 0 starts at ls: the adjoint's start).
 struct SegTable {
     int lmax = -1;
     DevBuf st;          // double2 [(lmax+1) * nb16 * 64]
@@ -156,8 +157,8 @@ int launch_ring_weight(const mlcr_geom *g, const double *in, double *out, hipStr
 int adjoint_chunks(const mlcr_geom *g, int lmax);
 // matrix-core Legendre adjoint, 8 RHS per wave; dbl selects float64 MFMA
 // (else float32).
-int launch_legendre_adjoint_mfma(const LegendreArgs &a, const double2 *G, double *P,
-                                 int *nchunks_out, bool dbl);
+int launch_legendre_adjoint_mfma(const LegendreArgs &a, const SegTable *st, const double2 *G,
+                                 double *P, int *nchunks_out, bool dbl);
 int adjoint_chunks_mfma(const mlcr_geom *g, int lmax);
 // split-bfloat16 matrix-core Legendre kernels (legendre_b3.hip): U in blocks
 // of 16 l-steps per order, hi/lo bf16 planes; P as for the float32 adjoint.
@@ -171,8 +172,8 @@ int launch_legendre_synth_seg(const LegendreArgs &a, const SegTable *t, const vo
                               int prec);
 int launch_pack_b3(int lmax, int nrhs, const double *x, const double *dl, void *U, hipStream_t s);
 int launch_legendre_synth_b3(const LegendreArgs &a, const void *U, double2 *F);
-int launch_legendre_adjoint_b3(const LegendreArgs &a, const double2 *G, double *P,
-                               int *nchunks_out);
+int launch_legendre_adjoint_b3(const LegendreArgs &a, const SegTable *st, const double2 *G,
+                               double *P, int *nchunks_out);
 // T layout ([RHS chunk][m][l - m][RC][cos, sin]) of the Legendre kernels
 int synth_rc(int nrhs);
 int adj_rc(int nrhs);
