@@ -33,12 +33,15 @@ PEAK_BF16 = 2.5e15            # MI355X dense bf16 MFMA FLOP/s
 # profiles/apply_A_c5_r8_hbm_traffic.md for the kernels as they are now.
 # Key: (library timer name, Legendre path, workload, RHS per launch).
 MEASURED_TRAFFIC = {
-    ("legendre_adjoint", "fp32", "c5", 8): 34.732e9 + 8.596e9,
-    ("legendre_adjoint", "fp64", "c5", 8): 34.731e9 + 8.596e9,
-    ("legendre_synth", "fp32", "c5", 8): 1.664e9 + 8.637e9,
-    ("legendre_synth", "fp64", "c5", 8): 1.992e9 + 8.611e9,
-    ("ring_apply", "fp32", "c5", 8): 4 * (1.424e9 + 1.074e9),
-    ("ring_apply", "fp64", "c5", 8): 4 * (1.415e9 + 1.074e9),
+    ("legendre_adjoint", "bf16x3", "c5", 8): 34.994e9 + 8.596e9,
+    ("legendre_adjoint", "fp32", "c5", 8): 34.963e9 + 8.596e9,
+    ("legendre_adjoint", "fp64", "c5", 8): 34.986e9 + 8.596e9,
+    ("legendre_synth", "bf16x3", "c5", 8): 3.775e9 + 8.602e9,
+    ("legendre_synth", "fp32", "c5", 8): 6.761e9 + 8.726e9,
+    ("legendre_synth", "fp64", "c5", 8): 12.085e9 + 8.664e9,
+    ("ring_apply", "bf16x3", "c5", 8): 1.782e9 + 1.074e9 + 3 * (1.300e9 + 1.074e9),
+    ("ring_apply", "fp32", "c5", 8): 1.782e9 + 1.074e9 + 3 * (1.298e9 + 1.074e9),
+    ("ring_apply", "fp64", "c5", 8): 1.784e9 + 1.074e9 + 3 * (1.298e9 + 1.074e9),
 }
 
 
@@ -256,7 +259,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c5")
     ap.add_argument("--nrhs", type=int, default=0)
-    ap.add_argument("--paths", default="fp32,bf16x3,fp64",
+    ap.add_argument("--paths", default="bf16x3,fp32,fp64",
                     help="Legendre paths to time; the first is the reported value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--solve", action="store_true",
