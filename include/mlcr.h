@@ -145,6 +145,17 @@ void mlcr_op_destroy(mlcr_op *op);
 int apply_A(mlcr_op *op, int level, int nrhs, const double *dev_x, double *dev_y,
             int prec, void *stream);
 
+/* Top-level applies of a mixed batch of independent problems (each with its
+ * own operator, grid and band limit; Sec. 2.3 per problem): y_p = A_p x_p,
+ * p < nprob.  host_nrhs[nprob]: RHS per problem (NULL: 1 each);
+ * host_x / host_y[nprob]: device pointers laid out as for apply_A.  The
+ * problems run concurrently on library-owned streams (problems on the same
+ * grid in call order on one of them), forked from and joined back into
+ * `stream`, so the call is ordered on `stream` like apply_A.  Results equal
+ * the single applies.  EINVAL on a NULL entry or nrhs out of range. */
+int apply_A_grouped(int nprob, mlcr_op *const *ops, const int *host_nrhs,
+                    const double *const *host_x, double *const *host_y, int prec, void *stream);
+
 /* Define level h >= 1 of the operator: band limit lmax_h and the
  * cumulative low-pass filter f^h_l (host_fl[lmax_h+1], f^h_l = 0 allowed),
  * so that A_h = D_h + B_h Y^T N^-1 Y B_h with D_h = diag(f^2 / C_l) and
@@ -177,10 +188,13 @@ int mlcr_op_level_lmax(const mlcr_op *op, int h);
  * filter of eq. fourth-power-beam (q = 0.1 at 2570/3000 of the band limit on
  * the first level, 1536/2048 on the second); levels with N_side^h <= 256 use
  * Gaussians of FWHM two pixels and 6 N_side^h, down to N_side^h = 32.
- * Modes with C_l = 0 get the wide prior C_0 = C_1 = C_2 inside the coarse
- * hierarchy (as in Sec. 4.1); the top level keeps them removed.  The pixel
- * smoothers are block-Jacobi on the k x k tiles.  Recursion counts: the
- * top and the finest pixel level run once down and once up, the others
+ * A multi-level ladder needs C_l > 0 for every l (the paper's wide prior
+ * C_0 = C_1 = C_2, Sec. 4.1; EINVAL otherwise); an operator small enough for
+ * the dense bottom alone also accepts C_l = 0 (modes removed).  The pixel
+ * smoothers are one symmetric multicolour block Gauss-Seidel sweep over the
+ * k x k tiles and their neighbour couplings (Sec. 3.4's block pattern).
+ * Recursion counts: the top and the finest pixel level run once down and
+ * once up, the others
  * twice (partial W-cycle, Sec. 4.1), the last pixel level once into the
  * dense bottom.
  * ---------------------------------------------------------------------- */
@@ -222,6 +236,19 @@ int mlcr_solver_top_dinv(const mlcr_solver *s, double *dev_out, void *stream);
  * Returns MLCR_ENOCONV (x and info still valid) if rtol is not reached. */
 int wcycle_solve(mlcr_solver *s, int nrhs, const double *dev_b, double *dev_x, double rtol,
                  int max_cycles, int prec, mlcr_solve_info *host_info, void *stream);
+
+/* wcycle_solve for a mixed batch of independent problems (one solver each,
+ * every solver at most once): the cycles of all unfinished problems are
+ * issued on library-owned streams (forked from and joined back into
+ * `stream`, problems on the same grid sharing one) before any residual is
+ * read back, so small problems overlap on the GPU.  host_nrhs[nprob] (NULL:
+ * 1 each); host_b / host_x[nprob]: device pointers as for wcycle_solve;
+ * host_info: sum of nrhs entries in problem order, or NULL.  Each problem
+ * stops at its own convergence; results equal the single solves.
+ * MLCR_ENOCONV if any problem misses rtol (x and info still valid). */
+int wcycle_solve_grouped(int nprob, mlcr_solver *const *s, const int *host_nrhs,
+                         const double *const *host_b, double *const *host_x, double rtol,
+                         int max_cycles, int prec, mlcr_solve_info *host_info, void *stream);
 
 /* ---- host-only helpers (no GPU needed) ---- */
 /* HEALPix NESTED to RING pixel index (Gorski et al. 2005); the tiles of the

@@ -39,6 +39,9 @@ SIGNATURES = {
     "mlcr_solver_top_dinv": (c_int, [c_void_p, c_void_p, c_void_p]),
     "wcycle_solve": (c_int, [c_void_p, c_int, c_void_p, c_void_p, ctypes.c_double, c_int, c_int,
                              c_void_p, c_void_p]),
+    "apply_A_grouped": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    "wcycle_solve_grouped": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_double,
+                                     c_int, c_int, c_void_p, c_void_p]),
     "mlcr_nest2ring": (c_int, [c_int, c_ll, c_void_p, c_void_p]),
     "mlcr_tile_graph": (c_int, [c_int, c_int, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_int),
                                 ctypes.POINTER(c_int)]),

@@ -271,6 +271,60 @@ class Solver:
             pass
 
 
+def _ptrs(seq) -> "ctypes.Array":
+    return (ctypes.c_void_p * len(seq))(*[ctypes.c_void_p(v) for v in seq])
+
+
+def apply_A_grouped(ops, xs, prec: int = FP64, outs=None):
+    """Top-level y_p = A_p x_p for a mixed batch (one operator per problem),
+    run concurrently in the library; see include/mlcr.h."""
+    n = len(ops)
+    if n < 1 or len(xs) != n:
+        raise ValueError("need one x per operator")
+    ys = outs if outs is not None else [None] * n
+    nr = (ctypes.c_int * n)()
+    for p, (op, x) in enumerate(zip(ops, xs)):
+        _dev(x, "x")
+        nr[p] = _batch(x, nalm(op.lmax), "x")
+        if nr[p] > op.max_nrhs:
+            raise ValueError("nrhs exceeds the operator's max_nrhs")
+        if ys[p] is None:
+            ys[p] = torch.empty_like(x)
+    check(load().apply_A_grouped(n, _ptrs([op.handle.value for op in ops]), ctypes.cast(nr, ctypes.c_void_p),
+                                 _ptrs([x.data_ptr() for x in xs]), _ptrs([y.data_ptr() for y in ys]),
+                                 int(prec), _stream()))
+    return ys
+
+
+def solve_grouped(solvers, bs, rtol: float = 1e-8, max_cycles: int = 50, prec: int = FP64,
+                  raise_on_noconv: bool = True):
+    """wcycle_solve for a mixed batch (one solver per problem, each at most
+    once); returns (xs, infos) with infos[p] a list of dicts per RHS."""
+    from ._lib import SolveInfo
+    n = len(solvers)
+    if n < 1 or len(bs) != n:
+        raise ValueError("need one b per solver")
+    nr = (ctypes.c_int * n)()
+    xs = []
+    for p, (S, b) in enumerate(zip(solvers, bs)):
+        _dev(b, "b")
+        nr[p] = _batch(b, nalm(S.op.lmax), "b")
+        xs.append(torch.zeros_like(b))
+    infos = (SolveInfo * sum(nr))()
+    rc = load().wcycle_solve_grouped(n, _ptrs([S._h.value for S in solvers]), ctypes.cast(nr, ctypes.c_void_p),
+                                     _ptrs([b.data_ptr() for b in bs]), _ptrs([x.data_ptr() for x in xs]),
+                                     float(rtol), int(max_cycles), int(prec),
+                                     ctypes.cast(infos, ctypes.c_void_p), _stream())
+    flat = [{k: getattr(i, k) for k, _ in SolveInfo._fields_} for i in infos]
+    out, o = [], 0
+    for p in range(n):
+        out.append(flat[o: o + nr[p]])
+        o += nr[p]
+    if rc != 0 and not (rc == -5 and not raise_on_noconv):
+        check(rc)
+    return xs, out
+
+
 def nest2ring(nside: int, nest) -> np.ndarray:
     nest = np.ascontiguousarray(np.asarray(nest, dtype=np.int64))
     out = np.empty_like(nest)

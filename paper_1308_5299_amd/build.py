@@ -15,7 +15,8 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmlcr.so")
 SOURCES = ["api.cpp", "geometry.cpp", "legendre.hip", "ringfft.hip", "solver.cpp", "tiles.cpp",
            "solver_kernels.hip", "legendre_mfma.hip",
-           "legendre_b3.hip", "legendre_seg.hip"]
+           "legendre_b3.hip", "legendre_seg.hip",
+           "streams.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

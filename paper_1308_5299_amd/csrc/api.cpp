@@ -508,4 +508,24 @@ int apply_A(mlcr_op *op, int level, int nrhs, const double *x, double *y, int pr
     return apply_level(op, level, nrhs, x, y, prec, (hipStream_t)stream);
 }
 
+int apply_A_grouped(int nprob, mlcr_op *const *ops, const int *nrhs, const double *const *x,
+                    double *const *y, int prec, void *stream) {
+    if (nprob < 1) return fail(MLCR_EINVAL, "nprob must be >= 1");
+    if (!ops || !x || !y) return fail(MLCR_EINVAL, "NULL argument");
+    int rc;
+    if ((rc = check_prec(prec))) return rc;
+    std::vector<const void *> keys(nprob);
+    for (int p = 0; p < nprob; p++) {
+        if (!ops[p] || !x[p] || !y[p]) return fail(MLCR_EINVAL, "NULL operator or vector in the group");
+        if (nrhs && nrhs[p] < 1) return fail(MLCR_EINVAL, "nrhs must be >= 1");
+        keys[p] = ops[p]->g;
+    }
+    StreamFork f;
+    if ((rc = f.begin((hipStream_t)stream, keys))) return rc;
+    for (int p = 0; p < nprob && rc == MLCR_OK; p++)
+        rc = apply_level(ops[p], 0, nrhs ? nrhs[p] : 1, x[p], y[p], prec, f.item_stream[p]);
+    const int rj = f.join();
+    return rc ? rc : rj;
+}
+
 }  // extern "C"

@@ -129,6 +129,16 @@ struct mlcr_op {
 
 namespace mlcr {
 
+// Independent work items on pooled streams (streams.cpp): items with the same
+// key (the grid whose workspaces they use) share a stream.
+struct StreamFork {
+    hipStream_t parent = nullptr;
+    std::vector<hipStream_t> item_stream;   // per item
+    std::vector<hipStream_t> used;
+    int begin(hipStream_t parent, const std::vector<const void *> &keys);
+    int join();
+};
+
 // Raise a kernel's dynamic LDS limit to `bytes` when it exceeds the 64 KiB
 // default (gfx950 allows up to 160 KiB per workgroup, static plus dynamic).
 int ensure_dynamic_lds(const void *func, size_t bytes);

@@ -774,85 +774,190 @@ int mlcr_solver_top_dinv(const mlcr_solver *S, double *out, void *stream) {
     return MLCR_OK;
 }
 
-int wcycle_solve(mlcr_solver *S, int nrhs, const double *b, double *x, double rtol, int max_cycles,
-                 int prec, mlcr_solve_info *info, void *stream) {
-    if (!S || !b || !x) return fail(MLCR_EINVAL, "NULL argument");
-    if (nrhs < 1 || nrhs > S->max_nrhs) return fail(MLCR_EINVAL, "nrhs out of [1, max_nrhs]");
-    if (max_cycles < 1) return fail(MLCR_EINVAL, "max_cycles must be >= 1");
-    if (!(rtol >= 0.0)) return fail(MLCR_EINVAL, "rtol must be >= 0");
-    if (prec != MLCR_FP64 && prec != MLCR_FP32 && prec != MLCR_BF16X3)
-        return fail(MLCR_EINVAL, "unknown precision");
-    hipStream_t s = (hipStream_t)stream;
-    mlcr_op *op = S->op;
-    const int lmax = op->lmax;
-    const long long na = nalm_l(lmax);
-    int rc;
-    // x holds the start vector; excluded modes are projected out
-    if ((rc = launch_residual(x, nullptr, x, S->top_act.as<double>(), lmax, nrhs, s))) return rc;
-    std::vector<double> hn(2 * nrhs), rho0(nrhs), rho(nrhs, 0.0);
-    std::vector<int> done(nrhs, 0), cyc(nrhs, 0);
-    auto residual_norms = [&](std::vector<double> &out) -> int {
-        int r2;
-        if ((r2 = apply_level(op, 0, nrhs, x, S->to.as<double>(), MLCR_FP64, s))) return r2;
-        if ((r2 = launch_residual(b, S->to.as<double>(), S->ro.as<double>(), S->top_act.as<double>(),
-                                  lmax, nrhs, s)))
-            return r2;
-        if ((r2 = launch_wnorms(S->ro.as<double>(), b, S->sinv.as<double>(), lmax, nrhs,
+namespace mlcr {
+
+// One CR-Solve (Fig. code:mg, correction form) split into steps that only
+// enqueue work and steps that read the residual norms back, so that several
+// solves on different streams can be interleaved cycle by cycle.
+struct SolveRun {
+    mlcr_solver *S;
+    int nrhs, prec;
+    const double *b;
+    double *x;
+    double rtol;
+    hipStream_t s;
+    std::vector<double> hn, rho0, rho;
+    std::vector<int> done, cyc;
+    std::vector<int> nr;
+    int B = 0, it = 0;
+    bool all = false;
+
+    SolveRun(mlcr_solver *S_, int n, const double *b_, double *x_, double rt, int p, hipStream_t st)
+        : S(S_), nrhs(n), prec(p), b(b_), x(x_), rtol(rt), s(st), hn(2 * n), rho0(n), rho(n, 0.0),
+          done(n, 0), cyc(n, 0) {
+        nr.resize(S->plan.H + 1);
+        nr[0] = S->plan.nrec_top;
+        for (int h = 0; h < S->plan.H; h++) nr[h + 1] = S->plan.nrec[h];
+        B = S->direct ? 0 : S->plan.H + 1;
+    }
+    // r = b - A x in float64 and its S^-1 norms, copied to hn (not yet waited on)
+    int enqueue_residual() {
+        mlcr_op *op = S->op;
+        int rc;
+        if ((rc = apply_level(op, 0, nrhs, x, S->to.as<double>(), MLCR_FP64, s))) return rc;
+        if ((rc = launch_residual(b, S->to.as<double>(), S->ro.as<double>(), S->top_act.as<double>(),
+                                  op->lmax, nrhs, s)))
+            return rc;
+        if ((rc = launch_wnorms(S->ro.as<double>(), b, S->sinv.as<double>(), op->lmax, nrhs,
                                 S->partial.as<double>(), S->norms.as<double>(), s)))
-            return r2;
+            return rc;
+        return MLCR_OK;
+    }
+    int read_norms(std::vector<double> &out) {
         MLCR_HIP_CHECK(hipMemcpyAsync(hn.data(), S->norms.ptr, 2 * nrhs * sizeof(double),
                                       hipMemcpyDeviceToHost, s));
         MLCR_HIP_CHECK(hipStreamSynchronize(s));
         for (int r = 0; r < nrhs; r++)
             out[r] = hn[2 * r + 1] > 0 ? std::sqrt(hn[2 * r] / hn[2 * r + 1]) : 0.0;
         return MLCR_OK;
-    };
-    if ((rc = residual_norms(rho0))) return rc;
-    rho = rho0;
-    GpuOps ops(S, nrhs, prec, s);
-    std::vector<int> nr(S->plan.H + 1);
-    nr[0] = S->plan.nrec_top;
-    for (int h = 0; h < S->plan.H; h++) nr[h + 1] = S->plan.nrec[h];
-    const int B = S->direct ? 0 : S->plan.H + 1;
-    bool all = true;
-    for (int r = 0; r < nrhs; r++) all = all && rho[r] <= rtol;
-    int it = 0;
-    while (!all && it < max_cycles) {
-        // correction form of CR-Solve: solve A c = r with one cycle from c = 0,
-        // then x += c and r = b - A x in float64 (iterative refinement)
+    }
+    int enqueue_start() {
+        int rc;
+        // x holds the start vector; excluded modes are projected out
+        if ((rc = launch_residual(x, nullptr, x, S->top_act.as<double>(), S->op->lmax, nrhs, s)))
+            return rc;
+        return enqueue_residual();
+    }
+    int finish_start() {
+        int rc;
+        if ((rc = read_norms(rho0))) return rc;
+        rho = rho0;
+        all = true;
+        for (int r = 0; r < nrhs; r++) all = all && rho[r] <= rtol;
+        return MLCR_OK;
+    }
+    // one cycle: solve A c = r from c = 0, x += c, then the new residual
+    int enqueue_cycle() {
+        const int lmax = S->op->lmax;
+        const long long na = nalm_l(lmax);
+        int rc;
         MLCR_HIP_CHECK(hipMemcpyAsync(S->b0.ptr, S->ro.ptr, (size_t)nrhs * na * sizeof(double),
                                       hipMemcpyDeviceToDevice, s));
         MLCR_HIP_CHECK(hipMemsetAsync(S->x0.ptr, 0, (size_t)nrhs * na * sizeof(double), s));
+        GpuOps ops(S, nrhs, prec, s);
         if ((rc = cr_cycle(ops, 0, B, nr, true))) return rc;
         if ((rc = launch_axpy_l(x, S->x0.as<double>(), S->top_act.as<double>(), nullptr, lmax, nrhs,
                                 s)))
             return rc;
         it++;
-        if ((rc = residual_norms(rho))) return rc;
+        return enqueue_residual();
+    }
+    int finish_cycle() {
+        int rc;
+        if ((rc = read_norms(rho))) return rc;
         all = true;
         for (int r = 0; r < nrhs; r++) {
             if (!done[r]) cyc[r] = it;
             if (rho[r] <= rtol) done[r] = 1;
             all = all && done[r];
         }
+        return MLCR_OK;
     }
-    // ||S^{1/2} r|| for the a-posteriori max-pixel-error bound
-    if ((rc = launch_wnorms(S->ro.as<double>(), nullptr, S->chalf.as<double>(), lmax, nrhs,
-                            S->partial.as<double>(), S->norms.as<double>(), s)))
-        return rc;
-    MLCR_HIP_CHECK(hipMemcpyAsync(hn.data(), S->norms.ptr, 2 * nrhs * sizeof(double),
-                                  hipMemcpyDeviceToHost, s));
-    MLCR_HIP_CHECK(hipStreamSynchronize(s));
-    if (info)
-        for (int r = 0; r < nrhs; r++) {
-            info[r].cycles = cyc[r];
-            info[r].rho0 = rho0[r];
-            info[r].rho = rho[r];
-            info[r].s_half_res = std::sqrt(hn[2 * r]);
-            info[r].converged = rho[r] <= rtol;
-        }
-    if (!all) return fail(MLCR_ENOCONV, "rtol not reached within max_cycles");
+    // ||S^{1/2} r|| for the a-posteriori max-pixel-error bound, and the report
+    int finish(mlcr_solve_info *info) {
+        int rc;
+        if ((rc = launch_wnorms(S->ro.as<double>(), nullptr, S->chalf.as<double>(), S->op->lmax,
+                                nrhs, S->partial.as<double>(), S->norms.as<double>(), s)))
+            return rc;
+        MLCR_HIP_CHECK(hipMemcpyAsync(hn.data(), S->norms.ptr, 2 * nrhs * sizeof(double),
+                                      hipMemcpyDeviceToHost, s));
+        MLCR_HIP_CHECK(hipStreamSynchronize(s));
+        if (info)
+            for (int r = 0; r < nrhs; r++) {
+                info[r].cycles = cyc[r];
+                info[r].rho0 = rho0[r];
+                info[r].rho = rho[r];
+                info[r].s_half_res = std::sqrt(hn[2 * r]);
+                info[r].converged = rho[r] <= rtol;
+            }
+        return MLCR_OK;
+    }
+};
+
+static int check_solve_args(mlcr_solver *S, int nrhs, const double *b, double *x, double rtol,
+                            int max_cycles, int prec) {
+    if (!S || !b || !x) return fail(MLCR_EINVAL, "NULL argument");
+    if (nrhs < 1 || nrhs > S->max_nrhs) return fail(MLCR_EINVAL, "nrhs out of [1, max_nrhs]");
+    if (max_cycles < 1) return fail(MLCR_EINVAL, "max_cycles must be >= 1");
+    if (!(rtol >= 0.0)) return fail(MLCR_EINVAL, "rtol must be >= 0");
+    if (prec != MLCR_FP64 && prec != MLCR_FP32 && prec != MLCR_BF16X3)
+        return fail(MLCR_EINVAL, "unknown precision");
+    return MLCR_OK;
+}
+
+}  // namespace mlcr
+
+int wcycle_solve(mlcr_solver *S, int nrhs, const double *b, double *x, double rtol, int max_cycles,
+                 int prec, mlcr_solve_info *info, void *stream) {
+    int rc;
+    if ((rc = check_solve_args(S, nrhs, b, x, rtol, max_cycles, prec))) return rc;
+    SolveRun run(S, nrhs, b, x, rtol, prec, (hipStream_t)stream);
+    if ((rc = run.enqueue_start()) || (rc = run.finish_start())) return rc;
+    while (!run.all && run.it < max_cycles)
+        if ((rc = run.enqueue_cycle()) || (rc = run.finish_cycle())) return rc;
+    if ((rc = run.finish(info))) return rc;
+    if (!run.all) return fail(MLCR_ENOCONV, "rtol not reached within max_cycles");
     return MLCR_OK;
 }
 
 }  // extern "C"
+
+int wcycle_solve_grouped(int nprob, mlcr_solver *const *S, const int *nrhs, const double *const *b,
+                         double *const *x, double rtol, int max_cycles, int prec,
+                         mlcr_solve_info *info, void *stream) {
+    if (nprob < 1) return fail(MLCR_EINVAL, "nprob must be >= 1");
+    if (!S || !b || !x) return fail(MLCR_EINVAL, "NULL argument");
+    int rc;
+    std::vector<const void *> keys(nprob);
+    for (int p = 0; p < nprob; p++) {
+        if ((rc = check_solve_args(S[p], nrhs ? nrhs[p] : 1, b[p], x[p], rtol, max_cycles, prec)))
+            return rc;
+        for (int q = 0; q < p; q++)
+            if (S[q] == S[p]) return fail(MLCR_EINVAL, "a solver appears twice in the group");
+        keys[p] = S[p]->op->g;
+    }
+    StreamFork f;
+    if ((rc = f.begin((hipStream_t)stream, keys))) return rc;
+    std::vector<std::unique_ptr<SolveRun>> runs;
+    for (int p = 0; p < nprob; p++)
+        runs.emplace_back(new SolveRun(S[p], nrhs ? nrhs[p] : 1, b[p], x[p], rtol, prec,
+                                       f.item_stream[p]));
+    // all problems' work is enqueued before any result is read back
+    for (auto &r : runs)
+        if (!rc) rc = r->enqueue_start();
+    for (auto &r : runs)
+        if (!rc) rc = r->finish_start();
+    for (int c = 0; c < max_cycles && !rc; c++) {
+        bool any = false;
+        for (auto &r : runs)
+            if (!rc && !r->all) {
+                rc = r->enqueue_cycle();
+                any = true;
+            }
+        if (!any) break;
+        for (auto &r : runs)
+            if (!rc && r->it == c + 1) rc = r->finish_cycle();
+    }
+    bool all = true;
+    long long off = 0;
+    for (auto &r : runs) {
+        if (!rc) rc = r->finish(info ? info + off : nullptr);
+        off += r->nrhs;
+        all = all && r->all;
+    }
+    const int rj = f.join();
+    if (rc) return rc;
+    if (rj) return rj;
+    if (!all) return fail(MLCR_ENOCONV, "rtol not reached within max_cycles (some problem)");
+    return MLCR_OK;
+}
