@@ -252,6 +252,52 @@ def solve_bench(mlcr, torch, cfg, geom, op, xt, R, paths, max_cycles, target=1e-
     return out
 
 
+def mixed_bench(mlcr, torch, paths, rtol=1e-8, max_cycles=40):
+    """Mixed batch of independent problems (one RHS each, own grid and band
+    limit): the problems solved one after another vs one grouped solve."""
+    import workloads
+    precs = {"fp64": mlcr.FP64, "fp32": mlcr.FP32, "bf16x3": mlcr.BF16X3}
+    probs, grids = [], {}
+    t0 = time.time()
+    for k, name in enumerate(workloads.MIXED_BATCH):
+        cfg = workloads.get_config(name)
+        if name not in grids:
+            d = workloads.workload_inputs(cfg)
+            g = mlcr.Geometry(cfg.nside, cfg.lmax)
+            op = mlcr.Operator(g, d["cl"], d["bl"], torch.from_numpy(d["ninv"]).cuda(), max_nrhs=1)
+            grids[name] = (g, op)
+        g, op = grids[name]
+        S = mlcr.Solver(op, max_nrhs=1)
+        xt = torch.from_numpy(workloads.prior_sample(cfg, k)[None]).cuda()
+        probs.append((name, S, mlcr.apply_A(op, xt)))
+    torch.cuda.synchronize()
+    log(f"[bench] mixed batch {workloads.MIXED_BATCH}: setup {time.time() - t0:.1f}s")
+    out = {"metric": "mixed-batch W-cycle solve time to rtol", "unit": "s", "higher_is_better": False,
+           "n_gpus": 1, "rtol": rtol,
+           "config": {"workload": "mixed batch: " + ", ".join(
+               f"{n} (N_side {workloads.get_config(n).nside}, lmax {workloads.get_config(n).lmax})"
+               for n in workloads.MIXED_BATCH) + ", 1 RHS each"},
+           "paths": {}}
+    for p in paths:
+        for _, S, b in probs:        # untimed: tables and workspaces on first use
+            S.solve(b, rtol=0.0, max_cycles=1, prec=precs[p], raise_on_noconv=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _, S, b in probs:
+            S.solve(b, rtol=rtol, max_cycles=max_cycles, prec=precs[p])
+        torch.cuda.synchronize()
+        seq = time.perf_counter() - t
+        t = time.perf_counter()
+        _, infos = mlcr.solve_grouped([S for _, S, _ in probs], [b for _, _, b in probs], rtol=rtol,
+                                      max_cycles=max_cycles, prec=precs[p])
+        torch.cuda.synchronize()
+        grp = time.perf_counter() - t
+        cyc = [i[0]["cycles"] for i in infos]
+        log(f"[bench] mixed {p}: one after another {seq:.2f}s, grouped {grp:.2f}s, cycles {cyc}")
+        out["paths"][p] = {"sequential_s": seq, "grouped_s": grp, "speedup": seq / grp, "cycles": cyc}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -262,6 +308,9 @@ def main():
     ap.add_argument("--paths", default="bf16x3,fp32,fp64",
                     help="Legendre paths to time; the first is the reported value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mixed", action="store_true",
+                    help="time the mixed batch of independent problems solved one after another "
+                         "and as one grouped solve")
     ap.add_argument("--solve", action="store_true",
                     help="time W-cycle solves to 1e-3 uK max pixel error (manufactured "
                          "solutions) with the float64 and mixed paths instead of applies")
@@ -271,9 +320,8 @@ def main():
                          "known-size reference for HBM traffic counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design "
-              "(RHS sharding, or an m/ring all-to-all per SHT) is described in DESIGN.md and "
-              "is not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path "
+              "(RHS sharding, or an m/ring all-to-all per SHT) is not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -292,6 +340,10 @@ def main():
     import paper_1308_5299_amd as mlcr
     import workloads
 
+    if args.mixed:
+        paths = [p.strip() for p in args.paths.split(",") if p.strip()]
+        print(json.dumps(mixed_bench(mlcr, torch, paths)), flush=True)
+        return
     cfg = workloads.get_config(args.config)
     R = args.nrhs or cfg.nrhs
     paths = [p.strip() for p in args.paths.split(",") if p.strip()]

@@ -26,6 +26,7 @@ definitions in Seljebotn et al. (2013):
                 cr-system plus fluctuation terms), manufactured solutions
                 (Sec. 4.1) and an a-posteriori max-pixel-error certificate.
 
-Parity status of every function is listed in the design doc; every function here
-is pinned by a ``-m "not gpu"`` test in ``tests/test_oracle_*.py``.
+Every function here is pinned by a ``-m "not gpu"`` test in
+``tests/test_oracle_*.py`` against closed forms, library routines, brute
+force or invariants of the mathematics.
 """
