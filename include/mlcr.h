@@ -237,6 +237,30 @@ int mlcr_solver_top_dinv(const mlcr_solver *s, double *dev_out, void *stream);
 int wcycle_solve(mlcr_solver *s, int nrhs, const double *dev_b, double *dev_x, double rtol,
                  int max_cycles, int prec, mlcr_solve_info *host_info, void *stream);
 
+/* CR-Solve by flexible preconditioned conjugate gradients in float64 with
+ * one CR-Cycle from zero as the preconditioner, the alternative named in the
+ * caption of Fig. code:mg: alpha = <r, z> / <p, A p>, x += alpha p,
+ * r -= alpha A p, z = CR-Cycle(r) in `prec`, beta = <r, z - z_old> /
+ * <r_old, z_old>, p = z + beta p, per RHS, until rho <= rtol (as for
+ * wcycle_solve) or max_iter iterations (one cycle and one float64 apply
+ * each).  Arguments, layouts, info (cycles = iterations) and errors as for
+ * wcycle_solve. */
+int pcg_solve(mlcr_solver *s, int nrhs, const double *dev_b, double *dev_x, double rtol,
+              int max_iter, int prec, mlcr_solve_info *host_info, void *stream);
+
+/* Right-hand side of the CR system (Sec. 2.3, eq. cr-system and the
+ * fluctuation terms that turn its solution into a posterior sample):
+ *     b = B Y^T (N^-1 d + N^-1/2 w2) + S^-1/2 w1
+ * on the active modes of op (0 on excluded ones).
+ *   dev_d:  [nrhs][12 nside^2] data maps (RING);
+ *   dev_w1: [nrhs][(lmax+1)^2] white noise, or NULL;
+ *   dev_w2: [nrhs][12 nside^2] white noise, or NULL;
+ *   dev_b:  [nrhs][(lmax+1)^2] output.
+ * With dev_w1 = dev_w2 = NULL the solution of A x = b is the Wiener-filtered
+ * (maximum-likelihood) map.  float64 throughout; 1 <= nrhs <= max_nrhs. */
+int mlcr_cr_rhs(mlcr_op *op, int nrhs, const double *dev_d, const double *dev_w1,
+                const double *dev_w2, double *dev_b, void *stream);
+
 /* wcycle_solve for a mixed batch of independent problems (one solver each,
  * every solver at most once): the cycles of all unfinished problems are
  * issued on library-owned streams (forked from and joined back into

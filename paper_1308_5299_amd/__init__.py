@@ -7,12 +7,12 @@ torch supplies device memory and streams, every step runs in libmlcr.so.
 """
 from ._lib import MLCRError, load as load_library  # noqa: F401
 from .api import (BF16X3, FP32, FP64, Geometry, KernelTimer, Operator, Solver, apply_A,  # noqa: F401
-                  apply_A_grouped, solve_grouped,
+                  apply_A_grouped, solve_grouped, cr_rhs,
                   cycle_counts, ladder_plan, nest2ring, sht_adjoint, sht_synth, tile_graph)
 
 from . import autograd  # noqa: F401,E402
 
 __all__ = ["autograd", "MLCRError", "load_library", "BF16X3", "FP32", "FP64", "Geometry", "Operator",
-           "apply_A", "apply_A_grouped", "solve_grouped", "sht_adjoint", "sht_synth", "KernelTimer",
+           "apply_A", "apply_A_grouped", "solve_grouped", "cr_rhs", "sht_adjoint", "sht_synth", "KernelTimer",
            "Solver", "nest2ring", "tile_graph",
            "ladder_plan", "cycle_counts"]

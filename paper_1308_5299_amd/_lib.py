@@ -39,6 +39,9 @@ SIGNATURES = {
     "mlcr_solver_top_dinv": (c_int, [c_void_p, c_void_p, c_void_p]),
     "wcycle_solve": (c_int, [c_void_p, c_int, c_void_p, c_void_p, ctypes.c_double, c_int, c_int,
                              c_void_p, c_void_p]),
+    "pcg_solve": (c_int, [c_void_p, c_int, c_void_p, c_void_p, ctypes.c_double, c_int, c_int,
+                          c_void_p, c_void_p]),
+    "mlcr_cr_rhs": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "apply_A_grouped": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     "wcycle_solve_grouped": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_double,
                                      c_int, c_int, c_void_p, c_void_p]),

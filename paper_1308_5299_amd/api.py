@@ -179,6 +179,24 @@ class Operator:
             pass
 
 
+def cr_rhs(op: Operator, d: torch.Tensor, w1: torch.Tensor | None = None,
+           w2: torch.Tensor | None = None) -> torch.Tensor:
+    """b = B Y^T (N^-1 d + N^-1/2 w2) + S^-1/2 w1 (Sec. 2.3); w1 = w2 = None
+    gives the Wiener-filter (maximum-likelihood) right-hand side."""
+    _dev(d, "d")
+    npix = int(op.ninv.numel())
+    nrhs = _batch(d, npix, "d")
+    b = torch.empty((nrhs, nalm(op.lmax)), dtype=torch.float64, device=d.device)
+    for t, n, name in ((w1, nalm(op.lmax), "w1"), (w2, npix, "w2")):
+        if t is not None:
+            _dev(t, name)
+            if _batch(t, n, name) != nrhs:
+                raise ValueError(f"{name} must have the batch size of d")
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p()
+    check(load().mlcr_cr_rhs(op.handle, nrhs, ptr(d), ptr(w1), ptr(w2), ptr(b), _stream()))
+    return b
+
+
 def apply_A(op: Operator, x: torch.Tensor, level: int = 0, prec: int = FP64,
             out: torch.Tensor | None = None) -> torch.Tensor:
     lmax = op.level_lmax[level]
@@ -254,6 +272,24 @@ class Solver:
         rc = load().wcycle_solve(self._h, nrhs, ctypes.c_void_p(b.data_ptr()),
                                  ctypes.c_void_p(x.data_ptr()), float(rtol), int(max_cycles),
                                  int(prec), ctypes.cast(infos, ctypes.c_void_p), _stream())
+        out = [{k: getattr(i, k) for k, _ in SolveInfo._fields_} for i in infos]
+        if rc != 0 and not (rc == -5 and not raise_on_noconv):
+            check(rc)
+        return x, out
+
+    def solve_pcg(self, b: torch.Tensor, x0: torch.Tensor | None = None, rtol: float = 1e-8,
+                  max_iter: int = 50, prec: int = FP64, raise_on_noconv: bool = True):
+        """Conjugate gradients with one CR-Cycle as the preconditioner;
+        returns (x, infos) like solve()."""
+        from ._lib import SolveInfo
+
+        _dev(b, "b")
+        nrhs = _batch(b, nalm(self.op.lmax), "b")
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        infos = (SolveInfo * nrhs)()
+        rc = load().pcg_solve(self._h, nrhs, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                              float(rtol), int(max_iter), int(prec), ctypes.cast(infos, ctypes.c_void_p),
+                              _stream())
         out = [{k: getattr(i, k) for k, _ in SolveInfo._fields_} for i in infos]
         if rc != 0 and not (rc == -5 and not raise_on_noconv):
             check(rc)

@@ -452,6 +452,7 @@ void mlcr_op_destroy(mlcr_op *op) {
         L.d.release();
         L.bh.release();
     }
+    op->rhs_pix.release();
     delete op;
 }
 

@@ -124,6 +124,7 @@ struct mlcr_op {
     int lmax = 0, max_nrhs = 0;
     const double *ninv = nullptr;
     std::vector<double> cl, bl;
+    mlcr::DevBuf rhs_pix;   // workspace of mlcr_cr_rhs
     mlcr_level levels[16];
 };
 

@@ -226,6 +226,9 @@ struct mlcr_solver {
     DevBuf b_idx, b_inv, xb, bb;
     // outer loop
     DevBuf sinv, chalf, partial, norms, ro, to;
+    // conjugate gradients: search direction, previous preconditioned residual,
+    // per-RHS coefficients
+    DevBuf pcg_p, pcg_zo, pcg_coef;
     std::vector<float> ridge_summary;
     int mode = 0;
     ~mlcr_solver() {
@@ -960,4 +963,106 @@ int wcycle_solve_grouped(int nprob, mlcr_solver *const *S, const int *nrhs, cons
     if (rj) return rj;
     if (!all) return fail(MLCR_ENOCONV, "rtol not reached within max_cycles (some problem)");
     return MLCR_OK;
+}
+
+// Flexible preconditioned conjugate gradients on A x = b in float64 with one
+// CR-Cycle from zero (in `prec`) as the preconditioner (the alternative the
+// caption of Fig. code:mg names).  beta = <r_new, z_new - z_old> / <r_old,
+// z_old> (Polak-Ribiere form), which tolerates the small asymmetry a
+// mixed-precision cycle has.
+int pcg_solve(mlcr_solver *S, int nrhs, const double *b, double *x, double rtol, int max_iter,
+              int prec, mlcr_solve_info *info, void *stream) {
+    int rc;
+    if ((rc = check_solve_args(S, nrhs, b, x, rtol, max_iter, prec))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    mlcr_op *op = S->op;
+    const int lmax = op->lmax;
+    const long long na = nalm_l(lmax);
+    const size_t vbytes = (size_t)S->max_nrhs * na * sizeof(double);
+    if (S->pcg_p.reserve(vbytes) || S->pcg_zo.reserve(vbytes) ||
+        S->pcg_coef.reserve(4 * (size_t)S->max_nrhs * sizeof(double)))
+        return fail(MLCR_ENOMEM, "conjugate-gradient workspace allocation failed");
+    SolveRun run(S, nrhs, b, x, rtol, prec, s);
+    if ((rc = run.enqueue_start()) || (rc = run.finish_start())) return rc;
+    double *r = S->ro.as<double>(), *q = S->to.as<double>(), *z = S->x0.as<double>();
+    double *p = S->pcg_p.as<double>(), *zo = S->pcg_zo.as<double>();
+    double *al = S->pcg_coef.as<double>(), *be = al + S->max_nrhs;
+    std::vector<double> h(2 * nrhs), rz(nrhs, 0.0), ca(nrhs), cb(nrhs);
+    const std::vector<double> ones(nrhs, 1.0);
+    auto dots = [&](const double *a1, const double *b1, const double *c1, const double *d1) -> int {
+        int r2;
+        if ((r2 = launch_dots(a1, b1, c1, d1, lmax, nrhs, S->partial.as<double>(),
+                              S->norms.as<double>(), s)))
+            return r2;
+        MLCR_HIP_CHECK(hipMemcpyAsync(h.data(), S->norms.ptr, 2 * nrhs * sizeof(double),
+                                      hipMemcpyDeviceToHost, s));
+        MLCR_HIP_CHECK(hipStreamSynchronize(s));
+        return MLCR_OK;
+    };
+    auto coefs = [&](const std::vector<double> &a1, const std::vector<double> &b1) -> int {
+        MLCR_HIP_CHECK(hipMemcpyAsync(al, a1.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+        MLCR_HIP_CHECK(hipMemcpyAsync(be, b1.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+        return MLCR_OK;
+    };
+    auto precond = [&]() -> int {     // z = M r: one cycle from zero on r
+        MLCR_HIP_CHECK(hipMemcpyAsync(S->b0.ptr, r, (size_t)nrhs * na * sizeof(double),
+                                      hipMemcpyDeviceToDevice, s));
+        MLCR_HIP_CHECK(hipMemsetAsync(z, 0, (size_t)nrhs * na * sizeof(double), s));
+        GpuOps ops(S, nrhs, prec, s);
+        return cr_cycle(ops, 0, run.B, run.nr, true);
+    };
+    if (!run.all) {
+        if ((rc = precond())) return rc;
+        MLCR_HIP_CHECK(hipMemcpyAsync(p, z, (size_t)nrhs * na * sizeof(double),
+                                      hipMemcpyDeviceToDevice, s));
+        if ((rc = dots(r, z, nullptr, nullptr))) return rc;
+        for (int k = 0; k < nrhs; k++) rz[k] = h[2 * k];
+    }
+    while (!run.all && run.it < max_iter) {
+        // alpha = <r, z> / <p, A p>; x += alpha p; r -= alpha A p
+        if ((rc = apply_level(op, 0, nrhs, p, q, MLCR_FP64, s))) return rc;
+        if ((rc = dots(p, q, nullptr, nullptr))) return rc;
+        for (int k = 0; k < nrhs; k++) ca[k] = (run.done[k] || !(h[2 * k] > 0)) ? 0.0 : rz[k] / h[2 * k];
+        if ((rc = coefs(ca, ones))) return rc;
+        if ((rc = launch_lincomb(p, x, x, al, be, na, nrhs, s))) return rc;
+        for (int k = 0; k < nrhs; k++) ca[k] = -ca[k];
+        if ((rc = coefs(ca, ones))) return rc;
+        if ((rc = launch_lincomb(q, r, r, al, be, na, nrhs, s))) return rc;
+        run.it++;
+        if ((rc = launch_wnorms(r, b, S->sinv.as<double>(), lmax, nrhs, S->partial.as<double>(),
+                                S->norms.as<double>(), s)))
+            return rc;
+        if ((rc = run.finish_cycle())) return rc;
+        if (run.all) break;
+        // z_new = M r; beta = <r, z_new - z_old> / <r_old, z_old>; p = z_new + beta p
+        MLCR_HIP_CHECK(hipMemcpyAsync(zo, z, (size_t)nrhs * na * sizeof(double),
+                                      hipMemcpyDeviceToDevice, s));
+        if ((rc = precond())) return rc;
+        if ((rc = dots(r, z, r, zo))) return rc;
+        for (int k = 0; k < nrhs; k++) {
+            cb[k] = (run.done[k] || !(rz[k] > 0)) ? 0.0 : (h[2 * k] - h[2 * k + 1]) / rz[k];
+            rz[k] = h[2 * k];
+        }
+        if ((rc = coefs(ones, cb))) return rc;
+        if ((rc = launch_lincomb(z, p, p, al, be, na, nrhs, s))) return rc;
+    }
+    if ((rc = run.finish(info))) return rc;
+    if (!run.all) return fail(MLCR_ENOCONV, "rtol not reached within max_iter");
+    return MLCR_OK;
+}
+
+int mlcr_cr_rhs(mlcr_op *op, int nrhs, const double *d, const double *w1, const double *w2,
+                double *b, void *stream) {
+    if (!op || !d || !b) return fail(MLCR_EINVAL, "NULL argument");
+    if (nrhs < 1 || nrhs > op->max_nrhs) return fail(MLCR_EINVAL, "nrhs out of [1, max_nrhs]");
+    hipStream_t s = (hipStream_t)stream;
+    mlcr_geom *g = op->g;
+    int rc;
+    if (op->rhs_pix.reserve((size_t)nrhs * g->npix * sizeof(double)))
+        return fail(MLCR_ENOMEM, "right-hand-side workspace allocation failed");
+    double *pix = op->rhs_pix.as<double>();
+    if ((rc = launch_cr_pix(d, w2, op->ninv, pix, g->npix, nrhs, s))) return rc;
+    if ((rc = sht_adjoint(g, op->lmax, nrhs, pix, b, MLCR_FP64, s))) return rc;
+    const mlcr_level &L = op->levels[0];
+    return launch_cr_combine(b, w1, L.bh.as<double>(), L.d.as<double>(), b, op->lmax, nrhs, s);
 }

@@ -44,6 +44,17 @@ int launch_dense_inverse(const double *L, int n, double *inv, hipStream_t s);
 int launch_dense_apply(const double *Ainv, int n, const int *act_idx, const double *b, double *x,
                        long long nalm, int nrhs, hipStream_t s);
 int launch_unit_vectors(double *x, long long nalm, const int *idx, int j0, int np, hipStream_t s);
+// per-RHS dot products (c, d may be null), out[2 r], out[2 r + 1]
+int launch_dots(const double *a, const double *b, const double *c, const double *d, int lmax,
+                int nrhs, double *partial, double *out, hipStream_t s);
+// out = al[r] u + be[r] v, n values per RHS (al, be: device arrays per RHS)
+int launch_lincomb(const double *u, const double *v, double *out, const double *al,
+                   const double *be, long long n, int nrhs, hipStream_t s);
+// CR right-hand side: pix = N^-1 d + N^-1/2 w2; b = bh v + sqrt(dd) w1
+int launch_cr_pix(const double *d, const double *w2, const double *ninv, double *pix,
+                  long long npix, int nrhs, hipStream_t s);
+int launch_cr_combine(const double *v, const double *w1, const double *bh, const double *dd,
+                      double *b, int lmax, int nrhs, hipStream_t s);
 
 // legendre.hip: adjoint with lambda^2 (diagonal of Y^T N^-1 Y)
 int launch_legendre_adjoint_sq(const LegendreArgs &a, const double2 *G, double *P,

@@ -140,6 +140,87 @@ __global__ __launch_bounds__(256) void k_wnorms_final(const double *__restrict__
     }
 }
 
+// per RHS: out[2 r] = <a, b>, out[2 r + 1] = <c, d> over all coefficients
+// (c, d may be null: 0); partial sums per order m, then k_wnorms_final
+__global__ __launch_bounds__(256) void k_dots(const double *__restrict__ a,
+                                              const double *__restrict__ b,
+                                              const double *__restrict__ c,
+                                              const double *__restrict__ d, int lmax,
+                                              double *__restrict__ partial) {
+    const int m = blockIdx.x, rr = blockIdx.y;
+    const long long nalm = (long long)(lmax + 1) * (lmax + 1);
+    const int nl = lmax - m + 1;
+    const int cnt = (m == 0) ? nl : 2 * nl;
+    const long long off = (long long)rr * nalm + cos_base(m, lmax);
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        s1 = fma(a[off + i], b[off + i], s1);
+        if (c) s2 = fma(c[off + i], d[off + i], s2);
+    }
+    __shared__ double ra[256], rb[256];
+    ra[threadIdx.x] = s1;
+    rb[threadIdx.x] = s2;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            ra[threadIdx.x] += ra[threadIdx.x + st];
+            rb[threadIdx.x] += rb[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[((long long)rr * (lmax + 1) + m) * 2] = ra[0];
+        partial[((long long)rr * (lmax + 1) + m) * 2 + 1] = rb[0];
+    }
+}
+
+// out = al[r] u + be[r] v per RHS r, flat (out may alias u or v)
+__global__ __launch_bounds__(256) void k_lincomb(const double *u, const double *v, double *out,
+                                                 const double *__restrict__ al,
+                                                 const double *__restrict__ be, long long n) {
+    const int rr = blockIdx.y;
+    const double a = al[rr], b = be[rr];
+    const long long base = (long long)rr * n;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        out[base + i] = a * u[base + i] + b * v[base + i];
+}
+
+// CR right-hand side, pixel part: pix = N^-1 d + N^-1/2 w2 (w2 may be null)
+__global__ __launch_bounds__(256) void k_cr_pix(const double *__restrict__ d,
+                                                const double *__restrict__ w2,
+                                                const double *__restrict__ ninv,
+                                                double *__restrict__ pix, long long npix) {
+    const int rr = blockIdx.y;
+    const long long base = (long long)rr * npix;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < npix;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double w = ninv[i];
+        double v = w * d[base + i];
+        if (w2) v = fma(sqrt(w), w2[base + i], v);
+        pix[base + i] = v;
+    }
+}
+
+// CR right-hand side, harmonic part: b = bh[l] v + sqrt(dd[l]) w1 (w1 may be null)
+__global__ __launch_bounds__(256) void k_cr_combine(const double *v,
+                                                    const double *__restrict__ w1,
+                                                    const double *__restrict__ bh,
+                                                    const double *__restrict__ dd,
+                                                    double *b, int lmax) {
+    const int m = blockIdx.x, rr = blockIdx.y;
+    const long long nalm = (long long)(lmax + 1) * (lmax + 1);
+    const int nl = lmax - m + 1;
+    const int cnt = (m == 0) ? nl : 2 * nl;
+    const long long off = (long long)rr * nalm + cos_base(m, lmax);
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const int l = m + (i < nl ? i : i - nl);
+        double o = bh[l] * v[off + i];
+        if (w1) o = fma(sqrt(dd[l]), w1[off + i], o);
+        b[off + i] = o;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // top-level diagonal: the ring sums of eq. Ni-dense at frequencies 0 and 2m
 // ---------------------------------------------------------------------------
@@ -680,6 +761,40 @@ int launch_dense_apply(const double *Ainv, int n, const int *act_idx, const doub
 int launch_unit_vectors(double *x, long long nalm, const int *idx, int j0, int np, hipStream_t s) {
     MLCR_HIP_CHECK(hipMemsetAsync(x, 0, (size_t)np * nalm * sizeof(double), s));
     hipLaunchKernelGGL(k_unit_vectors, dim3((np + 63) / 64), dim3(64), 0, s, x, nalm, idx, j0, np);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_dots(const double *a, const double *b, const double *c, const double *d, int lmax,
+                int nrhs, double *partial, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_dots, dim3(lmax + 1, nrhs), dim3(256), 0, s, a, b, c, d, lmax, partial);
+    MLCR_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_wnorms_final, dim3(nrhs), dim3(256), 0, s, partial, lmax + 1, out);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_lincomb(const double *u, const double *v, double *out, const double *al,
+                   const double *be, long long n, int nrhs, hipStream_t s) {
+    const long long blocks = std::min<long long>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_lincomb, dim3((unsigned)blocks, nrhs), dim3(256), 0, s, u, v, out, al, be,
+                       n);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_cr_pix(const double *d, const double *w2, const double *ninv, double *pix,
+                  long long npix, int nrhs, hipStream_t s) {
+    const long long blocks = std::min<long long>((npix + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_cr_pix, dim3((unsigned)blocks, nrhs), dim3(256), 0, s, d, w2, ninv, pix,
+                       npix);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_cr_combine(const double *v, const double *w1, const double *bh, const double *dd,
+                      double *b, int lmax, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_cr_combine, dim3(lmax + 1, nrhs), dim3(256), 0, s, v, w1, bh, dd, b, lmax);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }
