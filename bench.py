@@ -204,7 +204,7 @@ def roofline(kernels, cfg, R, path: str):
     return roof
 
 
-def solve_bench(mlcr, torch, cfg, geom, op, xt, R, paths, max_cycles, target=1e-3):
+def solve_bench(mlcr, torch, cfg, geom, op, xt, R, paths, max_cycles, target=1e-3, pcg=False):
     """W-cycle solves of b = A x_true (x_true ~ N(0, S), b by the float64
     apply); cycle by cycle, the max pixel error |Y (x - x_true)| (float64
     synthesis, all pixels) until every RHS is within `target` uK.  Reports
@@ -246,6 +246,21 @@ def solve_bench(mlcr, torch, cfg, geom, op, xt, R, paths, max_cycles, target=1e-
         ok = hist[-1]["max_err_uK"] <= target
         out["paths"][p] = {"time_s": elapsed if ok else None, "cycles": len(hist),
                            "reached": ok, "history": hist}
+        if pcg:
+            # CG with the cycle as preconditioner: k iterations from zero, k = 1, 2, ...
+            # until the error is within target (each run timed whole)
+            for k in range(1, max_cycles + 1):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                x, info = S.solve_pcg(b, rtol=0.0, max_iter=k, prec=precs[p], raise_on_noconv=False)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t
+                err = float(mlcr.sht_synth(geom, x - xt).abs().amax())
+                log(f"[bench] {p} pcg {k} iterations: max pixel error {err:.3e} uK, {el:.2f}s")
+                if err <= target:
+                    break
+            out["paths"][p]["pcg"] = {"time_s": el if err <= target else None, "iterations": k,
+                                      "max_err_uK": err}
     t64 = out["paths"].get("fp64", {}).get("time_s")
     for p, v in out["paths"].items():
         v["speedup_vs_fp64"] = (t64 / v["time_s"]) if (t64 and v["time_s"]) else None
@@ -308,6 +323,8 @@ def main():
     ap.add_argument("--paths", default="bf16x3,fp32,fp64",
                     help="Legendre paths to time; the first is the reported value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pcg", action="store_true",
+                    help="with --solve: also time CG with the cycle as preconditioner")
     ap.add_argument("--mixed", action="store_true",
                     help="time the mixed batch of independent problems solved one after another "
                          "and as one grouped solve")
@@ -366,8 +383,8 @@ def main():
     log(f"[bench] geometry + operator ready in {time.time() - t0:.1f}s")
 
     if args.solve:
-        print(json.dumps(solve_bench(mlcr, torch, cfg, geom, op, x, R, paths, args.max_cycles)),
-              flush=True)
+        print(json.dumps(solve_bench(mlcr, torch, cfg, geom, op, x, R, paths, args.max_cycles,
+                                     pcg=args.pcg)), flush=True)
         return
 
     res, outs = {}, {}
