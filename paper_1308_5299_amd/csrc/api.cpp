@@ -59,7 +59,8 @@ int ensure_dynamic_lds(const void *func, size_t bytes) {
 
 static void release_geom(mlcr_geom *g) {
     DevBuf *bufs[] = {&g->ring_z, &g->ring_s, &g->ring_w, &g->rings, &g->lens, &g->order, &g->T, &g->Bf,
-                      &g->W, &g->ab, &g->aboff, &g->seed, &g->zeros, &g->wsF, &g->wsP, &g->wsU};
+                      &g->W, &g->Bf32, &g->W32, &g->ab, &g->aboff, &g->seed, &g->zeros, &g->wsF, &g->wsP,
+                      &g->wsU};
     for (DevBuf *b : bufs) b->release();
     for (SegTable &t : g->seg) {
         t.st.release();
@@ -219,7 +220,7 @@ int apply_level(mlcr_op *op, int level, int nrhs, const double *x, double *y, in
     if ((rc = legendre_synth_any(a, x, L.bh.as<double>(), g, F, prec))) return rc;
     {
         KTimer t("ring_apply", s);
-        if ((rc = launch_ring_apply(g, lmax, nrhs, F, ninv, s))) return rc;
+        if ((rc = launch_ring_apply(g, lmax, nrhs, F, ninv, prec != MLCR_FP64, s))) return rc;
     }
     if ((rc = legendre_adjoint_any(a, F, g, x, L.d.as<double>(), L.bh.as<double>(), y, prec)))
         return rc;

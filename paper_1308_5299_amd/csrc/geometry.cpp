@@ -314,6 +314,14 @@ static int finish_geometry(mlcr_geom *g, int lmax, const std::vector<double> &z,
     if ((rc = up(g->T, T.data(), T.size() * sizeof(double2)))) return rc;
     if ((rc = up(g->Bf, Bf.data(), Bf.size() * sizeof(double2)))) return rc;
     if ((rc = up(g->W, W.data(), W.size() * sizeof(double2)))) return rc;
+    {
+        // float32 copies for the mixed-precision operator step's FFTs
+        std::vector<float2> Bf32(Bf.size()), W32(W.size());
+        for (size_t i = 0; i < Bf.size(); i++) Bf32[i] = make_float2((float)Bf[i].x, (float)Bf[i].y);
+        for (size_t i = 0; i < W.size(); i++) W32[i] = make_float2((float)W[i].x, (float)W[i].y);
+        if ((rc = up(g->Bf32, Bf32.data(), Bf32.size() * sizeof(float2)))) return rc;
+        if ((rc = up(g->W32, W32.data(), W32.size() * sizeof(float2)))) return rc;
+    }
     if ((rc = up(g->ab, ab.data(), ab.size() * sizeof(double2)))) return rc;
     if ((rc = up(g->aboff, aboff.data(), aboff.size() * sizeof(long long)))) return rc;
     if ((rc = up(g->seed, seed.data(), seed.size() * sizeof(double)))) return rc;

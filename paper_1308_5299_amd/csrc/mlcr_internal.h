@@ -97,6 +97,7 @@ struct mlcr_geom {
     mlcr::DevBuf T;                     // double2, all twiddle tables
     mlcr::DevBuf Bf;                    // double2, all Bluestein filters
     mlcr::DevBuf W;                     // double2, e^{-2 pi i j / Wmax}, j < Wmax
+    mlcr::DevBuf Bf32, W32;             // float2 copies of Bf and W (float32 operator FFTs)
     mlcr::DevBuf ab;                    // double2 (A_lm, B_lm) recurrence coefficients
     mlcr::DevBuf aboff;                 // long long per m
     mlcr::DevBuf seed;                  // double per m: seed constant of lambda_mm
@@ -161,8 +162,9 @@ int launch_ring_synth(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, 
                       hipStream_t s);
 int launch_ring_adjoint(const mlcr_geom *g, int lmax, int nrhs, const double *map, double2 *G,
                         hipStream_t s);
+// f32: FFTs in float32 (LDS buffer and Bluestein filter), fold/unfold in float64
 int launch_ring_apply(const mlcr_geom *g, int lmax, int nrhs, double2 *FG, const double *ninv,
-                      hipStream_t s);
+                      bool f32, hipStream_t s);
 // out[p] = W_ring(p) in[p]: a map times the grid's quadrature weights
 int launch_ring_weight(const mlcr_geom *g, const double *in, double *out, hipStream_t s);
 int adjoint_chunks(const mlcr_geom *g, int lmax);

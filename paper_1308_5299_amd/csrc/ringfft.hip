@@ -30,6 +30,8 @@ namespace mlcr {
 static constexpr int kRingThreads = 512;
 static constexpr double kSqrt2 = 1.4142135623730950488;
 
+// Complex arithmetic on double2 (float64 path) and float2 (the float32 FFT of
+// the mixed-precision operator step).
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -37,44 +39,83 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+template <typename C>
+struct ScalarOf;
+template <>
+struct ScalarOf<double2> {
+    typedef double T;
+};
+template <>
+struct ScalarOf<float2> {
+    typedef float T;
+};
+
+template <typename C>
+__device__ __forceinline__ C to_c(double2 v);
+template <>
+__device__ __forceinline__ double2 to_c<double2>(double2 v) { return v; }
+template <>
+__device__ __forceinline__ float2 to_c<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ double2 to_d(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d(float2 v) { return make_double2((double)v.x, (double)v.y); }
 
 // Small DFTs in registers.  Forward: X_r = sum_j x_j e^{-2 pi i j r / R};
 // INV flips the sign of the exponent.
-template <bool INV>
-__device__ __forceinline__ double2 mul_mi(double2 a) {      // a * (-i), or a * i if INV
-    return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+template <bool INV, typename C>
+__device__ __forceinline__ C mul_mi(C a) {      // a * (-i), or a * i if INV
+    C o;
+    o.x = INV ? -a.y : a.y;
+    o.y = INV ? a.x : -a.x;
+    return o;
 }
 
-template <bool INV>
-__device__ __forceinline__ void dft4(double2 &x0, double2 &x1, double2 &x2, double2 &x3) {
-    const double2 a = cadd(x0, x2), b = csub(x0, x2), c = cadd(x1, x3);
-    const double2 d = mul_mi<INV>(csub(x1, x3));
+template <bool INV, typename C>
+__device__ __forceinline__ void dft4(C &x0, C &x1, C &x2, C &x3) {
+    const C a = cadd(x0, x2), b = csub(x0, x2), c = cadd(x1, x3);
+    const C d = mul_mi<INV>(csub(x1, x3));
     x0 = cadd(a, c);
     x2 = csub(a, c);
     x1 = cadd(b, d);
     x3 = csub(b, d);
 }
 
-template <int R, bool INV>
-__device__ __forceinline__ void dft(double2 (&x)[R]) {
+template <int R, bool INV, typename C>
+__device__ __forceinline__ void dft(C (&x)[R]) {
+    typedef typename ScalarOf<C>::T S;
     if constexpr (R == 2) {
-        const double2 a = x[0];
+        const C a = x[0];
         x[0] = cadd(a, x[1]);
         x[1] = csub(a, x[1]);
     } else if constexpr (R == 4) {
         dft4<INV>(x[0], x[1], x[2], x[3]);
     } else {
         // radix-2 split into even and odd 4-point DFTs, then w^r = e^{-2 pi i r / 8}
-        double2 e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
-        double2 o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
+        C e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
+        C o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
         dft4<INV>(e0, e1, e2, e3);
         dft4<INV>(o0, o1, o2, o3);
-        constexpr double h = 0.70710678118654752440;
-        const double2 w1o = INV ? make_double2(h * (o1.x - o1.y), h * (o1.x + o1.y))
-                                : make_double2(h * (o1.x + o1.y), h * (o1.y - o1.x));
-        const double2 w2o = mul_mi<INV>(o2);
-        const double2 w3o = INV ? make_double2(-h * (o3.x + o3.y), h * (o3.x - o3.y))
-                                : make_double2(h * (o3.y - o3.x), -h * (o3.x + o3.y));
+        constexpr S h = (S)0.70710678118654752440;
+        C w1o, w3o;
+        if (INV) {
+            w1o.x = h * (o1.x - o1.y);
+            w1o.y = h * (o1.x + o1.y);
+            w3o.x = -h * (o3.x + o3.y);
+            w3o.y = h * (o3.x - o3.y);
+        } else {
+            w1o.x = h * (o1.x + o1.y);
+            w1o.y = h * (o1.y - o1.x);
+            w3o.x = h * (o3.y - o3.x);
+            w3o.y = -h * (o3.x + o3.y);
+        }
+        const C w2o = mul_mi<INV>(o2);
         x[0] = cadd(e0, o0);
         x[4] = csub(e0, o0);
         x[1] = cadd(e1, w1o);
@@ -90,13 +131,12 @@ __device__ __forceinline__ void dft(double2 (&x)[R]) {
 // butterfly i (k = i mod p) reads x[i + j M/R], scales input j by
 // w^{j k} with w = e^{-2 pi i / (p R)}, does an R-point DFT and writes
 // output r to x[(i - k) R + k + r p].  W[j] = e^{-2 pi i j / Wmax}.
-template <int R, bool INV, int NT>
-__device__ __forceinline__ void fft_pass(double2 *buf, int M, int p, const double2 *__restrict__ W,
-                                         int Wmax) {
+template <int R, bool INV, int NT, typename C>
+__device__ __forceinline__ void fft_pass(C *buf, int M, int p, const C *__restrict__ W, int Wmax) {
     constexpr int CMAX = 8192 / (R * NT) > 0 ? 8192 / (R * NT) : 1;
     const int T = M / R;
     const int ts = Wmax / (p * R);
-    double2 v[CMAX][R];
+    C v[CMAX][R];
 #pragma unroll
     for (int c = 0; c < CMAX; c++) {
         const int i = threadIdx.x + c * NT;
@@ -107,7 +147,7 @@ __device__ __forceinline__ void fft_pass(double2 *buf, int M, int p, const doubl
             if (p > 1) {
 #pragma unroll
                 for (int j = 1; j < R; j++) {
-                    double2 w = W[j * k * ts];
+                    C w = W[j * k * ts];
                     if (INV) w.y = -w.y;
                     v[c][j] = cmul(v[c][j], w);
                 }
@@ -132,8 +172,8 @@ __device__ __forceinline__ void fft_pass(double2 *buf, int M, int p, const doubl
 // Unnormalized DFT of size M (a power of two, M <= 8192) held in LDS, in
 // place, all threads of the block taking part: one radix-2 or radix-4 pass
 // when log2 M is not a multiple of 3, then radix-8 passes.
-template <bool INV, int NT>
-__device__ void lds_fft_t(double2 *buf, int M, const double2 *__restrict__ W, int Wmax) {
+template <bool INV, int NT, typename C>
+__device__ void lds_fft_t(C *buf, int M, const C *__restrict__ W, int Wmax) {
     const int lg = 31 - __clz(M);
     int p = 1;
     if (lg % 3 == 1) {
@@ -146,9 +186,9 @@ __device__ void lds_fft_t(double2 *buf, int M, const double2 *__restrict__ W, in
     for (; p < M; p *= 8) fft_pass<8, INV, NT>(buf, M, p, W, Wmax);
 }
 
-template <int NT>
-__device__ __forceinline__ void lds_fft(double2 *buf, int M, bool inverse,
-                                        const double2 *__restrict__ W, int Wmax) {
+template <int NT, typename C>
+__device__ __forceinline__ void lds_fft(C *buf, int M, bool inverse, const C *__restrict__ W,
+                                        int Wmax) {
     if (inverse) lds_fft_t<true, NT>(buf, M, W, Wmax);
     else lds_fft_t<false, NT>(buf, M, W, Wmax);
 }
@@ -174,15 +214,20 @@ __device__ __forceinline__ double2 chirp(const double2 *__restrict__ TN, int t, 
 }
 
 // MODE 0: F -> map.  MODE 1: map -> G.  MODE 2: F -> N^-1 map -> G (G over F).
-template <int MODE, int NT>
+// C: complex type of the LDS buffer, the FFTs and the Bluestein filter
+// (double2, or float2 for the mixed-precision operator step); the fold and
+// unfold with their phases run in float64 either way.
+template <int MODE, int NT, typename C>
 __global__ __launch_bounds__(NT) void k_ring(
     const double2 *Fin, double2 *Gout, const double *__restrict__ map_in,
     double *__restrict__ map_out, const double *__restrict__ ninv,
     const RingInfo *__restrict__ rings, const LenInfo *__restrict__ lens,
-    const int *__restrict__ order, const double2 *__restrict__ T, const double2 *__restrict__ Bf,
-    const double2 *__restrict__ W, int Wmax, int lmax, long long fstride, long long npix,
+    const int *__restrict__ order, const double2 *__restrict__ T, const C *__restrict__ Bf,
+    const C *__restrict__ W, int Wmax, int lmax, long long fstride, long long npix,
     int goff, int gcount, int nrhs) {
-    extern __shared__ double2 buf[];
+    typedef typename ScalarOf<C>::T S;
+    extern __shared__ __align__(16) unsigned char smem_ring[];
+    C *buf = reinterpret_cast<C *>(smem_ring);
     const int xcd = blockIdx.x & 7, seq = blockIdx.x >> 3;
     const int jr = (seq / nrhs) * 8 + xcd;
     if (jr >= gcount) return;
@@ -195,15 +240,16 @@ __global__ __launch_bounds__(NT) void k_ring(
     const double2 *TN = T + L.toff;
     const bool blue = L.boff >= 0;
     const int M = L.M;
-    const double2 *Bk = Bf + (blue ? L.boff : 0);
-    const double invM = 1.0 / (double)M;
+    const C *Bk = Bf + (blue ? L.boff : 0);
+    const S invM = (S)(1.0 / (double)M);
     const int ld = lmax + 1;
     const long long pix0 = (long long)r * npix + ri.start;
+    const C czero = to_c<C>(make_double2(0.0, 0.0));
 
     if (MODE != 1) {
         const double2 *Fk = Fin + (long long)r * fstride + (long long)k * ld;
         if (blue)
-            for (int t = n + tid; t < M; t += NT) buf[t] = make_double2(0.0, 0.0);
+            for (int t = n + tid; t < M; t += NT) buf[t] = czero;
         // Z_k = (G_k + G_{k+n}) + i w^k (G_k - G_{k+n}),  G_q = (Hhat_q + conj Hhat_{N-q}) / 2,
         // w = e^{2 pi i / N}: the length-n DFT input whose inverse is z_t = f_2t + i f_2t+1.
         for (int kk = tid; 2 * kk <= n; kk += NT) {
@@ -218,7 +264,7 @@ __global__ __launch_bounds__(NT) void k_ring(
                 const double2 d = cmul(TN[2 * kk], csub(g0, g1));
                 double2 Z = make_double2(g0.x + g1.x - d.y, g0.y + g1.y + d.x);
                 if (blue) Z = cmul(Z, chirp(TN, kk, N));
-                buf[kk] = Z;
+                buf[kk] = to_c<C>(Z);
             }
             const int k2 = n - kk;
             if (kk > 0 && k2 > kk) {
@@ -227,7 +273,7 @@ __global__ __launch_bounds__(NT) void k_ring(
                 const double2 d = cmul(TN[2 * k2], csub(g0, g1));
                 double2 Z = make_double2(g0.x + g1.x - d.y, g0.y + g1.y + d.x);
                 if (blue) Z = cmul(Z, chirp(TN, k2, N));
-                buf[k2] = Z;
+                buf[k2] = to_c<C>(Z);
             }
         }
         __syncthreads();
@@ -239,23 +285,26 @@ __global__ __launch_bounds__(NT) void k_ring(
             __syncthreads();
             lds_fft<NT>(buf, M, true, W, Wmax);
             for (int t = tid; t < n; t += NT)
-                buf[t] = cscale(cmul(buf[t], chirp(TN, t, N)), invM);
+                buf[t] = cscale(cmul(buf[t], to_c<C>(chirp(TN, t, N))), invM);
             __syncthreads();
         }
         if (MODE == 0) {
             double2 *out = reinterpret_cast<double2 *>(map_out + pix0);
-            for (int t = tid; t < n; t += NT) out[t] = buf[t];
+            for (int t = tid; t < n; t += NT) out[t] = to_d(buf[t]);
             return;
         }
         const double2 *ni = reinterpret_cast<const double2 *>(ninv + ri.start);
         for (int t = tid; t < n; t += NT) {
             const double2 w = ni[t];
-            const double2 v = buf[t];
-            buf[t] = make_double2(v.x * w.x, v.y * w.y);
+            const C v = buf[t];
+            C o;
+            o.x = v.x * (S)w.x;
+            o.y = v.y * (S)w.y;
+            buf[t] = o;
         }
     } else {
         const double2 *in = reinterpret_cast<const double2 *>(map_in + pix0);
-        for (int t = tid; t < n; t += NT) buf[t] = in[t];
+        for (int t = tid; t < n; t += NT) buf[t] = to_c<C>(in[t]);
     }
     // forward DFT of z (adjoint direction)
     if (!blue) {
@@ -263,14 +312,14 @@ __global__ __launch_bounds__(NT) void k_ring(
         lds_fft<NT>(buf, n, false, W, Wmax);
     } else {
         for (int t = tid; t < M; t += NT)
-            buf[t] = (t < n) ? cmul(buf[t], cconj(chirp(TN, t, N))) : make_double2(0.0, 0.0);
+            buf[t] = (t < n) ? cmul(buf[t], to_c<C>(cconj(chirp(TN, t, N)))) : czero;
         __syncthreads();
         lds_fft<NT>(buf, M, false, W, Wmax);
         for (int t = tid; t < M; t += NT) buf[t] = cmul(buf[t], cconj(Bk[t]));
         __syncthreads();
         lds_fft<NT>(buf, M, true, W, Wmax);
         for (int t = tid; t < n; t += NT)
-            buf[t] = cscale(cmul(buf[t], cconj(chirp(TN, t, N))), invM);
+            buf[t] = cscale(cmul(buf[t], to_c<C>(cconj(chirp(TN, t, N)))), invM);
         __syncthreads();
     }
     // unfold: Y_q from the half-length transform, then G_m for m = 0..lmax
@@ -279,7 +328,7 @@ __global__ __launch_bounds__(NT) void k_ring(
         const int q = m % N;
         const int kq = q % n;
         const int kc = kq == 0 ? 0 : n - kq;
-        const double2 A = buf[kq], B = cconj(buf[kc]);
+        const double2 A = to_d(buf[kq]), B = cconj(to_d(buf[kc]));
         const double2 E = cscale(cadd(A, B), 0.5);
         const double2 D = csub(A, B);
         const double2 O = make_double2(0.5 * D.y, -0.5 * D.x);     // (A - B) / (2i)
@@ -291,19 +340,19 @@ __global__ __launch_bounds__(NT) void k_ring(
     }
 }
 
-template <int MODE, int NT>
+template <int MODE, int NT, typename C>
 static int launch_group(const mlcr_geom *g, const RingGroup &grp, int lmax, int nrhs,
                         const double2 *F, double2 *G, const double *map_in, double *map_out,
-                        const double *ninv, long long fstride, hipStream_t s) {
-    const size_t lds = (size_t)grp.mmax * sizeof(double2);
-    int rc = ensure_dynamic_lds((const void *)k_ring<MODE, NT>, lds);
+                        const double *ninv, long long fstride, const C *Bf, const C *W,
+                        hipStream_t s) {
+    const size_t lds = (size_t)grp.mmax * sizeof(C);
+    int rc = ensure_dynamic_lds((const void *)k_ring<MODE, NT, C>, lds);
     if (rc) return rc;
     const long long nblk = 8LL * ((grp.count + 7) / 8) * nrhs;
-    hipLaunchKernelGGL((k_ring<MODE, NT>), dim3((unsigned)nblk), dim3(NT), lds, s, F, G, map_in,
+    hipLaunchKernelGGL((k_ring<MODE, NT, C>), dim3((unsigned)nblk), dim3(NT), lds, s, F, G, map_in,
                        map_out, ninv, g->rings.as<RingInfo>(), g->lens.as<LenInfo>(),
-                       g->order.as<int>(), g->T.as<double2>(), g->Bf.as<double2>(),
-                       g->W.as<double2>(), g->Wmax, lmax, fstride, g->npix, grp.off, grp.count,
-                       nrhs);
+                       g->order.as<int>(), g->T.as<double2>(), Bf, W, g->Wmax, lmax, fstride,
+                       g->npix, grp.off, grp.count, nrhs);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }
@@ -311,29 +360,40 @@ static int launch_group(const mlcr_geom *g, const RingGroup &grp, int lmax, int 
 // Groups whose FFT fills 128 KiB of LDS run one workgroup per CU: they get
 // 1024 threads (one butterfly per thread and radix-8 pass) so the CU still
 // holds 16 waves; the others use 512.
-template <int MODE>
-static int launch_ring(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, double2 *G,
-                       const double *map_in, double *map_out, const double *ninv,
-                       hipStream_t s) {
+template <int MODE, typename C>
+static int launch_ring_t(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, double2 *G,
+                         const double *map_in, double *map_out, const double *ninv, const C *Bf,
+                         const C *W, hipStream_t s) {
     const long long fstride = (long long)g->nrings * (lmax + 1);
     for (const RingGroup &grp : g->ring_groups) {
         const int rc = grp.mmax > 4096
                            ? launch_group<MODE, 1024>(g, grp, lmax, nrhs, F, G, map_in, map_out,
-                                                      ninv, fstride, s)
+                                                      ninv, fstride, Bf, W, s)
                            : launch_group<MODE, kRingThreads>(g, grp, lmax, nrhs, F, G, map_in,
-                                                              map_out, ninv, fstride, s);
+                                                              map_out, ninv, fstride, Bf, W, s);
         if (rc) return rc;
     }
     return MLCR_OK;
 }
 
+template <int MODE>
+static int launch_ring(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, double2 *G,
+                       const double *map_in, double *map_out, const double *ninv, bool f32,
+                       hipStream_t s) {
+    if (f32)
+        return launch_ring_t<MODE>(g, lmax, nrhs, F, G, map_in, map_out, ninv, g->Bf32.as<float2>(),
+                                   g->W32.as<float2>(), s);
+    return launch_ring_t<MODE>(g, lmax, nrhs, F, G, map_in, map_out, ninv, g->Bf.as<double2>(),
+                               g->W.as<double2>(), s);
+}
+
 int launch_ring_synth(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, double *map,
                       hipStream_t s) {
-    return launch_ring<0>(g, lmax, nrhs, F, nullptr, nullptr, map, nullptr, s);
+    return launch_ring<0>(g, lmax, nrhs, F, nullptr, nullptr, map, nullptr, false, s);
 }
 int launch_ring_adjoint(const mlcr_geom *g, int lmax, int nrhs, const double *map, double2 *G,
                         hipStream_t s) {
-    return launch_ring<1>(g, lmax, nrhs, nullptr, G, map, nullptr, nullptr, s);
+    return launch_ring<1>(g, lmax, nrhs, nullptr, G, map, nullptr, nullptr, false, s);
 }
 // one workgroup per ring
 __global__ __launch_bounds__(256) void k_ring_weight(const double *__restrict__ in,
@@ -353,8 +413,8 @@ int launch_ring_weight(const mlcr_geom *g, const double *in, double *out, hipStr
 }
 
 int launch_ring_apply(const mlcr_geom *g, int lmax, int nrhs, double2 *FG, const double *ninv,
-                      hipStream_t s) {
-    return launch_ring<2>(g, lmax, nrhs, FG, FG, nullptr, nullptr, ninv, s);
+                      bool f32, hipStream_t s) {
+    return launch_ring<2>(g, lmax, nrhs, FG, FG, nullptr, nullptr, ninv, f32, s);
 }
 
 }  // namespace mlcr
