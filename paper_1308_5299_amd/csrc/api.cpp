@@ -188,13 +188,15 @@ static int legendre_adjoint_any(const LegendreArgs &a, const double2 *G, mlcr_ge
     if (mm && (rc = seg_table(g, a.lmax, a.stream, &st))) return rc;
     {
         KTimer t("legendre_adjoint", a.stream);
-        if (prec == MLCR_BF16X3) rc = launch_legendre_adjoint_b3(a, st, G, P, &nch);
+        if (prec == MLCR_BF16X3) rc = launch_legendre_adjoint_b3(a, st, G, (float *)P, &nch);
         else if (mm) rc = launch_legendre_adjoint_mfma(a, st, G, P, &nch, prec == MLCR_FP64);
         else rc = launch_legendre_adjoint(a, G, P, &nch);
         if (rc) return rc;
     }
     KTimer t("unpack", a.stream);
-    return launch_unpack_t(a.lmax, a.nrhs, mm ? 8 : adj_rc(a.nrhs), nch, P, x, d, bh, y, a.stream);
+    // the matrix-core adjoints of the mixed paths store float32 partial sums
+    return launch_unpack_t(a.lmax, a.nrhs, mm ? 8 : adj_rc(a.nrhs), nch, P,
+                           mm && prec != MLCR_FP64, x, d, bh, y, a.stream);
 }
 
 }  // namespace mlcr

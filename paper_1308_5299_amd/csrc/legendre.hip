@@ -513,7 +513,8 @@ __global__ __launch_bounds__(256) void k_pack_t(const double *__restrict__ x,
 // tiles of 64 l are read row by row (the T layout is contiguous in
 // (l, r, cs)), summed over the chunks, transposed in LDS and written out
 // along l, so both sides stream.
-__global__ __launch_bounds__(256) void k_unpack_t(const double *__restrict__ P, int nchunks,
+template <typename PT>
+__global__ __launch_bounds__(256) void k_unpack_t(const PT *__restrict__ P, int nchunks,
                                                   int nrhs, int RC, const double *__restrict__ x,
                                                   const double *__restrict__ d,
                                                   const double *__restrict__ bh,
@@ -528,14 +529,14 @@ __global__ __launch_bounds__(256) void k_unpack_t(const double *__restrict__ P, 
     const int NC = 2 * RC;
     const long long ob = cos_base(m, lmax);
     const long long cstride = (long long)nrc * tri * NC;
-    const double *Pb = P + ((long long)rc * tri + tri_off(m, lmax)) * NC;
+    const PT *Pb = P + ((long long)rc * tri + tri_off(m, lmax)) * NC;
     for (int base = 0; base < nl; base += TL) {
         const int nt = min(TL, nl - base);
         for (int e = threadIdx.x; e < nt * NC; e += blockDim.x) {
             const int j = e / NC, comp = e % NC;
-            const double *src = Pb + (long long)base * NC + e;
+            const PT *src = Pb + (long long)base * NC + e;
             double acc = 0.0;
-            for (int c = 0; c < nchunks; c++) acc += src[c * cstride];
+            for (int c = 0; c < nchunks; c++) acc += (double)src[c * cstride];
             tile[j * 17 + comp] = acc;
         }
         __syncthreads();
@@ -592,12 +593,16 @@ int launch_pack_t(int lmax, int nrhs, int RC, const double *x, const double *dl,
     return MLCR_OK;
 }
 
-int launch_unpack_t(int lmax, int nrhs, int RC, int nchunks, const double *P, const double *x,
-                    const double *d, const double *bh, double *y, hipStream_t s) {
+int launch_unpack_t(int lmax, int nrhs, int RC, int nchunks, const void *P, bool pf32,
+                    const double *x, const double *d, const double *bh, double *y, hipStream_t s) {
     if (RC > 8) return fail(MLCR_EINVAL, "unpack supports at most 8 RHS per chunk");
     const int nrc = (nrhs + RC - 1) / RC;
-    hipLaunchKernelGGL(k_unpack_t, dim3(lmax + 1, nrc), dim3(256), 0, s, P, nchunks, nrhs, RC, x,
-                       d, bh, y, lmax);
+    if (pf32)
+        hipLaunchKernelGGL(k_unpack_t<float>, dim3(lmax + 1, nrc), dim3(256), 0, s,
+                           (const float *)P, nchunks, nrhs, RC, x, d, bh, y, lmax);
+    else
+        hipLaunchKernelGGL(k_unpack_t<double>, dim3(lmax + 1, nrc), dim3(256), 0, s,
+                           (const double *)P, nchunks, nrhs, RC, x, d, bh, y, lmax);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }

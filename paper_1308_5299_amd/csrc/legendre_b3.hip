@@ -30,10 +30,10 @@ namespace mlcr {
 // = ring); lane i + 16 kg reads rings 32 c + 8 kg .. + 7 of row i as its A
 // operand, the B operand holds the split even/odd ring sums of G for the same
 // rings.  The W tiles are summed in LDS and the chunk's partial sum stored
-// once (float64, T layout), exactly as the float32 adjoint does.
+// once (T layout, float32 partial sums), exactly as the float32 adjoint does.
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_ladj_b3(
-    const double2 *__restrict__ G, long long fstride, int nrhs, double *__restrict__ P, int lmax,
+    const double2 *__restrict__ G, long long fstride, int nrhs, float *__restrict__ P, int lmax,
     const double *__restrict__ rz, const double2 *__restrict__ ab,
     const long long *__restrict__ aboff, const double2 *__restrict__ st,
     const int *__restrict__ stsc, const int *__restrict__ lstab, int nb16, int nrings, int npairs,
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
     const double2 *abm = ab + aboff[m] - (m + 1);
     const int ld = lmax + 1;
     const int kg = lane >> 4, jc = lane & 15;
-    double *Pm = P + (((long long)chunk * nrc + rc) * tri + tri_off_m(m, lmax)) * 16;
+    float *Pm = P + (((long long)chunk * nrc + rc) * tri + tri_off_m(m, lmax)) * 16;
     const int rB = min(rc * 8 + (jc >> 1), nrhs - 1), csB = jc & 1;
 
     const int pb = chunk * W + wv;
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
     }
     // mode -1: before tw (or no block), 0: all lanes range-scaled, 1: some, 2: none
     int mode = -1;
-    for (int o = threadIdx.x; o < min(32 * t0, nl) * 16; o += 64 * W) Pm[o] = 0.0;
+    for (int o = threadIdx.x; o < min(32 * t0, nl) * 16; o += 64 * W) Pm[o] = 0.f;
     for (int t = t0; t < ntile; t++) {
         __syncthreads();
         if (threadIdx.x < kChunkM) {
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
 #pragma unroll
             for (int w = 0; w < W; w++)
                 a += (double)reinterpret_cast<const float *>(lam_all + w * LSB)[o];
-            Pm[(long long)(lb0 + lr) * 16 + (o & 15)] = a;
+            Pm[(long long)(lb0 + lr) * 16 + (o & 15)] = (float)a;
         }
     }
 }
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
 // launchers
 // ---------------------------------------------------------------------------
 template <int W>
-static int launch_ladj_b3_w(const LegendreArgs &a, const SegTable *st, const double2 *G, double *P,
+static int launch_ladj_b3_w(const LegendreArgs &a, const SegTable *st, const double2 *G, float *P,
                             int nchunks) {
     const mlcr_geom *g = a.g;
     const int npb = (g->npairs + 63) / 64;
@@ -237,7 +237,7 @@ static int launch_ladj_b3_w(const LegendreArgs &a, const SegTable *st, const dou
 
 // Same split-K chunking and P layout as the float32 adjoint (adjoint_chunks_mfma).
 int launch_legendre_adjoint_b3(const LegendreArgs &a, const SegTable *st, const double2 *G,
-                               double *P, int *nchunks_out) {
+                               float *P, int *nchunks_out) {
     if (st->lmax != a.lmax) return fail(MLCR_EINVAL, "start-state table of another band limit");
     const int npb = (a.g->npairs + 63) / 64;
     const int nchunks = adjoint_chunks_mfma(a.g, a.lmax);

@@ -55,11 +55,12 @@ struct Mma<double> {
 // 16 odd l - m) every wave forms its block's contribution
 //     D_even[l_i, c] = sum_k Lambda[ring_k, l_2i] g_even[ring_k, c]
 // with 16 MFMAs of 4 ring pairs each (likewise odd), the W tiles are summed
-// in LDS, and the chunk's partial sum is stored once (float64, T layout);
-// the chunks are added in the unpack step.
+// in LDS, and the chunk's partial sum is stored once (T layout, in the
+// contraction type: float32 for the mixed path, float64 for the float64
+// path); the chunks are added in float64 in the unpack step.
 template <typename T, int W>
 __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
-    const double2 *__restrict__ G, long long fstride, int nrhs, double *__restrict__ P, int lmax,
+    const double2 *__restrict__ G, long long fstride, int nrhs, T *__restrict__ P, int lmax,
     const double *__restrict__ rz, const double2 *__restrict__ ab,
     const long long *__restrict__ aboff, const double2 *__restrict__ st,
     const int *__restrict__ stsc, const int *__restrict__ lstab, int nb16, int nrings, int npairs,
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
     const double2 *abm = ab + aboff[m] - (m + 1);
     const int ld = lmax + 1;
     const int kq = lane >> 4, jc = lane & 15;
-    double *Pm = P + (((long long)chunk * nrc + rc) * tri + tri_off_m(m, lmax)) * 16;
+    T *Pm = P + (((long long)chunk * nrc + rc) * tri + tri_off_m(m, lmax)) * 16;
     const int rB = min(rc * 8 + (jc >> 1), nrhs - 1), csB = jc & 1;
 
     const int pb = chunk * W + wv;
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
     }
     // mode -1: before tw (or no block), 0: all lanes range-scaled, 1: some, 2: none
     int mode = -1;
-    for (int o = threadIdx.x; o < min(32 * t0, nl) * 16; o += 64 * W) Pm[o] = 0.0;
+    for (int o = threadIdx.x; o < min(32 * t0, nl) * 16; o += 64 * W) Pm[o] = (T)0;
     for (int t = t0; t < ntile; t++) {
         __syncthreads();
         if (threadIdx.x < kChunkM) {
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
             double a = 0.0;
 #pragma unroll
             for (int w = 0; w < W; w++) a += (double)lam_all[w * LS + o];
-            Pm[(long long)(lb0 + lr) * 16 + (o & 15)] = a;
+            Pm[(long long)(lb0 + lr) * 16 + (o & 15)] = (T)a;
         }
     }
 }
@@ -215,7 +216,7 @@ int adjoint_chunks_mfma(const mlcr_geom *g, int lmax) {
 }
 
 template <typename T, int W>
-static int launch_ladj_wg(const LegendreArgs &a, const SegTable *st, const double2 *G, double *P,
+static int launch_ladj_wg(const LegendreArgs &a, const SegTable *st, const double2 *G, T *P,
                           int nchunks) {
     const mlcr_geom *g = a.g;
     const int npb = (g->npairs + 63) / 64;
@@ -235,7 +236,7 @@ static int launch_ladj_wg(const LegendreArgs &a, const SegTable *st, const doubl
 }
 
 template <typename T>
-static int launch_ladj_t(const LegendreArgs &a, const SegTable *st, const double2 *G, double *P,
+static int launch_ladj_t(const LegendreArgs &a, const SegTable *st, const double2 *G, T *P,
                          int nchunks) {
     switch (adj_waves((a.g->npairs + 63) / 64)) {
     case 8: return launch_ladj_wg<T, 8>(a, st, G, P, nchunks);
@@ -247,11 +248,11 @@ static int launch_ladj_t(const LegendreArgs &a, const SegTable *st, const double
 
 // P: double T layout with 8 RHS per chunk
 int launch_legendre_adjoint_mfma(const LegendreArgs &a, const SegTable *st, const double2 *G,
-                                 double *P, int *nchunks_out, bool dbl) {
+                                 void *P, int *nchunks_out, bool dbl) {
     if (st->lmax != a.lmax) return fail(MLCR_EINVAL, "start-state table of another band limit");
     const int nchunks = adjoint_chunks_mfma(a.g, a.lmax);
-    const int rc = dbl ? launch_ladj_t<double>(a, st, G, P, nchunks)
-                       : launch_ladj_t<float>(a, st, G, P, nchunks);
+    const int rc = dbl ? launch_ladj_t<double>(a, st, G, (double *)P, nchunks)
+                       : launch_ladj_t<float>(a, st, G, (float *)P, nchunks);
     if (rc) return rc;
     *nchunks_out = nchunks;
     return MLCR_OK;

@@ -170,8 +170,9 @@ int launch_ring_weight(const mlcr_geom *g, const double *in, double *out, hipStr
 int adjoint_chunks(const mlcr_geom *g, int lmax);
 // matrix-core Legendre adjoint, 8 RHS per wave; dbl selects float64 MFMA
 // (else float32).
+// P holds float64 partial sums for dbl, float32 otherwise
 int launch_legendre_adjoint_mfma(const LegendreArgs &a, const SegTable *st, const double2 *G,
-                                 double *P, int *nchunks_out, bool dbl);
+                                 void *P, int *nchunks_out, bool dbl);
 int adjoint_chunks_mfma(const mlcr_geom *g, int lmax);
 // split-bfloat16 matrix-core Legendre kernels (legendre_b3.hip): U in blocks
 // of 16 l-steps per order, hi/lo bf16 planes; P as for the float32 adjoint.
@@ -186,14 +187,15 @@ int launch_legendre_synth_seg(const LegendreArgs &a, const SegTable *t, const vo
 int launch_pack_b3(int lmax, int nrhs, const double *x, const double *dl, void *U, hipStream_t s);
 int launch_legendre_synth_b3(const LegendreArgs &a, const void *U, double2 *F);
 int launch_legendre_adjoint_b3(const LegendreArgs &a, const SegTable *st, const double2 *G,
-                               double *P, int *nchunks_out);
+                               float *P, int *nchunks_out);
 // T layout ([RHS chunk][m][l - m][RC][cos, sin]) of the Legendre kernels
 int synth_rc(int nrhs);
 int adj_rc(int nrhs);
 long long tlayout_doubles(int lmax, int nrhs, int rc);
 int launch_pack_t(int lmax, int nrhs, int RC, const double *x, const double *dl, double *U,
                   hipStream_t s);
-int launch_unpack_t(int lmax, int nrhs, int RC, int nchunks, const double *P, const double *x,
-                    const double *d, const double *bh, double *y, hipStream_t s);
+// P: partial sums in float64, or float32 (pf32) from the mixed-precision adjoints
+int launch_unpack_t(int lmax, int nrhs, int RC, int nchunks, const void *P, bool pf32,
+                    const double *x, const double *d, const double *bh, double *y, hipStream_t s);
 
 }  // namespace mlcr
