@@ -123,13 +123,17 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
     // mode -1: before tw (or no block), 0: all lanes range-scaled, 1: some, 2: none
     int mode = -1;
     for (int o = threadIdx.x; o < min(32 * t0, nl) * 16; o += 64 * W) Pm[o] = (T)0;
+    // coefficients of tile t + 1 are loaded while tile t computes
+    auto coef_at = [&](int t) {
+        const int l = m + t * 32 + (int)threadIdx.x;
+        return (threadIdx.x < kChunkM && l + 1 <= lmax) ? abm[l + 1] : make_double2(0.0, 0.0);
+    };
+    double2 cpre = coef_at(t0);
     for (int t = t0; t < ntile; t++) {
         __syncthreads();
-        if (threadIdx.x < kChunkM) {
-            const int l = m + t * 32 + threadIdx.x;
-            sab[threadIdx.x] = (l + 1 <= lmax) ? abm[l + 1] : make_double2(0.0, 0.0);
-        }
+        if (threadIdx.x < kChunkM) sab[threadIdx.x] = cpre;
         __syncthreads();
+        if (t + 1 < ntile) cpre = coef_at(t + 1);
         if (t == tw) {
             const long long tix = ((long long)m * nb16 + 4 * pb + (lane >> 4)) * 64 + (lane & 15);
             const double2 s0 = st[tix];

@@ -153,10 +153,16 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
         // reads land in the next order's blocks or in the zeroed pad after the
         // last one; lambda is exactly 0 there (zero coefficients past lmax).
         const int q0 = seg0 / 16;
-        auto stage = [&](int t) {
-            __syncthreads();
+        // Coefficients of step t: lane i + 16 kg holds the one for step i of
+        // segment kg.  Loads for step t + 1 are issued before step t computes
+        // (software pipelining), so their latency hides behind the recurrence.
+        auto coef_at = [&](int t) {
             const int l = m + seg0 + 16 * t + jc;
-            sab[kg * CS + jc] = (l + 1 <= lmax) ? abm[l + 1] : make_double2(0.0, 0.0);
+            return (l + 1 <= lmax) ? abm[l + 1] : make_double2(0.0, 0.0);
+        };
+        auto stage = [&](double2 c) {
+            __syncthreads();
+            sab[kg * CS + jc] = c;
             __syncthreads();
         };
         auto all_in_range = [&]() {
@@ -182,10 +188,11 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
         };
         if constexpr (P == kSegPB3) {
             const uint4 *Ub = reinterpret_cast<const uint4 *>(Uv) + (ub + q0) * 64 + jc;
-            auto body = [&](int t, auto checked) {
-                uint4 bu[4];
+            auto load_u = [&](int t, uint4 (&bu)[4]) {
 #pragma unroll
                 for (int ph = 0; ph < 4; ph++) bu[ph] = Ub[(long long)t * 64 + ph * 16];
+            };
+            auto body = [&](const uint4 (&bu)[4], auto checked) {
                 uint4 ah[NB][2], al[NB][2];
 #pragma unroll
                 for (int d = 0; d < 4; d++) {           // steps 4 d .. 4 d + 3
@@ -224,23 +231,33 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
                     acc[nb][1] = mma_b3(al[nb][1], bu[2], acc[nb][1]);
                 }
             };
+            double2 cpre = coef_at(0);
+            uint4 ucur[4], unext[4];
+            load_u(0, ucur);
+            auto iter = [&](int t, auto checked) {
+                stage(cpre);
+#pragma unroll
+                for (int ph = 0; ph < 4; ph++) unext[ph] = ucur[ph];
+                if (t + 1 < nt) {
+                    cpre = coef_at(t + 1);
+                    load_u(t + 1, unext);
+                }
+                body(ucur, checked);
+#pragma unroll
+                for (int ph = 0; ph < 4; ph++) ucur[ph] = unext[ph];
+            };
             int t = 0;
-            for (; t < nt && !all_in_range(); t++) {
-                stage(t);
-                body(t, std::true_type{});
-            }
-            for (; t < nt; t++) {
-                stage(t);
-                body(t, std::false_type{});
-            }
+            for (; t < nt && !all_in_range(); t++) iter(t, std::true_type{});
+            for (; t < nt; t++) iter(t, std::false_type{});
         } else {
             constexpr int NV = 16 * (int)sizeof(T) / 16;     // uint4 per lane per block
             const uint4 *Ub = reinterpret_cast<const uint4 *>(reinterpret_cast<const T *>(Uv) +
                                                               ((ub + q0) * 16 + jc) * 16);
-            auto body = [&](int t, auto checked) {
-                uint4 raw[NV];
+            auto load_u = [&](int t, uint4 (&raw)[NV]) {
 #pragma unroll
                 for (int v = 0; v < NV; v++) raw[v] = Ub[(long long)t * 16 * NV + v];
+            };
+            auto body = [&](const uint4 (&raw)[NV], auto checked) {
 #pragma unroll
                 for (int s = 0; s < 16; s++) {
                     const double2 c = sab[kg * CS + s];
@@ -255,15 +272,19 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
                     }
                 }
             };
+            // (U is not prefetched here: the extra registers cost these
+            // wider-accumulator variants more occupancy than the latency they hide)
+            double2 cpre = coef_at(0);
+            auto iter = [&](int t, auto checked) {
+                stage(cpre);
+                uint4 ucur[NV];
+                load_u(t, ucur);
+                if (t + 1 < nt) cpre = coef_at(t + 1);
+                body(ucur, checked);
+            };
             int t = 0;
-            for (; t < nt && !all_in_range(); t++) {
-                stage(t);
-                body(t, std::true_type{});
-            }
-            for (; t < nt; t++) {
-                stage(t);
-                body(t, std::false_type{});
-            }
+            for (; t < nt && !all_in_range(); t++) iter(t, std::true_type{});
+            for (; t < nt; t++) iter(t, std::false_type{});
         }
     }
     // D[i][j] of chain nb: ring pair 64 pb + 16 nb + i, column j = jc = (rhs,
