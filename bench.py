@@ -204,7 +204,8 @@ def roofline(kernels, cfg, R, path: str):
     return roof
 
 
-def solve_bench(mlcr, torch, cfg, geom, op, xt, R, paths, max_cycles, target=1e-3, pcg=False):
+def solve_bench(mlcr, torch, cfg, geom, op, xt, R, paths, max_cycles, target=1e-3, pcg=False,
+                graph=False):
     """W-cycle solves of b = A x_true (x_true ~ N(0, S), b by the float64
     apply); cycle by cycle, the max pixel error |Y (x - x_true)| (float64
     synthesis, all pixels) until every RHS is within `target` uK.  Reports
@@ -228,6 +229,8 @@ def solve_bench(mlcr, torch, cfg, geom, op, xt, R, paths, max_cycles, target=1e-
         S.solve(b, rtol=0.0, max_cycles=1, prec=precs[p], raise_on_noconv=False)
     torch.cuda.synchronize()
     for p in paths:
+        # error history: one cycle per call (each call also recomputes the
+        # starting residual, so these times are not the solve time)
         x = torch.zeros_like(b)
         elapsed, hist = 0.0, []
         for c in range(max_cycles):
@@ -238,14 +241,32 @@ def solve_bench(mlcr, torch, cfg, geom, op, xt, R, paths, max_cycles, target=1e-
             torch.cuda.synchronize()
             elapsed += time.perf_counter() - t
             err = float(mlcr.sht_synth(geom, x - xt).abs().amax())
-            hist.append({"cycle": c + 1, "t": round(elapsed, 4), "max_err_uK": err,
-                         "rho": max(i["rho"] for i in info)})
-            log(f"[bench] {p} cycle {c + 1}: max pixel error {err:.3e} uK, {elapsed:.2f}s")
+            hist.append({"cycle": c + 1, "max_err_uK": err, "rho": max(i["rho"] for i in info)})
+            log(f"[bench] {p} cycle {c + 1}: max pixel error {err:.3e} uK")
             if err <= target:
                 break
         ok = hist[-1]["max_err_uK"] <= target
-        out["paths"][p] = {"time_s": elapsed if ok else None, "cycles": len(hist),
-                           "reached": ok, "history": hist}
+        nc = len(hist)
+        # the solve time: those cycles in one call, timed whole (direct launches,
+        # then with the cycles replayed from a HIP graph if asked)
+        times = {}
+        for mode in ((False, True) if graph else (False,)):
+            S.set_graph(mode)
+            S.solve(b, rtol=0.0, max_cycles=nc, prec=precs[p], raise_on_noconv=False)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            x1, _ = S.solve(b, rtol=0.0, max_cycles=nc, prec=precs[p], raise_on_noconv=False)
+            torch.cuda.synchronize()
+            times[mode] = time.perf_counter() - t
+            err1 = float(mlcr.sht_synth(geom, x1 - xt).abs().amax())
+            log(f"[bench] {p}: {nc} cycles in one call ({'graph' if mode else 'direct'}): "
+                f"{times[mode]:.3f}s, max pixel error {err1:.3e} uK")
+        S.set_graph(False)
+        out["paths"][p] = {"time_s": times[False] if ok else None, "cycles": nc, "reached": ok,
+                           "history": hist}
+        if graph:
+            out["paths"][p]["graph_time_s"] = times[True] if ok else None
+            out["paths"][p]["graph_stats"] = S.graph_stats()
         if pcg:
             # CG with the cycle as preconditioner: k iterations from zero, k = 1, 2, ...
             # until the error is within target (each run timed whole)
@@ -323,6 +344,8 @@ def main():
     ap.add_argument("--paths", default="bf16x3,fp32,fp64",
                     help="Legendre paths to time; the first is the reported value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="with --solve: also time whole solves with the cycle replayed from a HIP graph")
     ap.add_argument("--pcg", action="store_true",
                     help="with --solve: also time CG with the cycle as preconditioner")
     ap.add_argument("--mixed", action="store_true",
@@ -384,7 +407,7 @@ def main():
 
     if args.solve:
         print(json.dumps(solve_bench(mlcr, torch, cfg, geom, op, x, R, paths, args.max_cycles,
-                                     pcg=args.pcg)), flush=True)
+                                     pcg=args.pcg, graph=args.graph)), flush=True)
         return
 
     res, outs = {}, {}

@@ -237,6 +237,18 @@ int mlcr_solver_top_dinv(const mlcr_solver *s, double *dev_out, void *stream);
 int wcycle_solve(mlcr_solver *s, int nrhs, const double *dev_b, double *dev_x, double rtol,
                  int max_cycles, int prec, mlcr_solve_info *host_info, void *stream);
 
+/* Graph mode for wcycle_solve / wcycle_solve_grouped (default off): each
+ * solve runs its first cycle with direct launches, captures its second cycle
+ * (every kernel and device copy of the CR-Cycle plus the float64 residual)
+ * into a HIP graph and replays it for the cycles after; results are
+ * identical to direct launches.  The solve runs on a library-owned stream
+ * forked from and joined back into the caller's stream; a capture that fails
+ * falls back to direct launches.  The graph lives for one solve call. */
+int mlcr_solver_set_graph(mlcr_solver *s, int on);
+/* Cycles launched from a graph so far, and graph captures that fell back to
+ * direct launches, over the solver's lifetime (NULL outputs are skipped). */
+int mlcr_solver_graph_stats(const mlcr_solver *s, long long *replays, long long *fallbacks);
+
 /* CR-Solve by flexible preconditioned conjugate gradients in float64 with
  * one CR-Cycle from zero as the preconditioner, the alternative named in the
  * caption of Fig. code:mg: alpha = <r, z> / <p, A p>, x += alpha p,

@@ -39,6 +39,8 @@ SIGNATURES = {
     "mlcr_solver_top_dinv": (c_int, [c_void_p, c_void_p, c_void_p]),
     "wcycle_solve": (c_int, [c_void_p, c_int, c_void_p, c_void_p, ctypes.c_double, c_int, c_int,
                              c_void_p, c_void_p]),
+    "mlcr_solver_set_graph": (c_int, [c_void_p, c_int]),
+    "mlcr_solver_graph_stats": (c_int, [c_void_p, ctypes.POINTER(c_ll), ctypes.POINTER(c_ll)]),
     "pcg_solve": (c_int, [c_void_p, c_int, c_void_p, c_void_p, ctypes.c_double, c_int, c_int,
                           c_void_p, c_void_p]),
     "mlcr_cr_rhs": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),

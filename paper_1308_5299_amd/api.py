@@ -277,6 +277,15 @@ class Solver:
             check(rc)
         return x, out
 
+    def set_graph(self, on: bool = True) -> None:
+        """Replay the cycles of each solve from a captured HIP graph."""
+        check(load().mlcr_solver_set_graph(self._h, 1 if on else 0))
+
+    def graph_stats(self) -> dict:
+        r, f = ctypes.c_longlong(), ctypes.c_longlong()
+        check(load().mlcr_solver_graph_stats(self._h, ctypes.byref(r), ctypes.byref(f)))
+        return {"replays": r.value, "fallbacks": f.value}
+
     def solve_pcg(self, b: torch.Tensor, x0: torch.Tensor | None = None, rtol: float = 1e-8,
                   max_iter: int = 50, prec: int = FP64, raise_on_noconv: bool = True):
         """Conjugate gradients with one CR-Cycle as the preconditioner;

@@ -231,6 +231,8 @@ struct mlcr_solver {
     DevBuf pcg_p, pcg_zo, pcg_coef;
     std::vector<float> ridge_summary;
     int mode = 0;
+    int graph = 0;          // replay cycles 2.. of a solve from a captured graph
+    long long graph_replays = 0, graph_fallbacks = 0;
     ~mlcr_solver() {
         for (auto &L : lev)
             if (L->geom) mlcr_geom_destroy(L->geom);
@@ -315,8 +317,7 @@ struct GpuOps : CycleOps {
         if ((rc = launch_transfer(Rv(h), Lmax(h), Bv(h + 1), Lmax(h + 1), w, Lmax(h + 1), false, R,
                                   s)))
             return rc;
-        MLCR_HIP_CHECK(hipMemsetAsync(X(h + 1), 0, (size_t)R * nalm_l(Lmax(h + 1)) * sizeof(double), s));
-        return MLCR_OK;
+        return launch_fill_zero(X(h + 1), (long long)R * nalm_l(Lmax(h + 1)), s);
     }
     int prolong_up(int h) override {
         const double *w = h == 0 ? S->top_wdown.as<double>() : S->lev[h - 1]->wdown.as<double>();
@@ -839,21 +840,66 @@ struct SolveRun {
         for (int r = 0; r < nrhs; r++) all = all && rho[r] <= rtol;
         return MLCR_OK;
     }
-    // one cycle: solve A c = r from c = 0, x += c, then the new residual
-    int enqueue_cycle() {
+    // one cycle: solve A c = r from c = 0, x += c, then the new residual.
+    // Only kernels and device copies: in graph mode cycle 2 is captured
+    // (every workspace has reached its size in cycle 1) and later cycles
+    // replay it; a capture that fails falls back to direct launches.
+    hipGraphExec_t exec = nullptr;
+    bool graph_off = false;
+    ~SolveRun() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+    int enqueue_cycle_body() {
         const int lmax = S->op->lmax;
         const long long na = nalm_l(lmax);
         int rc;
         MLCR_HIP_CHECK(hipMemcpyAsync(S->b0.ptr, S->ro.ptr, (size_t)nrhs * na * sizeof(double),
                                       hipMemcpyDeviceToDevice, s));
-        MLCR_HIP_CHECK(hipMemsetAsync(S->x0.ptr, 0, (size_t)nrhs * na * sizeof(double), s));
+        if ((rc = launch_fill_zero(S->x0.as<double>(), (long long)nrhs * na, s))) return rc;
         GpuOps ops(S, nrhs, prec, s);
         if ((rc = cr_cycle(ops, 0, B, nr, true))) return rc;
         if ((rc = launch_axpy_l(x, S->x0.as<double>(), S->top_act.as<double>(), nullptr, lmax, nrhs,
                                 s)))
             return rc;
-        it++;
         return enqueue_residual();
+    }
+    int enqueue_cycle() {
+        int rc = MLCR_OK;
+        if (!S->graph || graph_off || it == 0) {
+            rc = enqueue_cycle_body();
+        } else if (exec) {
+            MLCR_HIP_CHECK(hipGraphLaunch(exec, s));
+            S->graph_replays++;
+        } else if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
+            (void)hipGetLastError();
+            graph_off = true;
+            S->graph_fallbacks++;
+            rc = enqueue_cycle_body();
+        } else {
+            rc = enqueue_cycle_body();
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(s, &graph);
+            if (rc) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            hipError_t ei = e;
+            if (e == hipSuccess && graph) ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (e != hipSuccess || !graph || ei != hipSuccess) {
+                (void)hipGetLastError();
+                exec = nullptr;
+                graph_off = true;
+                S->graph_fallbacks++;
+                rc = enqueue_cycle_body();      // the captured work did not run: run it now
+            } else {
+                MLCR_HIP_CHECK(hipGraphLaunch(exec, s));
+                S->graph_replays++;
+            }
+        }
+        if (rc) return rc;
+        it++;
+        return MLCR_OK;
     }
     int finish_cycle() {
         int rc;
@@ -904,12 +950,39 @@ int wcycle_solve(mlcr_solver *S, int nrhs, const double *b, double *x, double rt
                  int prec, mlcr_solve_info *info, void *stream) {
     int rc;
     if ((rc = check_solve_args(S, nrhs, b, x, rtol, max_cycles, prec))) return rc;
-    SolveRun run(S, nrhs, b, x, rtol, prec, (hipStream_t)stream);
-    if ((rc = run.enqueue_start()) || (rc = run.finish_start())) return rc;
-    while (!run.all && run.it < max_cycles)
-        if ((rc = run.enqueue_cycle()) || (rc = run.finish_cycle())) return rc;
-    if ((rc = run.finish(info))) return rc;
-    if (!run.all) return fail(MLCR_ENOCONV, "rtol not reached within max_cycles");
+    // graph mode runs on a pooled stream (the caller's may be the legacy
+    // default stream, which cannot be captured), forked and joined by events
+    StreamFork f;
+    hipStream_t s = (hipStream_t)stream;
+    if (S->graph) {
+        if ((rc = f.begin(s, {S->op->g}))) return rc;
+        s = f.item_stream[0];
+    }
+    {
+        SolveRun run(S, nrhs, b, x, rtol, prec, s);
+        if (!(rc = run.enqueue_start()) && !(rc = run.finish_start()))
+            while (!run.all && run.it < max_cycles)
+                if ((rc = run.enqueue_cycle()) || (rc = run.finish_cycle())) break;
+        if (!rc) rc = run.finish(info);
+        if (!rc && !run.all) rc = fail(MLCR_ENOCONV, "rtol not reached within max_cycles");
+    }
+    if (S->graph) {
+        const int rj = f.join();
+        if (!rc) rc = rj;
+    }
+    return rc;
+}
+
+int mlcr_solver_set_graph(mlcr_solver *S, int on) {
+    if (!S) return fail(MLCR_EINVAL, "NULL argument");
+    S->graph = on ? 1 : 0;
+    return MLCR_OK;
+}
+
+int mlcr_solver_graph_stats(const mlcr_solver *S, long long *replays, long long *fallbacks) {
+    if (!S) return fail(MLCR_EINVAL, "NULL argument");
+    if (replays) *replays = S->graph_replays;
+    if (fallbacks) *fallbacks = S->graph_fallbacks;
     return MLCR_OK;
 }
 
@@ -1007,7 +1080,7 @@ int pcg_solve(mlcr_solver *S, int nrhs, const double *b, double *x, double rtol,
     auto precond = [&]() -> int {     // z = M r: one cycle from zero on r
         MLCR_HIP_CHECK(hipMemcpyAsync(S->b0.ptr, r, (size_t)nrhs * na * sizeof(double),
                                       hipMemcpyDeviceToDevice, s));
-        MLCR_HIP_CHECK(hipMemsetAsync(z, 0, (size_t)nrhs * na * sizeof(double), s));
+        if (int r2 = launch_fill_zero(z, (long long)nrhs * na, s)) return r2;
         GpuOps ops(S, nrhs, prec, s);
         return cr_cycle(ops, 0, run.B, run.nr, true);
     };

@@ -44,6 +44,7 @@ int launch_dense_inverse(const double *L, int n, double *inv, hipStream_t s);
 int launch_dense_apply(const double *Ainv, int n, const int *act_idx, const double *b, double *x,
                        long long nalm, int nrhs, hipStream_t s);
 int launch_unit_vectors(double *x, long long nalm, const int *idx, int j0, int np, hipStream_t s);
+int launch_fill_zero(double *p, long long n, hipStream_t s);
 // per-RHS dot products (c, d may be null), out[2 r], out[2 r + 1]
 int launch_dots(const double *a, const double *b, const double *c, const double *d, int lmax,
                 int nrhs, double *partial, double *out, hipStream_t s);

@@ -140,6 +140,13 @@ __global__ __launch_bounds__(256) void k_wnorms_final(const double *__restrict__
     }
 }
 
+// p[0..n) = 0 (a kernel, not a memset: the cycle may be captured into a graph)
+__global__ __launch_bounds__(256) void k_fill_zero(double *__restrict__ p, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
 // per RHS: out[2 r] = <a, b>, out[2 r + 1] = <c, d> over all coefficients
 // (c, d may be null: 0); partial sums per order m, then k_wnorms_final
 __global__ __launch_bounds__(256) void k_dots(const double *__restrict__ a,
@@ -617,6 +624,14 @@ static inline unsigned nblk(long long n, int bs) {
     return (unsigned)std::min<long long>(std::max<long long>(b, 1), 65535LL * 4);
 }
 
+int launch_fill_zero(double *p, long long n, hipStream_t s) {
+    if (n <= 0) return MLCR_OK;
+    const long long blocks = std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
 int launch_transfer(const double *src, int lmax_src, double *dst, int lmax_dst, const double *w,
                     int lmax_w, bool add, int nrhs, hipStream_t s) {
     const int grid_m = std::max(lmax_dst, lmax_w) + 1;
@@ -628,7 +643,8 @@ int launch_transfer(const double *src, int lmax_src, double *dst, int lmax_dst, 
         const long long nd = (long long)(lmax_dst + 1) * (lmax_dst + 1);
         for (int r = 0; r < nrhs; r++) {
             const long long off = cos_base(lmax_w + 1, lmax_dst);
-            MLCR_HIP_CHECK(hipMemsetAsync(dst + r * nd + off, 0, (nd - off) * sizeof(double), s));
+            const int rc = launch_fill_zero(dst + r * nd + off, nd - off, s);
+            if (rc) return rc;
         }
     }
     return MLCR_OK;
@@ -798,5 +814,6 @@ int launch_cr_combine(const double *v, const double *w1, const double *bh, const
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }
+
 
 }  // namespace mlcr
