@@ -59,7 +59,7 @@ int ensure_dynamic_lds(const void *func, size_t bytes) {
 
 static void release_geom(mlcr_geom *g) {
     DevBuf *bufs[] = {&g->ring_z, &g->ring_s, &g->ring_w, &g->rings, &g->lens, &g->order, &g->T, &g->Bf,
-                      &g->W, &g->Bf32, &g->W32, &g->ab, &g->aboff, &g->seed, &g->zeros, &g->wsF, &g->wsP,
+                      &g->W, &g->Bf32, &g->W32, &g->ab, &g->alpha, &g->cfac, &g->aboff, &g->seed, &g->zeros, &g->wsF, &g->wsP,
                       &g->wsU};
     for (DevBuf *b : bufs) b->release();
     for (SegTable &t : g->seg) {
@@ -164,7 +164,7 @@ static int legendre_synth_any(const LegendreArgs &a, const double *x, const doub
         void *U = g->wsU.ptr;
         {
             KTimer t("pack", a.stream);
-            if ((rc = launch_pack_seg(a.lmax, a.nrhs, x, dl, U, prec, a.stream))) return rc;
+            if ((rc = launch_pack_seg(a.g, a.lmax, a.nrhs, x, dl, U, prec, a.stream))) return rc;
         }
         KTimer t("legendre_synth", a.stream);
         return launch_legendre_synth_seg(a, st, U, F, prec);
@@ -196,7 +196,8 @@ static int legendre_adjoint_any(const LegendreArgs &a, const double2 *G, mlcr_ge
     KTimer t("unpack", a.stream);
     // the matrix-core adjoints of the mixed paths store float32 partial sums
     return launch_unpack_t(a.lmax, a.nrhs, mm ? 8 : adj_rc(a.nrhs), nch, P,
-                           mm && prec != MLCR_FP64, x, d, bh, y, a.stream);
+                           mm && prec != MLCR_FP64, mm ? a.g->cfac.as<double>() : nullptr,
+                           a.g->lmax, x, d, bh, y, a.stream);
 }
 
 }  // namespace mlcr

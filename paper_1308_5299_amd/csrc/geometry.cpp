@@ -236,8 +236,14 @@ static int finish_geometry(mlcr_geom *g, int lmax, const std::vector<double> &z,
     // ---- Legendre recurrence (Sec. 3.2 normalization) ----
     // lambda_lm = A_lm z lambda_{l-1,m} - B_lm lambda_{l-2,m}, l >= m+1, with
     // A_lm = sqrt((4 l^2 - 1) / (l^2 - m^2)), B_lm = A_lm / A_{l-1,m}, B_{m+1,m} = 0.
+    // The matrix-core kernels run the same recurrence on mu_lm = lambda_lm / c_lm,
+    // c_mm = c_{m+1,m} = 1, c_lm = B_lm c_{l-2,m}, which has the two-operation form
+    //     mu_lm = alpha_lm z mu_{l-1,m} - mu_{l-2,m},  alpha_lm = A_lm c_{l-1,m} / c_lm;
+    // c is folded into their inputs and outputs (0.11 <= c <= 1.13, 1.5 <= alpha <= 182 for lmax <= 16384).
     const long long nab = (long long)lmax * (lmax + 1) / 2;
+    const long long ntri = (long long)(lmax + 1) * (lmax + 2) / 2;
     std::vector<double2> ab(std::max<long long>(nab, 1));
+    std::vector<double> alpha(std::max<long long>(nab, 1)), cfac(ntri);
     std::vector<long long> aboff(lmax + 1);
     std::vector<double> seed(lmax + 1);
     long double prod = 1.0L;     // prod_{k=1..m} (2k-1)/(2k)
@@ -250,10 +256,18 @@ static int finish_geometry(mlcr_geom *g, int lmax, const std::vector<double> &z,
     {
         auto fill_m = [&](int m) {
             long double aprev = 0.0L;
+            long double c2 = 1.0L, c1 = 1.0L;          // c_{l-2}, c_{l-1}
+            const long long to = (long long)m * (lmax + 1) - (long long)m * (m - 1) / 2;
+            cfac[to] = 1.0;
             for (int l = m + 1; l <= lmax; l++) {
                 long double a = sqrtl((4.0L * l * l - 1.0L) / ((long double)(l - m) * (l + m)));
                 long double b = (l == m + 1) ? 0.0L : a / aprev;
                 ab[aboff[m] + (l - m - 1)] = make_double2((double)a, (double)b);
+                const long double c = (l == m + 1) ? 1.0L : b * c2;
+                alpha[aboff[m] + (l - m - 1)] = (double)(a * c1 / c);
+                cfac[to + (l - m)] = (double)c;
+                c2 = c1;
+                c1 = c;
                 aprev = a;
             }
         };
@@ -323,6 +337,8 @@ static int finish_geometry(mlcr_geom *g, int lmax, const std::vector<double> &z,
         if ((rc = up(g->W32, W32.data(), W32.size() * sizeof(float2)))) return rc;
     }
     if ((rc = up(g->ab, ab.data(), ab.size() * sizeof(double2)))) return rc;
+    if ((rc = up(g->alpha, alpha.data(), alpha.size() * sizeof(double)))) return rc;
+    if ((rc = up(g->cfac, cfac.data(), cfac.size() * sizeof(double)))) return rc;
     if ((rc = up(g->aboff, aboff.data(), aboff.size() * sizeof(long long)))) return rc;
     if ((rc = up(g->seed, seed.data(), seed.size() * sizeof(double)))) return rc;
     std::vector<double> zeros(lmax + 1, 0.0);

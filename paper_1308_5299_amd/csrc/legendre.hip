@@ -515,7 +515,8 @@ __global__ __launch_bounds__(256) void k_pack_t(const double *__restrict__ x,
 // along l, so both sides stream.
 template <typename PT>
 __global__ __launch_bounds__(256) void k_unpack_t(const PT *__restrict__ P, int nchunks,
-                                                  int nrhs, int RC, const double *__restrict__ x,
+                                                  int nrhs, int RC, const double *__restrict__ cf,
+                                                  int glmax, const double *__restrict__ x,
                                                   const double *__restrict__ d,
                                                   const double *__restrict__ bh,
                                                   double *__restrict__ y, int lmax) {
@@ -546,6 +547,7 @@ __global__ __launch_bounds__(256) void k_unpack_t(const PT *__restrict__ P, int 
             if (r >= nrhs || (m == 0 && cs == 1)) continue;
             const int l = m + base + j;
             double v = tile[j * 17 + comp];
+            if (cf) v *= cf[tri_off(m, glmax) + l - m];
             if (bh) v *= bh[l];
             const long long idx = (long long)r * nalm + ob + (long long)cs * nl + base + j;
             if (d) v = fma(d[l], x[idx], v);
@@ -594,15 +596,16 @@ int launch_pack_t(int lmax, int nrhs, int RC, const double *x, const double *dl,
 }
 
 int launch_unpack_t(int lmax, int nrhs, int RC, int nchunks, const void *P, bool pf32,
-                    const double *x, const double *d, const double *bh, double *y, hipStream_t s) {
+                    const double *cf, int glmax, const double *x, const double *d,
+                    const double *bh, double *y, hipStream_t s) {
     if (RC > 8) return fail(MLCR_EINVAL, "unpack supports at most 8 RHS per chunk");
     const int nrc = (nrhs + RC - 1) / RC;
     if (pf32)
         hipLaunchKernelGGL(k_unpack_t<float>, dim3(lmax + 1, nrc), dim3(256), 0, s,
-                           (const float *)P, nchunks, nrhs, RC, x, d, bh, y, lmax);
+                           (const float *)P, nchunks, nrhs, RC, cf, glmax, x, d, bh, y, lmax);
     else
         hipLaunchKernelGGL(k_unpack_t<double>, dim3(lmax + 1, nrc), dim3(256), 0, s,
-                           (const double *)P, nchunks, nrhs, RC, x, d, bh, y, lmax);
+                           (const double *)P, nchunks, nrhs, RC, cf, glmax, x, d, bh, y, lmax);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }

@@ -34,14 +34,14 @@ namespace mlcr {
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_ladj_b3(
     const double2 *__restrict__ G, long long fstride, int nrhs, float *__restrict__ P, int lmax,
-    const double *__restrict__ rz, const double2 *__restrict__ ab,
+    const double *__restrict__ rz, const double *__restrict__ alpha,
     const long long *__restrict__ aboff, const double2 *__restrict__ st,
     const int *__restrict__ stsc, const int *__restrict__ lstab, int nb16, int nrings, int npairs,
     int npb, int nchunks, long long total) {
     constexpr int RW = 72;                      // bf16 per row: 64 rings + 8 pad (144 B)
     constexpr int LSB = 2 * 32 * RW * 2;        // bytes per wave: [hl][p * 16 + i][RW]
     extern __shared__ __align__(16) unsigned char smem[];
-    double2 *sab = reinterpret_cast<double2 *>(smem);
+    double *sab = reinterpret_cast<double *>(smem);
     unsigned char *lam_all = smem + kChunkM * sizeof(double2);
     int m, chunk, rc;
     bool ok;
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
     const int nl = lmax - m + 1;
     const long long tri = (long long)(lmax + 1) * (lmax + 2) / 2;
     const int nrc = (nrhs + 7) / 8;
-    const double2 *abm = ab + aboff[m] - (m + 1);
+    const double *abm = alpha + aboff[m] - (m + 1);
     const int ld = lmax + 1;
     const int kg = lane >> 4, jc = lane & 15;
     float *Pm = P + (((long long)chunk * nrc + rc) * tri + tri_off_m(m, lmax)) * 16;
@@ -112,9 +112,9 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
     // coefficients of tile t + 1 are loaded while tile t computes
     auto coef_at = [&](int t) {
         const int l = m + t * 32 + (int)threadIdx.x;
-        return (threadIdx.x < kChunkM && l + 1 <= lmax) ? abm[l + 1] : make_double2(0.0, 0.0);
+        return (threadIdx.x < kChunkM && l + 1 <= lmax) ? abm[l + 1] : 0.0;
     };
-    double2 cpre = coef_at(t0);
+    double cpre = coef_at(t0);
     for (int t = t0; t < ntile; t++) {
         __syncthreads();
         if (threadIdx.x < kChunkM) sab[threadIdx.x] = cpre;
@@ -162,13 +162,11 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
 #pragma unroll 8
                 for (int i = 0; i < 16; i++) {
                     const float fe = (float)L.l1;
-                    double2 c = sab[2 * i];
-                    double nv = fma(c.x, L.z * L.l1, -c.y * L.l2);
+                    double nv = fma(sab[2 * i] * L.z, L.l1, -L.l2);
                     L.l2 = L.l1;
                     L.l1 = nv;
                     const float fo = (float)L.l1;
-                    c = sab[2 * i + 1];
-                    nv = fma(c.x, L.z * L.l1, -c.y * L.l2);
+                    nv = fma(sab[2 * i + 1] * L.z, L.l1, -L.l2);
                     L.l2 = L.l1;
                     L.l1 = nv;
                     unsigned h, l;
@@ -232,7 +230,7 @@ static int launch_ladj_b3_w(const LegendreArgs &a, const SegTable *st, const dou
     int rc = ensure_dynamic_lds((const void *)k_ladj_b3<W>, lds);
     if (rc) return rc;
     hipLaunchKernelGGL((k_ladj_b3<W>), dim3((unsigned)grid), dim3(64 * W), lds, a.stream, G,
-                       fstride, a.nrhs, P, a.lmax, g->ring_z.as<double>(), g->ab.as<double2>(),
+                       fstride, a.nrhs, P, a.lmax, g->ring_z.as<double>(), g->alpha.as<double>(),
                        g->aboff.as<long long>(), st->st.as<double2>(), st->sc.as<int>(),
                        st->ls.as<int>(), 4 * npb, g->nrings, g->npairs, npb, nchunks, total);
     MLCR_HIP_CHECK(hipGetLastError());

@@ -71,12 +71,15 @@ __device__ __forceinline__ long long tri_off_m(int m, int lmax) {
     return (long long)m * (lmax + 1) - (long long)m * (m - 1) / 2;
 }
 
-// one ring pair per lane
+// one ring pair per lane, on the scaled recurrence mu_l = alpha_l z mu_{l-1} -
+// mu_{l-2} (lambda_l = c_l mu_l; the coefficient tables hold alpha, the
+// kernels' inputs and outputs carry c), values below range carried as
+// v 2^{-512 sc}
 struct Lane1 {
     int sc;
     double z, l1, l2;
-    __device__ __forceinline__ void step_rescale(double2 c) {
-        const double nv = fma(c.x, z * l1, -c.y * l2);
+    __device__ __forceinline__ void step_rescale(double a) {
+        const double nv = fma(a * z, l1, -l2);
         l2 = l1;
         l1 = nv;
         if (sc > 0 && fabs(nv) >= 0x1p400) {
@@ -86,15 +89,15 @@ struct Lane1 {
         }
     }
     __device__ __forceinline__ double w() const { return sc == 0 ? l1 : 0.0; }
-    __device__ __forceinline__ void step(double2 c) {
-        const double nv = fma(c.x, z * l1, -c.y * l2);
+    __device__ __forceinline__ void step(double a) {
+        const double nv = fma(a * z, l1, -l2);
         l2 = l1;
         l1 = nv;
     }
     // Range check after a run of 4 plain steps taken while every lane of the
-    // wave is still scaled (contributing nothing).  One step grows |lambda|
-    // by at most 2 max A_lm < 2 sqrt(2 lmax + 2) (< 2^8.5 for lmax <= 16384),
-    // so 4 steps stay far below overflow, and a lane that enters range inside
+    // wave is still scaled (contributing nothing).  One step grows
+    // max(|mu_l|, |mu_{l-1}|) by at most max alpha_lm + 1 (< 2^7.6 for
+    // lmax <= 16384), so 4 steps stay far below overflow, and a lane that enters range inside
     // a run has values below 2^-112 * 2^34 = 2^-78 there, too small to
     // change any sum.
     __device__ __forceinline__ void check_range() {
@@ -112,9 +115,9 @@ __device__ __forceinline__ int wave_mode1(const Lane1 &L) {
     return 1;
 }
 
-// U layout: per RHS chunk of 8 and order m, blocks of 16 l-steps; block q of
-// order m holds [p][hl][column j][8 bf16], element e at l = m + 16 q + 2 e + p
-// (1 KiB per block).  Order m has ceil((lmax - m + 1) / 16) blocks.
+// U layout: per RHS chunk of 8 and order m, blocks of 16 l-steps (the element
+// order inside a block depends on the arithmetic).  Order m has
+// ceil((lmax - m + 1) / 16) blocks followed by kSegOrderPad zeroed ones.
 __host__ __device__ inline long long b3_ceil16_sum(long long n) {   // sum_{k=1..n} ceil(k / 16)
     const long long q = n / 16, r = n % 16;
     return 8 * q * (q + 1) + r * (q + 1);
@@ -123,8 +126,14 @@ __host__ __device__ inline long long b3_qoff(int m, int lmax) {
     return b3_ceil16_sum(lmax + 1) - b3_ceil16_sum(lmax + 1 - m);
 }
 
-// zeroed blocks after the last U block of the segment-parallel synthesis
-constexpr int kSegPadBlocks = 4;
+// Zeroed blocks after each order's last U block: the trailing segments of
+// the segment-parallel synthesis run up to 63 steps past lmax, where the
+// scaled recurrence does not vanish (mu_l = -mu_{l-2} once alpha is 0).
+constexpr int kSegOrderPad = 3;
+__host__ __device__ inline long long seg_qoff(int m, int lmax) {
+    return b3_qoff(m, lmax) + (long long)kSegOrderPad * m;
+}
+__host__ __device__ inline long long seg_qtot(int lmax) { return seg_qoff(lmax + 1, lmax); }
 
 // split-bfloat16 operands (v_mfma_f32_16x16x32_bf16)
 typedef float f4b __attribute__((ext_vector_type(4)));

@@ -35,7 +35,7 @@ constexpr int kSegP32 = 0, kSegP64 = 1, kSegPB3 = 2;
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_seg_init(int lmax, const double *__restrict__ rz,
                                                  const double *__restrict__ rs,
-                                                 const double2 *__restrict__ ab,
+                                                 const double *__restrict__ alpha,
                                                  const long long *__restrict__ aboff,
                                                  const double *__restrict__ seedc, int npairs,
                                                  int npb, int nb16, long long total,
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(64) void k_seg_init(int lmax, const double *__restr
     const int b16 = pb * 4 + (lane >> 4);
     const int kp = pb * 64 + lane;
     const bool valid = kp < npairs;
-    const double2 *abm = ab + aboff[m] - (m + 1);
+    const double *abm = alpha + aboff[m] - (m + 1);
     const int nl = lmax - m + 1;
     const int nu = (nl + 15) / 16;
     Lane1 L;
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(64) void k_seg_init(int lmax, const double *__restr
 #pragma unroll
         for (int s = 0; s < 16; s++) {
             const int l = m + 16 * u + s;
-            L.step(l + 1 <= lmax ? abm[l + 1] : make_double2(0.0, 0.0));
+            L.step(l + 1 <= lmax ? abm[l + 1] : 0.0);
             if ((s & 3) == 3) L.check_range();
         }
     };
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(64) void k_seg_init(int lmax, const double *__restr
 template <int P>
 __global__ __launch_bounds__(64) void k_lsynth_seg(
     const void *__restrict__ Uv, int nrhs, double2 *__restrict__ F, long long fstride, int lmax,
-    const double *__restrict__ rz, const double2 *__restrict__ ab,
+    const double *__restrict__ rz, const double *__restrict__ alpha,
     const long long *__restrict__ aboff, const double2 *__restrict__ st,
     const int *__restrict__ stsc, const int *__restrict__ lstab, int nrings, int npairs, int nb16,
     int npb, long long total) {
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
     typedef typename std::conditional<P == kSegP64, d4s, f4b>::type acc_t;
     constexpr int NB = 4;
     constexpr int CS = 17;                      // padded coefficient row per segment
-    __shared__ double2 sab[4 * CS];
+    __shared__ double sab[4 * CS];
     int m, pb, rc;
     bool ok;
     decode_item_m(total, lmax, npb, m, pb, rc, ok);
@@ -147,20 +147,19 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
             L[nb].sc = stsc[tix];
         }
         const int seg0 = ls + kg * n4;                  // this lane's segment, offset from m
-        const long long ub = (long long)rc * b3_qoff(lmax + 1, lmax) + b3_qoff(m, lmax);
-        const double2 *abm = ab + aboff[m] - (m + 1);
-        // U block of step t: seg0 / 16 + t.  Past the order's last block the
-        // reads land in the next order's blocks or in the zeroed pad after the
-        // last one; lambda is exactly 0 there (zero coefficients past lmax).
+        const long long ub = (long long)rc * seg_qtot(lmax) + seg_qoff(m, lmax);
+        const double *abm = alpha + aboff[m] - (m + 1);
+        // U block of step t: seg0 / 16 + t.  The last segment ends at most
+        // 63 steps past lmax, inside the order's zeroed pad blocks.
         const int q0 = seg0 / 16;
         // Coefficients of step t: lane i + 16 kg holds the one for step i of
         // segment kg.  Loads for step t + 1 are issued before step t computes
         // (software pipelining), so their latency hides behind the recurrence.
         auto coef_at = [&](int t) {
             const int l = m + seg0 + 16 * t + jc;
-            return (l + 1 <= lmax) ? abm[l + 1] : make_double2(0.0, 0.0);
+            return (l + 1 <= lmax) ? abm[l + 1] : 0.0;
         };
-        auto stage = [&](double2 c) {
+        auto stage = [&](double c) {
             __syncthreads();
             sab[kg * CS + jc] = c;
             __syncthreads();
@@ -172,7 +171,7 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
             return __all(in);
         };
         // lambda of chain nb at the current step (0 while range-scaled), then one step
-        auto advance = [&](Lane1 &C, double2 c, int s, auto checked) -> double {
+        auto advance = [&](Lane1 &C, double c, int s, auto checked) -> double {
             double v;
             if constexpr (decltype(checked)::value) {
                 v = C.sc == 0 ? C.l1 : 0.0;
@@ -180,7 +179,7 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
                 if ((s & 3) == 3) C.check_range();
             } else {
                 v = C.l1;
-                const double nv = fma(c.x, C.z * C.l1, -c.y * C.l2);
+                const double nv = fma(c * C.z, C.l1, -C.l2);
                 C.l2 = C.l1;
                 C.l1 = nv;
             }
@@ -200,7 +199,7 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
 #pragma unroll
                     for (int s4 = 0; s4 < 4; s4++) {
                         const int s = 4 * d + s4;
-                        const double2 c = sab[kg * CS + s];
+                        const double c = sab[kg * CS + s];
 #pragma unroll
                         for (int nb = 0; nb < NB; nb++) f[nb][s4] = (float)advance(L[nb], c, s, checked);
                     }
@@ -231,7 +230,7 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
                     acc[nb][1] = mma_b3(al[nb][1], bu[2], acc[nb][1]);
                 }
             };
-            double2 cpre = coef_at(0);
+            double cpre = coef_at(0);
             uint4 ucur[4], unext[4];
             load_u(0, ucur);
             auto iter = [&](int t, auto checked) {
@@ -260,7 +259,7 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
             auto body = [&](const uint4 (&raw)[NV], auto checked) {
 #pragma unroll
                 for (int s = 0; s < 16; s++) {
-                    const double2 c = sab[kg * CS + s];
+                    const double c = sab[kg * CS + s];
                     const T u = reinterpret_cast<const T *>(raw)[s];
 #pragma unroll
                     for (int nb = 0; nb < NB; nb++) {
@@ -274,7 +273,7 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
             };
             // (U is not prefetched here: the extra registers cost these
             // wider-accumulator variants more occupancy than the latency they hide)
-            double2 cpre = coef_at(0);
+            double cpre = coef_at(0);
             auto iter = [&](int t, auto checked) {
                 stage(cpre);
                 uint4 ucur[NV];
@@ -309,12 +308,14 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
     }
 }
 
-// U from x (and the per-l weights dl, e.g. the beam): one workgroup per
-// (m, RHS chunk); tiles of 64 l are read along l for each of the 16 columns
-// (j = 2 r + cos/sin) into LDS and written as whole 16-step blocks.
+// U from x, times c_lm (lambda = c mu) and the per-l weights dl (e.g. the
+// beam): one workgroup per (m, RHS chunk); tiles of 64 l are read along l for
+// each of the 16 columns (j = 2 r + cos/sin) into LDS and written as whole
+// 16-step blocks, then the order's zeroed pad blocks.
 template <int P>
 __global__ __launch_bounds__(256) void k_pack_seg(const double *__restrict__ x,
                                                   const double *__restrict__ dl,
+                                                  const double *__restrict__ cfac, int glmax,
                                                   void *__restrict__ Uv, int lmax, int nrhs) {
     constexpr int TL = 64;
     __shared__ double tile[16][TL + 1];
@@ -322,12 +323,13 @@ __global__ __launch_bounds__(256) void k_pack_seg(const double *__restrict__ x,
     const long long nalm = (long long)(lmax + 1) * (lmax + 1);
     const int nl = lmax - m + 1;
     const long long ob = cos_base(m, lmax);
-    const long long qb = (long long)rc * b3_qoff(lmax + 1, lmax) + b3_qoff(m, lmax);
+    const long long qb = (long long)rc * seg_qtot(lmax) + seg_qoff(m, lmax);
+    const double *cm = cfac + tri_off_m(m, glmax) - m;   // c_lm at cm[l]
     constexpr int BU = P == kSegP64 ? 128 : 64;          // uint4 per 16-step block
     uint4 *U = reinterpret_cast<uint4 *>(Uv);
-    if (m == 0 && rc == 0) {                             // zeroed pad after the last block
-        uint4 *pad = U + (long long)gridDim.y * b3_qoff(lmax + 1, lmax) * BU;
-        for (int i = threadIdx.x; i < kSegPadBlocks * BU; i += blockDim.x)
+    {
+        uint4 *pad = U + (qb + (nl + 15) / 16) * BU;
+        for (int i = threadIdx.x; i < kSegOrderPad * BU; i += blockDim.x)
             pad[i] = make_uint4(0u, 0u, 0u, 0u);
     }
     for (int base = 0; base < nl; base += TL) {
@@ -336,7 +338,7 @@ __global__ __launch_bounds__(256) void k_pack_seg(const double *__restrict__ x,
             const int r = rc * 8 + (j >> 1), cs = j & 1;
             double v = 0.0;
             if (base + o < nl && r < nrhs && !(m == 0 && cs == 1)) {
-                v = x[(long long)r * nalm + ob + (long long)cs * nl + base + o];
+                v = x[(long long)r * nalm + ob + (long long)cs * nl + base + o] * cm[m + base + o];
                 if (dl) v *= dl[m + base + o];
             }
             tile[j][o] = v;
@@ -382,11 +384,8 @@ __global__ __launch_bounds__(256) void k_pack_seg(const double *__restrict__ x,
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-// 4 zeroed pad blocks follow the last block (reads of the last order's
-// trailing segments).
 long long seg_u_bytes(int lmax, int nrhs, int prec) {
-    return ((long long)((nrhs + 7) / 8) * b3_qoff(lmax + 1, lmax) + kSegPadBlocks) *
-           (prec == MLCR_FP64 ? 2048 : 1024);
+    return (long long)((nrhs + 7) / 8) * seg_qtot(lmax) * (prec == MLCR_FP64 ? 2048 : 1024);
 }
 
 int seg_table(mlcr_geom *g, int lmax, hipStream_t s, const SegTable **out) {
@@ -410,7 +409,7 @@ int seg_table(mlcr_geom *g, int lmax, hipStream_t s, const SegTable **out) {
     const long long total = mitems(lmax, npb, 1);
     const long long grid = ((total + 7) / 8) * 8;
     hipLaunchKernelGGL(k_seg_init, dim3((unsigned)grid), dim3(64), 0, s, lmax, g->ring_z.as<double>(),
-                       g->ring_s.as<double>(), g->ab.as<double2>(), g->aboff.as<long long>(),
+                       g->ring_s.as<double>(), g->alpha.as<double>(), g->aboff.as<long long>(),
                        g->seed.as<double>(), g->npairs, npb, nb16, total, t.st.as<double2>(),
                        t.sc.as<int>(), t.ls.as<int>());
     hipError_t e = hipGetLastError();
@@ -425,18 +424,18 @@ int seg_table(mlcr_geom *g, int lmax, hipStream_t s, const SegTable **out) {
     return MLCR_OK;
 }
 
-int launch_pack_seg(int lmax, int nrhs, const double *x, const double *dl, void *U, int prec,
-                    hipStream_t s) {
+int launch_pack_seg(const mlcr_geom *g, int lmax, int nrhs, const double *x, const double *dl,
+                    void *U, int prec, hipStream_t s) {
     const int nrc = (nrhs + 7) / 8;
     if (prec == MLCR_BF16X3)
-        hipLaunchKernelGGL(k_pack_seg<kSegPB3>, dim3(lmax + 1, nrc), dim3(256), 0, s, x, dl, U,
-                           lmax, nrhs);
+        hipLaunchKernelGGL(k_pack_seg<kSegPB3>, dim3(lmax + 1, nrc), dim3(256), 0, s, x, dl,
+                           g->cfac.as<double>(), g->lmax, U, lmax, nrhs);
     else if (prec == MLCR_FP64)
-        hipLaunchKernelGGL(k_pack_seg<kSegP64>, dim3(lmax + 1, nrc), dim3(256), 0, s, x, dl, U,
-                           lmax, nrhs);
+        hipLaunchKernelGGL(k_pack_seg<kSegP64>, dim3(lmax + 1, nrc), dim3(256), 0, s, x, dl,
+                           g->cfac.as<double>(), g->lmax, U, lmax, nrhs);
     else
-        hipLaunchKernelGGL(k_pack_seg<kSegP32>, dim3(lmax + 1, nrc), dim3(256), 0, s, x, dl, U,
-                           lmax, nrhs);
+        hipLaunchKernelGGL(k_pack_seg<kSegP32>, dim3(lmax + 1, nrc), dim3(256), 0, s, x, dl,
+                           g->cfac.as<double>(), g->lmax, U, lmax, nrhs);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }
@@ -452,7 +451,7 @@ int launch_legendre_synth_seg(const LegendreArgs &a, const SegTable *t, const vo
     const long long grid = ((total + 7) / 8) * 8;
     const long long fstride = (long long)g->nrings * (a.lmax + 1);
 #define MLCR_SEG_ARGS                                                                           \
-    U, a.nrhs, F, fstride, a.lmax, g->ring_z.as<double>(), g->ab.as<double2>(),                 \
+    U, a.nrhs, F, fstride, a.lmax, g->ring_z.as<double>(), g->alpha.as<double>(),               \
         g->aboff.as<long long>(), t->st.as<double2>(), t->sc.as<int>(), t->ls.as<int>(),         \
         g->nrings, g->npairs, nb16, npb, total
     if (prec == MLCR_BF16X3)

@@ -99,6 +99,8 @@ struct mlcr_geom {
     mlcr::DevBuf W;                     // double2, e^{-2 pi i j / Wmax}, j < Wmax
     mlcr::DevBuf Bf32, W32;             // float2 copies of Bf and W (float32 operator FFTs)
     mlcr::DevBuf ab;                    // double2 (A_lm, B_lm) recurrence coefficients
+    mlcr::DevBuf alpha;                 // double alpha_lm (same index as ab): mu recurrence
+    mlcr::DevBuf cfac;                  // double c_lm, [tri_off(m) + l - m] for this lmax
     mlcr::DevBuf aboff;                 // long long per m
     mlcr::DevBuf seed;                  // double per m: seed constant of lambda_mm
     mlcr::DevBuf zeros;                 // double[lmax+1] of zeros (absent sine block of m = 0)
@@ -174,14 +176,12 @@ int adjoint_chunks(const mlcr_geom *g, int lmax);
 int launch_legendre_adjoint_mfma(const LegendreArgs &a, const SegTable *st, const double2 *G,
                                  void *P, int *nchunks_out, bool dbl);
 int adjoint_chunks_mfma(const mlcr_geom *g, int lmax);
-// split-bfloat16 matrix-core Legendre kernels (legendre_b3.hip): U in blocks
-// of 16 l-steps per order, hi/lo bf16 planes; P as for the float32 adjoint.
-long long b3_u_bytes(int lmax, int nrhs);
+// split-bfloat16 matrix-core adjoint (legendre_b3.hip): P as for the float32 adjoint.
 // segment-parallel synthesis (legendre_seg.hip); prec: MLCR_FP32 / FP64 / BF16X3
 long long seg_u_bytes(int lmax, int nrhs, int prec);
 int seg_table(mlcr_geom *g, int lmax, hipStream_t s, const SegTable **out);
-int launch_pack_seg(int lmax, int nrhs, const double *x, const double *dl, void *U, int prec,
-                    hipStream_t s);
+int launch_pack_seg(const mlcr_geom *g, int lmax, int nrhs, const double *x, const double *dl,
+                    void *U, int prec, hipStream_t s);
 int launch_legendre_synth_seg(const LegendreArgs &a, const SegTable *t, const void *U, double2 *F,
                               int prec);
 int launch_pack_b3(int lmax, int nrhs, const double *x, const double *dl, void *U, hipStream_t s);
@@ -194,8 +194,11 @@ int adj_rc(int nrhs);
 long long tlayout_doubles(int lmax, int nrhs, int rc);
 int launch_pack_t(int lmax, int nrhs, int RC, const double *x, const double *dl, double *U,
                   hipStream_t s);
-// P: partial sums in float64, or float32 (pf32) from the mixed-precision adjoints
+// P: partial sums in float64, or float32 (pf32) from the mixed-precision adjoints;
+// cf (optional): c_lm of a geometry of band limit glmax, multiplied into the sums
+// (the matrix-core adjoints run the scaled recurrence mu = lambda / c)
 int launch_unpack_t(int lmax, int nrhs, int RC, int nchunks, const void *P, bool pf32,
-                    const double *x, const double *d, const double *bh, double *y, hipStream_t s);
+                    const double *cf, int glmax, const double *x, const double *d,
+                    const double *bh, double *y, hipStream_t s);
 
 }  // namespace mlcr

@@ -358,8 +358,8 @@ static int setup_top_diag(mlcr_solver *S, hipStream_t s) {
     LegendreArgs a{g, lmax, 1, s};
     int nch = 0;
     if ((rc = launch_legendre_adjoint_sq(a, G2.as<double2>(), g->wsP.as<double>(), &nch))) return rc;
-    if ((rc = launch_unpack_t(lmax, 1, adj_rc(1), nch, g->wsP.as<double>(), false, nullptr, nullptr,
-                              nullptr, q.as<double>(), s)))
+    if ((rc = launch_unpack_t(lmax, 1, adj_rc(1), nch, g->wsP.as<double>(), false, nullptr, 0,
+                              nullptr, nullptr, nullptr, q.as<double>(), s)))
         return rc;
     if ((rc = alloc(S->top_dinv, (size_t)nalm_l(lmax) * sizeof(double)))) return rc;
     const mlcr_level &L0 = op->levels[0];
