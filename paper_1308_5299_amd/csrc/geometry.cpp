@@ -302,9 +302,10 @@ static int finish_geometry(mlcr_geom *g, int lmax, const std::vector<double> &z,
         g->ring_groups.clear();
         for (int j = 0; j < nr;) {
             const int b = bucket(order[j]);
-            RingGroup grp{j, 0, 0};
+            RingGroup grp{j, 0, 0, 1 << 30};
             while (j < nr && bucket(order[j]) == b) {
                 grp.mmax = std::max(grp.mmax, li[ri[order[j]].tab].M);
+                grp.nmin = std::min(grp.nmin, ri[order[j]].nphi);
                 grp.count++;
                 j++;
             }

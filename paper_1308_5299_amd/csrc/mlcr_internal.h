@@ -62,6 +62,7 @@ struct LenInfo {
 // rings order[off .. off+count) share one ring-kernel launch; mmax = largest FFT size
 struct RingGroup {
     int off, count, mmax;
+    int nmin;           // smallest ring length N in the group
 };
 
 // Recurrence start states of the matrix-core Legendre kernels at one band

@@ -28,6 +28,10 @@
 namespace mlcr {
 
 static constexpr int kRingThreads = 512;
+// Rings of at most kFoldMax pixels fold their coefficients cooperatively
+// (all threads of the block, partial sums in LDS): there the fold
+// sum over m = q mod N has (lmax + 1) / N terms per residue q.
+static constexpr int kFoldMax = 1024;
 static constexpr double kSqrt2 = 1.4142135623730950488;
 
 // Complex arithmetic on double2 (float64 path) and float2 (the float32 FFT of
@@ -208,6 +212,35 @@ __device__ __forceinline__ double2 hhat(const double2 *__restrict__ Fk, int q, i
     return cmul(make_double2(ax, ay), TN[(q * p) % (2 * N)]);
 }
 
+// Hhat_q for every q < N (N <= kFoldMax) into hb, all NT threads taking part:
+// G = max(1, NT / N) threads per residue q sum every G-th term of its fold,
+// and the G partial sums are added in a fixed order (deterministic).
+template <int NT>
+__device__ void fold_coop(const double2 *__restrict__ Fk, int N, int p, int lmax,
+                          const double2 *__restrict__ TN, double2 *hb, double2 *pb) {
+    const int G = N >= NT ? 1 : NT / N;
+    for (int t = threadIdx.x; t < G * N; t += NT) {
+        const int q = t % N, g = t / N;
+        double ax = 0.0, ay = 0.0;
+        int j = g;
+        for (int m = q + g * N; m <= lmax; m += G * N, j += G) {
+            const double2 f = Fk[m];
+            double w = (m == 0) ? 1.0 : kSqrt2;
+            if ((j * p) & 1) w = -w;
+            ax = fma(w, f.x, ax);
+            ay = fma(-w, f.y, ay);
+        }
+        pb[t] = make_double2(ax, ay);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < N; q += NT) {
+        double2 s = pb[q];
+        for (int g = 1; g < G; g++) s = cadd(s, pb[g * N + q]);
+        hb[q] = cmul(s, TN[(q * p) % (2 * N)]);
+    }
+    __syncthreads();
+}
+
 // chirp q_t = e^{i pi t^2 / n} = T_N[2 t^2 mod 2N]
 __device__ __forceinline__ double2 chirp(const double2 *__restrict__ TN, int t, int N) {
     return TN[(int)((2LL * t * t) % (2LL * N))];
@@ -224,7 +257,7 @@ __global__ __launch_bounds__(NT) void k_ring(
     const RingInfo *__restrict__ rings, const LenInfo *__restrict__ lens,
     const int *__restrict__ order, const double2 *__restrict__ T, const C *__restrict__ Bf,
     const C *__restrict__ W, int Wmax, int lmax, long long fstride, long long npix,
-    int goff, int gcount, int nrhs) {
+    int goff, int gcount, int nrhs, int hoff) {
     typedef typename ScalarOf<C>::T S;
     extern __shared__ __align__(16) unsigned char smem_ring[];
     C *buf = reinterpret_cast<C *>(smem_ring);
@@ -250,14 +283,21 @@ __global__ __launch_bounds__(NT) void k_ring(
         const double2 *Fk = Fin + (long long)r * fstride + (long long)k * ld;
         if (blue)
             for (int t = n + tid; t < M; t += NT) buf[t] = czero;
+        // folded coefficients: in LDS for short rings (hoff: byte offset of
+        // kFoldMax + max(NT, kFoldMax) double2 past the FFT buffer), else per
+        // thread from F
+        const bool coop = N <= kFoldMax;            // uniform over the block
+        double2 *hb = reinterpret_cast<double2 *>(smem_ring + hoff);
+        if (coop) fold_coop<NT>(Fk, N, p, lmax, TN, hb, hb + kFoldMax);
+        auto H = [&](int q) { return coop ? hb[q] : hhat(Fk, q, N, p, lmax, TN); };
         // Z_k = (G_k + G_{k+n}) + i w^k (G_k - G_{k+n}),  G_q = (Hhat_q + conj Hhat_{N-q}) / 2,
         // w = e^{2 pi i / N}: the length-n DFT input whose inverse is z_t = f_2t + i f_2t+1.
         for (int kk = tid; 2 * kk <= n; kk += NT) {
             const int i1 = kk == 0 ? 0 : N - kk;
-            const double2 H0 = hhat(Fk, kk, N, p, lmax, TN);
-            const double2 H1 = hhat(Fk, i1, N, p, lmax, TN);
-            const double2 H2 = hhat(Fk, kk + n, N, p, lmax, TN);
-            const double2 H3 = hhat(Fk, n - kk, N, p, lmax, TN);
+            const double2 H0 = H(kk);
+            const double2 H1 = H(i1);
+            const double2 H2 = H(kk + n);
+            const double2 H3 = H(n - kk);
             {
                 const double2 g0 = cscale(cadd(H0, cconj(H1)), 0.5);
                 const double2 g1 = cscale(cadd(H2, cconj(H3)), 0.5);
@@ -345,14 +385,19 @@ static int launch_group(const mlcr_geom *g, const RingGroup &grp, int lmax, int 
                         const double2 *F, double2 *G, const double *map_in, double *map_out,
                         const double *ninv, long long fstride, const C *Bf, const C *W,
                         hipStream_t s) {
-    const size_t lds = (size_t)grp.mmax * sizeof(C);
+    // FFT buffer, then (groups with short rings, synthesis direction) the
+    // cooperative fold's coefficients and partial sums
+    const size_t hoff = ((size_t)grp.mmax * sizeof(C) + 15) / 16 * 16;
+    const bool fold = MODE != 1 && grp.nmin <= kFoldMax;
+    const size_t lds = fold ? hoff + (size_t)(kFoldMax + std::max(NT, kFoldMax)) * sizeof(double2)
+                            : (size_t)grp.mmax * sizeof(C);
     int rc = ensure_dynamic_lds((const void *)k_ring<MODE, NT, C>, lds);
     if (rc) return rc;
     const long long nblk = 8LL * ((grp.count + 7) / 8) * nrhs;
     hipLaunchKernelGGL((k_ring<MODE, NT, C>), dim3((unsigned)nblk), dim3(NT), lds, s, F, G, map_in,
                        map_out, ninv, g->rings.as<RingInfo>(), g->lens.as<LenInfo>(),
                        g->order.as<int>(), g->T.as<double2>(), Bf, W, g->Wmax, lmax, fstride,
-                       g->npix, grp.off, grp.count, nrhs);
+                       g->npix, grp.off, grp.count, nrhs, (int)hoff);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }
