@@ -26,10 +26,10 @@ namespace mlcr {
 // adjoint: one workgroup of W waves per (m, chunk of W ring-pair blocks, 8 RHS)
 // ---------------------------------------------------------------------------
 // Wave w owns ring-pair block chunk * W + w.  Per tile of 32 l-steps each lane
-// writes its ring's lambdas (hi and lo planes, row = (parity, l index), column
-// = ring); lane i + 16 kg reads rings 32 c + 8 kg .. + 7 of row i as its A
-// operand, the B operand holds the split even/odd ring sums of G for the same
-// rings.  The W tiles are summed in LDS and the chunk's partial sum stored
+// writes its ring's lambdas in float32 (row = (parity, l index), column =
+// ring); lane i + 16 kg reads rings 32 c + 8 kg .. + 7 of row i (two 16-byte
+// reads) and splits them into its hi and lo A operands; the B operand holds
+// the split even/odd ring sums of G for the same rings.  The W tiles are summed in LDS and the chunk's partial sum stored
 // once (T layout, float32 partial sums), exactly as the float32 adjoint does.
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_ladj_b3(
@@ -38,8 +38,9 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
     const long long *__restrict__ aboff, const double2 *__restrict__ st,
     const int *__restrict__ stsc, const int *__restrict__ lstab, int nb16, int nrings, int npairs,
     int npb, int nchunks, long long total) {
-    constexpr int RW = 72;                      // bf16 per row: 64 rings + 8 pad (144 B)
-    constexpr int LSB = 2 * 32 * RW * 2;        // bytes per wave: [hl][p * 16 + i][RW]
+    constexpr int RW = 68;                      // floats per row: 64 rings + 4 pad; the
+                                                // 16 rows read by 16 lanes start 4 banks apart
+    constexpr int LSB = 32 * RW * 4;            // bytes per wave: [p * 16 + i][RW]
     extern __shared__ __align__(16) unsigned char smem[];
     double *sab = reinterpret_cast<double *>(smem);
     unsigned char *lam_all = smem + kChunkM * sizeof(double2);
@@ -48,9 +49,8 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
     decode_item_m(total, lmax, nchunks, m, chunk, rc, ok);
     if (!ok) return;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    unsigned short *lamh = reinterpret_cast<unsigned short *>(lam_all + wv * LSB);
-    unsigned short *laml = lamh + 32 * RW;
-    float *tile = reinterpret_cast<float *>(lam_all + wv * LSB);
+    float *lam = reinterpret_cast<float *>(lam_all + wv * LSB);
+    float *tile = lam;
     const int nl = lmax - m + 1;
     const long long tri = (long long)(lmax + 1) * (lmax + 2) / 2;
     const int nrc = (nrhs + 7) / 8;
@@ -146,35 +146,23 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
             if (mode == 1) {
 #pragma unroll 4
                 for (int i = 0; i < 16; i++) {
-                    const float fe = (float)L.w();
+                    lam[i * RW + lane] = (float)L.w();
                     L.step_rescale(sab[2 * i]);
-                    const float fo = (float)L.w();
+                    lam[(16 + i) * RW + lane] = (float)L.w();
                     L.step_rescale(sab[2 * i + 1]);
-                    unsigned h, l;
-                    split2(fe, fo, h, l);
-                    lamh[i * RW + lane] = (unsigned short)h;
-                    lamh[(16 + i) * RW + lane] = (unsigned short)(h >> 16);
-                    laml[i * RW + lane] = (unsigned short)l;
-                    laml[(16 + i) * RW + lane] = (unsigned short)(l >> 16);
                 }
                 mode = wave_mode1(L);
             } else {
 #pragma unroll 8
                 for (int i = 0; i < 16; i++) {
-                    const float fe = (float)L.l1;
+                    lam[i * RW + lane] = (float)L.l1;
                     double nv = fma(sab[2 * i] * L.z, L.l1, -L.l2);
                     L.l2 = L.l1;
                     L.l1 = nv;
-                    const float fo = (float)L.l1;
+                    lam[(16 + i) * RW + lane] = (float)L.l1;
                     nv = fma(sab[2 * i + 1] * L.z, L.l1, -L.l2);
                     L.l2 = L.l1;
                     L.l1 = nv;
-                    unsigned h, l;
-                    split2(fe, fo, h, l);
-                    lamh[i * RW + lane] = (unsigned short)h;
-                    lamh[(16 + i) * RW + lane] = (unsigned short)(h >> 16);
-                    laml[i * RW + lane] = (unsigned short)l;
-                    laml[(16 + i) * RW + lane] = (unsigned short)(l >> 16);
                 }
             }
             __builtin_amdgcn_s_waitcnt(0xc07f);     // this wave's LDS writes landed
@@ -183,9 +171,14 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
             for (int p = 0; p < 2; p++)
 #pragma unroll
                 for (int c = 0; c < 2; c++) {
-                    const int off = (16 * p + jc) * RW + 32 * c + 8 * kg;
-                    const uint4 ah = *reinterpret_cast<const uint4 *>(lamh + off);
-                    const uint4 al = *reinterpret_cast<const uint4 *>(laml + off);
+                    const float4 *src =
+                        reinterpret_cast<const float4 *>(lam + (16 * p + jc) * RW + 32 * c + 8 * kg);
+                    const float4 f0 = src[0], f1 = src[1];
+                    uint4 ah, al;
+                    split2(f0.x, f0.y, ah.x, al.x);
+                    split2(f0.z, f0.w, ah.y, al.y);
+                    split2(f1.x, f1.y, ah.z, al.z);
+                    split2(f1.z, f1.w, ah.w, al.w);
                     D[p][c] = mma_b3(ah, bh[c][p], D[p][c]);
                     D[p][c] = mma_b3(ah, bl[c][p], D[p][c]);
                     D[p][c] = mma_b3(al, bh[c][p], D[p][c]);
@@ -226,7 +219,7 @@ static int launch_ladj_b3_w(const LegendreArgs &a, const SegTable *st, const dou
     const long long total = mitems(a.lmax, nchunks, nrc);
     const long long grid = ((total + 7) / 8) * 8;
     const long long fstride = (long long)g->nrings * (a.lmax + 1);
-    const size_t lds = kChunkM * sizeof(double2) + (size_t)W * (2 * 32 * 72 * 2);
+    const size_t lds = kChunkM * sizeof(double2) + (size_t)W * (32 * 68 * 4);
     int rc = ensure_dynamic_lds((const void *)k_ladj_b3<W>, lds);
     if (rc) return rc;
     hipLaunchKernelGGL((k_ladj_b3<W>), dim3((unsigned)grid), dim3(64 * W), lds, a.stream, G,
