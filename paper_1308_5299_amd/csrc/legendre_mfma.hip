@@ -54,7 +54,9 @@ struct Mma<double> {
 // Wave w owns ring-pair block chunk * W + w.  Per tile of 32 l (16 even +
 // 16 odd l - m) every wave forms its block's contribution
 //     D_even[l_i, c] = sum_k Lambda[ring_k, l_2i] g_even[ring_k, c]
-// with 16 MFMAs of 4 ring pairs each (likewise odd), the W tiles are summed
+// with 16 MFMAs of 4 ring pairs each (likewise odd): MFMA g takes ring pair
+// 16 k + g as its k-th, so lane i + 16 k reads its 16 A values (row i,
+// ring pairs 16 k .. 16 k + 15) with 16-byte LDS reads.  The W tiles are summed
 // in LDS, and the chunk's partial sum is stored once (T layout, in the
 // contraction type: float32 for the mixed path, float64 for the float64
 // path); the chunks are added in float64 in the unpack step.
@@ -66,8 +68,12 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
     const int *__restrict__ stsc, const int *__restrict__ lstab, int nb16, int nrings, int npairs,
     int npb, int nchunks, long long total) {
     typedef Mma<T> M;
-    constexpr int SL = 66;                       // padded lambda row: operand reads hit 64 banks
-    constexpr int LS = 32 * SL;                  // lambda tile of one wave
+    // lambda tile of one wave: row (parity p, index i) = 16 p + i, padded so
+    // that rows stay 16-byte aligned and the 16 rows read by 16 lanes start
+    // 4 banks apart
+    constexpr int SL = sizeof(T) == 8 ? 66 : 68;
+    constexpr int LS = 32 * SL;
+    constexpr int VW = 16 / sizeof(T);           // values per 16-byte read
     extern __shared__ __align__(16) unsigned char smem[];
     double *sab = reinterpret_cast<double *>(smem);
     T *lam_all = reinterpret_cast<T *>(smem + kChunkM * sizeof(double2));
@@ -103,13 +109,13 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
     int t0 = ntile;
     for (int w = 0; w < W; w++)
         if (chunk * W + w < npb) t0 = min(t0, lstab[(long long)m * nb16 + 4 * (chunk * W + w)] / 32);
-    // B operands: ring pair 4 g + kq of this block, column jc
+    // B operands: ring pair 16 kq + g of this block, column jc
     T ge[16], go[16];
     {
         const double *Gr = reinterpret_cast<const double *>(G + (long long)rB * fstride);
 #pragma unroll
         for (int g = 0; g < 16; g++) {
-            const int p = pb * 64 + 4 * g + kq;
+            const int p = pb * 64 + 16 * kq + g;
             double gn = 0.0, gs = 0.0;
             if (active && p < npairs) {
                 const int north = p, south = nrings - 1 - p;
@@ -157,7 +163,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
             if (mode == 1) {
 #pragma unroll 4
                 for (int s = 0; s < 32; s++) {
-                    lam[s * SL + lane] = M::cvt(L.w());
+                    lam[((s & 1) * 16 + (s >> 1)) * SL + lane] = M::cvt(L.w());
                     L.step_rescale(sab[s]);
                 }
                 mode = wave_mode1(L);
@@ -165,7 +171,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
                 // steady state: every lane in range, plain recurrence
 #pragma unroll 8
                 for (int s = 0; s < 32; s++) {
-                    lam[s * SL + lane] = M::cvt(L.l1);
+                    lam[((s & 1) * 16 + (s >> 1)) * SL + lane] = M::cvt(L.l1);
                     const double nv = fma(sab[s] * L.z, L.l1, -L.l2);
                     L.l2 = L.l1;
                     L.l1 = nv;
@@ -173,12 +179,18 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
             }
             __builtin_amdgcn_s_waitcnt(0xc07f);     // this wave's LDS writes landed
             __builtin_amdgcn_wave_barrier();
+            const T *re = lam + jc * SL + 16 * kq;         // row (even, jc)
+            const T *ro = re + 16 * SL;                     // row (odd, jc)
 #pragma unroll
-            for (int g = 0; g < 16; g++) {
-                const T ae = lam[(2 * jc) * SL + 4 * g + kq];
-                const T ao = lam[(2 * jc + 1) * SL + 4 * g + kq];
-                DE = M::mma(ae, ge[g], DE);
-                DO = M::mma(ao, go[g], DO);
+            for (int g0 = 0; g0 < 16; g0 += VW) {
+                typedef T v16 __attribute__((ext_vector_type(VW)));
+                const v16 ae = *reinterpret_cast<const v16 *>(re + g0);
+                const v16 ao = *reinterpret_cast<const v16 *>(ro + g0);
+#pragma unroll
+                for (int u = 0; u < VW; u++) {
+                    DE = M::mma(ae[u], ge[g0 + u], DE);
+                    DO = M::mma(ao[u], go[g0 + u], DO);
+                }
             }
         }
         // the wave's tile (32 l x 16 columns) into its own LDS area
@@ -227,7 +239,7 @@ static int launch_ladj_wg(const LegendreArgs &a, const SegTable *st, const doubl
     const long long total = mitems(a.lmax, nchunks, nrc);
     const long long grid = ((total + 7) / 8) * 8;
     const long long fstride = (long long)g->nrings * (a.lmax + 1);
-    const size_t lds = kChunkM * sizeof(double2) + (size_t)W * 32 * 66 * sizeof(T);
+    const size_t lds = kChunkM * sizeof(double2) + (size_t)W * 32 * (sizeof(T) == 8 ? 66 : 68) * sizeof(T);
     int rc = ensure_dynamic_lds((const void *)k_ladj_mfma<T, W>, lds);
     if (rc) return rc;
     hipLaunchKernelGGL((k_ladj_mfma<T, W>), dim3((unsigned)grid), dim3(64 * W), lds, a.stream, G,
