@@ -536,8 +536,18 @@ __global__ __launch_bounds__(256) void k_unpack_t(const PT *__restrict__ P, int 
         for (int e = threadIdx.x; e < nt * NC; e += blockDim.x) {
             const int j = e / NC, comp = e % NC;
             const PT *src = Pb + (long long)base * NC + e;
+            // chunks added in order; loads issued 4 at a time
             double acc = 0.0;
-            for (int c = 0; c < nchunks; c++) acc += (double)src[c * cstride];
+            int c = 0;
+            for (; c + 4 <= nchunks; c += 4) {
+                const PT v0 = src[c * cstride], v1 = src[(c + 1) * cstride];
+                const PT v2 = src[(c + 2) * cstride], v3 = src[(c + 3) * cstride];
+                acc += (double)v0;
+                acc += (double)v1;
+                acc += (double)v2;
+                acc += (double)v3;
+            }
+            for (; c < nchunks; c++) acc += (double)src[c * cstride];
             tile[j * 17 + comp] = acc;
         }
         __syncthreads();

@@ -42,14 +42,17 @@ __device__ __forceinline__ void seed_lambda_m(double s, int m, double c, double 
     }
 }
 
-// Work item w = ((rc * (lmax+1)) + mi) * npb + pb: the ring-pair blocks of one
-// order are adjacent, so they run together and share that order's
-// coefficients (and U rows) through L2, while their F/G accesses spread over
-// all rings (all memory channels).  Each XCD (workgroup id mod 8) gets one
-// contiguous run of items; orders are visited 0, lmax, 1, lmax-1, ... so
-// every run holds the same mix of long and short orders.
+// Work item w = ((rc * ng + gi) * npb + pb) * 8 + mo, order m = 8 g + mo in
+// groups g of 8 consecutive orders (ng = ceil((lmax + 1) / 8) groups, items
+// past lmax exit at once).  The 8 orders of a group run side by side and
+// share the 128-byte lines of F and G (16 B per order, ring and RHS), which
+// are then fetched or written once; the ring-pair blocks of one order stay
+// close and share its coefficients and U rows through L2.  Each XCD
+// (workgroup id mod 8) gets one contiguous run of items; groups are visited
+// 0, ng-1, 1, ng-2, ... so every run holds the same mix of long and short
+// orders.
 __host__ __device__ inline long long mitems(int lmax, int npb, int nrc) {
-    return (long long)(lmax + 1) * npb * nrc;
+    return (long long)((lmax + 8) / 8) * 8 * npb * nrc;
 }
 
 __device__ __forceinline__ void decode_item_m(long long total, int lmax, int npb, int &m, int &pb,
@@ -59,12 +62,16 @@ __device__ __forceinline__ void decode_item_m(long long total, int lmax, int npb
     const long long w = (b & 7) * per + (b >> 3);
     ok = w < total;
     if (!ok) return;
-    const int nm = lmax + 1;
-    pb = (int)(w % npb);
-    const long long rest = w / npb;
-    const int mi = (int)(rest % nm);
-    rc = (int)(rest / nm);
-    m = (mi & 1) ? (lmax - (mi >> 1)) : (mi >> 1);
+    const int ng = (lmax + 8) / 8;
+    const int mo = (int)(w & 7);
+    long long rest = w >> 3;
+    pb = (int)(rest % npb);
+    rest /= npb;
+    const int gi = (int)(rest % ng);
+    rc = (int)(rest / ng);
+    const int g = (gi & 1) ? (ng - 1 - (gi >> 1)) : (gi >> 1);
+    m = 8 * g + mo;
+    ok = m <= lmax;
 }
 
 __device__ __forceinline__ long long tri_off_m(int m, int lmax) {
