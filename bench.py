@@ -33,15 +33,15 @@ PEAK_BF16 = 2.5e15            # MI355X dense bf16 MFMA FLOP/s
 # profiles/apply_A_c5_r8_hbm_traffic.md for the kernels as they are now.
 # Key: (library timer name, Legendre path, workload, RHS per launch).
 MEASURED_TRAFFIC = {
-    ("legendre_adjoint", "bf16x3", "c5", 8): 34.994e9 + 8.596e9,
-    ("legendre_adjoint", "fp32", "c5", 8): 34.963e9 + 8.596e9,
-    ("legendre_adjoint", "fp64", "c5", 8): 34.986e9 + 8.596e9,
-    ("legendre_synth", "bf16x3", "c5", 8): 3.775e9 + 8.602e9,
-    ("legendre_synth", "fp32", "c5", 8): 6.761e9 + 8.726e9,
-    ("legendre_synth", "fp64", "c5", 8): 12.085e9 + 8.664e9,
-    ("ring_apply", "bf16x3", "c5", 8): 1.782e9 + 1.074e9 + 3 * (1.300e9 + 1.074e9),
-    ("ring_apply", "fp32", "c5", 8): 1.782e9 + 1.074e9 + 3 * (1.298e9 + 1.074e9),
-    ("ring_apply", "fp64", "c5", 8): 1.784e9 + 1.074e9 + 3 * (1.298e9 + 1.074e9),
+    ("legendre_adjoint", "bf16x3", "c5", 8): 8.907e9 + 4.313e9,
+    ("legendre_adjoint", "fp32", "c5", 8): 8.815e9 + 4.310e9,
+    ("legendre_adjoint", "fp64", "c5", 8): 8.599e9 + 8.596e9,
+    ("legendre_synth", "bf16x3", "c5", 8): 3.992e9 + 8.670e9,
+    ("legendre_synth", "fp32", "c5", 8): 8.176e9 + 9.790e9,
+    ("legendre_synth", "fp64", "c5", 8): 16.415e9 + 9.840e9,
+    ("ring_apply", "bf16x3", "c5", 8): 1.927e9 + 1.074e9 + 3 * (1.281e9 + 1.075e9),
+    ("ring_apply", "fp32", "c5", 8): 1.928e9 + 1.074e9 + 3 * (1.281e9 + 1.075e9),
+    ("ring_apply", "fp64", "c5", 8): 1.784e9 + 1.074e9 + 3 * (1.294e9 + 1.075e9),
 }
 
 
