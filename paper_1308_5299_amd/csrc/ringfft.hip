@@ -131,29 +131,64 @@ __device__ __forceinline__ void dft(C (&x)[R]) {
     }
 }
 
+// Twiddles of one radix-8 pass (stride p) for this thread's butterflies i
+// (k = i mod p): w, w^2 and w^4 with w = e^{-2 pi i k / (8 p)} (conjugated
+// for the inverse), read from W[j] = e^{-2 pi i j / Wmax}.  The other powers
+// are products of these (at most two roundings past the table's).  They are
+// loaded one pass ahead, so the table latency hides behind the current
+// pass.
+template <bool INV, int NT, typename C>
+struct Tw8 {
+    static constexpr int CM = 8192 / (8 * NT) > 0 ? 8192 / (8 * NT) : 1;
+    C w1[CM], w2[CM], w4[CM];
+    __device__ __forceinline__ void load(int M, int p, const C *__restrict__ W, int Wmax) {
+        const int T = M / 8;
+        const int ts = Wmax / (8 * p);
+#pragma unroll
+        for (int c = 0; c < CM; c++) {
+            const int i = threadIdx.x + c * NT;
+            if (i < T) {
+                const int k = i & (p - 1);
+                w1[c] = W[k * ts];
+                w2[c] = W[2 * k * ts];
+                w4[c] = W[4 * k * ts];
+                if (INV) {
+                    w1[c].y = -w1[c].y;
+                    w2[c].y = -w2[c].y;
+                    w4[c].y = -w4[c].y;
+                }
+            }
+        }
+    }
+};
+
 // One radix-R Stockham pass over the M values in LDS (stride p so far):
 // butterfly i (k = i mod p) reads x[i + j M/R], scales input j by
 // w^{j k} with w = e^{-2 pi i / (p R)}, does an R-point DFT and writes
-// output r to x[(i - k) R + k + r p].  W[j] = e^{-2 pi i j / Wmax}.
+// output r to x[(i - k) R + k + r p].  tw: the pass's twiddles (radix 8,
+// p > 1), null for p = 1.
 template <int R, bool INV, int NT, typename C>
-__device__ __forceinline__ void fft_pass(C *buf, int M, int p, const C *__restrict__ W, int Wmax) {
+__device__ __forceinline__ void fft_pass(C *buf, int M, int p, const Tw8<INV, NT, C> *tw) {
     constexpr int CMAX = 8192 / (R * NT) > 0 ? 8192 / (R * NT) : 1;
     const int T = M / R;
-    const int ts = Wmax / (p * R);
     C v[CMAX][R];
 #pragma unroll
     for (int c = 0; c < CMAX; c++) {
         const int i = threadIdx.x + c * NT;
         if (i < T) {
-            const int k = i & (p - 1);
 #pragma unroll
             for (int j = 0; j < R; j++) v[c][j] = buf[i + j * T];
-            if (p > 1) {
-#pragma unroll
-                for (int j = 1; j < R; j++) {
-                    C w = W[j * k * ts];
-                    if (INV) w.y = -w.y;
-                    v[c][j] = cmul(v[c][j], w);
+            if constexpr (R == 8) {
+                if (tw) {
+                    const C w1 = tw->w1[c], w2 = tw->w2[c], w4 = tw->w4[c];
+                    const C w3 = cmul(w1, w2);
+                    v[c][1] = cmul(v[c][1], w1);
+                    v[c][2] = cmul(v[c][2], w2);
+                    v[c][3] = cmul(v[c][3], w3);
+                    v[c][4] = cmul(v[c][4], w4);
+                    v[c][5] = cmul(v[c][5], cmul(w1, w4));
+                    v[c][6] = cmul(v[c][6], cmul(w2, w4));
+                    v[c][7] = cmul(v[c][7], cmul(w3, w4));
                 }
             }
         }
@@ -174,20 +209,23 @@ __device__ __forceinline__ void fft_pass(C *buf, int M, int p, const C *__restri
 }
 
 // Unnormalized DFT of size M (a power of two, M <= 8192) held in LDS, in
-// place, all threads of the block taking part: one radix-2 or radix-4 pass
-// when log2 M is not a multiple of 3, then radix-8 passes.
+// place, all threads of the block taking part: one radix-2, radix-4 or
+// radix-8 pass with stride 1 (no twiddles), then radix-8 passes.
 template <bool INV, int NT, typename C>
 __device__ void lds_fft_t(C *buf, int M, const C *__restrict__ W, int Wmax) {
+    if (M < 2) return;
     const int lg = 31 - __clz(M);
-    int p = 1;
-    if (lg % 3 == 1) {
-        fft_pass<2, INV, NT>(buf, M, p, W, Wmax);
-        p = 2;
-    } else if (lg % 3 == 2) {
-        fft_pass<4, INV, NT>(buf, M, p, W, Wmax);
-        p = 4;
+    const int p1 = lg % 3 == 1 ? 2 : (lg % 3 == 2 ? 4 : 8);   // stride after the first pass
+    Tw8<INV, NT, C> tw{}, tn{};
+    if (p1 < M) tw.load(M, p1, W, Wmax);
+    if (p1 == 2) fft_pass<2, INV, NT>(buf, M, 1, (const Tw8<INV, NT, C> *)nullptr);
+    else if (p1 == 4) fft_pass<4, INV, NT>(buf, M, 1, (const Tw8<INV, NT, C> *)nullptr);
+    else fft_pass<8, INV, NT>(buf, M, 1, (const Tw8<INV, NT, C> *)nullptr);
+    for (int p = p1; p < M; p *= 8) {
+        if (8 * p < M) tn.load(M, 8 * p, W, Wmax);
+        fft_pass<8, INV, NT>(buf, M, p, &tw);
+        tw = tn;
     }
-    for (; p < M; p *= 8) fft_pass<8, INV, NT>(buf, M, p, W, Wmax);
 }
 
 template <int NT, typename C>
