@@ -344,6 +344,9 @@ def main():
     ap.add_argument("--paths", default="bf16x3,fp32,fp64",
                     help="Legendre paths to time; the first is the reported value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default launch shapes instead of tuning each "
+                         "path on the workload before timing it")
     ap.add_argument("--graph", action="store_true",
                     help="with --solve: also time whole solves with the cycle replayed from a HIP graph")
     ap.add_argument("--pcg", action="store_true",
@@ -378,6 +381,7 @@ def main():
         return
 
     import paper_1308_5299_amd as mlcr
+    from paper_1308_5299_amd import autotune
     import workloads
 
     if args.mixed:
@@ -410,8 +414,15 @@ def main():
                                      pcg=args.pcg, graph=args.graph)), flush=True)
         return
 
-    res, outs = {}, {}
+    res, outs, tuned = {}, {}, {}
     for p in paths:
+        if not args.no_autotune:
+            # launch shapes picked by timing each choice on this workload (not timed)
+            t0 = time.time()
+            tr = autotune.tune(op, R, precs[p], reps=2)
+            tuned[p] = tr["tuning"]
+            log(f"[bench] {p} autotune {tr['tuning']} in {time.time() - t0:.1f}s: "
+                f"{tr['timings_ms']}")
         y = torch.empty_like(x)
         res[p] = run_path(mlcr, torch, op, x, y, precs[p], args.steps, args.warmup, p)
         outs[p] = y
@@ -459,6 +470,7 @@ def main():
         "cpu_baseline": cpu,
         "other_paths": others,
         "mixed_vs_fp64_rel_l2": err or None,
+        "tuning": tuned or None,
     }
     print(json.dumps(out), flush=True)
 

@@ -106,6 +106,25 @@ int mlcr_geom_info(const mlcr_geom *g, int *nside, int *lmax, long long *npix, i
 /* Quadrature weight of one pixel of each ring, host_w[nrings]: 4 pi / N_pix
  * for HEALPix (equal area), W_k = w_k 2 pi / nphi for Gauss-Legendre. */
 int mlcr_geom_weights(const mlcr_geom *g, double *host_w);
+/* Launch shapes of the transform kernels on this geometry for one arithmetic
+ * path (prec = MLCR_FP64 / FP32 / BF16X3), as chosen by an autotuner (the
+ * Python package's autotune module times every choice on the workload):
+ *   adjoint_waves  4 or 8: ring-pair blocks of 64 per matrix-core adjoint
+ *                  workgroup (the split-K chunk count is blocks / waves);
+ *   synth_chains   2 or 4: recurrence chains per lane of the matrix-core
+ *                  synthesis (16 x chains ring pairs per wave);
+ *   ring_threads   512 or 1024: threads per ring workgroup for FFT sizes
+ *                  above 4096 (smaller FFTs always use 512).
+ * Defaults 8, 4, 1024.  Results agree between choices up to rounding order.
+ * Host-side only; applies to launches made after the call (a solver's
+ * captured cycle graph keeps the shapes it was captured with) and only to
+ * this geometry (not to the Gauss-Legendre geometries of an operator's
+ * lower levels).  Errors: MLCR_EINVAL for another value or precision. */
+int mlcr_geom_set_tuning(mlcr_geom *g, int prec, int adjoint_waves, int synth_chains,
+                         int ring_threads);
+/* The current launch shapes of one path; any out pointer may be NULL. */
+int mlcr_geom_get_tuning(const mlcr_geom *g, int prec, int *adjoint_waves, int *synth_chains,
+                         int *ring_threads);
 
 /* Spherical harmonic synthesis map = Y alm (Sec. 2.1, eq. sh-synthesis),
  * evaluated exactly at the pixel centres (no quadrature, any lmax <= the

@@ -11,8 +11,9 @@ from .api import (BF16X3, FP32, FP64, Geometry, KernelTimer, Operator, Solver, a
                   cycle_counts, ladder_plan, nest2ring, sht_adjoint, sht_synth, tile_graph)
 
 from . import autograd  # noqa: F401,E402
+from . import autotune  # noqa: F401,E402
 
-__all__ = ["autograd", "MLCRError", "load_library", "BF16X3", "FP32", "FP64", "Geometry", "Operator",
+__all__ = ["autograd", "autotune", "MLCRError", "load_library", "BF16X3", "FP32", "FP64", "Geometry", "Operator",
            "apply_A", "apply_A_grouped", "solve_grouped", "cr_rhs", "sht_adjoint", "sht_synth", "KernelTimer",
            "Solver", "nest2ring", "tile_graph",
            "ladder_plan", "cycle_counts"]

@@ -20,6 +20,9 @@ SIGNATURES = {
     "mlcr_geom_create": (c_int, [c_int, c_int, ctypes.POINTER(c_void_p)]),
     "mlcr_geom_create_gl": (c_int, [c_int, c_int, c_int, ctypes.POINTER(c_void_p)]),
     "mlcr_geom_weights": (c_int, [c_void_p, c_void_p]),
+    "mlcr_geom_set_tuning": (c_int, [c_void_p, c_int, c_int, c_int, c_int]),
+    "mlcr_geom_get_tuning": (c_int, [c_void_p, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                                     ctypes.POINTER(c_int)]),
     "mlcr_geom_destroy": (None, [c_void_p]),
     "mlcr_geom_info": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
                                ctypes.POINTER(c_ll), ctypes.POINTER(c_int)]),

@@ -70,6 +70,21 @@ class Geometry:
         check(load().mlcr_geom_weights(self._h, w.ctypes.data))
         return w
 
+    def set_tuning(self, prec: int, adjoint_waves: int, synth_chains: int,
+                   ring_threads: int) -> None:
+        """Launch shapes of one arithmetic path on this geometry
+        (mlcr_geom_set_tuning): adjoint_waves 4 or 8, synth_chains 2 or 4,
+        ring_threads 512 or 1024."""
+        check(load().mlcr_geom_set_tuning(self._h, int(prec), int(adjoint_waves),
+                                          int(synth_chains), int(ring_threads)))
+
+    def get_tuning(self, prec: int) -> dict:
+        """The current launch shapes of one arithmetic path."""
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(load().mlcr_geom_get_tuning(self._h, int(prec), ctypes.byref(a), ctypes.byref(b),
+                                          ctypes.byref(c)))
+        return {"adjoint_waves": a.value, "synth_chains": b.value, "ring_threads": c.value}
+
     @property
     def handle(self):
         return self._h

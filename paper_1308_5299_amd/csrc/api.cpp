@@ -78,9 +78,11 @@ static long long nalm_of(int lmax) { return (long long)(lmax + 1) * (lmax + 1); 
 // Workspaces of one transform of nrhs right-hand sides at band limit lmax.
 static int reserve_ws(mlcr_geom *g, int lmax, int nrhs) {
     const size_t fbytes = (size_t)nrhs * g->nrings * (lmax + 1) * sizeof(double2);
+    int mchunks = 0;                    // most matrix-core chunks of any path's tuning
+    for (int p = 0; p < 3; p++) mchunks = std::max(mchunks, adjoint_chunks_mfma(g, lmax, p));
     const size_t pbytes =
         std::max((size_t)adjoint_chunks(g, lmax) * tlayout_doubles(lmax, nrhs, adj_rc(nrhs)),
-                 (size_t)adjoint_chunks_mfma(g, lmax) * tlayout_doubles(lmax, nrhs, 8)) *
+                 (size_t)mchunks * tlayout_doubles(lmax, nrhs, 8)) *
         sizeof(double);
     const size_t ubytes =
         std::max((size_t)tlayout_doubles(lmax, nrhs, synth_rc(nrhs)) * sizeof(double),
@@ -223,7 +225,7 @@ int apply_level(mlcr_op *op, int level, int nrhs, const double *x, double *y, in
     if ((rc = legendre_synth_any(a, x, L.bh.as<double>(), g, F, prec))) return rc;
     {
         KTimer t("ring_apply", s);
-        if ((rc = launch_ring_apply(g, lmax, nrhs, F, ninv, prec != MLCR_FP64, s))) return rc;
+        if ((rc = launch_ring_apply(g, lmax, nrhs, F, ninv, prec, s))) return rc;
     }
     if ((rc = legendre_adjoint_any(a, F, g, x, L.d.as<double>(), L.bh.as<double>(), y, prec)))
         return rc;
@@ -335,6 +337,36 @@ int mlcr_geom_info(const mlcr_geom *g, int *nside, int *lmax, long long *npix, i
     if (lmax) *lmax = g->lmax;
     if (npix) *npix = g->npix;
     if (nrings) *nrings = g->nrings;
+    return MLCR_OK;
+}
+
+int mlcr_geom_set_tuning(mlcr_geom *g, int prec, int adjoint_waves, int synth_chains,
+                         int ring_threads) {
+    if (!g) return fail(MLCR_EINVAL, "geometry is NULL");
+    int rc;
+    if ((rc = check_prec(prec))) return rc;
+    if (adjoint_waves != 4 && adjoint_waves != 8)
+        return fail(MLCR_EINVAL, "adjoint_waves must be 4 or 8");
+    if (synth_chains != 2 && synth_chains != 4)
+        return fail(MLCR_EINVAL, "synth_chains must be 2 or 4");
+    if (ring_threads != 512 && ring_threads != 1024)
+        return fail(MLCR_EINVAL, "ring_threads must be 512 or 1024");
+    Tuning &t = g->tune[prec];
+    t.adj_waves = adjoint_waves;
+    t.synth_chains = synth_chains;
+    t.ring_threads = ring_threads;
+    return MLCR_OK;
+}
+
+int mlcr_geom_get_tuning(const mlcr_geom *g, int prec, int *adjoint_waves, int *synth_chains,
+                         int *ring_threads) {
+    if (!g) return fail(MLCR_EINVAL, "geometry is NULL");
+    int rc;
+    if ((rc = check_prec(prec))) return rc;
+    const Tuning &t = g->tune[prec];
+    if (adjoint_waves) *adjoint_waves = t.adj_waves;
+    if (synth_chains) *synth_chains = t.synth_chains;
+    if (ring_threads) *ring_threads = t.ring_threads;
     return MLCR_OK;
 }
 

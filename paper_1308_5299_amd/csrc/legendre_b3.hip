@@ -230,17 +230,17 @@ static int launch_ladj_b3_w(const LegendreArgs &a, const SegTable *st, const dou
     return MLCR_OK;
 }
 
-// Same split-K chunking and P layout as the float32 adjoint (adjoint_chunks_mfma).
+// Same split-K chunking (with this path's tuned waves per workgroup) and P
+// layout as the float32 adjoint.
 int launch_legendre_adjoint_b3(const LegendreArgs &a, const SegTable *st, const double2 *G,
                                float *P, int *nchunks_out) {
     if (st->lmax != a.lmax) return fail(MLCR_EINVAL, "start-state table of another band limit");
-    const int npb = (a.g->npairs + 63) / 64;
-    const int nchunks = adjoint_chunks_mfma(a.g, a.lmax);
-    const int W = (npb + nchunks - 1) / nchunks;
+    const int nchunks = adjoint_chunks_mfma(a.g, a.lmax, MLCR_BF16X3);
+    const int W = adjoint_waves(a.g, MLCR_BF16X3);
     int rc;
-    if (W > 4) rc = launch_ladj_b3_w<8>(a, st, G, P, nchunks);
-    else if (W > 2) rc = launch_ladj_b3_w<4>(a, st, G, P, nchunks);
-    else if (W > 1) rc = launch_ladj_b3_w<2>(a, st, G, P, nchunks);
+    if (W == 8) rc = launch_ladj_b3_w<8>(a, st, G, P, nchunks);
+    else if (W == 4) rc = launch_ladj_b3_w<4>(a, st, G, P, nchunks);
+    else if (W == 2) rc = launch_ladj_b3_w<2>(a, st, G, P, nchunks);
     else rc = launch_ladj_b3_w<1>(a, st, G, P, nchunks);
     if (rc) return rc;
     *nchunks_out = nchunks;

@@ -218,15 +218,21 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-// Waves per adjoint workgroup: one ring-pair block each, up to 8.
-static int adj_waves(int npb) { return npb >= 8 ? 8 : (npb >= 4 ? 4 : (npb >= 2 ? 2 : 1)); }
+// Waves per adjoint workgroup: one ring-pair block each, the path's tuned
+// count (8 or 4), halved while it exceeds the number of blocks.
+int adjoint_waves(const mlcr_geom *g, int prec) {
+    const int npb = (g->npairs + 63) / 64;
+    int w = g->tune[prec].adj_waves;
+    while (w > 1 && w > npb) w >>= 1;
+    return w;
+}
 
 // Split-K over ring-pair blocks: a workgroup sums W blocks for one order m,
 // the chunks are added in the unpack step.
-int adjoint_chunks_mfma(const mlcr_geom *g, int lmax) {
+int adjoint_chunks_mfma(const mlcr_geom *g, int lmax, int prec) {
     (void)lmax;
     const int npb = (g->npairs + 63) / 64;
-    const int W = adj_waves(npb);
+    const int W = adjoint_waves(g, prec);
     return (npb + W - 1) / W;
 }
 
@@ -252,8 +258,8 @@ static int launch_ladj_wg(const LegendreArgs &a, const SegTable *st, const doubl
 
 template <typename T>
 static int launch_ladj_t(const LegendreArgs &a, const SegTable *st, const double2 *G, T *P,
-                         int nchunks) {
-    switch (adj_waves((a.g->npairs + 63) / 64)) {
+                         int nchunks, int prec) {
+    switch (adjoint_waves(a.g, prec)) {
     case 8: return launch_ladj_wg<T, 8>(a, st, G, P, nchunks);
     case 4: return launch_ladj_wg<T, 4>(a, st, G, P, nchunks);
     case 2: return launch_ladj_wg<T, 2>(a, st, G, P, nchunks);
@@ -265,9 +271,10 @@ static int launch_ladj_t(const LegendreArgs &a, const SegTable *st, const double
 int launch_legendre_adjoint_mfma(const LegendreArgs &a, const SegTable *st, const double2 *G,
                                  void *P, int *nchunks_out, bool dbl) {
     if (st->lmax != a.lmax) return fail(MLCR_EINVAL, "start-state table of another band limit");
-    const int nchunks = adjoint_chunks_mfma(a.g, a.lmax);
-    const int rc = dbl ? launch_ladj_t<double>(a, st, G, (double *)P, nchunks)
-                       : launch_ladj_t<float>(a, st, G, (float *)P, nchunks);
+    const int prec = dbl ? MLCR_FP64 : MLCR_FP32;
+    const int nchunks = adjoint_chunks_mfma(a.g, a.lmax, prec);
+    const int rc = dbl ? launch_ladj_t<double>(a, st, G, (double *)P, nchunks, prec)
+                       : launch_ladj_t<float>(a, st, G, (float *)P, nchunks, prec);
     if (rc) return rc;
     *nchunks_out = nchunks;
     return MLCR_OK;

@@ -102,13 +102,15 @@ __global__ __launch_bounds__(64) void k_seg_init(int lmax, const double *__restr
 // ---------------------------------------------------------------------------
 // synthesis: one wave per (m, 64 ring pairs, 8 RHS)
 // ---------------------------------------------------------------------------
-// Lane i + 16 kg runs 4 recurrence chains, ring pairs 16 nb + i of the wave's
-// 64 (nb = 0..3), over segment kg; the 4 chains share the segment, the
-// coefficients and the B operand, and feed 4 MFMAs (one per 16 ring pairs).
+// Lane i + 16 kg runs NB recurrence chains (NB = 4, or 2 as a tuning choice),
+// ring pairs 16 nb + i of the wave's 16 NB (nb = 0..NB-1), over segment kg;
+// the chains share the segment, the coefficients and the B operand, and feed
+// NB MFMAs (one per 16 ring pairs).  With NB = 2 two waves cover one 64-pair
+// block of the start-state table (its offset ls is the block's).
 // U (per RHS chunk, order m, block q of 16 l-steps from m):
 //   float32 / float64: [j][16] values, element s at l = m + 16 q + s;
 //   split bf16: [p][hl][j][8], element e at l = m + 16 q + 2 e + p.
-template <int P>
+template <int P, int NB>
 __global__ __launch_bounds__(64) void k_lsynth_seg(
     const void *__restrict__ Uv, int nrhs, double2 *__restrict__ F, long long fstride, int lmax,
     const double *__restrict__ rz, const double *__restrict__ alpha,
@@ -117,13 +119,16 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
     int npb, long long total) {
     typedef typename std::conditional<P == kSegP64, double, float>::type T;
     typedef typename std::conditional<P == kSegP64, d4s, f4b>::type acc_t;
-    constexpr int NB = 4;
+    static_assert(NB == 4 || NB == 2, "4 or 2 chains per lane");
+    constexpr int NH = 4 / NB;                  // waves per 64-pair block
     constexpr int CS = 17;                      // padded coefficient row per segment
     __shared__ double sab[4 * CS];
     int m, pb, rc;
     bool ok;
-    decode_item_m(total, lmax, npb, m, pb, rc, ok);
+    decode_item_m(total, lmax, npb * NH, m, pb, rc, ok);
     if (!ok) return;
+    const int g0 = (pb % NH) * NB;              // first 16-pair group of the block
+    pb /= NH;
     const int lane = threadIdx.x, kg = lane >> 4, jc = lane & 15;
     const int nl = lmax - m + 1;
     const int ls = lstab[(long long)m * nb16 + 4 * pb];
@@ -138,9 +143,9 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
         Lane1 L[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; nb++) {
-            const int kp = pb * 64 + 16 * nb + jc;
+            const int kp = pb * 64 + 16 * (g0 + nb) + jc;
             L[nb].z = kp < npairs ? rz[kp] : 0.0;
-            const long long tix = ((long long)m * nb16 + 4 * pb + nb) * 64 + lane;
+            const long long tix = ((long long)m * nb16 + 4 * pb + g0 + nb) * 64 + lane;
             const double2 s0 = st[tix];
             L[nb].l1 = s0.x;
             L[nb].l2 = s0.y;
@@ -286,7 +291,7 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
             for (; t < nt; t++) iter(t, std::false_type{});
         }
     }
-    // D[i][j] of chain nb: ring pair 64 pb + 16 nb + i, column j = jc = (rhs,
+    // D[i][j] of chain nb: ring pair 64 pb + 16 (g0 + nb) + i, column j = jc = (rhs,
     // cos/sin); element v of lane j + 16 kg holds row i = 4 kg + v (float32
     // result) or kg + 4 v (float64)
     const int r = rc * 8 + (jc >> 1), cs = jc & 1;
@@ -298,7 +303,7 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
 #pragma unroll
             for (int v = 0; v < 4; v++) {
                 const int i = P == kSegP64 ? kg + 4 * v : 4 * kg + v;
-                const int p = pb * 64 + 16 * nb + i;
+                const int p = pb * 64 + 16 * (g0 + nb) + i;
                 if (p >= npairs) continue;
                 const double e = (double)acc[nb][0][v], o = (double)acc[nb][1][v];
                 const int north = p, south = nrings - 1 - p;
@@ -447,22 +452,28 @@ int launch_legendre_synth_seg(const LegendreArgs &a, const SegTable *t, const vo
     const int nb16 = 4 * ((g->npairs + 63) / 64);
     const int npb = (g->npairs + 63) / 64;
     const int nrc = (a.nrhs + 7) / 8;
-    const long long total = mitems(a.lmax, npb, nrc);
+    const int nb = g->tune[prec].synth_chains;          // chains per lane: 4 or 2
+    const long long total = mitems(a.lmax, npb * (4 / nb), nrc);
     const long long grid = ((total + 7) / 8) * 8;
     const long long fstride = (long long)g->nrings * (a.lmax + 1);
 #define MLCR_SEG_ARGS                                                                           \
     U, a.nrhs, F, fstride, a.lmax, g->ring_z.as<double>(), g->alpha.as<double>(),               \
         g->aboff.as<long long>(), t->st.as<double2>(), t->sc.as<int>(), t->ls.as<int>(),         \
         g->nrings, g->npairs, nb16, npb, total
-    if (prec == MLCR_BF16X3)
-        hipLaunchKernelGGL(k_lsynth_seg<kSegPB3>, dim3((unsigned)grid), dim3(64), 0, a.stream,
-                           MLCR_SEG_ARGS);
-    else if (prec == MLCR_FP64)
-        hipLaunchKernelGGL(k_lsynth_seg<kSegP64>, dim3((unsigned)grid), dim3(64), 0, a.stream,
-                           MLCR_SEG_ARGS);
-    else
-        hipLaunchKernelGGL(k_lsynth_seg<kSegP32>, dim3((unsigned)grid), dim3(64), 0, a.stream,
-                           MLCR_SEG_ARGS);
+#define MLCR_SEG_LAUNCH(PP, NBV)                                                                \
+    hipLaunchKernelGGL((k_lsynth_seg<PP, NBV>), dim3((unsigned)grid), dim3(64), 0, a.stream,     \
+                       MLCR_SEG_ARGS)
+    if (prec == MLCR_BF16X3) {
+        if (nb == 2) MLCR_SEG_LAUNCH(kSegPB3, 2);
+        else MLCR_SEG_LAUNCH(kSegPB3, 4);
+    } else if (prec == MLCR_FP64) {
+        if (nb == 2) MLCR_SEG_LAUNCH(kSegP64, 2);
+        else MLCR_SEG_LAUNCH(kSegP64, 4);
+    } else {
+        if (nb == 2) MLCR_SEG_LAUNCH(kSegP32, 2);
+        else MLCR_SEG_LAUNCH(kSegP32, 4);
+    }
+#undef MLCR_SEG_LAUNCH
 #undef MLCR_SEG_ARGS
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;

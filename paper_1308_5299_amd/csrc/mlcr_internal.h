@@ -78,6 +78,16 @@ struct SegTable {
     DevBuf ls;          // int     [(lmax+1) * nb16]
 };
 
+// Launch shapes of the transform kernels, one set per arithmetic path
+// (index MLCR_FP64 / MLCR_FP32 / MLCR_BF16X3), chosen by the caller (the
+// autotuner) through mlcr_geom_set_tuning.  Results do not depend on them
+// beyond rounding order.
+struct Tuning {
+    int adj_waves = 8;        // ring-pair blocks (waves) per matrix-core adjoint workgroup: 4, 8
+    int synth_chains = 4;     // recurrence chains per lane, segment synthesis: 2, 4
+    int ring_threads = 1024;  // threads per ring workgroup, FFT size above 4096: 512, 1024
+};
+
 }  // namespace mlcr
 
 struct mlcr_geom {
@@ -86,6 +96,7 @@ struct mlcr_geom {
     long long npix = 0;
     int lds_cplx = 0;       // largest complex FFT buffer of any ring
     int Wmax = 0;           // size of the power-of-two twiddle table
+    mlcr::Tuning tune[3];   // launch shapes per arithmetic path
 
     // device tables
     mlcr::DevBuf ring_z, ring_s;        // per ring: cos, sin theta (double)
@@ -165,9 +176,10 @@ int launch_ring_synth(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, 
                       hipStream_t s);
 int launch_ring_adjoint(const mlcr_geom *g, int lmax, int nrhs, const double *map, double2 *G,
                         hipStream_t s);
-// f32: FFTs in float32 (LDS buffer and Bluestein filter), fold/unfold in float64
+// prec: the arithmetic path; its FFTs run in float32 (LDS buffer and
+// Bluestein filter) on the mixed paths, fold/unfold in float64 always
 int launch_ring_apply(const mlcr_geom *g, int lmax, int nrhs, double2 *FG, const double *ninv,
-                      bool f32, hipStream_t s);
+                      int prec, hipStream_t s);
 // out[p] = W_ring(p) in[p]: a map times the grid's quadrature weights
 int launch_ring_weight(const mlcr_geom *g, const double *in, double *out, hipStream_t s);
 int adjoint_chunks(const mlcr_geom *g, int lmax);
@@ -176,7 +188,8 @@ int adjoint_chunks(const mlcr_geom *g, int lmax);
 // P holds float64 partial sums for dbl, float32 otherwise
 int launch_legendre_adjoint_mfma(const LegendreArgs &a, const SegTable *st, const double2 *G,
                                  void *P, int *nchunks_out, bool dbl);
-int adjoint_chunks_mfma(const mlcr_geom *g, int lmax);
+int adjoint_chunks_mfma(const mlcr_geom *g, int lmax, int prec);
+int adjoint_waves(const mlcr_geom *g, int prec);
 // split-bfloat16 matrix-core adjoint (legendre_b3.hip): P as for the float32 adjoint.
 // segment-parallel synthesis (legendre_seg.hip); prec: MLCR_FP32 / FP64 / BF16X3
 long long seg_u_bytes(int lmax, int nrhs, int prec);

@@ -440,16 +440,16 @@ static int launch_group(const mlcr_geom *g, const RingGroup &grp, int lmax, int 
     return MLCR_OK;
 }
 
-// Groups whose FFT fills 128 KiB of LDS run one workgroup per CU: they get
-// 1024 threads (one butterfly per thread and radix-8 pass) so the CU still
-// holds 16 waves; the others use 512.
+// Groups with FFT size above 4096 use big_nt threads (1024 by default: one
+// butterfly per thread and radix-8 pass, so a CU holding one 128 KiB float64
+// workgroup still runs 16 waves); the others use 512.
 template <int MODE, typename C>
 static int launch_ring_t(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, double2 *G,
                          const double *map_in, double *map_out, const double *ninv, const C *Bf,
-                         const C *W, hipStream_t s) {
+                         const C *W, int big_nt, hipStream_t s) {
     const long long fstride = (long long)g->nrings * (lmax + 1);
     for (const RingGroup &grp : g->ring_groups) {
-        const int rc = grp.mmax > 4096
+        const int rc = grp.mmax > 4096 && big_nt == 1024
                            ? launch_group<MODE, 1024>(g, grp, lmax, nrhs, F, G, map_in, map_out,
                                                       ninv, fstride, Bf, W, s)
                            : launch_group<MODE, kRingThreads>(g, grp, lmax, nrhs, F, G, map_in,
@@ -461,22 +461,23 @@ static int launch_ring_t(const mlcr_geom *g, int lmax, int nrhs, const double2 *
 
 template <int MODE>
 static int launch_ring(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, double2 *G,
-                       const double *map_in, double *map_out, const double *ninv, bool f32,
+                       const double *map_in, double *map_out, const double *ninv, int prec,
                        hipStream_t s) {
-    if (f32)
+    const int big_nt = g->tune[prec].ring_threads;
+    if (prec != MLCR_FP64)
         return launch_ring_t<MODE>(g, lmax, nrhs, F, G, map_in, map_out, ninv, g->Bf32.as<float2>(),
-                                   g->W32.as<float2>(), s);
+                                   g->W32.as<float2>(), big_nt, s);
     return launch_ring_t<MODE>(g, lmax, nrhs, F, G, map_in, map_out, ninv, g->Bf.as<double2>(),
-                               g->W.as<double2>(), s);
+                               g->W.as<double2>(), big_nt, s);
 }
 
 int launch_ring_synth(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, double *map,
                       hipStream_t s) {
-    return launch_ring<0>(g, lmax, nrhs, F, nullptr, nullptr, map, nullptr, false, s);
+    return launch_ring<0>(g, lmax, nrhs, F, nullptr, nullptr, map, nullptr, MLCR_FP64, s);
 }
 int launch_ring_adjoint(const mlcr_geom *g, int lmax, int nrhs, const double *map, double2 *G,
                         hipStream_t s) {
-    return launch_ring<1>(g, lmax, nrhs, nullptr, G, map, nullptr, nullptr, false, s);
+    return launch_ring<1>(g, lmax, nrhs, nullptr, G, map, nullptr, nullptr, MLCR_FP64, s);
 }
 // one workgroup per ring
 __global__ __launch_bounds__(256) void k_ring_weight(const double *__restrict__ in,
@@ -496,8 +497,8 @@ int launch_ring_weight(const mlcr_geom *g, const double *in, double *out, hipStr
 }
 
 int launch_ring_apply(const mlcr_geom *g, int lmax, int nrhs, double2 *FG, const double *ninv,
-                      bool f32, hipStream_t s) {
-    return launch_ring<2>(g, lmax, nrhs, FG, FG, nullptr, nullptr, ninv, f32, s);
+                      int prec, hipStream_t s) {
+    return launch_ring<2>(g, lmax, nrhs, FG, FG, nullptr, nullptr, ninv, prec, s);
 }
 
 }  // namespace mlcr
