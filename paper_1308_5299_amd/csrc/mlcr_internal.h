@@ -198,8 +198,6 @@ int launch_pack_seg(const mlcr_geom *g, int lmax, int nrhs, const double *x, con
                     void *U, int prec, hipStream_t s);
 int launch_legendre_synth_seg(const LegendreArgs &a, const SegTable *t, const void *U, double2 *F,
                               int prec);
-int launch_pack_b3(int lmax, int nrhs, const double *x, const double *dl, void *U, hipStream_t s);
-int launch_legendre_synth_b3(const LegendreArgs &a, const void *U, double2 *F);
 int launch_legendre_adjoint_b3(const LegendreArgs &a, const SegTable *st, const double2 *G,
                                float *P, int *nchunks_out);
 // T layout ([RHS chunk][m][l - m][RC][cos, sin]) of the Legendre kernels
