@@ -30,18 +30,19 @@ PEAK_BF16 = 2.5e15            # MI355X dense bf16 MFMA FLOP/s
 
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE (x2.0) + WRITE_SIZE
 # (x1.0), the factors from a plain copy of known size; recorded in
-# profiles/apply_A_c5_r8_hbm_traffic.md for the kernels as they are now.
+# profiles/apply_A_c5_r8_hbm_traffic.md for the kernels as they are now, at
+# the default launch shapes (valid when the autotuner keeps them).
 # Key: (library timer name, Legendre path, workload, RHS per launch).
 MEASURED_TRAFFIC = {
-    ("legendre_adjoint", "bf16x3", "c5", 8): 8.907e9 + 4.313e9,
-    ("legendre_adjoint", "fp32", "c5", 8): 8.815e9 + 4.310e9,
+    ("legendre_adjoint", "bf16x3", "c5", 8): 8.919e9 + 4.313e9,
+    ("legendre_adjoint", "fp32", "c5", 8): 8.813e9 + 4.310e9,
     ("legendre_adjoint", "fp64", "c5", 8): 8.599e9 + 8.596e9,
-    ("legendre_synth", "bf16x3", "c5", 8): 3.992e9 + 8.670e9,
-    ("legendre_synth", "fp32", "c5", 8): 8.176e9 + 9.790e9,
-    ("legendre_synth", "fp64", "c5", 8): 16.415e9 + 9.840e9,
-    ("ring_apply", "bf16x3", "c5", 8): 1.927e9 + 1.074e9 + 3 * (1.281e9 + 1.075e9),
-    ("ring_apply", "fp32", "c5", 8): 1.928e9 + 1.074e9 + 3 * (1.281e9 + 1.075e9),
-    ("ring_apply", "fp64", "c5", 8): 1.784e9 + 1.074e9 + 3 * (1.294e9 + 1.075e9),
+    ("legendre_synth", "bf16x3", "c5", 8): 3.992e9 + 8.204e9,
+    ("legendre_synth", "fp32", "c5", 8): 8.170e9 + 9.794e9,
+    ("legendre_synth", "fp64", "c5", 8): 16.357e9 + 9.828e9,
+    ("ring_apply", "bf16x3", "c5", 8): 1.914e9 + 1.074e9 + 3 * (1.278e9 + 1.075e9),
+    ("ring_apply", "fp32", "c5", 8): 1.919e9 + 1.073e9 + 3 * (1.278e9 + 1.075e9),
+    ("ring_apply", "fp64", "c5", 8): 1.783e9 + 1.074e9 + 3 * (1.296e9 + 1.075e9),
 }
 
 
