@@ -60,8 +60,13 @@ struct Mma<double> {
 // in LDS, and the chunk's partial sum is stored once (T layout, in the
 // contraction type: float32 for the mixed path, float64 for the float64
 // path); the chunks are added in float64 in the unpack step.
+// The float64 tile would take 135 KiB of LDS per 8-wave workgroup (one
+// workgroup, 2 waves per SIMD): for T = double each tile runs the
+// recurrence twice from the tile's start state, storing the 16 even steps
+// and then the 16 odd steps in one half-size tile, so two workgroups fit
+// per CU (4 waves per SIMD, registers held to 128).
 template <typename T, int W>
-__global__ __launch_bounds__(64 * W) void k_ladj_mfma(
+__global__ __launch_bounds__(64 * W, sizeof(T) == 8 ? 4 : 1) void k_ladj_mfma(
     const double2 *__restrict__ G, long long fstride, int nrhs, T *__restrict__ P, int lmax,
     const double *__restrict__ rz, const double *__restrict__ alpha,
     const long long *__restrict__ aboff, const double2 *__restrict__ st,
@@ -72,7 +77,8 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
     // that rows stay 16-byte aligned and the 16 rows read by 16 lanes start
     // 4 banks apart
     constexpr int SL = sizeof(T) == 8 ? 66 : 68;
-    constexpr int LS = 32 * SL;
+    constexpr bool TWO = sizeof(T) == 8;         // two passes, half-size tile
+    constexpr int LS = (TWO ? 16 : 32) * SL;
     constexpr int VW = 16 / sizeof(T);           // values per 16-byte read
     extern __shared__ __align__(16) unsigned char smem[];
     double *sab = reinterpret_cast<double *>(smem);
@@ -159,6 +165,45 @@ __global__ __launch_bounds__(64 * W) void k_ladj_mfma(
                 }
                 mode = wave_mode1(L);
             }
+        } else if constexpr (TWO) {
+            // pass p stores the steps of parity p (rows 0..15), then its MFMAs
+            const Lane1 L0 = L;
+#pragma unroll
+            for (int p = 0; p < 2; p++) {
+                if (p == 1) {
+                    L = L0;
+                    __builtin_amdgcn_wave_barrier();    // even rows read before rewriting
+                }
+                if (mode == 1) {
+#pragma unroll 4
+                    for (int s = 0; s < 32; s++) {
+                        if ((s & 1) == p) lam[(s >> 1) * SL + lane] = L.w();
+                        L.step_rescale(sab[s]);
+                    }
+                } else {
+#pragma unroll 8
+                    for (int s = 0; s < 32; s++) {
+                        if ((s & 1) == p) lam[(s >> 1) * SL + lane] = L.l1;
+                        const double nv = fma(sab[s] * L.z, L.l1, -L.l2);
+                        L.l2 = L.l1;
+                        L.l1 = nv;
+                    }
+                }
+                __builtin_amdgcn_s_waitcnt(0xc07f);     // this wave's LDS writes landed
+                __builtin_amdgcn_wave_barrier();
+                const T *rr = lam + jc * SL + 16 * kq;
+#pragma unroll
+                for (int g0 = 0; g0 < 16; g0 += VW) {
+                    typedef T v16 __attribute__((ext_vector_type(VW)));
+                    const v16 a = *reinterpret_cast<const v16 *>(rr + g0);
+#pragma unroll
+                    for (int u = 0; u < VW; u++) {
+                        if (p == 0) DE = M::mma(a[u], ge[g0 + u], DE);
+                        else DO = M::mma(a[u], go[g0 + u], DO);
+                    }
+                }
+            }
+            if (mode == 1) mode = wave_mode1(L);
         } else {
             if (mode == 1) {
 #pragma unroll 4
@@ -245,7 +290,8 @@ static int launch_ladj_wg(const LegendreArgs &a, const SegTable *st, const doubl
     const long long total = mitems(a.lmax, nchunks, nrc);
     const long long grid = ((total + 7) / 8) * 8;
     const long long fstride = (long long)g->nrings * (a.lmax + 1);
-    const size_t lds = kChunkM * sizeof(double2) + (size_t)W * 32 * (sizeof(T) == 8 ? 66 : 68) * sizeof(T);
+    const size_t lds = kChunkM * sizeof(double2) +
+                       (size_t)W * (sizeof(T) == 8 ? 16 * 66 : 32 * 68) * sizeof(T);
     int rc = ensure_dynamic_lds((const void *)k_ladj_mfma<T, W>, lds);
     if (rc) return rc;
     hipLaunchKernelGGL((k_ladj_mfma<T, W>), dim3((unsigned)grid), dim3(64 * W), lds, a.stream, G,
