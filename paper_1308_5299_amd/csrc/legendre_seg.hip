@@ -6,10 +6,11 @@
 // a slice of the contraction index; here that slice is a contiguous
 // l-segment, so a lane runs the float64 recurrence (Sec. 3.2) of its ring
 // pairs over its own segment and its lambdas go straight into its A-operand
-// registers, with no exchange between lanes.  A wave covers 64 ring pairs and
-// 4 segments (kg = lane / 16) of [m + ls, lmax]: lane i + 16 kg runs 4 chains,
-// ring pairs 16 nb + i (nb = 0..3), which share the segment, the recurrence
-// coefficients and the B operand.  The recurrence state at each segment start
+// registers, with no exchange between lanes.  A wave covers 64 ring pairs
+// (32 with the 2-chain launch shape) and 4 segments (kg = lane / 16) of
+// [m + ls, lmax]: lane i + 16 kg runs 4 chains, ring pairs 16 nb + i
+// (nb = 0..3), which share the segment, the recurrence coefficients and the
+// B operand.  The recurrence state at each segment start
 // comes from a table made once per grid and band limit (k_seg_init), which
 // also records ls: below m + ls every lambda of the 64 ring pairs is below
 // 2^-112 (all lanes range-scaled) and contributes nothing, so those steps are

@@ -18,7 +18,8 @@
 //
 // In the fused operator kernel the map never leaves LDS: F is read, the map
 // is multiplied by N^-1 (0 in the mask, Sec. 2.3), and G is written over F.
-// One workgroup of 512 threads per (ring, right-hand side).  Rings are
+// One workgroup per (ring, right-hand side): 512 threads, or 1024 for FFT
+// sizes above 4096 (the default launch shape; 512 as a tuning choice).  Rings are
 // launched in groups of similar FFT size, each with the LDS its largest ring
 // needs; within a launch the rings are dealt round-robin to the eight XCDs
 // (workgroup id mod 8) and the right-hand sides of one ring run back to back
