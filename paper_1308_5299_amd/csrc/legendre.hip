@@ -508,8 +508,9 @@ __global__ __launch_bounds__(256) void k_pack_t(const double *__restrict__ x,
     }
 }
 
-// y[r][packed] = d[l] x + bh[l] sum_c P[c][rc][tri_off(m) + l - m][r][cs]
-// (d, x may be null; bh null means 1).  One workgroup per (m, RHS chunk):
+// y[r][packed] = d[l] x + bh[l] cf_lm sum_c P[c][rc][tri_off(m) + l - m][r][cs]
+// (d, x may be null; bh, cf null mean 1; cf_lm = cf[tri_off(m, glmax) + l - m],
+// the scale of the matrix-core kernels' recurrence).  One workgroup per (m, RHS chunk):
 // tiles of 64 l are read row by row (the T layout is contiguous in
 // (l, r, cs)), summed over the chunks, transposed in LDS and written out
 // along l, so both sides stream.
