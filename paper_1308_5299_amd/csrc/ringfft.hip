@@ -317,6 +317,31 @@ __global__ __launch_bounds__(NT) void k_ring(
     const int ld = lmax + 1;
     const long long pix0 = (long long)r * npix + ri.start;
     const C czero = to_c<C>(make_double2(0.0, 0.0));
+    // Bluestein chirps of this thread's t < n, held in registers for the up
+    // to three pointwise passes that use them (loaded here, ahead of use);
+    // in the 1024-thread launches only, where the registers are free
+    constexpr int KCH = NT >= 1024 ? 4 : 1;
+    const bool cch = NT >= 1024 && blue && n <= KCH * NT;
+    C chv[KCH];
+    if (cch) {
+#pragma unroll
+        for (int c = 0; c < KCH; c++) {
+            const int t = tid + c * NT;
+            chv[c] = t < n ? to_c<C>(chirp(TN, t, N)) : czero;
+        }
+    }
+    // buf[t] = op(buf[t], chirp_t) for t < n
+    auto with_chirp = [&](auto op) {
+        if (cch) {
+#pragma unroll
+            for (int c = 0; c < KCH; c++) {
+                const int t = tid + c * NT;
+                if (t < n) buf[t] = op(buf[t], chv[c]);
+            }
+        } else {
+            for (int t = tid; t < n; t += NT) buf[t] = op(buf[t], to_c<C>(chirp(TN, t, N)));
+        }
+    };
 
     if (MODE != 1) {
         const double2 *Fk = Fin + (long long)r * fstride + (long long)k * ld;
@@ -363,8 +388,12 @@ __global__ __launch_bounds__(NT) void k_ring(
             for (int t = tid; t < M; t += NT) buf[t] = cmul(buf[t], Bk[t]);
             __syncthreads();
             lds_fft<NT>(buf, M, true, W, Wmax);
-            for (int t = tid; t < n; t += NT)
-                buf[t] = cscale(cmul(buf[t], to_c<C>(chirp(TN, t, N))), invM);
+            if constexpr (NT >= 1024) {
+                with_chirp([&](C v, C ch) { return cscale(cmul(v, ch), invM); });
+            } else {
+                for (int t = tid; t < n; t += NT)
+                    buf[t] = cscale(cmul(buf[t], to_c<C>(chirp(TN, t, N))), invM);
+            }
             __syncthreads();
         }
         if (MODE == 0) {
@@ -390,15 +419,24 @@ __global__ __launch_bounds__(NT) void k_ring(
         __syncthreads();
         lds_fft<NT>(buf, n, false, W, Wmax);
     } else {
-        for (int t = tid; t < M; t += NT)
-            buf[t] = (t < n) ? cmul(buf[t], to_c<C>(cconj(chirp(TN, t, N)))) : czero;
+        if (NT >= 1024 && cch) {
+            for (int t = n + tid; t < M; t += NT) buf[t] = czero;
+            with_chirp([&](C v, C ch) { return cmul(v, cconj(ch)); });
+        } else {
+            for (int t = tid; t < M; t += NT)
+                buf[t] = (t < n) ? cmul(buf[t], to_c<C>(cconj(chirp(TN, t, N)))) : czero;
+        }
         __syncthreads();
         lds_fft<NT>(buf, M, false, W, Wmax);
         for (int t = tid; t < M; t += NT) buf[t] = cmul(buf[t], cconj(Bk[t]));
         __syncthreads();
         lds_fft<NT>(buf, M, true, W, Wmax);
-        for (int t = tid; t < n; t += NT)
-            buf[t] = cscale(cmul(buf[t], to_c<C>(cconj(chirp(TN, t, N)))), invM);
+        if constexpr (NT >= 1024) {
+            with_chirp([&](C v, C ch) { return cscale(cmul(v, cconj(ch)), invM); });
+        } else {
+            for (int t = tid; t < n; t += NT)
+                buf[t] = cscale(cmul(buf[t], to_c<C>(cconj(chirp(TN, t, N)))), invM);
+        }
         __syncthreads();
     }
     // unfold: Y_q from the half-length transform, then G_m for m = 0..lmax
