@@ -483,10 +483,17 @@ __global__ __launch_bounds__(64) void k_sgs_color(const double *__restrict__ r,
                 v[q][i] = q < nq ? (float)y[(long long)(r0 + q) * npix + pu] : 0.0f;
             __syncthreads();
             const float *Bs = off + (long long)sl * K2 * K2;
-            for (int j = 0; j < K2; j++) {
-                const float b = Bs[j * K2 + i];
+            // 16 block entries loaded before their products (a tile is one
+            // wave's sequential work, so load latency is what it waits on)
+#pragma unroll 1
+            for (int j0 = 0; j0 < K2; j0 += 16) {
+                float b[16];
 #pragma unroll
-                for (int q = 0; q < NQ; q++) acc[q] = fmaf(b, v[q][j], acc[q]);
+                for (int jj = 0; jj < 16; jj++) b[jj] = Bs[(j0 + jj) * K2 + i];
+#pragma unroll
+                for (int jj = 0; jj < 16; jj++)
+#pragma unroll
+                    for (int q = 0; q < NQ; q++) acc[q] = fmaf(b[jj], v[q][j0 + jj], acc[q]);
             }
             __syncthreads();
         }
@@ -500,10 +507,15 @@ __global__ __launch_bounds__(64) void k_sgs_color(const double *__restrict__ r,
         float o[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; q++) o[q] = 0.0f;
-        for (int j = 0; j < K2; j++) {
-            const float m = Mi[j * K2 + i];
+#pragma unroll 1
+        for (int j0 = 0; j0 < K2; j0 += 16) {
+            float mm[16];
 #pragma unroll
-            for (int q = 0; q < NQ; q++) o[q] = fmaf(m, v[q][j], o[q]);
+            for (int jj = 0; jj < 16; jj++) mm[jj] = Mi[(j0 + jj) * K2 + i];
+#pragma unroll
+            for (int jj = 0; jj < 16; jj++)
+#pragma unroll
+                for (int q = 0; q < NQ; q++) o[q] = fmaf(mm[jj], v[q][j0 + jj], o[q]);
         }
         __syncthreads();
         for (int q = 0; q < nq; q++) {
