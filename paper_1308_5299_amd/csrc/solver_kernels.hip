@@ -444,25 +444,31 @@ __global__ __launch_bounds__(256) void k_tile_factor(const double *__restrict__ 
 
 // One colour of the multicolour block symmetric Gauss-Seidel sweep on the
 // block-sparse pixel operator (Sec. 3.4 pattern: a tile and its neighbours).
-// Tiles of one colour are never neighbours, so each workgroup (one wave)
-// updates one tile with no ordering among them.  Thread i owns pixel i of the
+// Tiles of one colour are never neighbours, so each workgroup updates one
+// tile with no ordering among them.  Lane i of each wave owns pixel i of the
 // tile; blocks are float32 (the paper's smoother precision), maps float64.
 //   forward  (colours ascending):  y_t = D_t^-1 (r_t - sum_{u earlier} A_tu y_u)
 //   backward (colours descending): y_t -= D_t^-1 sum_{u later} A_tu y_u
 // so y ends as M r with M^-1 = (D + L) D^-1 (D + L^T).
+// A tile's work is a chain of dependent block products, so it is spread over
+// NW = 4 waves: wave w takes every NW-th neighbour block and a quarter of the
+// columns of D_t^-1, and the partial sums are added in LDS (wave order).
 template <bool FWD>
-__global__ __launch_bounds__(64) void k_sgs_color(const double *__restrict__ r,
-                                                  double *__restrict__ y, long long npix,
-                                                  int nrhs, const int *__restrict__ tilepix,
-                                                  const int *__restrict__ tiles,
-                                                  const int *__restrict__ nbptr,
-                                                  const int *__restrict__ nbs,
-                                                  const int *__restrict__ color, int kappa,
-                                                  const float *__restrict__ off,
-                                                  const float *__restrict__ minv) {
-    constexpr int K2 = kTileK2, NQ = 8;
-    __shared__ float v[NQ][K2];
-    const int t = tiles[blockIdx.x], i = threadIdx.x;
+__global__ __launch_bounds__(256) void k_sgs_color(const double *__restrict__ r,
+                                                   double *__restrict__ y, long long npix,
+                                                   int nrhs, const int *__restrict__ tilepix,
+                                                   const int *__restrict__ tiles,
+                                                   const int *__restrict__ nbptr,
+                                                   const int *__restrict__ nbs,
+                                                   const int *__restrict__ color, int kappa,
+                                                   const float *__restrict__ off,
+                                                   const float *__restrict__ minv) {
+    constexpr int K2 = kTileK2, NQ = 8, NW = 4, JW = K2 / NW;
+    static_assert(NQ % NW == 0 && K2 % (NW * 16) == 0, "tile shape");
+    __shared__ float v[NW][NQ][K2];              // per-wave neighbour values; then the right side
+    __shared__ float part[NW][NQ][K2];           // per-wave partial sums
+    const int t = tiles[blockIdx.x];
+    const int wv = threadIdx.x >> 6, i = threadIdx.x & 63;
     const long long pix = tilepix[(long long)t * K2 + i];
     const int s0 = nbptr[t], s1 = nbptr[t + 1];
     const float *Mi = minv + (long long)t * K2 * K2;
@@ -472,7 +478,7 @@ __global__ __launch_bounds__(64) void k_sgs_color(const double *__restrict__ r,
 #pragma unroll
         for (int q = 0; q < NQ; q++) acc[q] = 0.0f;
         bool any = false;
-        for (int sl = s0; sl < s1; sl++) {
+        for (int sl = s0 + wv; sl < s1; sl += NW) {
             const int u = nbs[sl];
             const int cu = color[u];
             if (FWD ? !(cu < kappa) : !(cu > kappa)) continue;
@@ -480,11 +486,11 @@ __global__ __launch_bounds__(64) void k_sgs_color(const double *__restrict__ r,
             const long long pu = tilepix[(long long)u * K2 + i];
 #pragma unroll
             for (int q = 0; q < NQ; q++)
-                v[q][i] = q < nq ? (float)y[(long long)(r0 + q) * npix + pu] : 0.0f;
-            __syncthreads();
+                v[wv][q][i] = q < nq ? (float)y[(long long)(r0 + q) * npix + pu] : 0.0f;
+            __builtin_amdgcn_s_waitcnt(0xc07f);     // this wave's LDS writes landed
+            __builtin_amdgcn_wave_barrier();
             const float *Bs = off + (long long)sl * K2 * K2;
-            // 16 block entries loaded before their products (a tile is one
-            // wave's sequential work, so load latency is what it waits on)
+            // 16 block entries loaded before their products
 #pragma unroll 1
             for (int j0 = 0; j0 < K2; j0 += 16) {
                 float b[16];
@@ -493,35 +499,52 @@ __global__ __launch_bounds__(64) void k_sgs_color(const double *__restrict__ r,
 #pragma unroll
                 for (int jj = 0; jj < 16; jj++)
 #pragma unroll
-                    for (int q = 0; q < NQ; q++) acc[q] = fmaf(b[jj], v[q][j0 + jj], acc[q]);
+                    for (int q = 0; q < NQ; q++) acc[q] = fmaf(b[jj], v[wv][q][j0 + jj], acc[q]);
             }
-            __syncthreads();
+            __builtin_amdgcn_wave_barrier();         // reads done before the next gather
         }
-        if (!FWD && !any) continue;
 #pragma unroll
-        for (int q = 0; q < NQ; q++)
-            v[q][i] = q < nq ? (FWD ? (float)r[(long long)(r0 + q) * npix + pix] - acc[q]
-                                    : acc[q])
-                             : 0.0f;
+        for (int q = 0; q < NQ; q++) part[wv][q][i] = acc[q];
+        if (!__syncthreads_or(any) && !FWD) continue;    // uniform over the workgroup
+        // right side for RHS q = NQ / NW * wv + qq, into v[0]
+#pragma unroll
+        for (int qq = 0; qq < NQ / NW; qq++) {
+            const int q = NQ / NW * wv + qq;
+            float tot = part[0][q][i];
+#pragma unroll
+            for (int w = 1; w < NW; w++) tot += part[w][q][i];
+            v[0][q][i] = q < nq ? (FWD ? (float)r[(long long)(r0 + q) * npix + pix] - tot : tot)
+                                : 0.0f;
+        }
         __syncthreads();
+        // D_t^-1 times the right side: wave w takes columns JW w .. JW w + JW - 1
         float o[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; q++) o[q] = 0.0f;
 #pragma unroll 1
-        for (int j0 = 0; j0 < K2; j0 += 16) {
+        for (int j0 = JW * wv; j0 < JW * (wv + 1); j0 += 16) {
             float mm[16];
 #pragma unroll
             for (int jj = 0; jj < 16; jj++) mm[jj] = Mi[(j0 + jj) * K2 + i];
 #pragma unroll
             for (int jj = 0; jj < 16; jj++)
 #pragma unroll
-                for (int q = 0; q < NQ; q++) o[q] = fmaf(mm[jj], v[q][j0 + jj], o[q]);
+                for (int q = 0; q < NQ; q++) o[q] = fmaf(mm[jj], v[0][q][j0 + jj], o[q]);
         }
+#pragma unroll
+        for (int q = 0; q < NQ; q++) part[wv][q][i] = o[q];
         __syncthreads();
-        for (int q = 0; q < nq; q++) {
+#pragma unroll
+        for (int qq = 0; qq < NQ / NW; qq++) {
+            const int q = NQ / NW * wv + qq;
+            if (q >= nq) continue;
+            float tot = part[0][q][i];
+#pragma unroll
+            for (int w = 1; w < NW; w++) tot += part[w][q][i];
             double *dst = y + (long long)(r0 + q) * npix + pix;
-            *dst = FWD ? (double)o[q] : *dst - (double)o[q];
+            *dst = FWD ? (double)tot : *dst - (double)tot;
         }
+        __syncthreads();                         // LDS free for the next RHS chunk
     }
 }
 
@@ -744,10 +767,10 @@ int launch_sgs_color(bool forward, const double *r, double *y, long long npix, i
                      const float *minv, hipStream_t s) {
     if (ntl <= 0) return MLCR_OK;
     if (forward)
-        hipLaunchKernelGGL(k_sgs_color<true>, dim3(ntl), dim3(64), 0, s, r, y, npix, nrhs, tilepix,
+        hipLaunchKernelGGL(k_sgs_color<true>, dim3(ntl), dim3(256), 0, s, r, y, npix, nrhs, tilepix,
                            tiles, nbptr, nbs, color, kappa, off, minv);
     else
-        hipLaunchKernelGGL(k_sgs_color<false>, dim3(ntl), dim3(64), 0, s, r, y, npix, nrhs, tilepix,
+        hipLaunchKernelGGL(k_sgs_color<false>, dim3(ntl), dim3(256), 0, s, r, y, npix, nrhs, tilepix,
                            tiles, nbptr, nbs, color, kappa, off, minv);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
