@@ -41,8 +41,14 @@ int DevBuf::reserve(size_t nbytes) {
     return MLCR_OK;
 }
 
+// Waits for the device first: a launch still queued may read the buffer
+// (an owner can go out of scope right after enqueueing work on it).  Never
+// called inside a captured region: buffers are made and dropped outside.
 void DevBuf::release() {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ptr);
+    }
     ptr = nullptr;
     bytes = 0;
 }

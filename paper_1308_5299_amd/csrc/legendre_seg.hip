@@ -425,7 +425,7 @@ int seg_table(mlcr_geom *g, int lmax, hipStream_t s, const SegTable **out) {
         t.ls.release();
         return fail(MLCR_EHIP, std::string("k_seg_init: ") + hipGetErrorString(e));
     }
-    g->seg.push_back(t);
+    g->seg.push_back(std::move(t));
     *out = &g->seg.back();
     return MLCR_OK;
 }

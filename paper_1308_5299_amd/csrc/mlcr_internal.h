@@ -28,9 +28,29 @@ int fail(int code, const std::string &msg);
 // ---------------------------------------------------------------------------
 // device buffer with grow-on-demand semantics
 // ---------------------------------------------------------------------------
+// Owns one device allocation (released when the owner goes away); movable,
+// not copyable.
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : ptr(o.ptr), bytes(o.bytes) {
+        o.ptr = nullptr;
+        o.bytes = 0;
+    }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) {
+            release();
+            ptr = o.ptr;
+            bytes = o.bytes;
+            o.ptr = nullptr;
+            o.bytes = 0;
+        }
+        return *this;
+    }
+    ~DevBuf() { release(); }
     int reserve(size_t nbytes);     // MLCR_OK or MLCR_ENOMEM
     void release();
     template <class T> T *as() const { return static_cast<T *>(ptr); }
