@@ -224,6 +224,7 @@ struct mlcr_solver {
     // bottom
     int lmax_b = 0, opl_b = 0, na = 0;
     DevBuf b_idx, b_inv, xb, bb;
+    DevBuf b_ws;                        // workspace of the dense bottom apply
     // outer loop
     DevBuf sinv, chalf, partial, norms, ro, to;
     // conjugate gradients: search direction, previous preconditioned residual,
@@ -330,10 +331,11 @@ struct GpuOps : CycleOps {
         if (S->direct)       // the top level itself is dense: x_0 = A^-1 b_0
             return launch_dense_apply(S->b_inv.as<double>(), S->na, S->b_idx.as<int>(),
                                       S->b0.as<double>(), S->x0.as<double>(), nalm_l(S->lmax_b),
-                                      R, s);
+                                      R, S->b_ws.as<double>(), s);
         (void)h;
         return launch_dense_apply(S->b_inv.as<double>(), S->na, S->b_idx.as<int>(),
-                                  S->bb.as<double>(), S->xb.as<double>(), nalm_l(S->lmax_b), R, s);
+                                  S->bb.as<double>(), S->xb.as<double>(), nalm_l(S->lmax_b), R,
+                                  S->b_ws.as<double>(), s);
     }
 };
 
@@ -552,6 +554,8 @@ static int setup_bottom(mlcr_solver *S, hipStream_t s) {
     MLCR_HIP_CHECK(hipStreamSynchronize(s));
     if (hinfo) return fail(MLCR_ENOTPD, "dense bottom-level matrix is not positive definite");
     if ((rc = alloc(S->b_inv, (size_t)na * na * sizeof(double)))) return rc;
+    if ((rc = alloc(S->b_ws, (size_t)dense_apply_ws_doubles(na, S->max_nrhs) * sizeof(double))))
+        return rc;
     if ((rc = launch_dense_inverse(Ad.as<double>(), na, S->b_inv.as<double>(), s))) return rc;
     MLCR_HIP_CHECK(hipStreamSynchronize(s));
     return MLCR_OK;

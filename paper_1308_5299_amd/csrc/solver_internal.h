@@ -41,8 +41,10 @@ int launch_dense_gather(const double *cols, long long ld, const int *act_idx, in
                         hipStream_t s);
 int launch_dense_cholesky(double *a, int n, int *info, hipStream_t s);
 int launch_dense_inverse(const double *L, int n, double *inv, hipStream_t s);
+// ws: dense_apply_ws_doubles(n, nrhs) doubles of device workspace
+long long dense_apply_ws_doubles(int n, int nrhs);
 int launch_dense_apply(const double *Ainv, int n, const int *act_idx, const double *b, double *x,
-                       long long nalm, int nrhs, hipStream_t s);
+                       long long nalm, int nrhs, double *ws, hipStream_t s);
 int launch_unit_vectors(double *x, long long nalm, const int *idx, int j0, int np, hipStream_t s);
 int launch_fill_zero(double *p, long long n, hipStream_t s);
 // per-RHS dot products (c, d may be null), out[2 r], out[2 r + 1]

@@ -632,16 +632,64 @@ __global__ __launch_bounds__(256) void k_dense_inverse(const double *__restrict_
 }
 
 // x[act_idx[i]] = sum_j Ainv[j][i] b[act_idx[j]]  (Ainv symmetric; x pre-cleared)
-__global__ __launch_bounds__(256) void k_dense_apply(const double *__restrict__ Ainv, int n,
-                                                     const int *__restrict__ act_idx,
-                                                     const double *__restrict__ b,
-                                                     double *__restrict__ x, long long nalm) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x, rr = blockIdx.y;
-    if (i >= n) return;
-    const double *br = b + (long long)rr * nalm;
+// x = A^-1 b on the active modes, in three steps: gather the active entries
+// of b (g[r][j]), partial products over kDenseJS column chunks (64 rows per
+// workgroup, 4 column lanes per row added in LDS in lane order), then the
+// chunk sums in chunk order, scattered into x.  Every row's sum is split
+// over many workgroups: one thread per row walking all n columns was bound
+// by its serial chain of loads.
+constexpr int kDenseJS = 8;
+
+__global__ __launch_bounds__(256) void k_dense_rhs(const double *__restrict__ b, long long nalm,
+                                                   const int *__restrict__ act_idx, int n,
+                                                   int nrhs, double *__restrict__ g) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= (long long)n * nrhs) return;
+    const int r = (int)(e / n), j = (int)(e % n);
+    g[e] = b[(long long)r * nalm + act_idx[j]];
+}
+
+__global__ __launch_bounds__(256) void k_dense_partial(const double *__restrict__ Ainv, int n,
+                                                       const double *__restrict__ g, int nrhs,
+                                                       double *__restrict__ part) {
+    constexpr int NQ = 8;
+    __shared__ double red[4][NQ][64];
+    const int l = threadIdx.x & 63, jl = threadIdx.x >> 6;
+    const int row = blockIdx.x * 64 + l, c = blockIdx.y, r0 = blockIdx.z * NQ;
+    const int jb = (int)((long long)n * c / kDenseJS), je = (int)((long long)n * (c + 1) / kDenseJS);
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; q++) acc[q] = 0.0;
+    if (row < n) {
+        for (int j = jb + jl; j < je; j += 4) {
+            const double a = Ainv[(long long)j * n + row];
+#pragma unroll
+            for (int q = 0; q < NQ; q++)
+                if (r0 + q < nrhs) acc[q] = fma(a, g[(long long)(r0 + q) * n + j], acc[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; q++) red[jl][q][l] = acc[q];
+    __syncthreads();
+    if (jl == 0 && row < n) {
+#pragma unroll
+        for (int q = 0; q < NQ; q++) {
+            if (r0 + q >= nrhs) break;
+            const double s = ((red[0][q][l] + red[1][q][l]) + red[2][q][l]) + red[3][q][l];
+            part[((long long)c * nrhs + r0 + q) * n + row] = s;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_dense_finish(const double *__restrict__ part, int n,
+                                                      int nrhs, const int *__restrict__ act_idx,
+                                                      double *__restrict__ x, long long nalm) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= (long long)n * nrhs) return;
+    const int r = (int)(e / n), i = (int)(e % n);
     double s = 0.0;
-    for (int j = 0; j < n; j++) s = fma(Ainv[(long long)j * n + i], br[act_idx[j]], s);
-    x[(long long)rr * nalm + act_idx[i]] = s;
+    for (int c = 0; c < kDenseJS; c++) s += part[((long long)c * nrhs + r) * n + i];
+    x[(long long)r * nalm + act_idx[i]] = s;
 }
 
 // unit vectors: x[p][idx[j0 + p]] = 1
@@ -800,11 +848,24 @@ int launch_dense_inverse(const double *L, int n, double *inv, hipStream_t s) {
     return MLCR_OK;
 }
 
+long long dense_apply_ws_doubles(int n, int nrhs) {
+    return (long long)(1 + kDenseJS) * nrhs * n;
+}
+
+// ws: dense_apply_ws_doubles(n, nrhs) doubles.  x is cleared with a fill
+// kernel (no memset node when a caller captures this in a graph).
 int launch_dense_apply(const double *Ainv, int n, const int *act_idx, const double *b, double *x,
-                       long long nalm, int nrhs, hipStream_t s) {
-    MLCR_HIP_CHECK(hipMemsetAsync(x, 0, (size_t)nrhs * nalm * sizeof(double), s));
-    hipLaunchKernelGGL(k_dense_apply, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, Ainv, n,
-                       act_idx, b, x, nalm);
+                       long long nalm, int nrhs, double *ws, hipStream_t s) {
+    int rc;
+    if ((rc = launch_fill_zero(x, (long long)nrhs * nalm, s))) return rc;
+    double *g = ws, *part = ws + (long long)nrhs * n;
+    const long long ne = (long long)n * nrhs;
+    hipLaunchKernelGGL(k_dense_rhs, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, b, nalm,
+                       act_idx, n, nrhs, g);
+    hipLaunchKernelGGL(k_dense_partial, dim3((n + 63) / 64, kDenseJS, (nrhs + 7) / 8), dim3(256), 0,
+                       s, Ainv, n, g, nrhs, part);
+    hipLaunchKernelGGL(k_dense_finish, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, part, n,
+                       nrhs, act_idx, x, nalm);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }
