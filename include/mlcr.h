@@ -52,14 +52,17 @@ enum {
     MLCR_EUNSUPPORTED = -6  /* valid request this build does not implement        */
 };
 
-/* Arithmetic of the Legendre contraction (the rest of every call is float64):
+/* Arithmetic of the Legendre contraction:
  *   MLCR_FP64   float64 throughout;
  *   MLCR_FP32   lambda and coefficients rounded to float32, float32 products
  *               and accumulation on the matrix cores;
  *   MLCR_BF16X3 each float32 operand split into bfloat16 hi + lo, products
  *               hi*hi + hi*lo + lo*hi with float32 accumulation (about
  *               3 * 2^-18 relative per product).
- * The recurrence, its seeds and range scaling are float64 in every mode. */
+ * The recurrence, its seeds and range scaling are float64 in every mode.  On
+ * the FP32 and BF16X3 paths the per-ring FFTs (and, in apply_A, the N^-1
+ * product between them) run in float32 as well; the ring fold and unfold
+ * with their phases, and every input and output, stay float64. */
 enum { MLCR_FP64 = 0, MLCR_FP32 = 1, MLCR_BF16X3 = 2 };
 
 typedef struct mlcr_geom mlcr_geom;

@@ -391,7 +391,7 @@ int sht_synth(mlcr_geom *g, int lmax, int nrhs, const double *alm, double *map, 
     if ((rc = legendre_synth_any(a, alm, nullptr, g, F, prec))) return rc;
     {
         KTimer t("ring_synth", s);
-        if ((rc = launch_ring_synth(g, lmax, nrhs, F, map, s))) return rc;
+        if ((rc = launch_ring_synth(g, lmax, nrhs, F, map, prec, s))) return rc;
     }
     return MLCR_OK;
 }
@@ -410,7 +410,7 @@ int sht_adjoint(mlcr_geom *g, int lmax, int nrhs, const double *map, double *alm
     double2 *G = g->wsF.as<double2>();
     {
         KTimer t("ring_adjoint", s);
-        if ((rc = launch_ring_adjoint(g, lmax, nrhs, map, G, s))) return rc;
+        if ((rc = launch_ring_adjoint(g, lmax, nrhs, map, G, prec, s))) return rc;
     }
     if ((rc = legendre_adjoint_any(a, G, g, nullptr, nullptr, nullptr, alm, prec))) return rc;
     return MLCR_OK;

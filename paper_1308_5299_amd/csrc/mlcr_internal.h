@@ -192,10 +192,11 @@ struct LegendreArgs {
 };
 int launch_legendre_synth(const LegendreArgs &a, const double *u, double2 *F);
 int launch_legendre_adjoint(const LegendreArgs &a, const double2 *G, double *P, int *nchunks_out);
+// prec: FFTs in float32 on the mixed paths (as launch_ring_apply)
 int launch_ring_synth(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, double *map,
-                      hipStream_t s);
+                      int prec, hipStream_t s);
 int launch_ring_adjoint(const mlcr_geom *g, int lmax, int nrhs, const double *map, double2 *G,
-                        hipStream_t s);
+                        int prec, hipStream_t s);
 // prec: the arithmetic path; its FFTs run in float32 (LDS buffer and
 // Bluestein filter) on the mixed paths, fold/unfold in float64 always
 int launch_ring_apply(const mlcr_geom *g, int lmax, int nrhs, double2 *FG, const double *ninv,

@@ -511,12 +511,12 @@ static int launch_ring(const mlcr_geom *g, int lmax, int nrhs, const double2 *F,
 }
 
 int launch_ring_synth(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, double *map,
-                      hipStream_t s) {
-    return launch_ring<0>(g, lmax, nrhs, F, nullptr, nullptr, map, nullptr, MLCR_FP64, s);
+                      int prec, hipStream_t s) {
+    return launch_ring<0>(g, lmax, nrhs, F, nullptr, nullptr, map, nullptr, prec, s);
 }
 int launch_ring_adjoint(const mlcr_geom *g, int lmax, int nrhs, const double *map, double2 *G,
-                        hipStream_t s) {
-    return launch_ring<1>(g, lmax, nrhs, nullptr, G, map, nullptr, nullptr, MLCR_FP64, s);
+                        int prec, hipStream_t s) {
+    return launch_ring<1>(g, lmax, nrhs, nullptr, G, map, nullptr, nullptr, prec, s);
 }
 // one workgroup per ring
 __global__ __launch_bounds__(256) void k_ring_weight(const double *__restrict__ in,

@@ -354,7 +354,7 @@ static int setup_top_diag(mlcr_solver *S, hipStream_t s) {
     if (g->wsP.reserve((size_t)adjoint_chunks(g, lmax) * tlayout_doubles(lmax, 1, adj_rc(1)) *
                        sizeof(double)))
         return fail(MLCR_ENOMEM, "workspace allocation failed");
-    if ((rc = launch_ring_adjoint(g, l2, 1, op->ninv, Xi.as<double2>(), s))) return rc;
+    if ((rc = launch_ring_adjoint(g, l2, 1, op->ninv, Xi.as<double2>(), MLCR_FP64, s))) return rc;
     if ((rc = launch_diag_pairs(Xi.as<double2>(), l2 + 1, G2.as<double2>(), lmax, g->nrings, s)))
         return rc;
     LegendreArgs a{g, lmax, 1, s};
