@@ -115,11 +115,18 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
         return (threadIdx.x < kChunkM && l + 1 <= lmax) ? abm[l + 1] : 0.0;
     };
     double cpre = coef_at(t0);
+    if (threadIdx.x < kChunkM) sab[threadIdx.x] = cpre;
+    if (t0 + 1 < ntile) cpre = coef_at(t0 + 1);
+    __syncthreads();
     for (int t = t0; t < ntile; t++) {
-        __syncthreads();
-        if (threadIdx.x < kChunkM) sab[threadIdx.x] = cpre;
-        __syncthreads();
-        if (t + 1 < ntile) cpre = coef_at(t + 1);
+        // coefficients of tile t in buffer (t - t0) & 1; those of tile t + 1
+        // go to the other buffer, whose last readers (tile t - 1) are past
+        // the barriers that ended the previous tile
+        const double *sb = sab + ((t - t0) & 1) * kChunkM;
+        if (t + 1 < ntile) {
+            if (threadIdx.x < kChunkM) sab[((t + 1 - t0) & 1) * kChunkM + threadIdx.x] = cpre;
+            if (t + 2 < ntile) cpre = coef_at(t + 2);
+        }
         if (t == tw) {
             const long long tix = ((long long)m * nb16 + 4 * pb + (lane >> 4)) * 64 + (lane & 15);
             const double2 s0 = st[tix];
@@ -136,7 +143,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
 #pragma unroll
                 for (int q = 0; q < 8; q++) {
 #pragma unroll
-                    for (int s = 0; s < 4; s++) L.step(sab[4 * q + s]);
+                    for (int s = 0; s < 4; s++) L.step(sb[4 * q + s]);
                     L.check_range();
                 }
                 mode = wave_mode1(L);
@@ -147,20 +154,20 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
 #pragma unroll 4
                 for (int i = 0; i < 16; i++) {
                     lam[i * RW + lane] = (float)L.w();
-                    L.step_rescale(sab[2 * i]);
+                    L.step_rescale(sb[2 * i]);
                     lam[(16 + i) * RW + lane] = (float)L.w();
-                    L.step_rescale(sab[2 * i + 1]);
+                    L.step_rescale(sb[2 * i + 1]);
                 }
                 mode = wave_mode1(L);
             } else {
 #pragma unroll 8
                 for (int i = 0; i < 16; i++) {
                     lam[i * RW + lane] = (float)L.l1;
-                    double nv = fma(sab[2 * i] * L.z, L.l1, -L.l2);
+                    double nv = fma(sb[2 * i] * L.z, L.l1, -L.l2);
                     L.l2 = L.l1;
                     L.l1 = nv;
                     lam[(16 + i) * RW + lane] = (float)L.l1;
-                    nv = fma(sab[2 * i + 1] * L.z, L.l1, -L.l2);
+                    nv = fma(sb[2 * i + 1] * L.z, L.l1, -L.l2);
                     L.l2 = L.l1;
                     L.l1 = nv;
                 }
@@ -184,8 +191,10 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
                     D[p][c] = mma_b3(al, bh[c][p], D[p][c]);
                 }
         }
-        // the wave's tile (32 l x 16 columns) into its own LDS area
-        __syncthreads();
+        // the wave's tile (32 l x 16 columns) into its own LDS area; the
+        // stores take the MFMA results, so they follow the wave's own reads
+        // of its lambda tile; other waves read the area only between the
+        // two barriers of a tile
 #pragma unroll
         for (int v = 0; v < 4; v++) {
             const int i = 4 * kg + v;
@@ -204,6 +213,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
                 a += (double)reinterpret_cast<const float *>(lam_all + w * LSB)[o];
             Pm[(long long)(lb0 + lr) * 16 + (o & 15)] = (float)a;
         }
+        __syncthreads();        // the tiles are read before the next lambdas overwrite them
     }
 }
 

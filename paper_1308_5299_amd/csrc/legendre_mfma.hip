@@ -141,11 +141,18 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 8 ? 4 : 1) void k_ladj_mfma(
         return (threadIdx.x < kChunkM && l + 1 <= lmax) ? abm[l + 1] : 0.0;
     };
     double cpre = coef_at(t0);
+    if (threadIdx.x < kChunkM) sab[threadIdx.x] = cpre;
+    if (t0 + 1 < ntile) cpre = coef_at(t0 + 1);
+    __syncthreads();
     for (int t = t0; t < ntile; t++) {
-        __syncthreads();
-        if (threadIdx.x < kChunkM) sab[threadIdx.x] = cpre;
-        __syncthreads();
-        if (t + 1 < ntile) cpre = coef_at(t + 1);
+        // coefficients of tile t in buffer (t - t0) & 1; those of tile t + 1
+        // go to the other buffer, whose last readers (tile t - 1) are past
+        // the barriers that ended the previous tile
+        const double *sb = sab + ((t - t0) & 1) * kChunkM;
+        if (t + 1 < ntile) {
+            if (threadIdx.x < kChunkM) sab[((t + 1 - t0) & 1) * kChunkM + threadIdx.x] = cpre;
+            if (t + 2 < ntile) cpre = coef_at(t + 2);
+        }
         if (t == tw) {
             const long long tix = ((long long)m * nb16 + 4 * pb + (lane >> 4)) * 64 + (lane & 15);
             const double2 s0 = st[tix];
@@ -160,7 +167,7 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 8 ? 4 : 1) void k_ladj_mfma(
 #pragma unroll
                 for (int q = 0; q < 8; q++) {
 #pragma unroll
-                    for (int s = 0; s < 4; s++) L.step(sab[4 * q + s]);
+                    for (int s = 0; s < 4; s++) L.step(sb[4 * q + s]);
                     L.check_range();
                 }
                 mode = wave_mode1(L);
@@ -178,13 +185,13 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 8 ? 4 : 1) void k_ladj_mfma(
 #pragma unroll 4
                     for (int s = 0; s < 32; s++) {
                         if ((s & 1) == p) lam[(s >> 1) * SL + lane] = L.w();
-                        L.step_rescale(sab[s]);
+                        L.step_rescale(sb[s]);
                     }
                 } else {
 #pragma unroll 8
                     for (int s = 0; s < 32; s++) {
                         if ((s & 1) == p) lam[(s >> 1) * SL + lane] = L.l1;
-                        const double nv = fma(sab[s] * L.z, L.l1, -L.l2);
+                        const double nv = fma(sb[s] * L.z, L.l1, -L.l2);
                         L.l2 = L.l1;
                         L.l1 = nv;
                     }
@@ -209,7 +216,7 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 8 ? 4 : 1) void k_ladj_mfma(
 #pragma unroll 4
                 for (int s = 0; s < 32; s++) {
                     lam[((s & 1) * 16 + (s >> 1)) * SL + lane] = M::cvt(L.w());
-                    L.step_rescale(sab[s]);
+                    L.step_rescale(sb[s]);
                 }
                 mode = wave_mode1(L);
             } else {
@@ -217,7 +224,7 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 8 ? 4 : 1) void k_ladj_mfma(
 #pragma unroll 8
                 for (int s = 0; s < 32; s++) {
                     lam[((s & 1) * 16 + (s >> 1)) * SL + lane] = M::cvt(L.l1);
-                    const double nv = fma(sab[s] * L.z, L.l1, -L.l2);
+                    const double nv = fma(sb[s] * L.z, L.l1, -L.l2);
                     L.l2 = L.l1;
                     L.l1 = nv;
                 }
@@ -238,8 +245,10 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 8 ? 4 : 1) void k_ladj_mfma(
                 }
             }
         }
-        // the wave's tile (32 l x 16 columns) into its own LDS area
-        __syncthreads();
+        // the wave's tile (32 l x 16 columns) into its own LDS area; the
+        // stores take the MFMA results, so they follow the wave's own reads
+        // of its lambda tile; other waves read the area only between the
+        // two barriers of a tile
 #pragma unroll
         for (int v = 0; v < 4; v++) {
             const int i = M::row(kq, v);
@@ -257,6 +266,7 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 8 ? 4 : 1) void k_ladj_mfma(
             for (int w = 0; w < W; w++) a += (double)lam_all[w * LS + o];
             Pm[(long long)(lb0 + lr) * 16 + (o & 15)] = (T)a;
         }
+        __syncthreads();        // the tiles are read before the next lambdas overwrite them
     }
 }
 
