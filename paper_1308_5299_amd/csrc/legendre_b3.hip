@@ -29,8 +29,11 @@ namespace mlcr {
 // writes its ring's lambdas in float32 (row = (parity, l index), column =
 // ring); lane i + 16 kg reads rings 32 c + 8 kg .. + 7 of row i (two 16-byte
 // reads) and splits them into its hi and lo A operands; the B operand holds
-// the split even/odd ring sums of G for the same rings.  The W tiles are summed in LDS and the chunk's partial sum stored
-// once (T layout, float32 partial sums), exactly as the float32 adjoint does.
+// the split even/odd ring sums of G for the same rings; both 32-ring halves
+// accumulate into one tile per parity.  The W tiles are summed in LDS in
+// float32 (8 terms: about 5e-7 relative, well inside the split products'
+// 1e-5) and the chunk's partial sum stored once (T layout, float32 partial
+// sums, added in float64 by the unpack step).
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_ladj_b3(
     const double2 *__restrict__ G, long long fstride, int nrhs, float *__restrict__ P, int lmax,
@@ -135,9 +138,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
             L.sc = stsc[tix];
             mode = wave_mode1(L);
         }
-        f4b D[2][2];
-#pragma unroll
-        for (int p = 0; p < 2; p++) D[p][0] = D[p][1] = (f4b){0.f, 0.f, 0.f, 0.f};
+        f4b D[2] = {(f4b){0.f, 0.f, 0.f, 0.f}, (f4b){0.f, 0.f, 0.f, 0.f}};   // [parity]
         if (mode <= 0) {
             if (mode == 0) {
 #pragma unroll
@@ -186,9 +187,9 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
                     split2(f0.z, f0.w, ah.y, al.y);
                     split2(f1.x, f1.y, ah.z, al.z);
                     split2(f1.z, f1.w, ah.w, al.w);
-                    D[p][c] = mma_b3(ah, bh[c][p], D[p][c]);
-                    D[p][c] = mma_b3(ah, bl[c][p], D[p][c]);
-                    D[p][c] = mma_b3(al, bh[c][p], D[p][c]);
+                    D[p] = mma_b3(ah, bh[c][p], D[p]);
+                    D[p] = mma_b3(ah, bl[c][p], D[p]);
+                    D[p] = mma_b3(al, bh[c][p], D[p]);
                 }
         }
         // the wave's tile (32 l x 16 columns) into its own LDS area; the
@@ -198,8 +199,8 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
 #pragma unroll
         for (int v = 0; v < 4; v++) {
             const int i = 4 * kg + v;
-            tile[(2 * i) * 16 + jc] = D[0][0][v] + D[0][1][v];
-            tile[(2 * i + 1) * 16 + jc] = D[1][0][v] + D[1][1][v];
+            tile[(2 * i) * 16 + jc] = D[0][v];
+            tile[(2 * i + 1) * 16 + jc] = D[1][v];
         }
         __syncthreads();
         // sum the W tiles; one store per output
@@ -207,11 +208,10 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
         for (int o = threadIdx.x; o < 512; o += 64 * W) {
             const int lr = o >> 4;
             if (m + lb0 + lr > lmax) continue;
-            double a = 0.0;
+            float a = 0.f;
 #pragma unroll
-            for (int w = 0; w < W; w++)
-                a += (double)reinterpret_cast<const float *>(lam_all + w * LSB)[o];
-            Pm[(long long)(lb0 + lr) * 16 + (o & 15)] = (float)a;
+            for (int w = 0; w < W; w++) a += reinterpret_cast<const float *>(lam_all + w * LSB)[o];
+            Pm[(long long)(lb0 + lr) * 16 + (o & 15)] = a;
         }
         __syncthreads();        // the tiles are read before the next lambdas overwrite them
     }
