@@ -34,15 +34,15 @@ PEAK_BF16 = 2.5e15            # MI355X dense bf16 MFMA FLOP/s
 # the default launch shapes (valid when the autotuner keeps them).
 # Key: (library timer name, Legendre path, workload, RHS per launch).
 MEASURED_TRAFFIC = {
-    ("legendre_adjoint", "bf16x3", "c5", 8): 8.946e9 + 4.313e9,
-    ("legendre_adjoint", "fp32", "c5", 8): 8.834e9 + 4.311e9,
-    ("legendre_adjoint", "fp64", "c5", 8): 9.051e9 + 8.596e9,
-    ("legendre_synth", "bf16x3", "c5", 8): 3.888e9 + 8.176e9,
-    ("legendre_synth", "fp32", "c5", 8): 8.145e9 + 9.788e9,
-    ("legendre_synth", "fp64", "c5", 8): 16.381e9 + 9.828e9,
+    ("legendre_adjoint", "bf16x3", "c5", 8): 8.936e9 + 4.314e9,
+    ("legendre_adjoint", "fp32", "c5", 8): 8.839e9 + 4.311e9,
+    ("legendre_adjoint", "fp64", "c5", 8): 9.036e9 + 8.596e9,
+    ("legendre_synth", "bf16x3", "c5", 8): 3.880e9 + 8.658e9,
+    ("legendre_synth", "fp32", "c5", 8): 8.155e9 + 9.799e9,
+    ("legendre_synth", "fp64", "c5", 8): 16.440e9 + 9.846e9,
     ("ring_apply", "bf16x3", "c5", 8): 1.836e9 + 1.074e9 + 3 * (1.278e9 + 1.075e9),
-    ("ring_apply", "fp32", "c5", 8): 1.837e9 + 1.074e9 + 3 * (1.278e9 + 1.075e9),
-    ("ring_apply", "fp64", "c5", 8): 1.772e9 + 1.074e9 + 3 * (1.293e9 + 1.075e9),
+    ("ring_apply", "fp32", "c5", 8): 1.836e9 + 1.074e9 + 3 * (1.278e9 + 1.075e9),
+    ("ring_apply", "fp64", "c5", 8): 1.772e9 + 1.074e9 + 3 * (1.294e9 + 1.075e9),
 }
 
 

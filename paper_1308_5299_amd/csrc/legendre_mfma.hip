@@ -57,9 +57,10 @@ struct Mma<double> {
 // with 16 MFMAs of 4 ring pairs each (likewise odd): MFMA g takes ring pair
 // 16 k + g as its k-th, so lane i + 16 k reads its 16 A values (row i,
 // ring pairs 16 k .. 16 k + 15) with 16-byte LDS reads.  The W tiles are summed
-// in LDS, and the chunk's partial sum is stored once (T layout, in the
-// contraction type: float32 for the mixed path, float64 for the float64
-// path); the chunks are added in float64 in the unpack step.
+// in LDS in the contraction type (float32 for the mixed path: 8 terms, about
+// 5e-7 relative; float64 for the float64 path), and the chunk's partial sum
+// is stored once (T layout, same type); the chunks are added in float64 in
+// the unpack step.
 // The float64 tile would take 135 KiB of LDS per 8-wave workgroup (one
 // workgroup, 2 waves per SIMD): for T = double each tile runs the
 // recurrence twice from the tile's start state, storing the 16 even steps
@@ -261,10 +262,10 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 8 ? 4 : 1) void k_ladj_mfma(
         for (int o = threadIdx.x; o < 512; o += 64 * W) {
             const int lr = o >> 4;
             if (m + lb0 + lr > lmax) continue;
-            double a = 0.0;
+            T a = (T)0;
 #pragma unroll
-            for (int w = 0; w < W; w++) a += (double)lam_all[w * LS + o];
-            Pm[(long long)(lb0 + lr) * 16 + (o & 15)] = (T)a;
+            for (int w = 0; w < W; w++) a += lam_all[w * LS + o];
+            Pm[(long long)(lb0 + lr) * 16 + (o & 15)] = a;
         }
         __syncthreads();        // the tiles are read before the next lambdas overwrite them
     }
