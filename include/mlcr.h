@@ -59,10 +59,12 @@ enum {
  *   MLCR_BF16X3 each float32 operand split into bfloat16 hi + lo, products
  *               hi*hi + hi*lo + lo*hi with float32 accumulation (about
  *               3 * 2^-18 relative per product).
- * The recurrence, its seeds and range scaling are float64 in every mode.  On
- * the FP32 and BF16X3 paths the per-ring FFTs (and, in apply_A, the N^-1
- * product between them) run in float32 as well; the ring fold and unfold
- * with their phases, and every input and output, stay float64. */
+ * On both mixed paths the adjoint's sums over the ring-pair blocks of one
+ * workgroup are float32 too; its per-workgroup partial sums are added in
+ * float64.  The recurrence, its seeds and range scaling are float64 in every
+ * mode.  On the FP32 and BF16X3 paths the per-ring FFTs (and, in apply_A,
+ * the N^-1 product between them) run in float32 as well; the ring fold and
+ * unfold with their phases, and every input and output, stay float64. */
 enum { MLCR_FP64 = 0, MLCR_FP32 = 1, MLCR_BF16X3 = 2 };
 
 typedef struct mlcr_geom mlcr_geom;
