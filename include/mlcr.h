@@ -29,8 +29,9 @@
  *   library never frees them.  Pointers named host_* are host memory read
  *   during the call only.  `stream` is a hipStream_t (NULL = default
  *   stream); all device work of a call is enqueued on it.
- * - prec selects the arithmetic of the Legendre contraction only
- *   (MLCR_FP64 or MLCR_FP32); inputs/outputs are always float64.
+ * - prec selects the arithmetic of the Legendre contraction and the ring
+ *   FFTs only (MLCR_FP64, MLCR_FP32 or MLCR_BF16X3, below); inputs and
+ *   outputs are always float64.
  * - Return value: 0 on success, a negative MLCR_E* code otherwise; a
  *   description is available from mlcr_last_error() (thread-local).
  *   Argument errors are detected before any device work is enqueued.
@@ -96,7 +97,7 @@ int mlcr_timing_get(int i, char *name, int name_len, double *total_ms, long long
  * grows on demand.  The handle may be used from one host thread at a time.
  * ---------------------------------------------------------------------- */
 int mlcr_geom_create(int nside, int lmax, mlcr_geom **out);
-/* Gauss-Legendre grid (Sec. 3.5): nrings rings at the nodes z_k of the
+/* Gauss-Legendre grid (Sec. 3.4): nrings rings at the nodes z_k of the
  * Legendre polynomial P_nrings, ordered north to south, each with nphi
  * equispaced pixels from phi = 0 (pixel index k nphi + j).  The quadrature
  * sum_k W_k sum_j f(theta_k, phi_j) (mlcr_geom_weights) is exact for
@@ -186,8 +187,31 @@ int apply_A_grouped(int nprob, mlcr_op *const *ops, const int *host_nrhs,
  * B_h = diag(f b_l p_l) (Sec. 3.2, eq. A_h).  1 <= h < 16. */
 int mlcr_op_set_level(mlcr_op *op, int h, int lmax_h, const double *host_fl);
 
+/* Replace the operator's prior spectrum (every defined level follows, with
+ * its own filter): host_cl[lmax+1] must be finite and > 0 exactly where the
+ * current C_l is (the set of unknowns stays the same).  Solvers built on op
+ * then solve the new system: their residuals, stopping norms and
+ * certificates use the new C_l, while their smoothers, top diagonal and
+ * dense bottom factor keep the values of the C_l they were built with and
+ * act as an approximate cycle (as when a C_l sampler reuses the hierarchy
+ * across nearby spectra).  Synchronous. */
+int mlcr_op_set_prior(mlcr_op *op, const double *host_cl);
+
+/* Gradient of a quadratic loss with respect to binned prior amplitudes
+ * (the differentiation form: C_l = q_beta C_fid_l for l in band beta, b
+ * held fixed).  With lam = A^-1 dL/dx and dA/dq_beta = -S^-1 / q_beta on the
+ * band,
+ *     host_out[beta] = sum_r sum_{l in beta, m} lam_lm x_lm / (q_beta C_l)
+ * over the operator's active modes, C_l the operator's current spectrum.
+ *   dev_lam, dev_x: [nrhs][(lmax+1)^2]; host_band[lmax+1]: band of each l
+ *   (-1: none, else 0..nbands-1); host_q[nbands] (NULL: all 1).
+ * Float64 throughout; synchronizes on `stream`. */
+int mlcr_prior_band_grad(mlcr_op *op, int nrhs, const double *dev_lam, const double *dev_x,
+                         const int *host_band, int nbands, const double *host_q,
+                         double *host_out, void *stream);
+
 /* Level h like mlcr_op_set_level, with Y^T N^-1 Y evaluated on a
- * Gauss-Legendre grid (Sec. 3.5, eqs. Ni-rewrite and Xi): xi = Y_obs^T N^-1
+ * Gauss-Legendre grid (Sec. 3.4, eqs. Ni-rewrite and Xi): xi = Y_obs^T N^-1
  * truncated at 2 lmax_h is synthesized on 2 lmax_h + 1 Gauss-Legendre rings
  * of nphi = the smallest power of two >= 4 lmax_h + 1 pixels and weighted
  * by the quadrature, which reproduces every coupling of Y_obs^T N^-1 Y_obs
@@ -206,7 +230,7 @@ int mlcr_op_level_lmax(const mlcr_op *op, int h);
  * high-pass filtered diagonal smoother diag(A)^-1; pixel levels h = 1..H,
  * each a band-limited level operator A_h (Sec. 3.2, eq. A_h) with a sibling
  * HEALPix grid of resolution N_side/2, N_side/4, ... and an error smoother
- * on k x k pixel tiles (k = 8, Sec. 3.4); and a dense bottom level solved
+ * on k x k pixel tiles (k = 8, Sec. 3.5); and a dense bottom level solved
  * exactly for l <= 40.  Default ladder (Sec. 3.2-3.4): pixel level 1 keeps
  * lmax; levels with N_side^h >= 512 are limited to 4 N_side^h and use the q_l
  * filter of eq. fourth-power-beam (q = 0.1 at 2570/3000 of the band limit on
@@ -216,7 +240,7 @@ int mlcr_op_level_lmax(const mlcr_op *op, int h);
  * C_0 = C_1 = C_2, Sec. 4.1; EINVAL otherwise); an operator small enough for
  * the dense bottom alone also accepts C_l = 0 (modes removed).  The pixel
  * smoothers are one symmetric multicolour block Gauss-Seidel sweep over the
- * k x k tiles and their neighbour couplings (Sec. 3.4's block pattern).
+ * k x k tiles and their neighbour couplings (Sec. 3.5's block pattern).
  * Recursion counts: the top and the finest pixel level run once down and
  * once up, the others
  * twice (partial W-cycle, Sec. 4.1), the last pixel level once into the
@@ -231,17 +255,87 @@ typedef struct {
                         /* (2l+1) C_l / 4 pi) it bounds the max pixel error of x       */
 } mlcr_solve_info;
 
-/* Build the solver for op: level geometries and operators, smoothers, the
- * top-level diagonal and the dense bottom factor (all computed on the GPU,
- * in float64; smoothers stored in float32, Sec. 3.4).  The operator and its
- * geometry must outlive the solver.  ENOTPD if the bottom matrix or a tile
- * cannot be factored even with a ridge. */
-int mlcr_solver_create(mlcr_op *op, int max_nrhs, mlcr_solver **out);
+/* The level ladder of a solver (Sec. 3.2 level structure, Sec. 3.3 filters,
+ * Sec. 3.4 band limits; Table cycle-cost for a worked example).
+ *   nlevels      pixel levels H, 0..8.  0: no pixel level; the dense solve
+ *                at lmax_dense = the operator's lmax (<= 64) is the solver.
+ *   nside[h]     N_side^h of pixel level h (finest first), a multiple of 8,
+ *                8 <= N_side^h <= 2048 (tiles are 8 x 8 nested pixels).
+ *   lmax[h]      band limit of level h: 1 <= lmax[0] <= the operator's lmax,
+ *                lmax[h] <= lmax[h-1].
+ *   nrec[h]      recursion count n_rec^h of level h into the next coarser
+ *                level (1 = V, 2 = W; 1..3).  nrec_top: the same for the top
+ *                level into pixel level 0 (1..3).
+ *   lmax_dense   band limit of the dense bottom level, 0 <= lmax_dense <=
+ *                lmax[H-1] and <= 64; the bottom solves A restricted to
+ *                l <= lmax_dense with the last pixel level's filter.
+ *   filter[h]    host [lmax[h]+1]: cumulative low-pass filter f~^h_l of
+ *                level h (eq. A_h; finite, and > 0 for l <= the next coarser
+ *                band limit, since restriction divides by it, eq. f_l).
+ *   highpass     host [lmax+1] high-pass h_l applied to the top level's
+ *                diagonal correction, or NULL for 1 - f~^0_l (0 above lmax[0]
+ *                taken as f~ = 0).
+ *   gl_levels    1: a coarse level evaluates Y^T N^-1 Y on a Gauss-Legendre
+ *                grid when that grid is smaller than the observation grid
+ *                (Sec. 3.4); 0: always on the observation grid.
+ * The descriptor is read during mlcr_solver_create only. */
+typedef struct {
+    int nlevels;
+    int nside[8];
+    int lmax[8];
+    int nrec[8];
+    int nrec_top;
+    int lmax_dense;
+    const double *filter[8];
+    const double *highpass;
+    int gl_levels;
+} mlcr_ladder_desc;
+
+/* The ladder mlcr_solver_create uses when given NULL, for an observation
+ * grid nside and band limit lmax: levels N_side/2, N_side/4, ... down to 32;
+ * band limits lmax on the first, 4 N_side^h on levels N_side^h >= 512 and
+ * 6 N_side^h below (Sec. 3.4), capped by the previous level; the q_l filter
+ * of eq. fourth-power-beam with q = 0.1 at 2570/3000 of the band limit on the
+ * first level and 1536/2048 on the second when N_side^h >= 512, else a
+ * Gaussian of FWHM two level pixels (Sec. 3.3); recursion 1 on the top and
+ * the last pixel level, 2 elsewhere (Sec. 4.1); dense bottom at l <= 40.
+ * host_filters [8 (lmax+1)] receives the filters; out->filter[h] points
+ * into it.  Host only. */
+int mlcr_ladder_default(int nside, int lmax, mlcr_ladder_desc *out, double *host_filters);
+/* Validate a ladder for an observation grid nside and an operator band
+ * limit lmax with the rules above (0 or MLCR_EINVAL with the reason).  Host
+ * only; mlcr_solver_create runs the same check. */
+int mlcr_ladder_check(int nside, int lmax, const mlcr_ladder_desc *ladder);
+
+/* Build the solver for op on a ladder (NULL = mlcr_ladder_default): level
+ * geometries and operators, smoothers, the top-level diagonal and the dense
+ * bottom factor (all computed on the GPU, in float64; smoothers stored in
+ * float32, Sec. 3.5).  The operator and its geometry must outlive the
+ * solver.  EINVAL for a ladder that fails mlcr_ladder_check, or C_l = 0 for
+ * some l with pixel levels; ENOTPD if the bottom matrix or a tile cannot be
+ * factored even with a ridge. */
+int mlcr_solver_create(mlcr_op *op, const mlcr_ladder_desc *ladder, int max_nrhs,
+                       mlcr_solver **out);
 void mlcr_solver_destroy(mlcr_solver *s);
 /* Pixel level count, bottom band limit, bottom unknowns and the largest tile
  * ridge alpha used (relative to the largest diagonal element of the block). */
 int mlcr_solver_info(const mlcr_solver *s, int *nlevels, int *lmax_bottom, int *n_bottom,
                      float *max_ridge);
+
+/* Per-level account of the cycles (Sec. 4.1, Table cycle-cost): with
+ * profiling on, wcycle_solve and pcg_solve bracket every step of every cycle
+ * with HIP events on their stream (graph mode is then not used) and add the
+ * times per level and kind of work.  Levels: 0 = top, 1..H pixel levels,
+ * H + 1 = dense bottom.  Kinds: 0 = applications of A_h (the residuals),
+ * 1 = level transforms Y_h and Y_h^T of the pixel smoother, 2 = the error
+ * smoother itself (top diagonal, pixel-domain M_h, or the dense solve),
+ * 3 = restriction, interpolation and vector updates.
+ * mlcr_solver_set_profile(on) also clears the totals.
+ * mlcr_solver_profile fills host_ms[4 L] and host_calls[4 L] (either may be
+ * NULL) for L = min(nlevels_max, H + 2) levels and returns H + 2. */
+int mlcr_solver_set_profile(mlcr_solver *s, int on);
+int mlcr_solver_profile(const mlcr_solver *s, int nlevels_max, double *host_ms,
+                        long long *host_calls);
 
 /* Copy of the top-level smoother's diagonal, 1 / diag(A) on active modes and
  * 0 elsewhere (dev_out: [(lmax+1)^2]); diag(Y^T N^-1 Y) comes from the ring
@@ -314,7 +408,7 @@ int wcycle_solve_grouped(int nprob, mlcr_solver *const *s, const int *host_nrhs,
 /* HEALPix NESTED to RING pixel index (Gorski et al. 2005); the tiles of the
  * pixel-level smoothers are nested blocks of k^2 pixels. */
 int mlcr_nest2ring(int nside, long long n, const long long *host_nest, long long *host_ring);
-/* Tile graph of the pixel-level smoothers (Sec. 3.4): tiles are the 8 x 8
+/* Tile graph of the pixel-level smoothers (Sec. 3.5): tiles are the 8 x 8
  * nested blocks, tile t = nested pixels [64 t, 64 t + 64), 12 (nside/8)^2 of
  * them (nside % 8 == 0).  Distances are between pixel centres in pixel widths
  * sqrt(4 pi / N_pix).

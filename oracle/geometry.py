@@ -75,7 +75,7 @@ def pixel_angles(geom: RingGeometry):
 
 
 def gauss_legendre_rings(nrings: int, nphi: int):
-    """Gauss-Legendre rings (Sec. 3.5): the nodes z_k of P_nrings, north to
+    """Gauss-Legendre rings (Sec. 3.4): the nodes z_k of P_nrings, north to
     south, each with nphi equispaced pixels from phi = 0.  Returns the ring
     geometry and the quadrature weight of one pixel of each ring,
     W_k = w_k 2 pi / nphi with w_k = 2 / ((1 - z_k^2) P'_n(z_k)^2).

@@ -31,9 +31,20 @@ import math
 import numpy as np
 
 
+_BINOM = [1]          # binom(2m, m) for m = 0, 1, ..., exact integers
+
+
+def _binom_2m_m(m: int) -> int:
+    """binom(2m, m), extended exactly: binom(2m+2, m+1) = binom(2m, m) 2 (2m+1) / (m+1)."""
+    while len(_BINOM) <= m:
+        k = len(_BINOM) - 1
+        _BINOM.append(_BINOM[k] * 2 * (2 * k + 1) // (k + 1))
+    return _BINOM[m]
+
+
 def seed_constant(m: int) -> float:
     """(-1)^m sqrt((2m+1)/(4 pi) * binom(2m,m)/4^m), the factor of sin^m theta."""
-    t = float(Fraction(math.comb(2 * m, m) * (2 * m + 1), 4 ** m))
+    t = float(Fraction(_binom_2m_m(m) * (2 * m + 1), 4 ** m))
     c = math.sqrt(t / (4.0 * math.pi))
     return -c if (m & 1) else c
 

@@ -84,32 +84,68 @@ def legendre_pair_m(x: np.ndarray, G, m: int, lmax: int, geom: RingGeometry):
     return F, A
 
 
+def _synth_orders(lmax: int, geom: RingGeometry, items):
+    """Legendre synthesis of the orders in items [(m, x^c_m, x^s_m)]."""
+    out = []
+    for m, xc, xs in items:
+        lam = lambda_table(m, lmax, geom.z, geom.sint)
+        out.append((m, xc @ lam, xs @ lam))
+    return out
+
+
+def _adjoint_orders(lmax: int, geom: RingGeometry, items):
+    """Legendre adjoint of the orders in items [(m, G^c_m, G^s_m)]."""
+    out = []
+    for m, gc, gs in items:
+        lam = lambda_table(m, lmax, geom.z, geom.sint)
+        out.append((m, gc @ lam.T, gs @ lam.T))
+    return out
+
+
+def _order_groups(lmax: int, geom: RingGeometry):
+    """Orders in interleaved groups, one per worker task; a single group for
+    small transforms (worker start-up would cost more than it saves)."""
+    from . import pool
+    if (lmax + 1) ** 2 * geom.nrings < 2e7:
+        return [list(range(lmax + 1))]
+    return pool.interleave(lmax + 1, 4 * pool.worker_count())
+
+
 def legendre_synth(x: np.ndarray, lmax: int, geom: RingGeometry):
-    """F^c, F^s of shape (..., nrings, lmax+1) from packed x of shape (..., nalm)."""
+    """F^c, F^s of shape (..., nrings, lmax+1) from packed x of shape (..., nalm).
+
+    Orders are independent; large transforms spread them over the oracle's
+    worker processes (``pool``), with the same per-order arithmetic."""
+    from . import pool
     x = np.asarray(x, dtype=np.float64)
     lead = x.shape[:-1]
     Fc = np.zeros(lead + (geom.nrings, lmax + 1))
     Fs = np.zeros_like(Fc)
-    for m in range(lmax + 1):
-        (fc, fs), _ = legendre_pair_m(x, None, m, lmax, geom)
-        Fc[..., :, m] = fc
-        Fs[..., :, m] = fs
+    groups = [(lmax, geom, [(m,) + tuple(np.ascontiguousarray(v) for v in split_m(x, m, lmax))
+                            for m in ms]) for ms in _order_groups(lmax, geom)]
+    for res in pool.run(_synth_orders, groups):
+        for m, fc, fs in res:
+            Fc[..., :, m] = fc
+            Fs[..., :, m] = fs
     return Fc, Fs
 
 
 def legendre_adjoint(Gc: np.ndarray, Gs: np.ndarray, lmax: int, geom: RingGeometry):
     """Transpose of ``legendre_synth``: packed x from G^c, G^s (..., nrings, lmax+1)."""
+    from . import pool
     lead = Gc.shape[:-2]
     x = np.zeros(lead + (nalm(lmax),))
-    for m in range(lmax + 1):
-        _, (ac, as_) = legendre_pair_m(None, (Gc[..., :, m], Gs[..., :, m]), m, lmax, geom)
-        if m == 0:
-            x[..., : lmax + 1] = ac
-        else:
-            b = block_base(m, lmax)
-            n = lmax - m + 1
-            x[..., b: b + n] = ac
-            x[..., b + n: b + 2 * n] = as_
+    groups = [(lmax, geom, [(m, np.ascontiguousarray(Gc[..., :, m]), np.ascontiguousarray(Gs[..., :, m]))
+                            for m in ms]) for ms in _order_groups(lmax, geom)]
+    for res in pool.run(_adjoint_orders, groups):
+        for m, ac, as_ in res:
+            if m == 0:
+                x[..., : lmax + 1] = ac
+            else:
+                b = block_base(m, lmax)
+                n = lmax - m + 1
+                x[..., b: b + n] = ac
+                x[..., b + n: b + 2 * n] = as_
     return x
 
 

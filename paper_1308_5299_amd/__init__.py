@@ -6,8 +6,8 @@ kernels behind a C ABI (include/mlcr.h).  This package is a thin binding:
 torch supplies device memory and streams, every step runs in libmlcr.so.
 """
 from ._lib import MLCRError, load as load_library  # noqa: F401
-from .api import (BF16X3, FP32, FP64, Geometry, KernelTimer, Operator, Solver, apply_A,  # noqa: F401
-                  apply_A_grouped, solve_grouped, cr_rhs,
+from .api import (BF16X3, FP32, FP64, Geometry, KernelTimer, Ladder, Operator, Solver,  # noqa: F401
+                  apply_A, apply_A_grouped, solve_grouped, cr_rhs, prior_band_grad,
                   cycle_counts, ladder_plan, nest2ring, sht_adjoint, sht_synth, tile_graph)
 
 from . import autograd  # noqa: F401,E402
@@ -15,5 +15,5 @@ from . import autotune  # noqa: F401,E402
 
 __all__ = ["autograd", "autotune", "MLCRError", "load_library", "BF16X3", "FP32", "FP64", "Geometry", "Operator",
            "apply_A", "apply_A_grouped", "solve_grouped", "cr_rhs", "sht_adjoint", "sht_synth", "KernelTimer",
-           "Solver", "nest2ring", "tile_graph",
+           "Solver", "Ladder", "prior_band_grad", "nest2ring", "tile_graph",
            "ladder_plan", "cycle_counts"]

@@ -35,7 +35,14 @@ SIGNATURES = {
     "mlcr_op_set_level_gl": (c_int, [c_void_p, c_int, c_int, c_dbl_p]),
     "mlcr_op_level_lmax": (c_int, [c_void_p, c_int]),
     "apply_A": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_int, c_void_p]),
-    "mlcr_solver_create": (c_int, [c_void_p, c_int, ctypes.POINTER(c_void_p)]),
+    "mlcr_solver_create": (c_int, [c_void_p, c_void_p, c_int, ctypes.POINTER(c_void_p)]),
+    "mlcr_ladder_default": (c_int, [c_int, c_int, c_void_p, c_void_p]),
+    "mlcr_ladder_check": (c_int, [c_int, c_int, c_void_p]),
+    "mlcr_solver_set_profile": (c_int, [c_void_p, c_int]),
+    "mlcr_solver_profile": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
+    "mlcr_op_set_prior": (c_int, [c_void_p, c_dbl_p]),
+    "mlcr_prior_band_grad": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_int, c_void_p,
+                                     c_void_p, c_void_p]),
     "mlcr_solver_destroy": (None, [c_void_p]),
     "mlcr_solver_info": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
                                  ctypes.POINTER(c_int), ctypes.POINTER(ctypes.c_float)]),
@@ -64,6 +71,13 @@ SIGNATURES = {
 }
 
 _lib = None
+
+
+class LadderDesc(ctypes.Structure):
+    """mlcr_ladder_desc (include/mlcr.h)."""
+    _fields_ = [("nlevels", ctypes.c_int), ("nside", ctypes.c_int * 8), ("lmax", ctypes.c_int * 8),
+                ("nrec", ctypes.c_int * 8), ("nrec_top", ctypes.c_int), ("lmax_dense", ctypes.c_int),
+                ("filter", c_dbl_p * 8), ("highpass", c_dbl_p), ("gl_levels", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

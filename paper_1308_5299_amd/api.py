@@ -175,6 +175,14 @@ class Operator:
                                        fl.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         self.level_lmax[int(h)] = int(lmax_h)
 
+    def set_prior(self, cl) -> None:
+        """Replace C_l (mlcr_op_set_prior): > 0 exactly where the current C_l is."""
+        cl = np.ascontiguousarray(np.asarray(cl, dtype=np.float64)[: self.lmax + 1])
+        if cl.size != self.lmax + 1:
+            raise ValueError("cl needs lmax+1 entries")
+        check(load().mlcr_op_set_prior(self._h, cl.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        self.cl = cl
+
     def set_level_gl(self, h: int, lmax_h: int, fl) -> None:
         """Level h with Y^T N^-1 Y on a Gauss-Legendre grid (downgraded N^-1)."""
         fl = np.ascontiguousarray(np.asarray(fl, dtype=np.float64)[: lmax_h + 1])
@@ -251,16 +259,94 @@ class KernelTimer:
         return False
 
 
+class Ladder:
+    """A solver ladder (mlcr_ladder_desc): pixel levels finest first, each with
+    N_side^h, lmax^h, n_rec^h and its cumulative filter f~^h_l; the top
+    level's recursion count, the dense bottom's band limit, an optional top
+    high-pass and whether coarse levels may use Gauss-Legendre grids."""
+
+    def __init__(self, nside, lmax, nrec, filters, nrec_top: int = 1, lmax_dense: int = 40,
+                 highpass=None, gl_levels: bool = True):
+        self.nside = [int(v) for v in nside]
+        self.lmax = [int(v) for v in lmax]
+        self.nrec = [int(v) for v in nrec]
+        self.filters = [np.ascontiguousarray(np.asarray(f, dtype=np.float64)) for f in filters]
+        self.nrec_top = int(nrec_top)
+        self.lmax_dense = int(lmax_dense)
+        self.highpass = None if highpass is None else np.ascontiguousarray(np.asarray(highpass, dtype=np.float64))
+        self.gl_levels = bool(gl_levels)
+        n = len(self.nside)
+        if not (len(self.lmax) == len(self.nrec) == len(self.filters) == n) or n > 8:
+            raise ValueError("one nside, lmax, nrec and filter per level, at most 8 levels")
+        for f, lm in zip(self.filters, self.lmax):
+            if f.size < lm + 1:
+                raise ValueError("a filter needs lmax^h + 1 entries")
+
+    @classmethod
+    def default(cls, nside: int, lmax: int) -> "Ladder":
+        """The ladder the library uses when given none (mlcr_ladder_default)."""
+        from ._lib import LadderDesc
+        d = LadderDesc()
+        buf = np.zeros(8 * (lmax + 1), dtype=np.float64)
+        check(load().mlcr_ladder_default(int(nside), int(lmax), ctypes.byref(d), buf.ctypes.data))
+        n = d.nlevels
+        filt = [buf[h * (lmax + 1): h * (lmax + 1) + d.lmax[h] + 1].copy() for h in range(n)]
+        return cls(list(d.nside[:n]), list(d.lmax[:n]), list(d.nrec[:n]), filt, d.nrec_top,
+                   d.lmax_dense, None, bool(d.gl_levels))
+
+    def desc(self):
+        """The C descriptor; its filter pointers point into this object's arrays."""
+        from ._lib import LadderDesc
+        dp = ctypes.POINTER(ctypes.c_double)
+        d = LadderDesc()
+        d.nlevels = len(self.nside)
+        for h in range(d.nlevels):
+            d.nside[h], d.lmax[h], d.nrec[h] = self.nside[h], self.lmax[h], self.nrec[h]
+            d.filter[h] = self.filters[h].ctypes.data_as(dp)
+        d.nrec_top = self.nrec_top
+        d.lmax_dense = self.lmax_dense
+        d.highpass = self.highpass.ctypes.data_as(dp) if self.highpass is not None else dp()
+        d.gl_levels = 1 if self.gl_levels else 0
+        return d
+
+    def check(self, nside_obs: int, lmax: int) -> None:
+        """mlcr_ladder_check: raises MLCRError with the reason if invalid."""
+        d = self.desc()
+        check(load().mlcr_ladder_check(int(nside_obs), int(lmax), ctypes.byref(d)))
+
+
 class Solver:
     """Multi-level CR solver (W-cycle) for an Operator; see include/mlcr.h."""
 
-    def __init__(self, op: Operator, max_nrhs: int = 1):
+    def __init__(self, op: Operator, max_nrhs: int = 1, ladder: Ladder | None = None):
         lib = load()
         self.op = op
         self.max_nrhs = int(max_nrhs)
+        self.ladder = ladder
         h = ctypes.c_void_p()
-        check(lib.mlcr_solver_create(op.handle, self.max_nrhs, ctypes.byref(h)))
+        d = ladder.desc() if ladder is not None else None
+        check(lib.mlcr_solver_create(op.handle, ctypes.byref(d) if d is not None else None,
+                                     self.max_nrhs, ctypes.byref(h)))
         self._h = h
+
+    def set_profile(self, on: bool = True) -> None:
+        """Per-level profile of the cycles (mlcr_solver_set_profile); clears it."""
+        check(load().mlcr_solver_set_profile(self._h, 1 if on else 0))
+
+    def profile(self) -> dict:
+        """{"ms": [levels][4], "calls": [levels][4]}: kinds = A_h applications,
+        level transforms, smoother, transfers; levels = top, pixel levels,
+        dense bottom."""
+        lib = load()
+        n = lib.mlcr_solver_profile(self._h, 0, None, None)
+        if n < 0:
+            check(n)
+        ms = np.zeros(4 * n)
+        calls = np.zeros(4 * n, dtype=np.int64)
+        r = lib.mlcr_solver_profile(self._h, n, ms.ctypes.data, calls.ctypes.data)
+        if r < 0:
+            check(r)
+        return {"ms": ms.reshape(n, 4), "calls": calls.reshape(n, 4)}
 
     def info(self) -> dict:
         nl, lb, nb = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
@@ -329,6 +415,27 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def prior_band_grad(op: Operator, lam: torch.Tensor, x: torch.Tensor, band, q=None) -> np.ndarray:
+    """dL/dq_beta = sum_{l in beta, m} lam_lm x_lm / (q_beta C_l) over RHS and the
+    operator's active modes (mlcr_prior_band_grad); band[l] = -1 or 0..B-1."""
+    _dev(lam, "lam")
+    _dev(x, "x")
+    nrhs = _batch(lam, nalm(op.lmax), "lam")
+    if _batch(x, nalm(op.lmax), "x") != nrhs:
+        raise ValueError("lam and x must have the same batch size")
+    band = np.ascontiguousarray(np.asarray(band, dtype=np.int32)[: op.lmax + 1])
+    if band.size != op.lmax + 1:
+        raise ValueError("band needs lmax+1 entries")
+    nb = int(band.max()) + 1 if q is None else len(q)
+    qa = None if q is None else np.ascontiguousarray(np.asarray(q, dtype=np.float64))
+    out = np.zeros(max(nb, 1), dtype=np.float64)
+    check(load().mlcr_prior_band_grad(op.handle, nrhs, ctypes.c_void_p(lam.data_ptr()),
+                                      ctypes.c_void_p(x.data_ptr()), band.ctypes.data, max(nb, 1),
+                                      qa.ctypes.data if qa is not None else None, out.ctypes.data,
+                                      _stream()))
+    return out
 
 
 def _ptrs(seq) -> "ctypes.Array":

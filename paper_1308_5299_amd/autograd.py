@@ -8,7 +8,9 @@
   symmetric) and returns dL/db = lam.  With the prior split into bands,
   C_l = q_beta C_fid_l for l in band beta, dA/dq_beta = -(1/q_beta^2) S_fid^-1
   on the band, so dL/dq_beta = sum_{l in beta, m} lam_lm x_lm / (q_beta^2 C_fid_l)
-  (b held fixed).  The solver must have been built for C = q C_fid.
+  (b held fixed); the library's mlcr_prior_band_grad forms that sum on the
+  device from the operator's current C_l = q_beta C_fid_l.  The solver's
+  operator must hold C = q C_fid.
 """
 from __future__ import annotations
 
@@ -94,16 +96,11 @@ class CRSolve(torch.autograd.Function):
                                   prec=ctx.prec)
         gq = None
         if ctx.has_q:
-            lmax = ctx.solver.op.lmax
-            L = torch.from_numpy(api.packed_ell(lmax)).to(x.device)
-            band = torch.from_numpy(band_index(lmax, ctx.edges)).to(x.device)[L]
-            cfid = torch.as_tensor(np.asarray(ctx.cl_fid, dtype=np.float64), device=x.device)[L]
-            inb = band >= 0
-            per = torch.zeros_like(lam)
-            per[:, inb] = lam[:, inb] * x[:, inb] / cfid[inb]
-            gq = torch.zeros(len(ctx.edges) - 1, dtype=torch.float64, device=x.device)
-            gq.index_add_(0, band[inb], per[:, inb].sum(0))
-            gq = gq / (q * q)
+            # dL/dq_beta = sum_{l in beta, m} lam x / (q_beta C_l), reduced in the library
+            op = ctx.solver.op
+            band = band_index(op.lmax, ctx.edges)
+            g = api.prior_band_grad(op, lam, x, band, q.detach().cpu().numpy())
+            gq = torch.from_numpy(g).to(x.device)
         return lam, gq, None, None, None, None, None, None
 
 

@@ -215,13 +215,19 @@ namespace mlcr {
 int apply_level(mlcr_op *op, int level, int nrhs, const double *x, double *y, int prec,
                 hipStream_t s) {
     if (!op || !x || !y) return fail(MLCR_EINVAL, "NULL argument");
-    if (x == y) return fail(MLCR_EINVAL, "x and y must not alias");
     if (level < 0 || level >= 16 || op->levels[level].lmax < 0)
         return fail(MLCR_EINVAL, "level not defined");
+    return apply_level_on(op, op->levels[level], nrhs, x, y, prec, s);
+}
+
+int apply_level_on(mlcr_op *op, const mlcr_level &L, int nrhs, const double *x, double *y,
+                   int prec, hipStream_t s) {
+    if (!op || !x || !y) return fail(MLCR_EINVAL, "NULL argument");
+    if (x == y) return fail(MLCR_EINVAL, "x and y must not alias");
+    if (L.lmax < 0) return fail(MLCR_EINVAL, "level not defined");
     if (nrhs < 1) return fail(MLCR_EINVAL, "nrhs must be >= 1");
     int rc;
     if ((rc = check_prec(prec))) return rc;
-    const mlcr_level &L = op->levels[level];
     mlcr_geom *g = L.gl ? L.gl : op->g;
     const double *ninv = L.gl ? L.gninv.as<double>() : op->ninv;
     const int lmax = L.lmax;
@@ -428,9 +434,11 @@ static void drop_gl(mlcr_level &L) {
     L.gninv.release();
 }
 
-static int upload_level(mlcr_level &L, int lmax_h, const std::vector<double> &cl,
-                        const std::vector<double> &bl, const double *fl) {
-    drop_gl(L);
+// d = f^2 / C_l and bh = f b_l of a level (0 on excluded modes), from its
+// stored filter
+static int level_tables(mlcr_level &L, int lmax_h, const std::vector<double> &cl,
+                        const std::vector<double> &bl) {
+    const double *fl = L.fl.empty() ? nullptr : L.fl.data();
     std::vector<double> d(lmax_h + 1), bh(lmax_h + 1);
     for (int l = 0; l <= lmax_h; l++) {
         const double f = fl ? fl[l] : 1.0;
@@ -446,6 +454,16 @@ static int upload_level(mlcr_level &L, int lmax_h, const std::vector<double> &cl
         return fail(MLCR_ENOMEM, "level table allocation failed");
     MLCR_HIP_CHECK(hipMemcpy(L.d.ptr, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice));
     MLCR_HIP_CHECK(hipMemcpy(L.bh.ptr, bh.data(), bh.size() * sizeof(double), hipMemcpyHostToDevice));
+    return MLCR_OK;
+}
+
+static int upload_level(mlcr_level &L, int lmax_h, const std::vector<double> &cl,
+                        const std::vector<double> &bl, const double *fl) {
+    drop_gl(L);
+    if (fl) L.fl.assign(fl, fl + lmax_h + 1);
+    else L.fl.clear();
+    int rc = level_tables(L, lmax_h, cl, bl);
+    if (rc) return rc;
     L.lmax = lmax_h;
     return MLCR_OK;
 }
@@ -511,19 +529,44 @@ int mlcr_op_set_level_gl(mlcr_op *op, int h, int lmax_h, const double *fl) {
     if (!op || !fl) return fail(MLCR_EINVAL, "NULL argument");
     if (h < 1 || h >= 16) return fail(MLCR_EINVAL, "level index must be in [1, 15]");
     if (lmax_h < 0 || lmax_h > op->lmax) return fail(MLCR_EINVAL, "lmax_h out of range");
+    return define_level(op, op->levels[h], lmax_h, fl, true);
+}
+
+}  // extern "C"
+
+namespace mlcr {
+
+void release_level(mlcr_level &L) {
+    drop_gl(L);
+    L.d.release();
+    L.bh.release();
+    L.fl.clear();
+    L.lmax = -1;
+}
+
+int refresh_level(mlcr_op *op, mlcr_level &L) {
+    return L.lmax >= 0 ? level_tables(L, L.lmax, op->cl, op->bl) : MLCR_OK;
+}
+
+// Level tables of band limit lmax_h and filter fl into L (f = 1 if fl is
+// NULL); with gl, Y^T N^-1 Y of the level on a Gauss-Legendre grid.
+int define_level(mlcr_op *op, mlcr_level &L, int lmax_h, const double *fl, bool gl) {
+    if (lmax_h < 0 || lmax_h > op->lmax) return fail(MLCR_EINVAL, "lmax_h out of range");
+    for (int l = 0; fl && l <= lmax_h; l++)
+        if (!std::isfinite(fl[l])) return fail(MLCR_EINVAL, "filter must be finite");
+    if (!gl) return upload_level(L, lmax_h, op->cl, op->bl, fl);
     const int lx = 2 * lmax_h;            // band limit of the downgraded N^-1
     if (lx > op->g->lmax)
         return fail(MLCR_EINVAL, "2 lmax_h exceeds the observation geometry's lmax");
     int nphi = 4;
     while (nphi < 4 * lmax_h + 1) nphi <<= 1;
     if (nphi > 16384) return fail(MLCR_EINVAL, "lmax_h too large for a Gauss-Legendre level");
-    int rc = mlcr_op_set_level(op, h, lmax_h, fl);
+    int rc = upload_level(L, lmax_h, op->cl, op->bl, fl);
     if (rc) return rc;
-    mlcr_level &L = op->levels[h];
     mlcr_geom *gg = nullptr;
     if ((rc = mlcr_geom_create_gl(lx, 2 * lmax_h + 1, nphi, &gg))) return rc;
     L.gl = gg;
-    // xi = Y_obs^T N^-1 (Sec. 3.5): every coupling of Y_obs^T N^-1 Y_obs between
+    // xi = Y_obs^T N^-1 (Sec. 3.4): every coupling of Y_obs^T N^-1 Y_obs between
     // modes l, l' <= lmax_h sees only xi_LM with L <= 2 lmax_h; synthesized on
     // the Gauss-Legendre grid and weighted by its quadrature, it reproduces
     // those couplings exactly (up to rounding)
@@ -536,6 +579,29 @@ int mlcr_op_set_level_gl(mlcr_op *op, int h, int lmax_h, const double *fl) {
     if ((rc = sht_synth(gg, lx, 1, xi.as<double>(), map.as<double>(), MLCR_FP64, nullptr))) return rc;
     if ((rc = launch_ring_weight(gg, map.as<double>(), L.gninv.as<double>(), nullptr))) return rc;
     MLCR_HIP_CHECK(hipDeviceSynchronize());
+    return MLCR_OK;
+}
+
+}  // namespace mlcr
+
+extern "C" {
+
+int mlcr_op_set_prior(mlcr_op *op, const double *cl) {
+    if (!op || !cl) return fail(MLCR_EINVAL, "NULL argument");
+    for (int l = 0; l <= op->lmax; l++) {
+        if (!std::isfinite(cl[l]) || cl[l] < 0.0) return fail(MLCR_EINVAL, "C_l must be finite and >= 0");
+        if ((cl[l] > 0.0) != (op->cl[l] > 0.0))
+            return fail(MLCR_EINVAL, "the new C_l must be > 0 exactly where the current one is (l = " +
+                                         std::to_string(l) + ")");
+    }
+    MLCR_HIP_CHECK(hipDeviceSynchronize());      // queued applies may read the level tables
+    op->cl.assign(cl, cl + op->lmax + 1);
+    for (auto &L : op->levels)
+        if (L.lmax >= 0) {
+            int rc = level_tables(L, L.lmax, op->cl, op->bl);
+            if (rc) return rc;
+        }
+    op->prior_version++;
     return MLCR_OK;
 }
 

@@ -146,6 +146,7 @@ struct mlcr_geom {
 
 struct mlcr_level {
     int lmax = -1;
+    std::vector<double> fl;     // host: the level's filter (empty: f = 1)
     mlcr::DevBuf d;     // double[lmax+1]: f^2 / C_l (0 for excluded modes)
     mlcr::DevBuf bh;    // double[lmax+1]: f b_l p_l (0 for excluded modes)
     // optional Gauss-Legendre evaluation of Y^T N^-1 Y (owned): the grid and
@@ -159,7 +160,9 @@ struct mlcr_op {
     int lmax = 0, max_nrhs = 0;
     const double *ninv = nullptr;
     std::vector<double> cl, bl;
+    int prior_version = 0;  // bumped by mlcr_op_set_prior
     mlcr::DevBuf rhs_pix;   // workspace of mlcr_cr_rhs
+    mlcr::DevBuf ell_ws;    // workspace of mlcr_prior_band_grad
     mlcr_level levels[16];
 };
 

@@ -72,6 +72,7 @@ struct Plan {
     std::vector<double> fl[8];
     std::vector<double> highpass;
     double omega = 1.0, omega_top = 1.0;
+    bool gl = true;         // coarse levels on Gauss-Legendre grids when cheaper
 };
 
 // q_l = exp(-l^2 (l+1)^2 lambda) with q_{lstar} = 0.1 (eq. fourth-power-beam)
@@ -142,10 +143,134 @@ static void default_plan(int nside_obs, int lmax, Plan &p) {
 }
 
 // ---------------------------------------------------------------------------
-// CR-Cycle recursion (Fig. code:mg), shared by the GPU and the counting backend
-// Levels: 0 = top spherical-harmonic level (diagonal smoother), 1..H pixel
-// levels, B = H + 1 dense bottom (or 0 when there is no pixel level).
+// ladder from a caller's descriptor
 // ---------------------------------------------------------------------------
+static constexpr int kMaxDenseL = 64;   // largest dense bottom band limit
+
+static int check_ladder(int nside_obs, int lmax, const mlcr_ladder_desc *d) {
+    if (!d) return fail(MLCR_EINVAL, "ladder is NULL");
+    const int H = d->nlevels;
+    if (H < 0 || H > 8) return fail(MLCR_EINVAL, "ladder: nlevels must be in [0, 8]");
+    if (d->nrec_top < 1 || d->nrec_top > 3) return fail(MLCR_EINVAL, "ladder: nrec_top must be in [1, 3]");
+    if (d->gl_levels != 0 && d->gl_levels != 1) return fail(MLCR_EINVAL, "ladder: gl_levels must be 0 or 1");
+    if (H == 0) {
+        if (d->lmax_dense != lmax || lmax > kMaxDenseL)
+            return fail(MLCR_EINVAL, "ladder: without pixel levels the dense solve must cover the "
+                                     "operator's lmax (<= 64)");
+        return MLCR_OK;
+    }
+    for (int h = 0; h < H; h++) {
+        const std::string lv = "ladder level " + std::to_string(h) + ": ";
+        if (d->nside[h] < kTile || d->nside[h] > 2048 || d->nside[h] % kTile)
+            return fail(MLCR_EINVAL, lv + "nside must be a multiple of 8 in [8, 2048]");
+        const int up = h == 0 ? lmax : d->lmax[h - 1];
+        if (d->lmax[h] < 1 || d->lmax[h] > up)
+            return fail(MLCR_EINVAL, lv + "lmax must be in [1, " + std::to_string(up) + "]");
+        if (d->nrec[h] < 1 || d->nrec[h] > 3) return fail(MLCR_EINVAL, lv + "nrec must be in [1, 3]");
+        if (!d->filter[h]) return fail(MLCR_EINVAL, lv + "filter is NULL");
+        const int lnext = h + 1 < H ? d->lmax[h + 1] : d->lmax_dense;
+        for (int l = 0; l <= d->lmax[h]; l++) {
+            const double f = d->filter[h][l];
+            if (!std::isfinite(f)) return fail(MLCR_EINVAL, lv + "filter must be finite");
+            if (l <= lnext && !(f > 0.0))
+                return fail(MLCR_EINVAL, lv + "filter must be > 0 up to the next level's lmax (l = " +
+                                             std::to_string(l) + ")");
+        }
+    }
+    if (d->lmax_dense < 0 || d->lmax_dense > d->lmax[H - 1] || d->lmax_dense > kMaxDenseL)
+        return fail(MLCR_EINVAL, "ladder: lmax_dense must be in [0, min(lmax[H-1], 64)]");
+    if (d->highpass)
+        for (int l = 0; l <= lmax; l++)
+            if (!std::isfinite(d->highpass[l])) return fail(MLCR_EINVAL, "ladder: highpass must be finite");
+    (void)nside_obs;
+    return MLCR_OK;
+}
+
+static void plan_from_desc(int lmax, const mlcr_ladder_desc *d, Plan &p) {
+    p = Plan();
+    p.H = d->nlevels;
+    p.nrec_top = d->nrec_top;
+    p.gl = d->gl_levels != 0;
+    if (p.H == 0) {
+        p.lmax_b = lmax;
+        return;
+    }
+    for (int h = 0; h < p.H; h++) {
+        p.nside[h] = d->nside[h];
+        p.lmax[h] = d->lmax[h];
+        p.nrec[h] = d->nrec[h];
+        p.fl[h].assign(d->filter[h], d->filter[h] + d->lmax[h] + 1);
+    }
+    p.lmax_b = d->lmax_dense;
+    p.highpass.resize(lmax + 1);
+    for (int l = 0; l <= lmax; l++)
+        p.highpass[l] = d->highpass ? d->highpass[l] : 1.0 - (l <= p.lmax[0] ? p.fl[0][l] : 0.0);
+}
+
+static void desc_from_plan(const Plan &p, int lmax, mlcr_ladder_desc *d, double *buf) {
+    std::memset(d, 0, sizeof(*d));
+    d->nlevels = p.H;
+    d->nrec_top = p.nrec_top;
+    d->lmax_dense = p.lmax_b;
+    d->gl_levels = p.gl ? 1 : 0;
+    for (int h = 0; h < p.H; h++) {
+        d->nside[h] = p.nside[h];
+        d->lmax[h] = p.lmax[h];
+        d->nrec[h] = p.nrec[h];
+        double *f = buf + (size_t)h * (lmax + 1);
+        std::copy(p.fl[h].begin(), p.fl[h].end(), f);
+        d->filter[h] = f;
+    }
+    d->highpass = nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// One multi-level cycle (Fig. code:mg) as a flat schedule of steps.
+// Levels: 0 = top spherical-harmonic level (diagonal smoother), 1..H pixel
+// levels, B = H + 1 the dense bottom (0 when there is no pixel level).
+// A level entered from above is smoothed, its residual restricted, and the
+// next coarser level entered n_rec times (from a zero correction) before the
+// correction is interpolated back and the level smoothed again.  The
+// schedule unrolls that into a step list with an explicit stack of the
+// levels that still owe visits to the level below them; the same list
+// drives the GPU cycle, the operation counts and the per-level profile.
+// ---------------------------------------------------------------------------
+enum StepKind { kStepSmooth = 0, kStepDown = 1, kStepUp = 2, kStepBottom = 3 };
+struct Step {
+    int kind, h;
+    bool xzero;     // kStepSmooth: the level's iterate is still zero (r = b)
+    bool enter;     // first step of a visit of level h
+};
+
+static void build_schedule(int B, const std::vector<int> &nrec, std::vector<Step> &out) {
+    out.clear();
+    struct Owed {
+        int h, left;
+    };
+    std::vector<Owed> stack;
+    auto enter = [&](int h, bool xzero) {
+        if (h == B) {
+            out.push_back({kStepBottom, h, true, true});
+            return;
+        }
+        out.push_back({kStepSmooth, h, xzero, true});
+        out.push_back({kStepDown, h, false, false});
+        stack.push_back({h, nrec[h]});
+    };
+    enter(0, true);
+    while (!stack.empty()) {
+        const int h = stack.back().h, left = stack.back().left;
+        if (left > 0) {
+            stack.back().left = left - 1;
+            enter(h + 1, left == nrec[h]);      // the coarse correction starts at zero
+        } else {
+            stack.pop_back();
+            out.push_back({kStepUp, h, false, false});
+            out.push_back({kStepSmooth, h, false, false});
+        }
+    }
+}
+
 struct CycleOps {
     virtual ~CycleOps() {}
     virtual int residual(int h, bool xzero) = 0;   // r_h = b_h - A_h x_h
@@ -156,19 +281,23 @@ struct CycleOps {
     virtual void visit(int h) = 0;
 };
 
-static int cr_cycle(CycleOps &o, int h, int B, const std::vector<int> &nrec, bool xzero) {
-    int rc;
-    o.visit(h);
-    if (h == B) return o.bottom(h);
-    if ((rc = o.residual(h, xzero))) return rc;      // pre-smoothing
-    if ((rc = o.smooth(h))) return rc;
-    if ((rc = o.residual(h, false))) return rc;      // restricted residual
-    if ((rc = o.restrict_down(h))) return rc;
-    for (int i = 0; i < nrec[h]; i++)                // recurse, c_H starts at 0
-        if ((rc = cr_cycle(o, h + 1, B, nrec, i == 0))) return rc;
-    if ((rc = o.prolong_up(h))) return rc;           // apply correction
-    if ((rc = o.residual(h, false))) return rc;      // post-smoothing
-    return o.smooth(h);
+static int run_schedule(CycleOps &o, const std::vector<Step> &sch) {
+    int rc = MLCR_OK;
+    for (const Step &st : sch) {
+        if (st.enter) o.visit(st.h);
+        switch (st.kind) {
+        case kStepSmooth:
+            if (!(rc = o.residual(st.h, st.xzero))) rc = o.smooth(st.h);
+            break;
+        case kStepDown:
+            if (!(rc = o.residual(st.h, false))) rc = o.restrict_down(st.h);
+            break;
+        case kStepUp: rc = o.prolong_up(st.h); break;
+        default: rc = o.bottom(st.h); break;
+        }
+        if (rc) return rc;
+    }
+    return MLCR_OK;
 }
 
 struct CountOps : CycleOps {
@@ -192,6 +321,62 @@ struct CountOps : CycleOps {
         return 0;
     }
     void visit(int h) override { c[4 * h]++; }
+};
+
+// Per-level profile: HIP event pairs around the steps of a cycle, added up
+// per (level, kind of work) when the solve reads its residual norms.
+struct Profile {
+    bool on = false;
+    std::vector<double> ms;             // [4 * levels]
+    std::vector<long long> calls;
+    struct Rec {
+        int slot;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    void reset(int levels) {
+        ms.assign(4 * levels, 0.0);
+        calls.assign(4 * levels, 0);
+    }
+    void drain() {
+        for (Rec &r : pending) {
+            float t = 0.f;
+            (void)hipEventSynchronize(r.b);
+            (void)hipEventElapsedTime(&t, r.a, r.b);
+            if (r.slot >= 0 && r.slot < (int)ms.size()) {
+                ms[r.slot] += t;
+                calls[r.slot]++;
+            }
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        pending.clear();
+    }
+};
+
+struct ProfScope {
+    Profile *p;
+    hipStream_t s;
+    int slot;
+    hipEvent_t a = nullptr;
+    ProfScope(Profile *p_, hipStream_t s_, int level, int kind) : p(p_), s(s_), slot(4 * level + kind) {
+        if (!p || !p->on) return;
+        if (hipEventCreate(&a) != hipSuccess) {
+            a = nullptr;
+            return;
+        }
+        (void)hipEventRecord(a, s);
+    }
+    ~ProfScope() {
+        if (!a) return;
+        hipEvent_t b = nullptr;
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return;
+        }
+        (void)hipEventRecord(b, s);
+        p->pending.push_back({slot, a, b});
+    }
 };
 
 }  // namespace mlcr
@@ -231,12 +416,21 @@ struct mlcr_solver {
     // per-RHS coefficients
     DevBuf pcg_p, pcg_zo, pcg_coef;
     std::vector<float> ridge_summary;
+    std::vector<Step> sched;            // one cycle's steps (build_schedule)
+    // the solver's own level operators A_h, index = level number (1..H
+    // pixel levels, H + 1 the dense bottom; 0 unused: the top is the
+    // operator's level 0), so solvers with different ladders can share op
+    std::vector<std::unique_ptr<mlcr_level>> slev;
+    Profile prof;
+    int prior_version = 0;              // op->prior_version the norms were made for
     int mode = 0;
     int graph = 0;          // replay cycles 2.. of a solve from a captured graph
     long long graph_replays = 0, graph_fallbacks = 0;
     ~mlcr_solver() {
         for (auto &L : lev)
             if (L->geom) mlcr_geom_destroy(L->geom);
+        for (auto &L : slev)
+            if (L) release_level(*L);
     }
 };
 
@@ -254,6 +448,14 @@ static int alloc(DevBuf &b, size_t bytes) {
     return MLCR_OK;
 }
 
+// A_h of the solver's level opl (0: the operator's top level)
+static int solver_apply(mlcr_solver *S, int opl, int nrhs, const double *x, double *y, int prec,
+                        hipStream_t s) {
+    if (opl == 0) return apply_level(S->op, 0, nrhs, x, y, prec, s);
+    if (opl >= (int)S->slev.size() || !S->slev[opl]) return fail(MLCR_EINVAL, "solver level not built");
+    return apply_level_on(S->op, *S->slev[opl], nrhs, x, y, prec, s);
+}
+
 struct GpuOps : CycleOps {
     mlcr_solver *S;
     int R, prec;
@@ -261,6 +463,11 @@ struct GpuOps : CycleOps {
     GpuOps(mlcr_solver *s_, int r, int p, hipStream_t st) : S(s_), R(r), prec(p), s(st) {}
     int H() const { return S->plan.H; }
     void visit(int) override {}
+    // profile slot kinds: A_h applications, level transforms, smoother, transfers
+    Profile *P() { return S->prof.on ? &S->prof : nullptr; }
+    int apply_h(int opl, int n, const double *x, double *y, int p) {
+        return solver_apply(S, opl, n, x, y, p, s);
+    }
 
     // buffers of level h
     double *X(int h) { return h == 0 ? S->x0.as<double>() : S->lev[h - 1]->x.as<double>(); }
@@ -275,20 +482,43 @@ struct GpuOps : CycleOps {
 
     int residual(int h, bool xzero) override {
         int rc;
-        if (xzero) return launch_residual(Bv(h), nullptr, Rv(h), Act(h), Lmax(h), R, s);
-        if ((rc = apply_level(S->op, Opl(h), R, X(h), Tv(h), prec, s))) return rc;
+        if (xzero) {
+            ProfScope ps(P(), s, h, 3);
+            return launch_residual(Bv(h), nullptr, Rv(h), Act(h), Lmax(h), R, s);
+        }
+        ProfScope ps(P(), s, h, 0);
+        if ((rc = apply_h(Opl(h), R, X(h), Tv(h), prec))) return rc;
         return launch_residual(Bv(h), Tv(h), Rv(h), Act(h), Lmax(h), R, s);
     }
     int smooth(int h) override {
-        if (h == 0)
+        if (h == 0) {
+            ProfScope ps(P(), s, 0, 2);
             return launch_axpy_l(X(0), Rv(0), S->top_hp.as<double>(), S->top_dinv.as<double>(),
                                  Lmax(0), R, s);
+        }
         PixLevel &L = *S->lev[h - 1];
         int rc;
         // x_h += Y_h^T M_h Y_h r_h  (eqs. pixel-correction-1..3)
-        if ((rc = sht_synth(L.geom, L.lmax, R, L.r.as<double>(), L.map.as<double>(), prec, s)))
-            return rc;
-        // c = M r: one multicolour block symmetric Gauss-Seidel sweep (Sec. 3.4 pattern)
+        {
+            ProfScope ps(P(), s, h, 1);
+            if ((rc = sht_synth(L.geom, L.lmax, R, L.r.as<double>(), L.map.as<double>(), prec, s)))
+                return rc;
+        }
+        if ((rc = sweep(L, h))) return rc;
+        {
+            ProfScope ps(P(), s, h, 1);
+            if ((rc = sht_adjoint(L.geom, L.lmax, R, L.cmap.as<double>(), L.t.as<double>(), prec, s)))
+                return rc;
+        }
+        ProfScope ps(P(), s, h, 3);
+        return launch_axpy_l(L.x.as<double>(), L.t.as<double>(), L.one.as<double>(), nullptr,
+                             L.lmax, R, s);
+    }
+    // c = M r on the level's map: one multicolour block symmetric Gauss-Seidel
+    // sweep over the tiles (Sec. 3.5 pattern)
+    int sweep(PixLevel &L, int h) {
+        int rc;
+        ProfScope ps(P(), s, h, 2);
         for (int pass = 0; pass < 2; pass++)
             for (int j = 0; j < L.n_sweep; j++) {
                 const int c = pass == 0 ? j : L.n_sweep - 1 - j;
@@ -301,12 +531,10 @@ struct GpuOps : CycleOps {
                                            L.off.as<float>(), L.minv.as<float>(), s)))
                     return rc;
             }
-        if ((rc = sht_adjoint(L.geom, L.lmax, R, L.cmap.as<double>(), L.t.as<double>(), prec, s)))
-            return rc;
-        return launch_axpy_l(L.x.as<double>(), L.t.as<double>(), L.one.as<double>(), nullptr,
-                             L.lmax, R, s);
+        return MLCR_OK;
     }
     int restrict_down(int h) override {
+        ProfScope ps(P(), s, h, 3);
         const double *w = h == 0 ? S->top_wdown.as<double>() : S->lev[h - 1]->wdown.as<double>();
         int rc;
         if (h + 1 == H() + 1) {          // into the dense bottom level
@@ -321,6 +549,7 @@ struct GpuOps : CycleOps {
         return launch_fill_zero(X(h + 1), (long long)R * nalm_l(Lmax(h + 1)), s);
     }
     int prolong_up(int h) override {
+        ProfScope ps(P(), s, h, 3);
         const double *w = h == 0 ? S->top_wdown.as<double>() : S->lev[h - 1]->wdown.as<double>();
         if (h + 1 == H() + 1)
             return launch_transfer(S->xb.as<double>(), S->lmax_b, X(h), Lmax(h), w, S->lmax_b,
@@ -328,6 +557,7 @@ struct GpuOps : CycleOps {
         return launch_transfer(X(h + 1), Lmax(h + 1), X(h), Lmax(h), w, Lmax(h + 1), true, R, s);
     }
     int bottom(int h) override {
+        ProfScope ps(P(), s, h, 2);
         if (S->direct)       // the top level itself is dense: x_0 = A^-1 b_0
             return launch_dense_apply(S->b_inv.as<double>(), S->na, S->b_idx.as<int>(),
                                       S->b0.as<double>(), S->x0.as<double>(), nalm_l(S->lmax_b),
@@ -449,7 +679,7 @@ static int setup_smoother(mlcr_solver *S, PixLevel &L, hipStream_t s) {
             if ((rc = sht_adjoint(L.geom, L.lmax, np, maps.as<double>(), U.as<double>(), MLCR_FP64,
                                   s)))
                 return rc;
-            if ((rc = apply_level(S->op, L.opl, np, U.as<double>(), V.as<double>(), MLCR_FP64, s)))
+            if ((rc = solver_apply(S, L.opl, np, U.as<double>(), V.as<double>(), MLCR_FP64, s)))
                 return rc;
             if ((rc = sht_synth(L.geom, L.lmax, np, V.as<double>(), maps.as<double>(), MLCR_FP64,
                                 s)))
@@ -540,7 +770,7 @@ static int setup_bottom(mlcr_solver *S, hipStream_t s) {
     for (int j0 = 0; j0 < na; j0 += P) {
         const int np = std::min(P, na - j0);
         if ((rc = launch_unit_vectors(X.as<double>(), nb, S->b_idx.as<int>(), j0, np, s))) return rc;
-        if ((rc = apply_level(op, S->opl_b, np, X.as<double>(), cols.as<double>() + (size_t)j0 * nb,
+        if ((rc = solver_apply(S, S->opl_b, np, X.as<double>(), cols.as<double>() + (size_t)j0 * nb,
                               MLCR_FP64, s)))
             return rc;
     }
@@ -561,18 +791,21 @@ static int setup_bottom(mlcr_solver *S, hipStream_t s) {
     return MLCR_OK;
 }
 
-// A coarse level evaluates Y^T N^-1 Y on a Gauss-Legendre grid (Sec. 3.5)
+// A coarse level evaluates Y^T N^-1 Y on a Gauss-Legendre grid (Sec. 3.4)
 // when that grid -- 2 lmax_h + 1 rings of the smallest power of two >=
 // 4 lmax_h + 1 pixels -- is smaller than the observation grid; otherwise on
 // the observation grid itself.  Both give the same operator (exactly, up to
 // rounding); only the cost differs.
-static int set_level_best(mlcr_op *op, int h, int lmax_h, const double *fl) {
+static int set_level_best(mlcr_solver *S, int h, int lmax_h, const double *fl, bool gl) {
+    mlcr_op *op = S->op;
     long long nphi = 4;
     while (nphi < 4LL * lmax_h + 1) nphi <<= 1;
     const long long gl_pix = (2LL * lmax_h + 1) * nphi;
-    if (2 * lmax_h <= op->g->lmax && nphi <= 16384 && gl_pix < op->g->npix)
-        return mlcr_op_set_level_gl(op, h, lmax_h, fl);
-    return mlcr_op_set_level(op, h, lmax_h, fl);
+    const bool use_gl = gl && 2 * lmax_h <= op->g->lmax && nphi <= 16384 && gl_pix < op->g->npix;
+    if ((int)S->slev.size() <= h) S->slev.resize(h + 1);
+    S->slev[h].reset(new (std::nothrow) mlcr_level());
+    if (!S->slev[h]) return fail(MLCR_ENOMEM, "host allocation failed");
+    return define_level(op, *S->slev[h], lmax_h, fl, use_gl);
 }
 
 static int solver_build(mlcr_solver *S, const Plan &p, hipStream_t s) {
@@ -582,6 +815,14 @@ static int solver_build(mlcr_solver *S, const Plan &p, hipStream_t s) {
     int rc;
     S->plan = p;
     S->direct = (p.H == 0);
+    {
+        std::vector<int> nr(p.H + 1);
+        nr[0] = p.nrec_top;
+        for (int h = 0; h < p.H; h++) nr[h + 1] = p.nrec[h];
+        build_schedule(S->direct ? 0 : p.H + 1, nr, S->sched);
+        S->prof.reset(p.H + 2);
+        S->prior_version = op->prior_version;
+    }
     std::vector<double> act0(lmax + 1);
     for (int l = 0; l <= lmax; l++) act0[l] = op->cl[l] > 0 ? 1.0 : 0.0;
     if ((rc = up(S->top_act, act0.data(), act0.size() * sizeof(double)))) return rc;
@@ -619,7 +860,7 @@ static int solver_build(mlcr_solver *S, const Plan &p, hipStream_t s) {
         L->lmax = p.lmax[h];
         L->opl = h + 1;
         if ((rc = mlcr_geom_create(L->nside, L->lmax, &L->geom))) return rc;
-        if ((rc = set_level_best(op, L->opl, L->lmax, p.fl[h].data()))) return rc;
+        if ((rc = set_level_best(S, L->opl, L->lmax, p.fl[h].data(), p.gl))) return rc;
         std::vector<double> act(L->lmax + 1), one(L->lmax + 1);
         for (int l = 0; l <= L->lmax; l++) {
             act[l] = op->cl[l] > 0 ? 1.0 : 0.0;
@@ -661,7 +902,7 @@ static int solver_build(mlcr_solver *S, const Plan &p, hipStream_t s) {
     S->opl_b = p.H + 1;
     {
         std::vector<double> fb(p.fl[p.H - 1].begin(), p.fl[p.H - 1].begin() + p.lmax_b + 1);
-        if ((rc = set_level_best(op, S->opl_b, S->lmax_b, fb.data()))) return rc;
+        if ((rc = set_level_best(S, S->opl_b, S->lmax_b, fb.data(), p.gl))) return rc;
     }
     const size_t bbytes = (size_t)R * nalm_l(S->lmax_b) * sizeof(double);
     if ((rc = alloc(S->xb, bbytes)) || (rc = alloc(S->bb, bbytes))) return rc;
@@ -725,25 +966,47 @@ int mlcr_cycle_counts(int nlevels, const int *nrec, int nrec_top, int ncycles, l
     nr[0] = nrec_top;
     for (int h = 0; h < nlevels; h++) nr[h + 1] = nrec[h];
     CountOps ops(B + 1, B);
+    std::vector<Step> sch;
+    build_schedule(B, nr, sch);
     for (int c = 0; c < ncycles; c++) {
-        cr_cycle(ops, 0, B, nr, true);
+        run_schedule(ops, sch);
         ops.c[1]++;     // float64 residual b - A x of CR-Solve at the top level
     }
     for (size_t i = 0; i < ops.c.size(); i++) counts[i] = ops.c[i];
     return MLCR_OK;
 }
 
-int mlcr_solver_create(mlcr_op *op, int max_nrhs, mlcr_solver **out) {
+int mlcr_ladder_default(int nside, int lmax, mlcr_ladder_desc *out, double *filters) {
+    if (nside < 1 || lmax < 0 || !out || !filters) return fail(MLCR_EINVAL, "bad argument");
+    Plan p;
+    default_plan(nside, lmax, p);
+    desc_from_plan(p, lmax, out, filters);
+    return MLCR_OK;
+}
+
+int mlcr_ladder_check(int nside, int lmax, const mlcr_ladder_desc *ladder) {
+    if (nside < 1 || lmax < 0) return fail(MLCR_EINVAL, "bad grid or band limit");
+    return check_ladder(nside, lmax, ladder);
+}
+
+int mlcr_solver_create(mlcr_op *op, const mlcr_ladder_desc *ladder, int max_nrhs,
+                       mlcr_solver **out) {
     if (!out) return fail(MLCR_EINVAL, "out is NULL");
     *out = nullptr;
     if (!op) return fail(MLCR_EINVAL, "operator is NULL");
     if (max_nrhs < 1) return fail(MLCR_EINVAL, "max_nrhs must be >= 1");
+    Plan p;
+    if (ladder) {
+        int rc = check_ladder(op->g->nside, op->lmax, ladder);
+        if (rc) return rc;
+        plan_from_desc(op->lmax, ladder, p);
+    } else {
+        default_plan(op->g->nside, op->lmax, p);
+    }
     mlcr_solver *S = new (std::nothrow) mlcr_solver();
     if (!S) return fail(MLCR_ENOMEM, "host allocation failed");
     S->op = op;
     S->max_nrhs = max_nrhs;
-    Plan p;
-    default_plan(op->g->nside, op->lmax, p);
     int rc = solver_build(S, p, nullptr);
     if (rc) {
         (void)hipDeviceSynchronize();
@@ -774,6 +1037,25 @@ int mlcr_solver_info(const mlcr_solver *S, int *nlevels, int *lmax_bottom, int *
     return MLCR_OK;
 }
 
+int mlcr_solver_set_profile(mlcr_solver *S, int on) {
+    if (!S) return fail(MLCR_EINVAL, "solver is NULL");
+    S->prof.drain();
+    S->prof.on = on != 0;
+    S->prof.reset(S->plan.H + 2);
+    return MLCR_OK;
+}
+
+int mlcr_solver_profile(const mlcr_solver *S, int nlevels_max, double *ms, long long *calls) {
+    if (!S || nlevels_max < 0) return fail(MLCR_EINVAL, "bad argument");
+    const_cast<mlcr_solver *>(S)->prof.drain();
+    const int L = std::min(nlevels_max, S->plan.H + 2);
+    for (int i = 0; i < 4 * L; i++) {
+        if (ms) ms[i] = i < (int)S->prof.ms.size() ? S->prof.ms[i] : 0.0;
+        if (calls) calls[i] = i < (int)S->prof.calls.size() ? S->prof.calls[i] : 0;
+    }
+    return S->plan.H + 2;
+}
+
 int mlcr_solver_top_dinv(const mlcr_solver *S, double *out, void *stream) {
     if (!S || !out) return fail(MLCR_EINVAL, "NULL argument");
     if (S->direct) return fail(MLCR_EINVAL, "solver has no top-level smoother (dense solve)");
@@ -796,23 +1078,20 @@ struct SolveRun {
     hipStream_t s;
     std::vector<double> hn, rho0, rho;
     std::vector<int> done, cyc;
-    std::vector<int> nr;
-    int B = 0, it = 0;
+    int it = 0;
     bool all = false;
 
     SolveRun(mlcr_solver *S_, int n, const double *b_, double *x_, double rt, int p, hipStream_t st)
         : S(S_), nrhs(n), prec(p), b(b_), x(x_), rtol(rt), s(st), hn(2 * n), rho0(n), rho(n, 0.0),
-          done(n, 0), cyc(n, 0) {
-        nr.resize(S->plan.H + 1);
-        nr[0] = S->plan.nrec_top;
-        for (int h = 0; h < S->plan.H; h++) nr[h + 1] = S->plan.nrec[h];
-        B = S->direct ? 0 : S->plan.H + 1;
-    }
+          done(n, 0), cyc(n, 0) {}
     // r = b - A x in float64 and its S^-1 norms, copied to hn (not yet waited on)
     int enqueue_residual() {
         mlcr_op *op = S->op;
         int rc;
-        if ((rc = apply_level(op, 0, nrhs, x, S->to.as<double>(), MLCR_FP64, s))) return rc;
+        {
+            ProfScope ps(S->prof.on ? &S->prof : nullptr, s, 0, 0);
+            if ((rc = apply_level(op, 0, nrhs, x, S->to.as<double>(), MLCR_FP64, s))) return rc;
+        }
         if ((rc = launch_residual(b, S->to.as<double>(), S->ro.as<double>(), S->top_act.as<double>(),
                                   op->lmax, nrhs, s)))
             return rc;
@@ -861,7 +1140,7 @@ struct SolveRun {
                                       hipMemcpyDeviceToDevice, s));
         if ((rc = launch_fill_zero(S->x0.as<double>(), (long long)nrhs * na, s))) return rc;
         GpuOps ops(S, nrhs, prec, s);
-        if ((rc = cr_cycle(ops, 0, B, nr, true))) return rc;
+        if ((rc = run_schedule(ops, S->sched))) return rc;
         if ((rc = launch_axpy_l(x, S->x0.as<double>(), S->top_act.as<double>(), nullptr, lmax, nrhs,
                                 s)))
             return rc;
@@ -869,7 +1148,7 @@ struct SolveRun {
     }
     int enqueue_cycle() {
         int rc = MLCR_OK;
-        if (!S->graph || graph_off || it == 0) {
+        if (!S->graph || graph_off || it == 0 || S->prof.on) {
             rc = enqueue_cycle_body();
         } else if (exec) {
             MLCR_HIP_CHECK(hipGraphLaunch(exec, s));
@@ -908,6 +1187,7 @@ struct SolveRun {
     int finish_cycle() {
         int rc;
         if ((rc = read_norms(rho))) return rc;
+        S->prof.drain();
         all = true;
         for (int r = 0; r < nrhs; r++) {
             if (!done[r]) cyc[r] = it;
@@ -945,6 +1225,22 @@ static int check_solve_args(mlcr_solver *S, int nrhs, const double *b, double *x
     if (!(rtol >= 0.0)) return fail(MLCR_EINVAL, "rtol must be >= 0");
     if (prec != MLCR_FP64 && prec != MLCR_FP32 && prec != MLCR_BF16X3)
         return fail(MLCR_EINVAL, "unknown precision");
+    // after mlcr_op_set_prior: the stopping norm and the certificate follow
+    // the operator's current spectrum (the hierarchy keeps its own)
+    if (S->prior_version != S->op->prior_version) {
+        const int lmax = S->op->lmax;
+        std::vector<double> sinv(lmax + 1), ch(lmax + 1);
+        for (int l = 0; l <= lmax; l++) {
+            sinv[l] = S->op->cl[l] > 0 ? 1.0 / S->op->cl[l] : 0.0;
+            ch[l] = S->op->cl[l];
+        }
+        int rc;
+        if ((rc = up(S->sinv, sinv.data(), sinv.size() * sizeof(double)))) return rc;
+        if ((rc = up(S->chalf, ch.data(), ch.size() * sizeof(double)))) return rc;
+        for (auto &L : S->slev)
+            if (L && (rc = refresh_level(S->op, *L))) return rc;
+        S->prior_version = S->op->prior_version;
+    }
     return MLCR_OK;
 }
 
@@ -1086,7 +1382,7 @@ int pcg_solve(mlcr_solver *S, int nrhs, const double *b, double *x, double rtol,
                                       hipMemcpyDeviceToDevice, s));
         if (int r2 = launch_fill_zero(z, (long long)nrhs * na, s)) return r2;
         GpuOps ops(S, nrhs, prec, s);
-        return cr_cycle(ops, 0, run.B, run.nr, true);
+        return run_schedule(ops, S->sched);
     };
     if (!run.all) {
         if ((rc = precond())) return rc;
@@ -1125,6 +1421,35 @@ int pcg_solve(mlcr_solver *S, int nrhs, const double *b, double *x, double rtol,
     }
     if ((rc = run.finish(info))) return rc;
     if (!run.all) return fail(MLCR_ENOCONV, "rtol not reached within max_iter");
+    return MLCR_OK;
+}
+
+int mlcr_prior_band_grad(mlcr_op *op, int nrhs, const double *lam, const double *x,
+                         const int *band, int nbands, const double *q, double *out, void *stream) {
+    if (!op || !lam || !x || !band || !out) return fail(MLCR_EINVAL, "NULL argument");
+    if (nrhs < 1) return fail(MLCR_EINVAL, "nrhs must be >= 1");
+    if (nbands < 1) return fail(MLCR_EINVAL, "nbands must be >= 1");
+    const int lmax = op->lmax;
+    for (int l = 0; l <= lmax; l++)
+        if (band[l] < -1 || band[l] >= nbands) return fail(MLCR_EINVAL, "band index out of range");
+    if (q)
+        for (int k = 0; k < nbands; k++)
+            if (!(q[k] > 0.0) || !std::isfinite(q[k])) return fail(MLCR_EINVAL, "q must be finite and > 0");
+    hipStream_t s = (hipStream_t)stream;
+    if (op->ell_ws.reserve((size_t)(lmax + 1) * sizeof(double)))
+        return fail(MLCR_ENOMEM, "band-gradient workspace allocation failed");
+    int rc;
+    if ((rc = launch_ell_dots(lam, x, lmax, nrhs, op->ell_ws.as<double>(), s))) return rc;
+    std::vector<double> per(lmax + 1);
+    MLCR_HIP_CHECK(hipMemcpyAsync(per.data(), op->ell_ws.ptr, per.size() * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+    MLCR_HIP_CHECK(hipStreamSynchronize(s));
+    // dL/dq_beta = -lam^T (dA/dq_beta) x, dA/dq_beta = -S^-1 / q_beta on the band
+    for (int k = 0; k < nbands; k++) out[k] = 0.0;
+    for (int l = 0; l <= lmax; l++)
+        if (band[l] >= 0 && op->cl[l] > 0.0) out[band[l]] += per[l] / op->cl[l];
+    if (q)
+        for (int k = 0; k < nbands; k++) out[k] /= q[k];
     return MLCR_OK;
 }
 

@@ -7,7 +7,7 @@
 
 namespace mlcr {
 
-// pixel-level tiles: k x k nested pixels, k = 8 on every level (Sec. 3.4)
+// pixel-level tiles: k x k nested pixels, k = 8 on every level (Sec. 3.5)
 constexpr int kTileK = 8;
 constexpr int kTileK2 = kTileK * kTileK;
 
@@ -50,6 +50,9 @@ int launch_fill_zero(double *p, long long n, hipStream_t s);
 // per-RHS dot products (c, d may be null), out[2 r], out[2 r + 1]
 int launch_dots(const double *a, const double *b, const double *c, const double *d, int lmax,
                 int nrhs, double *partial, double *out, hipStream_t s);
+// out[l] = sum over RHS and m of a_lm b_lm (cosine and sine entries of l)
+int launch_ell_dots(const double *a, const double *b, int lmax, int nrhs, double *out,
+                    hipStream_t s);
 // out = al[r] u + be[r] v, n values per RHS (al, be: device arrays per RHS)
 int launch_lincomb(const double *u, const double *v, double *out, const double *al,
                    const double *be, long long n, int nrhs, hipStream_t s);
@@ -63,9 +66,17 @@ int launch_cr_combine(const double *v, const double *w1, const double *bh, const
 int launch_legendre_adjoint_sq(const LegendreArgs &a, const double2 *G, double *P,
                                int *nchunks_out);
 
-// api.cpp: operator apply without the max_nrhs limit (workspaces grow)
+// api.cpp: operator apply without the max_nrhs limit (workspaces grow), on
+// one of the operator's levels or on a level held elsewhere (a solver's)
 int apply_level(mlcr_op *op, int level, int nrhs, const double *x, double *y, int prec,
                 hipStream_t s);
+int apply_level_on(mlcr_op *op, const mlcr_level &L, int nrhs, const double *x, double *y,
+                   int prec, hipStream_t s);
+// level tables (band limit, filter; gl: Gauss-Legendre evaluation of
+// Y^T N^-1 Y) into L; refresh after a prior change; release everything
+int define_level(mlcr_op *op, mlcr_level &L, int lmax_h, const double *fl, bool gl);
+int refresh_level(mlcr_op *op, mlcr_level &L);
+void release_level(mlcr_level &L);
 
 // HEALPix NESTED -> RING index (Gorski et al. 2005)
 long long nest2ring(int nside, long long ipnest);

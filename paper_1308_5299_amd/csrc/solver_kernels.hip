@@ -181,6 +181,33 @@ __global__ __launch_bounds__(256) void k_dots(const double *__restrict__ a,
     }
 }
 
+// per multipole l: out[l] = sum_r sum_{m <= l} a_lm b_lm over the cosine and
+// sine entries of l (one workgroup per l, fixed summation order)
+__global__ __launch_bounds__(256) void k_ell_dots(const double *__restrict__ a,
+                                                  const double *__restrict__ b, int lmax, int nrhs,
+                                                  double *__restrict__ out) {
+    const int l = blockIdx.x;
+    const long long nalm = (long long)(lmax + 1) * (lmax + 1);
+    const int cnt = 2 * l + 1;                 // entry 0: m = 0; 2 m - 1, 2 m: cos, sin of m
+    double acc = 0.0;
+    for (int rr = 0; rr < nrhs; rr++)
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+            const int m = (i + 1) / 2;
+            long long idx = cos_base(m, lmax) + (l - m);
+            if (m > 0 && (i & 1) == 0) idx += lmax - m + 1;      // sine block
+            const long long o = (long long)rr * nalm + idx;
+            acc = fma(a[o], b[o], acc);
+        }
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[l] = red[0];
+}
+
 // out = al[r] u + be[r] v per RHS r, flat (out may alias u or v)
 __global__ __launch_bounds__(256) void k_lincomb(const double *u, const double *v, double *out,
                                                  const double *__restrict__ al,
@@ -283,7 +310,7 @@ __global__ __launch_bounds__(256) void k_probe_maps(double *__restrict__ maps, l
     }
 }
 
-// Read the probe responses of the tiles u of one colour (Sec. 3.4 block pattern):
+// Read the probe responses of the tiles u of one colour (Sec. 3.5 block pattern):
 // at u itself into its diagonal block diag[u][i][c] (row-major, float64) and at
 // each neighbour t into the coupling block of the pair (t, u), off[slot][c][i]
 // (column c = probe position in u, row i = pixel of t; the slot is the entry of
@@ -369,7 +396,7 @@ __device__ bool lds_cholesky(double *a, int kk, double *flag) {
 }
 
 // Per tile: symmetrize the probed block, factor with the smallest ridge
-// alpha (bisection in log alpha, then 1.5 alpha, Sec. 3.4) that makes the
+// alpha (bisection in log alpha, then 1.5 alpha, Sec. 3.5) that makes the
 // Cholesky succeed, and store the inverse in float32 (column-major; it is
 // symmetric).  ridge_out[t] records the alpha used (relative to max |a_ii|).
 __global__ __launch_bounds__(256) void k_tile_factor(const double *__restrict__ blocks, int kk,
@@ -443,7 +470,7 @@ __global__ __launch_bounds__(256) void k_tile_factor(const double *__restrict__ 
 }
 
 // One colour of the multicolour block symmetric Gauss-Seidel sweep on the
-// block-sparse pixel operator (Sec. 3.4 pattern: a tile and its neighbours).
+// block-sparse pixel operator (Sec. 3.5 pattern: a tile and its neighbours).
 // Tiles of one colour are never neighbours, so each workgroup updates one
 // tile with no ordering among them.  Lane i of each wave owns pixel i of the
 // tile; blocks are float32 (the paper's smoother precision), maps float64.
@@ -882,6 +909,13 @@ int launch_dots(const double *a, const double *b, const double *c, const double 
     hipLaunchKernelGGL(k_dots, dim3(lmax + 1, nrhs), dim3(256), 0, s, a, b, c, d, lmax, partial);
     MLCR_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_wnorms_final, dim3(nrhs), dim3(256), 0, s, partial, lmax + 1, out);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_ell_dots(const double *a, const double *b, int lmax, int nrhs, double *out,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_ell_dots, dim3(lmax + 1), dim3(256), 0, s, a, b, lmax, nrhs, out);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }

@@ -1,4 +1,4 @@
-// Tile graph of the pixel-level error smoothers (Sec. 3.4).
+// Tile graph of the pixel-level error smoothers (Sec. 3.5).
 //
 // Each pixel level is cut into k x k tiles (nested blocks of k^2 pixels).  The
 // smoother keeps the couplings of Y_h A_h Y_h^T inside a tile and between

@@ -1,4 +1,4 @@
-"""Gauss-Legendre grids on the GPU (Sec. 3.5).
+"""Gauss-Legendre grids on the GPU (Sec. 3.4).
 
 * transforms on a Gauss-Legendre geometry against the oracle's transforms on
   its own Gauss-Legendre rings (power-of-two and Bluestein ring lengths);
@@ -14,7 +14,7 @@ import workloads
 from oracle import geometry as ogeo
 from oracle import operator as oop
 from oracle import sht as osht
-from tests.gpu_util import dev, host, rel2
+from tests.gpu_util import dev, host, parity
 
 pytestmark = pytest.mark.gpu
 
@@ -40,14 +40,14 @@ def test_gl_transforms_parity(mlcr, lmax, nrings, nphi, nrhs):
     y = rng.standard_normal((nrhs, nrings * nphi))
     f = host(mlcr.sht_synth(g, dev(x)))
     a = host(mlcr.sht_adjoint(g, dev(y)))
-    assert rel2(f, osht.synth_geom(x, lmax, og)) <= TOL
-    assert rel2(a, osht.adjoint_geom(y, lmax, og)) <= TOL
+    assert parity(f, osht.synth_geom(x, lmax, og)) <= TOL
+    assert parity(a, osht.adjoint_geom(y, lmax, og)) <= TOL
 
 
 @pytest.mark.parametrize("name,lmax_h", [("c1", 12), ("c2", 192)])
 def test_gl_level_operator_parity(mlcr, name, lmax_h):
     """A_h with Y^T N^-1 Y on the Gauss-Legendre grid equals the oracle's A_h
-    on the observation grid (Sec. 3.5, eqs. Ni-rewrite and Xi)."""
+    on the observation grid (Sec. 3.4, eqs. Ni-rewrite and Xi)."""
     print(f"case gl level {name} lmax_h={lmax_h}", flush=True)
     cfg = workloads.get_config(name)
     d = workloads.workload_inputs(cfg)
@@ -59,11 +59,11 @@ def test_gl_level_operator_parity(mlcr, name, lmax_h):
     x = np.random.default_rng(31).standard_normal((2, osht.nalm(lmax_h)))
     y = host(mlcr.apply_A(op, dev(x), level=1))
     yr = oop.apply_A(x, d["cl"], d["bl"], d["ninv"], cfg.nside, lmax_h=lmax_h, fl=f)
-    assert rel2(y, yr) <= TOL, rel2(y, yr)
+    assert parity(y, yr) <= TOL, parity(y, yr)
     # the same level on the observation grid agrees too (returns the level to it)
     op.set_level(1, lmax_h, f)
     y2 = host(mlcr.apply_A(op, dev(x), level=1))
-    assert rel2(y2, yr) <= TOL
+    assert parity(y2, yr) <= TOL
 
 
 def test_gl_errors(mlcr):

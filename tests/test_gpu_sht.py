@@ -1,7 +1,8 @@
 """GPU parity of the float64 transforms and operator against the oracle.
 
-Bar (FP64 path): ||y - y_oracle||_2 / ||y_oracle||_2 <= 1e-12, computed on
-the same seeded inputs.  Cases span several Legendre tiles and FFT length
+Bar (FP64 path): ||y - y_oracle||_2 / ||y_oracle||_2 <= 1e-12 and
+max |y - y_oracle| / max |y_oracle| <= 1e-12, computed on the same seeded
+inputs.  Cases span several Legendre tiles and FFT length
 classes with ragged tails: power-of-two and Bluestein rings, lmax above the
 grid's Nyquist (m folded modulo ring length), tiny grids and lmax = 0.
 """
@@ -12,7 +13,7 @@ import torch
 import workloads
 from oracle import operator as oop
 from oracle import sht as osht
-from tests.gpu_util import dev, host, rel2
+from tests.gpu_util import dev, host, maxrel, parity, rel2
 
 pytestmark = pytest.mark.gpu
 
@@ -40,8 +41,8 @@ def test_synth_adjoint_parity(mlcr, nside, lmax):
     a = host(mlcr.sht_adjoint(g, dev(y)))
     fr = osht.synth(x, lmax, nside)
     ar = osht.adjoint(y, lmax, nside)
-    assert rel2(f, fr) <= TOL, rel2(f, fr)
-    assert rel2(a, ar) <= TOL, rel2(a, ar)
+    assert parity(f, fr) <= TOL, parity(f, fr)
+    assert parity(a, ar) <= TOL, parity(a, ar)
 
 
 def test_batch_equals_singles(mlcr):
@@ -50,14 +51,15 @@ def test_batch_equals_singles(mlcr):
     x = np.random.default_rng(3).standard_normal((5, osht.nalm(lmax)))
     fb = host(mlcr.sht_synth(g, dev(x)))
     # 5 RHS run on the float64 matrix cores, a single RHS on the vector
-    # kernels: same sums, different rounding order
+    # kernels: same sums, different rounding order (a few units in the last
+    # place of the largest value per element, ~1e-14 in the 2-norm)
     for r in range(5):
         fs = host(mlcr.sht_synth(g, dev(x[r:r + 1])))
-        assert rel2(fb[r:r + 1], fs) <= 1e-14
+        assert rel2(fb[r:r + 1], fs) <= 1e-14 and maxrel(fb[r:r + 1], fs) <= 1e-13
     yb = host(mlcr.sht_adjoint(g, dev(fb)))
     for r in range(5):
         ys = host(mlcr.sht_adjoint(g, dev(fb[r:r + 1])))
-        assert rel2(yb[r:r + 1], ys) <= 1e-14
+        assert rel2(yb[r:r + 1], ys) <= 1e-14 and maxrel(yb[r:r + 1], ys) <= 1e-13
 
 
 def test_smaller_lmax_than_geometry(mlcr):
@@ -65,9 +67,9 @@ def test_smaller_lmax_than_geometry(mlcr):
     g = mlcr.Geometry(nside, lmax_g)
     x = np.random.default_rng(4).standard_normal((1, osht.nalm(lmax)))
     f = host(mlcr.sht_synth(g, dev(x), lmax=lmax))
-    assert rel2(f, osht.synth(x, lmax, nside)) <= TOL
+    assert parity(f, osht.synth(x, lmax, nside)) <= TOL
     a = host(mlcr.sht_adjoint(g, dev(f), lmax=lmax))
-    assert rel2(a, osht.adjoint(f, lmax, nside)) <= TOL
+    assert parity(a, osht.adjoint(f, lmax, nside)) <= TOL
 
 
 @pytest.mark.parametrize("name", ["c1", "c2"])
@@ -79,7 +81,7 @@ def test_apply_A_parity(mlcr, name):
     x = np.stack([workloads.prior_sample(cfg, r) for r in range(2)])
     y = host(mlcr.apply_A(op, dev(x)))
     yr = oop.apply_A(x, d["cl"], d["bl"], d["ninv"], cfg.nside)
-    assert rel2(y, yr) <= TOL, rel2(y, yr)
+    assert parity(y, yr) <= TOL, parity(y, yr)
     L = oop.mode_ell(cfg.lmax)
     assert np.all(y[:, d["cl"][L] == 0] == 0.0)
 
@@ -96,8 +98,8 @@ def test_fp64_mfma_parity(mlcr, nside, lmax, nrhs):
     y = rng.standard_normal((nrhs, 12 * nside * nside))
     f = host(mlcr.sht_synth(g, dev(x)))
     a = host(mlcr.sht_adjoint(g, dev(y)))
-    assert rel2(f, osht.synth(x, lmax, nside)) <= TOL, rel2(f, osht.synth(x, lmax, nside))
-    assert rel2(a, osht.adjoint(y, lmax, nside)) <= TOL, rel2(a, osht.adjoint(y, lmax, nside))
+    assert parity(f, osht.synth(x, lmax, nside)) <= TOL, parity(f, osht.synth(x, lmax, nside))
+    assert parity(a, osht.adjoint(y, lmax, nside)) <= TOL, parity(a, osht.adjoint(y, lmax, nside))
 
 
 def test_fp64_mfma_apply_parity(mlcr):
@@ -108,7 +110,7 @@ def test_fp64_mfma_apply_parity(mlcr):
     x = np.stack([workloads.prior_sample(cfg, r) for r in range(8)])
     y = host(mlcr.apply_A(op, dev(x)))
     yr = oop.apply_A(x, d["cl"], d["bl"], d["ninv"], cfg.nside)
-    assert rel2(y, yr) <= TOL, rel2(y, yr)
+    assert parity(y, yr) <= TOL, parity(y, yr)
 
 
 def test_level_operator_parity(mlcr):
@@ -122,7 +124,7 @@ def test_level_operator_parity(mlcr):
     x = np.random.default_rng(6).standard_normal((1, osht.nalm(lmax_h)))
     y = host(mlcr.apply_A(op, dev(x), level=1))
     yr = oop.apply_A(x, d["cl"], d["bl"], d["ninv"], cfg.nside, lmax_h=lmax_h, fl=f)
-    assert rel2(y, yr) <= TOL
+    assert parity(y, yr) <= TOL
 
 
 def test_errors(mlcr):
@@ -152,8 +154,8 @@ def test_fp32_synth_adjoint_parity(mlcr, nside, lmax, nrhs):
     y = rng.standard_normal((nrhs, 12 * nside * nside))
     f = host(mlcr.sht_synth(g, dev(x), prec=mlcr.FP32))
     a = host(mlcr.sht_adjoint(g, dev(y), prec=mlcr.FP32))
-    assert rel2(f, osht.synth(x, lmax, nside)) <= TOL32, rel2(f, osht.synth(x, lmax, nside))
-    assert rel2(a, osht.adjoint(y, lmax, nside)) <= TOL32, rel2(a, osht.adjoint(y, lmax, nside))
+    assert parity(f, osht.synth(x, lmax, nside)) <= TOL32, parity(f, osht.synth(x, lmax, nside))
+    assert parity(a, osht.adjoint(y, lmax, nside)) <= TOL32, parity(a, osht.adjoint(y, lmax, nside))
 
 
 def test_fp32_apply_parity(mlcr):
@@ -164,7 +166,7 @@ def test_fp32_apply_parity(mlcr):
     x = workloads.prior_sample(cfg, 0)[None, :]
     y = host(mlcr.apply_A(op, dev(x), prec=mlcr.FP32))
     yr = oop.apply_A(x, d["cl"], d["bl"], d["ninv"], cfg.nside)
-    assert rel2(y, yr) <= TOL32, rel2(y, yr)
+    assert parity(y, yr) <= TOL32, parity(y, yr)
 
 
 # Split-bfloat16 contraction: each float32 operand is carried as hi + lo
@@ -184,7 +186,7 @@ def test_bf16x3_synth_adjoint_parity(mlcr, nside, lmax, nrhs):
     y = rng.standard_normal((nrhs, 12 * nside * nside))
     f = host(mlcr.sht_synth(g, dev(x), prec=mlcr.BF16X3))
     a = host(mlcr.sht_adjoint(g, dev(y), prec=mlcr.BF16X3))
-    ef, ea = rel2(f, osht.synth(x, lmax, nside)), rel2(a, osht.adjoint(y, lmax, nside))
+    ef, ea = parity(f, osht.synth(x, lmax, nside)), parity(a, osht.adjoint(y, lmax, nside))
     print(f"bf16x3 synth rel {ef:.2e} adjoint rel {ea:.2e}", flush=True)
     assert ef <= TOLB3 and ea <= TOLB3, (ef, ea)
 
@@ -197,8 +199,8 @@ def test_bf16x3_apply_parity(mlcr):
     x = workloads.prior_sample(cfg, 0)[None, :]
     y = host(mlcr.apply_A(op, dev(x), prec=mlcr.BF16X3))
     yr = oop.apply_A(x, d["cl"], d["bl"], d["ninv"], cfg.nside)
-    print(f"bf16x3 apply rel {rel2(y, yr):.2e}", flush=True)
-    assert rel2(y, yr) <= TOLB3, rel2(y, yr)
+    print(f"bf16x3 apply rel {parity(y, yr):.2e}", flush=True)
+    assert parity(y, yr) <= TOLB3, parity(y, yr)
 
 
 @pytest.mark.parametrize("prec_name,nrhs,tol", [("fp64", 8, TOL), ("fp32", 3, TOL32),
@@ -216,5 +218,5 @@ def test_matrix_core_smaller_lmax_than_geometry(mlcr, prec_name, nrhs, tol):
     y = rng.standard_normal((nrhs, 12 * nside * nside))
     f = host(mlcr.sht_synth(g, dev(x), lmax=lmax, prec=prec))
     a = host(mlcr.sht_adjoint(g, dev(y), lmax=lmax, prec=prec))
-    ef, ea = rel2(f, osht.synth(x, lmax, nside)), rel2(a, osht.adjoint(y, lmax, nside))
+    ef, ea = parity(f, osht.synth(x, lmax, nside)), parity(a, osht.adjoint(y, lmax, nside))
     assert ef <= tol and ea <= tol, (ef, ea)

@@ -142,3 +142,54 @@ def test_s_inv_ratio_and_sigma_prior():
     assert abs(solve.sigma_prior(d["cl"]) - 100.0) < 1e-10       # C_0 = C_1 = 0 here
     b = np.random.default_rng(2).standard_normal(cfg.nalm)
     assert solve.s_inv_ratio(b, b, d["cl"]) == pytest.approx(1.0)
+
+
+def test_s_inv_ratio_hand_computed():
+    """sqrt(r^T S^-1 r / b^T S^-1 b) (Fig. code:mg's stopping quantity) on a
+    hand-computed case: lmax 3, C = (0, 0, 4, 9), so l < 2 is excluded and the
+    two active l carry different weights 1/4 and 1/9.  r has 2 at (l=2, m=0)
+    and 3 at (l=3, m=0); b has 1 at both; both have large values on excluded
+    modes, which must not count.  r^T S^-1 r = 4/4 + 9/9 = 2 and
+    b^T S^-1 b = 1/4 + 1/9 = 13/36, so the ratio is sqrt(72/13).  Weighting
+    by C instead of 1/C would give sqrt(97/13)."""
+    cl = np.array([0.0, 0.0, 4.0, 9.0])
+    n = sht.nalm(3)
+    r = np.zeros(n); b = np.zeros(n)
+    r[2], r[3] = 2.0, 3.0
+    b[2], b[3] = 1.0, 1.0
+    r[0], r[1], b[0], b[1] = 100.0, -50.0, 30.0, 7.0          # l = 0, 1: excluded
+    base = sht.block_base(1, 3)                               # m = 1 cosine block, l = 1 first
+    r[base], b[base] = 40.0, 11.0                             # (l=1, m=1): excluded
+    assert solve.s_inv_ratio(r, b, cl) == pytest.approx(math.sqrt(72.0 / 13.0), rel=1e-15)
+    # a sine entry at (l=3, m=2) enters with weight 1/9
+    s32 = sht.block_base(2, 3) + 2 + 1
+    r2 = r.copy(); r2[s32] = 3.0
+    assert solve.s_inv_ratio(r2, b, cl) == pytest.approx(math.sqrt(3.0 * 36.0 / 13.0), rel=1e-15)
+
+
+def test_certificate_is_attained_at_zero_noise():
+    """The certificate max_p |Y(x - x*)|_p <= sigma_prior ||S^{1/2} (b - A x)||
+    is tight: with N^-1 = 0 (A = S^-1) and a residual r proportional to the
+    row of Y at one pixel p, the error e = S r has e_p = sigma_prior^2 (Unsold,
+    sum_m Y_lm(p)^2 = (2l+1)/4 pi) while ||S^{1/2} r|| = sigma_prior, so the bound
+    equals the true max pixel error.  A sigma_prior or an S^{1/2} weighting
+    that is too large, or a residual taken against the wrong operator, breaks
+    the equality."""
+    cfg, d = _c1()
+    cl, bl = d["cl"], d["bl"]
+    L = op.mode_ell(cfg.lmax)
+    act = cl[L] > 0
+    rng = np.random.default_rng(5)
+    xstar = np.where(act, np.sqrt(np.where(act, cl[L], 0.0)) * rng.standard_normal(cfg.nalm), 0.0)
+    ninv0 = np.zeros(cfg.npix)
+    b = op.apply_A(xstar, cl, bl, ninv0, cfg.nside)
+    for p in (0, 1234, cfg.npix - 1):
+        delta = np.zeros(cfg.npix); delta[p] = 1.0
+        r = np.where(act, sht.adjoint(delta, cfg.lmax, cfg.nside), 0.0)     # row p of Y
+        x = xstar - np.where(act, cl[L], 0.0) * r                           # b - A x = r
+        bound, sn = solve.certificate(x, b, cl, bl, ninv0, cfg.nside)
+        assert sn == pytest.approx(solve.sigma_prior(cl), rel=1e-12)
+        true = solve.max_pixel_error(x, xstar, cfg.lmax, cfg.nside)
+        assert true == pytest.approx(bound, rel=1e-12), (p, true, bound)
+        e_p = sht.synth(xstar - x, cfg.lmax, cfg.nside)[p]
+        assert e_p == pytest.approx(solve.sigma_prior(cl) ** 2, rel=1e-12)

@@ -141,7 +141,7 @@ def test_gauss_legendre_rings(n):
 
 def test_gauss_legendre_quadrature_is_exact():
     """Y^T W Y = I on a Gauss-Legendre grid with lmax + 1 rings and
-    nphi > 2 lmax (the exact quadrature the coarse levels rely on, Sec. 3.5)."""
+    nphi > 2 lmax (the exact quadrature the coarse levels rely on, Sec. 3.4)."""
     lmax = 24
     g, W = geometry.gauss_legendre_rings(lmax + 1, 52)
     x = np.random.default_rng(21).standard_normal(sht.nalm(lmax))
@@ -151,7 +151,7 @@ def test_gauss_legendre_quadrature_is_exact():
 
 
 def test_downgraded_inverse_noise_identity():
-    """Sec. 3.5: for modes l, l' <= lh, Y_obs^T N^-1 Y_obs equals
+    """Sec. 3.4: for modes l, l' <= lh, Y_obs^T N^-1 Y_obs equals
     Y_GL^T W Ntilde Y_GL with Ntilde the synthesis of xi = Y_obs^T N^-1
     truncated at 2 lh on 2 lh + 1 Gauss-Legendre rings of > 4 lh pixels."""
     nside, lh = 8, 9

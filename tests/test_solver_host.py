@@ -133,3 +133,97 @@ def test_ladder_plan_rules():
     assert p["nrec"] == [2, 2, 2, 2, 2, 1] and p["nrec_top"] == 1 and p["lmax_bottom"] == 40
     small = m.ladder_plan(16, 32)
     assert small["nlevels"] == 0 and small["lmax_bottom"] == 32     # direct dense solve
+
+
+def test_ladder_default_matches_plan():
+    """mlcr_ladder_default reproduces mlcr_ladder_plan and its filters follow
+    the Sec. 3.3 forms: the q_l filter of eq. fourth-power-beam with
+    q = 0.1 at 2570/3000 of the band limit on the first level of N_side >= 512,
+    and a Gaussian of FWHM two level pixels on levels of N_side <= 256."""
+    import paper_1308_5299_amd as m
+    for nside, lmax in [(16, 32), (256, 512), (2048, 4096)]:
+        lad = m.Ladder.default(nside, lmax)
+        plan = m.ladder_plan(nside, lmax)
+        assert len(lad.nside) == plan["nlevels"]
+        assert lad.nside == plan["nside"] and lad.lmax == plan["lmax"] and lad.nrec == plan["nrec"]
+        assert lad.nrec_top == plan["nrec_top"] and lad.lmax_dense == plan["lmax_bottom"]
+        lad.check(nside, lmax)
+    lad = m.Ladder.default(2048, 4096)
+    ls = round(lad.lmax[0] * 2570 / 3000)
+    assert lad.filters[0][ls] == pytest.approx(0.1, rel=1e-12)
+    h = lad.nside.index(256)
+    pix = math.sqrt(4 * math.pi / (12 * 256 ** 2))
+    sig = 2 * pix / math.sqrt(8 * math.log(2))
+    ell = np.arange(lad.lmax[h] + 1)
+    np.testing.assert_allclose(lad.filters[h], np.exp(-0.5 * ell * (ell + 1) * sig * sig), rtol=1e-13)
+
+
+def _gauss(lmax, fwhm_px, nside):
+    pix = math.sqrt(4 * math.pi / (12 * nside ** 2))
+    sig = fwhm_px * pix / math.sqrt(8 * math.log(2))
+    ell = np.arange(lmax + 1)
+    return np.exp(-0.5 * ell * (ell + 1) * sig * sig)
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("nlevels", 9, b"nlevels"),
+    ("nside", [100, 64], b"multiple of 8"),
+    ("lmax", [600, 300], b"lmax must be in"),
+    ("lmax", [300, 384], b"lmax must be in"),
+    ("nrec", [2, 0], b"nrec must be in"),
+    ("nrec_top", 4, b"nrec_top"),
+    ("lmax_dense", 80, b"lmax_dense"),
+    ("gl_levels", 2, b"gl_levels"),
+    ("filter0", "zero", b"filter must be > 0"),
+    ("filter0", "nan", b"finite"),
+])
+def test_ladder_check_rejects(field, value, msg):
+    """A custom ladder is validated on the host before any device work."""
+    import ctypes
+    import paper_1308_5299_amd as m
+    from paper_1308_5299_amd import _lib
+    f0, f1 = _gauss(384, 2.0, 128), _gauss(300, 2.0, 64)
+    lad = m.Ladder([128, 64], [384, 300], [2, 1], [f0, f1], nrec_top=1, lmax_dense=40)
+    lad.check(256, 512)
+    if field == "filter0":
+        bad = f0.copy()
+        bad[10] = 0.0 if value == "zero" else np.nan
+        lad.filters[0] = bad
+    elif field in ("nside", "lmax", "nrec"):
+        setattr(lad, field, value)
+    else:
+        setattr(lad, field, value)
+    d = lad.desc()
+    if field in ("nlevels", "gl_levels"):
+        setattr(d, field, value)
+    lib = _lib.load()
+    assert lib.mlcr_ladder_check(256, 512, ctypes.byref(d)) == -1
+    assert msg in lib.mlcr_last_error(), lib.mlcr_last_error()
+
+
+def test_ladder_without_pixel_levels():
+    import ctypes
+    import paper_1308_5299_amd as m
+    from paper_1308_5299_amd import _lib
+    lib = _lib.load()
+    lad = m.Ladder([], [], [], [], nrec_top=1, lmax_dense=32)
+    lad.check(16, 32)
+    d = m.Ladder([], [], [], [], nrec_top=1, lmax_dense=40).desc()
+    assert lib.mlcr_ladder_check(16, 32, ctypes.byref(d)) == -1       # must cover lmax exactly
+    d = m.Ladder([], [], [], [], nrec_top=1, lmax_dense=100).desc()
+    assert lib.mlcr_ladder_check(64, 100, ctypes.byref(d)) == -1      # too large to be dense
+
+
+def test_schedule_visits_for_custom_counts():
+    """The cycle schedule visits level h prod_{k < h} n_rec^k times (the
+    recursion of Fig. code:mg), for counts the paper's table does not use."""
+    import paper_1308_5299_amd as m
+    nrec, top = [3, 1, 2], 2
+    c = m.cycle_counts(nrec, nrec_top=top, ncycles=1)
+    want = [1, top, top * 3, top * 3 * 1, top * 3 * 1 * 2]
+    np.testing.assert_array_equal(c[:, 0], want)
+    # pixel levels smooth twice per visit, two level SHTs per smoothing;
+    # the bottom is solved once per visit
+    np.testing.assert_array_equal(c[1:4, 3], 2 * np.array(want[1:4]))
+    np.testing.assert_array_equal(c[1:4, 2], 4 * np.array(want[1:4]))
+    assert c[4, 3] == want[4]
