@@ -140,6 +140,19 @@ int mlcr_geom_get_tuning(const mlcr_geom *g, int prec, int *adjoint_waves, int *
 int sht_synth(mlcr_geom *g, int lmax, int nrhs, const double *dev_alm, double *dev_map,
               int prec, void *stream);
 
+/* sht_synth with prec = MLCR_FP64 for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): it calls no hipMalloc, hipFree or allocating routine.
+ * Its workspaces (packed input and ring-major Fourier coefficients,
+ * 8 nrhs (lmax+1)(lmax+2) + 16 nrhs nrings (lmax+1) bytes, rounded) live in
+ * one fixed 64 MiB device array per GPU, held until the process ends;
+ * requests that need more return MLCR_EINVAL (use sht_synth).  Every call on
+ * a GPU shares that array: calls that overlap on one GPU race.  Runs the
+ * float64 vector Legendre kernels for any nrhs; results equal sht_synth's
+ * float64 path up to rounding order.  Arguments and layouts as sht_synth. */
+int sht_synth_noalloc(mlcr_geom *g, int lmax, int nrhs, const double *dev_alm, double *dev_map,
+                      void *stream);
+
 /* Adjoint synthesis alm = Y^T map (Sec. 2.1: the transpose of Y, with no
  * quadrature weights; used in place of analysis throughout the method).
  * Same layouts as sht_synth. */

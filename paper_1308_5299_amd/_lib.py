@@ -28,6 +28,7 @@ SIGNATURES = {
                                ctypes.POINTER(c_ll), ctypes.POINTER(c_int)]),
     "sht_synth": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_int, c_void_p]),
     "sht_adjoint": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_int, c_void_p]),
+    "sht_synth_noalloc": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p]),
     "mlcr_op_create": (c_int, [c_void_p, c_int, c_dbl_p, c_dbl_p, c_void_p, c_int,
                                ctypes.POINTER(c_void_p)]),
     "mlcr_op_destroy": (None, [c_void_p]),

@@ -53,13 +53,16 @@ void DevBuf::release() {
     bytes = 0;
 }
 
+// (kernels already raised are remembered in a fixed table: no heap use, so
+// the entry points that must not allocate can launch through here)
 int ensure_dynamic_lds(const void *func, size_t bytes) {
     if (bytes <= 64 * 1024) return MLCR_OK;
-    static std::vector<std::pair<const void *, size_t>> done;
-    for (auto &d : done)
-        if (d.first == func && d.second >= bytes) return MLCR_OK;
+    static std::pair<const void *, size_t> done[64];
+    static int ndone = 0;
+    for (int i = 0; i < ndone; i++)
+        if (done[i].first == func && done[i].second >= bytes) return MLCR_OK;
     MLCR_HIP_CHECK(hipFuncSetAttribute(func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-    done.push_back({func, bytes});
+    if (ndone < 64) done[ndone++] = {func, bytes};
     return MLCR_OK;
 }
 
