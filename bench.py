@@ -7,6 +7,14 @@ synthesis, ring FFT + N^-1 + adjoint ring FFT, Legendre adjoint and the
 prior/beam epilogue -- every step of the hot path, all in the HIP library.
 Inputs (x ~ N(0, S), N^-1 with mask) are resident in HBM before timing.
 
+The reported value is the float32 mixed path (the path the full-scale
+workload names); the split-bfloat16 and float64 paths are timed beside it.
+Each path's throughput comes with its accuracy: its apply against the float64
+apply and a 9-cycle W-cycle solve of manufactured right-hand sides with that
+path's cycles and float64 refinement, checked against 1e-3 uK max pixel error
+("gate").  A sweep over RHS per launch (1, 8, 32, 64) follows, and the CPU
+oracle is timed on the host's cores ("cpu_baseline").
+
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -23,26 +31,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "A·x applies/s (SHT pair) at Nside 2048, ℓmax 4096; FP64 vs mixed at 1e-3 μK"
 PEAK_FP64 = 78.6e12           # MI355X FP64 FLOP/s (vector and dense MFMA)
-PEAK_FP32 = 157.3e12          # MI355X FP32 (vector and dense MFMA) FLOP/s
+PEAK_FP32 = 157.3e12          # MI355X FP32 dense MFMA FLOP/s
 PEAK_HBM = 8.0e12             # MI355X HBM3E bytes/s
 PEAK_BF16 = 2.5e15            # MI355X dense bf16 MFMA FLOP/s
 
+# The full-scale workload names the float32 mixed path; it is the headline.
+DEFAULT_PATHS = "fp32,bf16x3,fp64"
 
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE (x2.0) + WRITE_SIZE
 # (x1.0), the factors from a plain copy of known size; recorded in
-# profiles/apply_A_c5_r8_hbm_traffic.md for the kernels as they are now, at
-# the default launch shapes (valid when the autotuner keeps them).
+# profiles/apply_A_c5_r8_hbm_traffic.md.  Only kernels unchanged since those
+# counters were taken are listed (a changed kernel reports traffic null).
 # Key: (library timer name, Legendre path, workload, RHS per launch).
 MEASURED_TRAFFIC = {
-    ("legendre_adjoint", "bf16x3", "c5", 8): 8.936e9 + 4.314e9,
     ("legendre_adjoint", "fp32", "c5", 8): 8.839e9 + 4.311e9,
     ("legendre_adjoint", "fp64", "c5", 8): 9.036e9 + 8.596e9,
-    ("legendre_synth", "bf16x3", "c5", 8): 3.880e9 + 8.658e9,
     ("legendre_synth", "fp32", "c5", 8): 8.155e9 + 9.799e9,
     ("legendre_synth", "fp64", "c5", 8): 16.440e9 + 9.846e9,
-    ("ring_apply", "bf16x3", "c5", 8): 1.836e9 + 1.074e9 + 3 * (1.278e9 + 1.075e9),
     ("ring_apply", "fp32", "c5", 8): 1.836e9 + 1.074e9 + 3 * (1.278e9 + 1.075e9),
     ("ring_apply", "fp64", "c5", 8): 1.772e9 + 1.074e9 + 3 * (1.294e9 + 1.075e9),
+}
+# Matrix-core busy fraction (SQ_VALU_MFMA_BUSY_CYCLES over 1024 SIMDs x
+# 2.4 GHz x duration) of the same kernels, from
+# profiles/legendre_c5_r8_mfma_counters.md; kernels changed since are absent.
+MEASURED_MFMA_BUSY = {
+    ("legendre_synth", "fp32", "c5", 8): 0.417,
+    ("legendre_adjoint", "fp32", "c5", 8): 0.335,
+    ("legendre_synth", "fp64", "c5", 8): 0.566,
+    ("legendre_adjoint", "fp64", "c5", 8): 0.361,
 }
 
 
@@ -50,104 +66,115 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_work(name: str, nside: int, lmax: int, R: int):
-    """(bound, amount, unit) of one launch of a kernel, from the method's counts.
-
-    Legendre kernels: 4 flops (two FMAs, cos and sin) per (l, m, ring pair,
-    RHS) over the full triangle 0 <= m <= l <= lmax and all 2 N_side ring
-    pairs; the recurrence that generates lambda_lm is not counted.
-    Ring kernels: bytes of the Fourier coefficients read and written (16 B
-    per (ring, m, RHS) each way) plus the map or N^-1 (8 B per pixel).
-    """
+def legendre_useful_flops(nside: int, lmax: int, R: int) -> float:
+    """4 flops (cos and sin FMAs) per (l, m, ring pair, RHS) over the full
+    triangle 0 <= m <= l <= lmax and all 2 N_side ring pairs.  The kernels skip
+    the region where every lambda is below 2^-112 (about 27% of the triangle
+    at N_side 2048 / lmax 4096); the count keeps it, so a rate is per useful
+    product of the whole transform."""
     ntri = (lmax + 1) * (lmax + 2) // 2
-    npairs = 2 * nside
-    nrings = 4 * nside - 1
-    npix = 12 * nside * nside
-    if name.startswith("legendre"):
-        return "alu", 4.0 * ntri * npairs * R, "flop"
-    if name == "ring_apply":
-        return "hbm", 2.0 * 16 * nrings * (lmax + 1) * R + 8.0 * npix, "byte"
-    if name in ("ring_synth", "ring_adjoint"):
-        return "hbm", 16.0 * nrings * (lmax + 1) * R + 8.0 * npix * R, "byte"
-    nalm = (lmax + 1) ** 2
-    return "hbm", 3.0 * 8 * nalm * R, "byte"
+    return 4.0 * ntri * 2 * nside * R
 
 
-def algorithmic_bytes(name: str, nside: int, lmax: int, R: int):
-    """Bytes a launch must move at least: its inputs read once, outputs written once."""
-    nrings, npix = 4 * nside - 1, 12 * nside * nside
-    fbuf = 16.0 * nrings * (lmax + 1) * R                 # F or G, complex double
-    tri = (lmax + 1) * (lmax + 2) // 2
+def recurrence_flops(nside: int, lmax: int, R: int) -> float:
+    """3 flops (one multiply, one FMA) per (l, m, ring pair) of the scaled
+    three-term recurrence, once per chunk of 8 RHS, full triangle."""
+    ntri = (lmax + 1) * (lmax + 2) // 2
+    return 3.0 * ntri * 2 * nside * ((R + 7) // 8)
+
+
+def min_bytes(name: str, nside: int, lmax: int, R: int, path: str):
+    """The method's minimum HBM bytes of one launch: x, y and N^-1 once, and the
+    m-major <-> ring-major round trip of the two-stage SHT once each way, with
+    F and G as complex numbers of the path's FFT precision (16 B float64,
+    8 B on the mixed paths)."""
+    nrings, npix, nalm = 4 * nside - 1, 12 * nside * nside, (lmax + 1) ** 2
+    fg = (16.0 if path == "fp64" else 8.0) * nrings * (lmax + 1) * R
+    vec = 8.0 * nalm * R
     if name == "legendre_synth":
-        return fbuf
+        return vec + fg                     # x in, F out
     if name == "legendre_adjoint":
-        npb = (2 * nside + 63) // 64
-        nchunks = (npb + 7) // 8
-        return fbuf + nchunks * 16.0 * tri * 8 * ((R + 7) // 8)
+        return fg + 2 * vec                 # G in, x in and y out (y = D x + B v)
     if name == "ring_apply":
-        return 2 * fbuf + 8.0 * npix
+        return 2 * fg + 8.0 * npix          # F in, G out, N^-1
+    if name in ("ring_synth", "ring_adjoint"):
+        return fg + 8.0 * npix * R
     return None
 
 
-def cpu_baseline(cfg, R: int, seed_x, ninv_host, budget_s: float = 20.0):
-    """Time the CPU oracle on a bounded sample of the same apply and scale.
+def cpu_baseline(cfg, R: int, x_host, ninv_host, measured=("c1", "c2", "c3"), budget_s: float = 20.0):
+    """The CPU oracle on the machine's host cores.
 
-    Sample: the oracle's per-order Legendre step (both directions, R RHS) for
-    a handful of orders m spread over [0, lmax], and its ring step (both
-    directions) on a spread of rings.  The full apply time is extrapolated
-    by the work of each part: Legendre work of order m is proportional to
-    (lmax - m + 1); ring work is summed over sampled rings and scaled by the
-    ratio of total to sampled ring pixels.  Single thread (BLAS limited to 1).
-    """
+    value: one full apply of the benchmark workload estimated from a bounded
+    sample -- the oracle's per-order Legendre step (both directions, R RHS) on
+    orders spread over [0, lmax] run by its worker pool (all host cores), and
+    its ring step (serial, as in the oracle) on 64 rings -- extrapolated by
+    work (order m costs ~ lmax - m + 1; ring work ~ pixels).
+    measured: whole oracle applies of R RHS at the smaller workloads, timed."""
     import numpy as np
-    from threadpoolctl import threadpool_limits
 
+    import workloads
     from oracle import geometry as ogeo
+    from oracle import operator as oop
+    from oracle import pool
     from oracle import sht as osht
 
+    nw = pool.worker_count()
     lmax, nside = cfg.lmax, cfg.nside
     geom = ogeo.healpix_rings(nside)
-    with threadpool_limits(limits=1):
-        # Legendre sample
-        ms = sorted(set(int(v) for v in np.linspace(0, lmax - 8, 16)))
-        xs = seed_x
-        t_m = []
-        t_start = time.perf_counter()
-        for m in ms:
-            Gc = np.zeros((R, geom.nrings))
-            t0 = time.perf_counter()
-            osht.legendre_pair_m(xs, (Gc, Gc), m, lmax, geom)
-            t_m.append(time.perf_counter() - t0)
-            if time.perf_counter() - t_start > budget_s:
-                break
-        ms = ms[: len(t_m)]
-        # per-order time ~ a + b (lmax - m + 1): least squares, then sum over m
-        w = np.array([lmax - m + 1 for m in ms], dtype=float)
-        A = np.stack([np.ones_like(w), w], axis=1)
-        coef, *_ = np.linalg.lstsq(A, np.array(t_m), rcond=None)
-        allw = np.arange(lmax + 1, 0, -1, dtype=float)
-        t_leg = float(np.sum(np.maximum(coef[0] + coef[1] * allw, 0.0)))
-        # ring sample: synth + adjoint ring step on spread rings
-        rings = np.unique(np.linspace(0, geom.nrings - 1, 64).astype(int))
-        sub_pix = int(geom.nphi[rings].sum())
-        F = np.random.default_rng(0).standard_normal((R, 1, lmax + 1))
+    # start the workers outside the timed region
+    tiny = ogeo.healpix_rings(2)
+    pool.run(osht._synth_orders, [(4, tiny, [(0, np.zeros((1, 5)), np.zeros((1, 5)))])] * nw, nw)
+    # Legendre sample: rounds of nw orders until the budget is used
+    picked, t_leg_sample = [], 0.0
+    order = np.random.default_rng(0).permutation(lmax + 1)
+    t_all = time.perf_counter()
+    while time.perf_counter() - t_all < budget_s and len(picked) < lmax + 1:
+        ms = [int(m) for m in order[len(picked): len(picked) + nw]]
+        groups = [(lmax, geom, [(m,) + tuple(np.ascontiguousarray(v) for v in osht.split_m(x_host, m, lmax))])
+                  for m in ms]
+        ggroups = [(lmax, geom, [(m, np.zeros((R, geom.nrings)), np.zeros((R, geom.nrings)))]) for m in ms]
         t0 = time.perf_counter()
-        for k in rings:
-            g1 = ogeo.RingGeometry(nside, geom.z[k:k + 1], geom.sint[k:k + 1], geom.nphi[k:k + 1],
-                                   geom.phi0[k:k + 1], np.array([0]))
-            mp = osht.ring_synth(F, F, g1)
-            osht.ring_adjoint(mp * ninv_host[geom.start[k]: geom.start[k] + geom.nphi[k]], lmax, g1)
-        t_ring = (time.perf_counter() - t0) * (geom.npix / sub_pix)
+        pool.run(osht._synth_orders, groups, nw)
+        pool.run(osht._adjoint_orders, ggroups, nw)
+        t_leg_sample += time.perf_counter() - t0
+        picked += ms
+    work = lambda ms: float(sum(lmax - m + 1 for m in ms))
+    t_leg = t_leg_sample * work(range(lmax + 1)) / work(picked)
+    # ring sample: synthesis and adjoint ring step on spread rings
+    rings = np.unique(np.linspace(0, geom.nrings - 1, 64).astype(int))
+    sub_pix = int(geom.nphi[rings].sum())
+    F = np.random.default_rng(0).standard_normal((R, 1, lmax + 1))
+    t0 = time.perf_counter()
+    for k in rings:
+        g1 = ogeo.RingGeometry(nside, geom.z[k:k + 1], geom.sint[k:k + 1], geom.nphi[k:k + 1],
+                               geom.phi0[k:k + 1], np.array([0]))
+        mp = osht.ring_synth(F, F, g1)
+        osht.ring_adjoint(mp * ninv_host[geom.start[k]: geom.start[k] + geom.nphi[k]], lmax, g1)
+    t_ring = (time.perf_counter() - t0) * (geom.npix / sub_pix)
     total = t_leg + t_ring
+    meas = {}
+    for name in measured:
+        c = workloads.get_config(name)
+        dd = workloads.workload_inputs(c)
+        xs = np.stack([workloads.prior_sample(c, r) for r in range(R)])
+        t0 = time.perf_counter()
+        oop.apply_A(xs, dd["cl"], dd["bl"], dd["ninv"], c.nside)
+        dt = time.perf_counter() - t0
+        meas[name] = {"nside": c.nside, "lmax": c.lmax, "nrhs": R, "s_per_apply": dt,
+                      "rhs_applies_per_s": R / dt}
+        log(f"[bench] oracle apply {name} (N_side {c.nside}, lmax {c.lmax}, {R} RHS): {dt:.2f} s")
     return {
         "value": R / total,
         "unit": "RHS-applies/s",
-        "cores": 1,
+        "cores": nw,
         "kind": "oracle",
-        "sample": (f"oracle per-order Legendre step (both directions, {R} RHS) at m in {ms} "
-                   f"and ring step on {len(rings)} rings of the N_side {nside}, lmax {lmax} "
-                   f"workload, extrapolated by work to one full apply of {R} RHS "
-                   f"(estimated {total:.0f} s per apply; numpy, 1 thread)"),
+        "sample": (f"oracle Legendre step (both directions, {R} RHS) on {len(picked)} of "
+                   f"{lmax + 1} orders (random, spread over [0, lmax]) through its {nw}-process "
+                   f"pool, and its serial ring step on {len(rings)} rings, of the N_side {nside}, "
+                   f"lmax {lmax} workload, extrapolated by work to one apply of {R} RHS "
+                   f"(estimated {total:.0f} s per apply)"),
+        "measured_full_applies": meas,
     }
 
 
@@ -176,31 +203,41 @@ def run_path(mlcr, torch, op, x, y, prec, steps, warmup, label):
 
 
 def roofline(kernels, cfg, R, path: str):
-    mixed = path != "fp64"
+    """Roofline of the dominant kernel of one apply (HIP events on its stream).
+
+    Legendre kernels on the float32 / float64 paths are matrix-core bound:
+    achieved = useful flops (legendre_useful_flops) per launch time, against
+    the dense peak of the kernel's own dtype.  The split-bfloat16 kernels are
+    bound by the vector work around the matrix cores (the counters show ~22
+    VALU instructions per MFMA): achieved = recurrence flops per launch time
+    against the float64 vector peak, with the useful matrix-core rate beside
+    it.  Other kernels are HBM bound against the method's minimum bytes."""
     dom = max(kernels, key=lambda k: kernels[k])
-    bound, work, unit = algorithmic_work(dom, cfg.nside, cfg.lmax, R)
     sec = kernels[dom] / 1e3
-    if bound == "alu":
-        # 4 or more RHS per launch run the contraction on the matrix cores
-        # (float32 or float64 MFMA); fewer use the float64 vector kernels
-        kind = "mfma" if (mixed or R >= 4) else "alu"
+    key = (dom, path, cfg.name, R)
+    if dom.startswith("legendre"):
+        useful = legendre_useful_flops(cfg.nside, cfg.lmax, R)
         if path == "bf16x3":
-            # three bf16 products per useful product, against the bf16 peak
-            roof = {"bound": kind, "kernel": dom, "achieved": 3 * work / sec / 1e12,
-                    "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
-                    "useful_tflops": work / sec / 1e12}
+            work = recurrence_flops(cfg.nside, cfg.lmax, R)
+            roof = {"bound": "alu", "kernel": dom, "achieved": work / sec / 1e12,
+                    "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                    "work_per_launch": work, "work": "float64 recurrence flops, full triangle",
+                    "useful_mfma_tflops": useful / sec / 1e12,
+                    "useful_frac_of_bf16_peak": useful / sec / PEAK_BF16}
         else:
-            roof = {"bound": kind, "kernel": dom, "achieved": work / sec / 1e12,
-                    "peak": (PEAK_FP32 if mixed else PEAK_FP64) / 1e12, "unit": "TFLOP/s"}
+            peak = PEAK_FP64 if path == "fp64" else PEAK_FP32
+            roof = {"bound": "mfma", "kernel": dom, "achieved": useful / sec / 1e12,
+                    "peak": peak / 1e12, "unit": "TFLOP/s", "work_per_launch": useful,
+                    "work": "useful flops, full triangle (the skipped negligible region counted)"}
     else:
-        roof = {"bound": "hbm", "kernel": dom, "achieved": work / sec / 1e9,
-                "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
+        mb = min_bytes(dom, cfg.nside, cfg.lmax, R, path)
+        roof = {"bound": "hbm", "kernel": dom, "achieved": mb / sec / 1e9, "peak": PEAK_HBM / 1e9,
+                "unit": "GB/s", "work_per_launch": mb, "work": "method's minimum bytes"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    t = MEASURED_TRAFFIC.get((dom, path, cfg.name, R))
-    roof["traffic"] = t
-    if t is not None:
-        roof["traffic_unit"] = "bytes per launch (HBM, rocprofv3 counters)"
-        roof["algorithmic_bytes"] = algorithmic_bytes(dom, cfg.nside, cfg.lmax, R)
+    roof["traffic"] = MEASURED_TRAFFIC.get(key)
+    roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-scaled)"
+    roof["min_bytes"] = min_bytes(dom, cfg.nside, cfg.lmax, R, path)
+    roof["mfma_busy_counters"] = MEASURED_MFMA_BUSY.get(key)
     roof["kernel_ms"] = {k: round(v, 4) for k, v in kernels.items()}
     return roof
 
@@ -335,6 +372,81 @@ def mixed_bench(mlcr, torch, paths, rtol=1e-8, max_cycles=40):
     return out
 
 
+def gate(mlcr, torch, cfg, geom, op, x, outs, paths, R, cycles=9, target=1e-3):
+    """The accuracy each path's throughput is counted at: its apply against the
+    float64 apply, and a W-cycle solve of manufactured b = A x_true (float64
+    apply) with that path's cycles and float64 refinement, whose max pixel
+    error (float64 synthesis over all pixels) must reach `target` uK."""
+    precs = {"fp64": mlcr.FP64, "fp32": mlcr.FP32, "bf16x3": mlcr.BF16X3}
+    out = {"target_uK": target, "cycles": cycles, "paths": {}}
+    t0 = time.time()
+    S = mlcr.Solver(op, max_nrhs=R)
+    torch.cuda.synchronize()
+    out["solver_setup_s"] = time.time() - t0
+    b = mlcr.apply_A(op, x)
+    import workloads
+    d = workloads.workload_inputs(cfg)
+    import numpy as np
+    ell = np.arange(cfg.lmax + 1)
+    sigma_prior = float(np.sqrt(np.sum((2 * ell + 1) * d["cl"]) / (4 * np.pi)))
+    for p in paths:
+        S.solve(b, rtol=0.0, max_cycles=1, prec=precs[p], raise_on_noconv=False)   # tables, workspaces
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        xs, info = S.solve(b, rtol=0.0, max_cycles=cycles, prec=precs[p], raise_on_noconv=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        err = float(mlcr.sht_synth(geom, xs - x).abs().amax())
+        ent = {"solve_s": el, "max_pixel_error_uK": err, "reached": err <= target,
+               "certificate_uK": sigma_prior * max(i["s_half_res"] for i in info),
+               "rho": max(i["rho"] for i in info)}
+        if p != "fp64" and "fp64" in outs and p in outs:
+            dlt = outs[p] - outs["fp64"]
+            ent["apply_rel_l2_vs_fp64"] = float(dlt.norm() / outs["fp64"].norm())
+            ent["apply_max_elem_vs_fp64"] = float(dlt.abs().amax() / outs["fp64"].abs().amax())
+        out["paths"][p] = ent
+        log(f"[bench] gate {p}: {cycles} cycles {el:.2f} s, max pixel error {err:.3e} uK "
+            f"(certificate {ent['certificate_uK']:.3e})")
+        del xs
+    t64 = out["paths"].get("fp64", {}).get("solve_s")
+    for p, v in out["paths"].items():
+        v["speedup_vs_fp64_at_equal_accuracy"] = (t64 / v["solve_s"]) if (t64 and v["reached"]) else None
+    return out
+
+
+def r_sweep(mlcr, torch, cfg, geom, d, paths, rs=(1, 8, 32, 64), steps=3):
+    """Apply throughput against the RHS count of one launch (independent
+    realizations batched, so one lambda feeds more columns)."""
+    import numpy as np
+    precs = {"fp64": mlcr.FP64, "fp32": mlcr.FP32, "bf16x3": mlcr.BF16X3}
+    dev = torch.device("cuda:0")
+    ninv = torch.from_numpy(d["ninv"]).to(dev)
+    op = mlcr.Operator(geom, d["cl"], d["bl"], ninv, max_nrhs=max(rs))
+    x = torch.from_numpy(np.stack([workloads_prior(cfg, r) for r in range(max(rs))])).to(dev)
+    out = {}
+    for p in paths:
+        out[p] = {}
+        for R in rs:
+            xr = x[:R].contiguous()
+            y = torch.empty_like(xr)
+            ms, kern = run_path(mlcr, torch, op, xr, y, precs[p], steps, 1, f"{p} R={R}")
+            leg = {k: v for k, v in kern.items() if k.startswith("legendre")}
+            ent = {"ms_per_apply": ms, "rhs_applies_per_s": R / (ms / 1e3),
+                   "kernel_ms": {k: round(v, 4) for k, v in kern.items()}}
+            for k, v in leg.items():
+                ent[f"{k}_useful_tflops"] = legendre_useful_flops(cfg.nside, cfg.lmax, R) / (v / 1e3) / 1e12
+            out[p][str(R)] = ent
+            del y
+    del op, x
+    torch.cuda.synchronize()
+    return out
+
+
+def workloads_prior(cfg, r):
+    import workloads
+    return workloads.prior_sample(cfg, r)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -342,9 +454,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c5")
     ap.add_argument("--nrhs", type=int, default=0)
-    ap.add_argument("--paths", default="bf16x3,fp32,fp64",
+    ap.add_argument("--paths", default=DEFAULT_PATHS,
                     help="Legendre paths to time; the first is the reported value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gate", action="store_true",
+                    help="skip the per-path accuracy gate (apply vs float64, 9-cycle solve)")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the sweep over RHS per launch (1, 8, 32, 64)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default launch shapes instead of tuning each "
                          "path on the workload before timing it")
@@ -427,29 +543,34 @@ def main():
         y = torch.empty_like(x)
         res[p] = run_path(mlcr, torch, op, x, y, precs[p], args.steps, args.warmup, p)
         outs[p] = y
-    # the mixed result against the float64 GPU apply (itself at 1e-12 of the oracle)
-    err = {}
-    if "fp64" in outs:
-        for p in outs:
-            if p == "fp64":
-                continue
-            err[p] = float((outs[p] - outs["fp64"]).norm() / outs["fp64"].norm())
-            log(f"[bench] {p} path vs fp64 path: relative l2 difference {err[p]:.3e}")
 
     head = paths[0]
     ms_step, kernels = res[head]
     value = R / (ms_step / 1e3)
     roof = roofline(kernels, cfg, R, head)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(cfg, R, x_host, d["ninv"])
-        log(f"[bench] cpu baseline {cpu['value']:.3e} {cpu['unit']}")
-
     others = {p: {"value": R / (res[p][0] / 1e3), "ms_per_step": res[p][0],
                   "roofline": roofline(res[p][1], cfg, R, p)}
               for p in paths[1:]}
+
+    gt = None
+    if not args.no_gate:
+        log("[bench] accuracy gate: applies vs float64 and 9-cycle solves per path")
+        gt = gate(mlcr, torch, cfg, geom, op, x, outs, paths, R)
+    del outs
+    sweep = None
+    if not args.no_sweep and cfg.name == "c5":
+        log("[bench] RHS sweep")
+        del op
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        sweep = r_sweep(mlcr, torch, cfg, geom, d, [p for p in ("fp32", "bf16x3") if p in paths])
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample (all host cores)")
+        cpu = cpu_baseline(cfg, R, x_host, d["ninv"])
+        log(f"[bench] cpu baseline {cpu['value']:.3e} {cpu['unit']} on {cpu['cores']} cores")
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -461,16 +582,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64"}[head],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[head],
         "data": "synthetic",
         "config": {"workload": f"{cfg.name}: HEALPix Nside {cfg.nside}, lmax {cfg.lmax}, "
-                               f"{R} RHS per apply, {head} Legendre path",
+                               f"{R} RHS per apply, {head} Legendre contraction and ring FFTs "
+                               f"(float64 recurrence seeds and scaling, float64 in/out)",
                    "nside": cfg.nside, "lmax": cfg.lmax, "nrhs": R, "prec": head,
                    "global_batch": R},
         "roofline": roof,
         "cpu_baseline": cpu,
         "other_paths": others,
-        "mixed_vs_fp64_rel_l2": err or None,
+        "gate": gt,
+        "rhs_sweep": sweep,
         "tuning": tuned or None,
     }
     print(json.dumps(out), flush=True)
