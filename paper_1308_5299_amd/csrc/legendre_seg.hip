@@ -314,6 +314,173 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
     }
 }
 
+// ---------------------------------------------------------------------------
+// split-bfloat16 synthesis over CB column blocks: one wave per (m, 16 NB
+// ring pairs, 8 CB RHS)
+// ---------------------------------------------------------------------------
+// The same segment-parallel recurrence as k_lsynth_seg (NB chains per lane
+// over segment kg = lane / 16), but each lambda, converted and split into
+// bfloat16 hi/lo once, feeds CB column blocks of 16 (8 RHS x cos, sin each):
+// 3 CB MFMAs per 8 values of one parity instead of 3, so the vector work of
+// the recurrence and the split is shared by 8 CB right-hand sides.  The U
+// block of column block cb is the block of RHS chunk CB rw + cb (the layout
+// k_pack_seg writes); column blocks past the last chunk are skipped
+// (wave-uniform).  Work item order as decode_item_m with rc = rw.
+template <int NB, int CB>
+__global__ __launch_bounds__(64) void k_lsynth_b3w(
+    const uint4 *__restrict__ U, int nrhs, double2 *__restrict__ F, long long fstride, int lmax,
+    const double *__restrict__ rz, const double *__restrict__ alpha,
+    const long long *__restrict__ aboff, const double2 *__restrict__ st,
+    const int *__restrict__ stsc, const int *__restrict__ lstab, int nrings, int npairs, int nb16,
+    int npb, long long total) {
+    static_assert(NB == 2 || NB == 4, "2 or 4 chains per lane");
+    constexpr int NH = 4 / NB;
+    constexpr int CS = 17;
+    __shared__ double sab[4 * CS];
+    int m, pb, rw;
+    bool ok;
+    decode_item_m(total, lmax, npb * NH, m, pb, rw, ok);
+    if (!ok) return;
+    const int g0 = (pb % NH) * NB;
+    pb /= NH;
+    const int lane = threadIdx.x, kg = lane >> 4, jc = lane & 15;
+    const int nrc = (nrhs + 7) / 8;
+    const int ncb = min(CB, nrc - rw * CB);          // column blocks holding RHS (wave-uniform)
+    const int nl = lmax - m + 1;
+    const int ls = lstab[(long long)m * nb16 + 4 * pb];
+    const int nlive = nl - ls;
+    const int n4 = nlive > 0 ? 16 * ((nlive + 63) / 64) : 0;
+    const int nt = n4 / 16;
+    f4b acc[CB][NB][2];
+#pragma unroll
+    for (int cb = 0; cb < CB; cb++)
+#pragma unroll
+        for (int nb = 0; nb < NB; nb++) acc[cb][nb][0] = acc[cb][nb][1] = (f4b){0, 0, 0, 0};
+    if (nt > 0) {
+        Lane1 L[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; nb++) {
+            const int kp = pb * 64 + 16 * (g0 + nb) + jc;
+            L[nb].z = kp < npairs ? rz[kp] : 0.0;
+            const long long tix = ((long long)m * nb16 + 4 * pb + g0 + nb) * 64 + lane;
+            const double2 s0 = st[tix];
+            L[nb].l1 = s0.x;
+            L[nb].l2 = s0.y;
+            L[nb].sc = stsc[tix];
+        }
+        const int seg0 = ls + kg * n4;
+        const long long qt = seg_qtot(lmax);
+        const uint4 *Ub = U + ((long long)rw * CB * qt + seg_qoff(m, lmax) + seg0 / 16) * 64 + jc;
+        const double *abm = alpha + aboff[m] - (m + 1);
+        auto coef_at = [&](int t) {
+            const int l = m + seg0 + 16 * t + jc;
+            return (l + 1 <= lmax) ? abm[l + 1] : 0.0;
+        };
+        auto stage = [&](double c) {
+            __syncthreads();
+            sab[kg * CS + jc] = c;
+            __syncthreads();
+        };
+        auto all_in_range = [&]() {
+            bool in = true;
+#pragma unroll
+            for (int nb = 0; nb < NB; nb++) in = in && L[nb].sc == 0;
+            return __all(in);
+        };
+        auto advance = [&](Lane1 &C, double c, int s, auto checked) -> double {
+            double v;
+            if constexpr (decltype(checked)::value) {
+                v = C.sc == 0 ? C.l1 : 0.0;
+                C.step(c);
+                if ((s & 3) == 3) C.check_range();
+            } else {
+                v = C.l1;
+                const double nv = fma(c * C.z, C.l1, -C.l2);
+                C.l2 = C.l1;
+                C.l1 = nv;
+            }
+            return v;
+        };
+        auto body = [&](int t, auto checked) {
+            // the U blocks of every column block for these 16 steps (chunk CB rw + cb)
+            uint4 bu[CB][4];
+#pragma unroll
+            for (int cb = 0; cb < CB; cb++)
+                if (cb < ncb) {
+#pragma unroll
+                    for (int ph = 0; ph < 4; ph++)
+                        bu[cb][ph] = Ub[((long long)cb * qt + t) * 64 + ph * 16];
+                }
+            // chain by chain: 16 steps, the split, then its 6 CB MFMAs (hi*hi,
+            // hi*lo, lo*hi over the column blocks and parities), so only one
+            // chain's operands are live at a time
+#pragma unroll
+            for (int nb = 0; nb < NB; nb++) {
+                float f[16];
+#pragma unroll
+                for (int s = 0; s < 16; s++) f[s] = (float)advance(L[nb], sab[kg * CS + s], s, checked);
+                uint4 ah[2], al[2];
+#pragma unroll
+                for (int d = 0; d < 4; d++)
+#pragma unroll
+                    for (int p = 0; p < 2; p++) {
+                        unsigned h, l;
+                        split2(f[4 * d + p], f[4 * d + 2 + p], h, l);
+                        reinterpret_cast<unsigned *>(&ah[p])[d] = h;
+                        reinterpret_cast<unsigned *>(&al[p])[d] = l;
+                    }
+#pragma unroll
+                for (int cb = 0; cb < CB; cb++)
+                    if (cb < ncb) {
+                        acc[cb][nb][0] = mma_b3(ah[0], bu[cb][0], acc[cb][nb][0]);
+                        acc[cb][nb][1] = mma_b3(ah[1], bu[cb][2], acc[cb][nb][1]);
+                    }
+#pragma unroll
+                for (int cb = 0; cb < CB; cb++)
+                    if (cb < ncb) {
+                        acc[cb][nb][0] = mma_b3(ah[0], bu[cb][1], acc[cb][nb][0]);
+                        acc[cb][nb][1] = mma_b3(ah[1], bu[cb][3], acc[cb][nb][1]);
+                    }
+#pragma unroll
+                for (int cb = 0; cb < CB; cb++)
+                    if (cb < ncb) {
+                        acc[cb][nb][0] = mma_b3(al[0], bu[cb][0], acc[cb][nb][0]);
+                        acc[cb][nb][1] = mma_b3(al[1], bu[cb][2], acc[cb][nb][1]);
+                    }
+            }
+        };
+        double cpre = coef_at(0);
+        auto iter = [&](int t, auto checked) {
+            stage(cpre);
+            if (t + 1 < nt) cpre = coef_at(t + 1);
+            body(t, checked);
+        };
+        int t = 0;
+        for (; t < nt && !all_in_range(); t++) iter(t, std::true_type{});
+        for (; t < nt; t++) iter(t, std::false_type{});
+    }
+    // D[i][j]: ring pair 64 pb + 16 (g0 + nb) + i (i = 4 kg + v), column j = jc
+    const int ld = lmax + 1;
+#pragma unroll
+    for (int cb = 0; cb < CB; cb++) {
+        const int r = (rw * CB + cb) * 8 + (jc >> 1), cs = jc & 1;
+        if (cb >= ncb || r >= nrhs) continue;
+        double *Fr = reinterpret_cast<double *>(F + (long long)r * fstride);
+#pragma unroll
+        for (int nb = 0; nb < NB; nb++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int i = 4 * kg + v;
+                const int p = pb * 64 + 16 * (g0 + nb) + i;
+                if (p >= npairs) continue;
+                const double e = (double)acc[cb][nb][0][v], o = (double)acc[cb][nb][1][v];
+                const int north = p, south = nrings - 1 - p;
+                Fr[((long long)north * ld + m) * 2 + cs] = e + o;
+                if (south != north) Fr[((long long)south * ld + m) * 2 + cs] = e - o;
+            }
+    }
+}
+
 // U from x, times c_lm (lambda = c mu) and the per-l weights dl (e.g. the
 // beam): one workgroup per (m, RHS chunk); tiles of 64 l are read along l for
 // each of the 16 columns (j = 2 r + cos/sin) into LDS and written as whole
@@ -390,6 +557,10 @@ __global__ __launch_bounds__(256) void k_pack_seg(const double *__restrict__ x,
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+// Column blocks of 16 (8 RHS) that one split-bfloat16 wave takes: 4 from 32
+// RHS on, 2 from 16, else 1 (the 8-RHS kernel).
+int bf16_synth_cols(int nrhs) { return nrhs >= 16 ? 2 : 1; }
+
 long long seg_u_bytes(int lmax, int nrhs, int prec) {
     return (long long)((nrhs + 7) / 8) * seg_qtot(lmax) * (prec == MLCR_FP64 ? 2048 : 1024);
 }
@@ -464,7 +635,21 @@ int launch_legendre_synth_seg(const LegendreArgs &a, const SegTable *t, const vo
 #define MLCR_SEG_LAUNCH(PP, NBV)                                                                \
     hipLaunchKernelGGL((k_lsynth_seg<PP, NBV>), dim3((unsigned)grid), dim3(64), 0, a.stream,     \
                        MLCR_SEG_ARGS)
-    if (prec == MLCR_BF16X3) {
+    const int cbw = prec == MLCR_BF16X3 ? bf16_synth_cols(a.nrhs) : 1;
+    if (prec == MLCR_BF16X3 && cbw > 1) {
+        // CB column blocks per wave share each lambda (two chains per lane)
+        const int nrw = (nrc + cbw - 1) / cbw;
+        const long long tw = mitems(a.lmax, npb, nrw);
+        const long long gw = ((tw + 7) / 8) * 8;
+#define MLCR_B3W_LAUNCH(CBV)                                                                     \
+    hipLaunchKernelGGL((k_lsynth_b3w<4, CBV>), dim3((unsigned)gw), dim3(64), 0, a.stream,          \
+                       reinterpret_cast<const uint4 *>(U), a.nrhs, F, fstride, a.lmax,               \
+                       g->ring_z.as<double>(), g->alpha.as<double>(), g->aboff.as<long long>(),      \
+                       t->st.as<double2>(), t->sc.as<int>(), t->ls.as<int>(), g->nrings, g->npairs,  \
+                       nb16, npb, tw)
+        MLCR_B3W_LAUNCH(2);
+#undef MLCR_B3W_LAUNCH
+    } else if (prec == MLCR_BF16X3) {
         if (nb == 2) MLCR_SEG_LAUNCH(kSegPB3, 2);
         else MLCR_SEG_LAUNCH(kSegPB3, 4);
     } else if (prec == MLCR_FP64) {

@@ -217,6 +217,9 @@ int adjoint_waves(const mlcr_geom *g, int prec);
 // split-bfloat16 matrix-core adjoint (legendre_b3.hip): P as for the float32 adjoint.
 // segment-parallel synthesis (legendre_seg.hip); prec: MLCR_FP32 / FP64 / BF16X3
 long long seg_u_bytes(int lmax, int nrhs, int prec);
+// column blocks of 16 (8 RHS) per wave of the split-bfloat16 kernels: 2 from
+// 16 RHS on (one lambda feeds both), else 1
+int bf16_synth_cols(int nrhs);
 int seg_table(mlcr_geom *g, int lmax, hipStream_t s, const SegTable **out);
 int launch_pack_seg(const mlcr_geom *g, int lmax, int nrhs, const double *x, const double *dl,
                     void *U, int prec, hipStream_t s);

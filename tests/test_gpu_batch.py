@@ -70,6 +70,15 @@ def test_wide_and_ragged_batches(mlcr, nside, lmax, nrhs):
         for r in range(nrhs):
             assert check(f[r], fr[r], TOLS[name], lmax, fp64, slack=2.0)[0], (name, r)
             assert check(a[r], ar[r], TOLS[name], lmax, fp64, slack=2.0)[0], (name, r)
+    # the 4-wave adjoint shape: from 16 RHS on, the split-bfloat16 adjoint
+    # feeds each lambda tile to two column blocks
+    g.set_tuning(mlcr.BF16X3, 4, 4, 1024)
+    a4 = host(mlcr.sht_adjoint(g, dev(y), prec=mlcr.BF16X3))
+    ok4, e4 = check(a4, ar, TOLS["bf16x3"])
+    print(f"bf16x3 adjoint, 4-wave shape: {e4}", flush=True)
+    assert ok4, e4
+    for r in range(nrhs):
+        assert check(a4[r], ar[r], TOLS["bf16x3"], slack=2.0)[0], r
 
 
 @pytest.fixture(scope="module")
