@@ -350,6 +350,14 @@ int mlcr_solver_set_profile(mlcr_solver *s, int on);
 int mlcr_solver_profile(const mlcr_solver *s, int nlevels_max, double *host_ms,
                         long long *host_calls);
 
+/* The dense bottom level (Sec. 3.2): the number n of its active modes, the
+ * assembled matrix A_B (dev_A: [n][n] float64, row-major, before factoring;
+ * entries from the ring Fourier sums of eq. Ni-dense on the level's grid,
+ * the Gauss-Legendre grid of Sec. 3.4 when the level uses one) and the
+ * packed positions of the modes in a vector of band limit lmax_bottom
+ * (host_idx[n]).  Any output may be NULL.  Synchronous. */
+int mlcr_solver_bottom(const mlcr_solver *s, int *n, double *dev_A, int *host_idx);
+
 /* Copy of the top-level smoother's diagonal, 1 / diag(A) on active modes and
  * 0 elsewhere (dev_out: [(lmax+1)^2]); diag(Y^T N^-1 Y) comes from the ring
  * sums of eq. Ni-dense at frequencies 0 and 2m.  EINVAL for a dense-only solver. */

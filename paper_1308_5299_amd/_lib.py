@@ -48,6 +48,7 @@ SIGNATURES = {
     "mlcr_solver_info": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
                                  ctypes.POINTER(c_int), ctypes.POINTER(ctypes.c_float)]),
     "mlcr_solver_top_dinv": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "mlcr_solver_bottom": (c_int, [c_void_p, ctypes.POINTER(c_int), c_void_p, c_void_p]),
     "wcycle_solve": (c_int, [c_void_p, c_int, c_void_p, c_void_p, ctypes.c_double, c_int, c_int,
                              c_void_p, c_void_p]),
     "mlcr_solver_set_graph": (c_int, [c_void_p, c_int]),

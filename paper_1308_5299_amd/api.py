@@ -356,6 +356,16 @@ class Solver:
         return {"nlevels": nl.value, "lmax_bottom": lb.value, "n_bottom": nb.value,
                 "max_ridge": rg.value}
 
+    def bottom(self):
+        """(A_B as an [n, n] float64 tensor, packed positions of its modes)."""
+        n = ctypes.c_int()
+        check(load().mlcr_solver_bottom(self._h, ctypes.byref(n), None, None))
+        A = torch.empty((n.value, n.value), dtype=torch.float64, device=self.op.ninv.device)
+        idx = np.zeros(n.value, dtype=np.int32)
+        check(load().mlcr_solver_bottom(self._h, ctypes.byref(n), ctypes.c_void_p(A.data_ptr()),
+                                        idx.ctypes.data))
+        return A, idx
+
     def top_dinv(self) -> torch.Tensor:
         out = torch.empty((nalm(self.op.lmax),), dtype=torch.float64, device=self.op.ninv.device)
         check(load().mlcr_solver_top_dinv(self._h, ctypes.c_void_p(out.data_ptr()), _stream()))

@@ -409,6 +409,7 @@ struct mlcr_solver {
     // bottom
     int lmax_b = 0, opl_b = 0, na = 0;
     DevBuf b_idx, b_inv, xb, bb;
+    DevBuf b_A;                         // the assembled dense matrix (before factoring)
     DevBuf b_ws;                        // workspace of the dense bottom apply
     // outer loop
     DevBuf sinv, chalf, partial, norms, ro, to;
@@ -742,42 +743,59 @@ static int setup_smoother(mlcr_solver *S, PixLevel &L, hipStream_t s) {
     return MLCR_OK;
 }
 
+// The dense bottom level: A_B over its active modes l <= lmax_b, its entries
+// from the ring Fourier sums of eq. Ni-dense on the level's grid -- the
+// Gauss-Legendre grid of its downgraded N^-1 (Sec. 3.4) when the level uses
+// one, which makes the cost O(lmax_b) per entry instead of O(lmax) -- then a
+// Cholesky factor and the explicit inverse (one GEMV per visit).
 static int setup_bottom(mlcr_solver *S, hipStream_t s) {
     mlcr_op *op = S->op;
     const int lb = S->lmax_b;
-    const long long nb = nalm_l(lb);
-    // active modes of the bottom level in packed order
+    // active modes of the bottom level in packed order, with (l, m, sine)
     const std::vector<double> &clb = op->cl;
-    std::vector<int> idx;
+    std::vector<int> idx, mode;
     {
         long long pos = 0;
         for (int l = 0; l <= lb; l++, pos++)
-            if (clb[l] > 0) idx.push_back((int)pos);
+            if (clb[l] > 0) {
+                idx.push_back((int)pos);
+                mode.push_back(l);
+            }
         for (int m = 1; m <= lb; m++)
             for (int cs = 0; cs < 2; cs++)
                 for (int l = m; l <= lb; l++, pos++)
-                    if (clb[l] > 0) idx.push_back((int)pos);
+                    if (clb[l] > 0) {
+                        idx.push_back((int)pos);
+                        mode.push_back(l | (m << 8) | (cs << 16));
+                    }
     }
     const int na = (int)idx.size();
     S->na = na;
     int rc;
-    if ((rc = up(S->b_idx, idx.data(), idx.size() * sizeof(int)))) return rc;
     if (na == 0) return fail(MLCR_EINVAL, "no active modes at the bottom level");
-    DevBuf cols, X, Ad, info;
-    const int P = 64;
-    if ((rc = alloc(cols, (size_t)na * nb * sizeof(double)))) return rc;
-    if ((rc = alloc(X, (size_t)P * nb * sizeof(double)))) return rc;
-    for (int j0 = 0; j0 < na; j0 += P) {
-        const int np = std::min(P, na - j0);
-        if ((rc = launch_unit_vectors(X.as<double>(), nb, S->b_idx.as<int>(), j0, np, s))) return rc;
-        if ((rc = solver_apply(S, S->opl_b, np, X.as<double>(), cols.as<double>() + (size_t)j0 * nb,
-                              MLCR_FP64, s)))
-            return rc;
-    }
+    if ((rc = up(S->b_idx, idx.data(), idx.size() * sizeof(int)))) return rc;
+    const mlcr_level &Lv = S->direct ? op->levels[0] : *S->slev[S->opl_b];
+    mlcr_geom *gb = Lv.gl ? Lv.gl : op->g;
+    const double *ninvb = Lv.gl ? Lv.gninv.as<double>() : op->ninv;
+    const int ldx = 2 * lb + 1;
+    DevBuf Xi, lt, dmode, Ad, info;
+    if ((rc = alloc(Xi, (size_t)gb->nrings * ldx * sizeof(double2)))) return rc;
+    if ((rc = alloc(lt, (size_t)gb->nrings * (lb + 1) * (lb + 2) / 2 * sizeof(double)))) return rc;
+    if ((rc = up(dmode, mode.data(), mode.size() * sizeof(int)))) return rc;
     if ((rc = alloc(Ad, (size_t)na * na * sizeof(double)))) return rc;
     if ((rc = alloc(info, sizeof(int)))) return rc;
-    if ((rc = launch_dense_gather(cols.as<double>(), nb, S->b_idx.as<int>(), na, Ad.as<double>(), s)))
+    // ring sums of the (downgraded) inverse-noise map at frequencies 0..2 lmax_b
+    if ((rc = launch_ring_adjoint(gb, 2 * lb, 1, ninvb, Xi.as<double2>(), MLCR_FP64, s))) return rc;
+    if ((rc = launch_dense_lambda(gb->ring_z.as<double>(), gb->ring_s.as<double>(), gb->nrings, lb,
+                                  lt.as<double>(), s)))
         return rc;
+    if ((rc = launch_dense_ringdft(Xi.as<double2>(), ldx, lt.as<double>(), lb, gb->nrings,
+                                   dmode.as<int>(), na, Lv.d.as<double>(), Lv.bh.as<double>(),
+                                   Ad.as<double>(), s)))
+        return rc;
+    if ((rc = alloc(S->b_A, (size_t)na * na * sizeof(double)))) return rc;
+    MLCR_HIP_CHECK(hipMemcpyAsync(S->b_A.ptr, Ad.ptr, (size_t)na * na * sizeof(double),
+                                  hipMemcpyDeviceToDevice, s));
     if ((rc = launch_dense_cholesky(Ad.as<double>(), na, info.as<int>(), s))) return rc;
     int hinfo = 0;
     MLCR_HIP_CHECK(hipMemcpyAsync(&hinfo, info.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1054,6 +1072,18 @@ int mlcr_solver_profile(const mlcr_solver *S, int nlevels_max, double *ms, long 
         if (calls) calls[i] = i < (int)S->prof.calls.size() ? S->prof.calls[i] : 0;
     }
     return S->plan.H + 2;
+}
+
+int mlcr_solver_bottom(const mlcr_solver *S, int *n, double *dev_A, int *host_idx) {
+    if (!S) return fail(MLCR_EINVAL, "solver is NULL");
+    if (n) *n = S->na;
+    if (dev_A)
+        MLCR_HIP_CHECK(hipMemcpy(dev_A, S->b_A.ptr, (size_t)S->na * S->na * sizeof(double),
+                                 hipMemcpyDeviceToDevice));
+    if (host_idx)
+        MLCR_HIP_CHECK(hipMemcpy(host_idx, S->b_idx.ptr, (size_t)S->na * sizeof(int),
+                                 hipMemcpyDeviceToHost));
+    return MLCR_OK;
 }
 
 int mlcr_solver_top_dinv(const mlcr_solver *S, double *out, void *stream) {

@@ -37,15 +37,20 @@ int launch_sgs_color(bool forward, const double *r, double *y, long long npix, i
                      const int *tilepix, const int *tiles, int ntl, const int *nbptr,
                      const int *nbs, const int *color, int kappa, const float *off,
                      const float *minv, hipStream_t s);
-int launch_dense_gather(const double *cols, long long ld, const int *act_idx, int na, double *Ad,
+// dense block of A_h from ring Fourier sums (eq. Ni-dense): lambda table
+// lt[nrings][(L+1)(L+2)/2] for l <= L (<= 127), then A over the active modes
+// (mode[i] = l | m << 8 | sine << 16) with the level's d and bh per l
+int launch_dense_lambda(const double *rz, const double *rs, int nrings, int L, double *lt,
                         hipStream_t s);
+int launch_dense_ringdft(const double2 *Xi, int ldx, const double *lt, int L, int nrings,
+                         const int *mode, int na, const double *d, const double *bh, double *A,
+                         hipStream_t s);
 int launch_dense_cholesky(double *a, int n, int *info, hipStream_t s);
 int launch_dense_inverse(const double *L, int n, double *inv, hipStream_t s);
 // ws: dense_apply_ws_doubles(n, nrhs) doubles of device workspace
 long long dense_apply_ws_doubles(int n, int nrhs);
 int launch_dense_apply(const double *Ainv, int n, const int *act_idx, const double *b, double *x,
                        long long nalm, int nrhs, double *ws, hipStream_t s);
-int launch_unit_vectors(double *x, long long nalm, const int *idx, int j0, int np, hipStream_t s);
 int launch_fill_zero(double *p, long long n, hipStream_t s);
 // per-RHS dot products (c, d may be null), out[2 r], out[2 r + 1]
 int launch_dots(const double *a, const double *b, const double *c, const double *d, int lmax,

@@ -576,19 +576,82 @@ __global__ __launch_bounds__(256) void k_sgs_color(const double *__restrict__ r,
 }
 
 // ---------------------------------------------------------------------------
-// dense bottom level
+// dense block of Y^T N^-1 Y from ring Fourier sums (eq. Ni-dense)
 // ---------------------------------------------------------------------------
-// gather the active rows/columns of the probed dense matrix and symmetrize
-__global__ __launch_bounds__(256) void k_dense_gather(const double *__restrict__ cols, long long ld,
-                                                      const int *__restrict__ act_idx, int na,
-                                                      double *__restrict__ Ad) {
+// lambda_lm(theta_k) for l <= L at one ring per workgroup, one thread per m:
+// the textbook recurrence (Sec. 3.2) from lambda_mm; for L <= 64 nothing
+// leaves the float64 range, so no scaling is needed.  lt[k][tri(l, m)].
+__global__ __launch_bounds__(128) void k_dense_lambda(const double *__restrict__ rz,
+                                                      const double *__restrict__ rs, int L,
+                                                      double *__restrict__ lt) {
+    const int k = blockIdx.x;
+    const int m = threadIdx.x;
+    if (m > L) return;
+    const double z = rz[k], sn = rs[k];
+    const long long tri = (long long)(L + 1) * (L + 2) / 2;
+    double *out = lt + (long long)k * tri + ((long long)m * (L + 1) - (long long)m * (m - 1) / 2);
+    double lmm = 0.28209479177387814347;            // 1 / sqrt(4 pi)
+    for (int j = 1; j <= m; j++) lmm *= -sqrt((2.0 * j + 1.0) / (2.0 * j)) * sn;
+    out[0] = lmm;
+    if (m == L) return;
+    double l2 = lmm, l1 = sqrt(2.0 * m + 3.0) * z * lmm;
+    out[1] = l1;
+    double aprev = sqrt(2.0 * m + 3.0);
+    for (int l = m + 2; l <= L; l++) {
+        const double a = sqrt((4.0 * l * l - 1.0) / ((double)(l - m) * (l + m)));
+        const double v = a * (z * l1 - l2 / aprev);
+        l2 = l1;
+        l1 = v;
+        aprev = a;
+        out[l - m] = v;
+    }
+}
+
+// A[i][j] = d_i delta_ij + bh_i bh_j K_ij over the active modes, with
+// K_ij = sum_k w_i w_j lambda_i(k) lambda_j(k) T_k: for real basis functions
+// with trigonometric parts t_i(m_i phi), t_j(m_j phi) the ring sum of
+// xi t_i t_j is half a combination of the ring sums C_k(D) = sum_j xi cos D phi
+// and S_k(D) = sum_j xi sin D phi at D = m_i - m_j and m_i + m_j:
+//   cos cos: (C(-) + C(+)) / 2     sin sin: (C(-) - C(+)) / 2
+//   cos sin: (S(+) - S(-)) / 2     sin cos: (S(+) + S(-)) / 2
+// Xi[k][D] holds (w_D C_k(D), w_D S_k(D)) (the ring adjoint's weights
+// w_0 = 1, w_D = sqrt 2).  mode[i] = l | m << 8 | sine << 16.
+__global__ __launch_bounds__(256) void k_dense_ringdft(const double2 *__restrict__ Xi, int ldx,
+                                                       const double *__restrict__ lt, int L,
+                                                       int nrings, const int *__restrict__ mode,
+                                                       int na, const double *__restrict__ d,
+                                                       const double *__restrict__ bh,
+                                                       double *__restrict__ A) {
+    const long long tri = (long long)(L + 1) * (L + 2) / 2;
     const long long n = (long long)na * na;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
          e += (long long)gridDim.x * blockDim.x) {
         const int i = (int)(e / na), j = (int)(e % na);
-        const double v1 = cols[(long long)j * ld + act_idx[i]];
-        const double v2 = cols[(long long)i * ld + act_idx[j]];
-        Ad[e] = 0.5 * (v1 + v2);
+        if (j < i) continue;
+        const int li = mode[i] & 255, mi = (mode[i] >> 8) & 255, si = mode[i] >> 16;
+        const int lj = mode[j] & 255, mj = (mode[j] >> 8) & 255, sj = mode[j] >> 16;
+        const long long ti = (long long)mi * (L + 1) - (long long)mi * (mi - 1) / 2 + (li - mi);
+        const long long tj = (long long)mj * (L + 1) - (long long)mj * (mj - 1) / 2 + (lj - mj);
+        const int dm = mi - mj, adm = dm < 0 ? -dm : dm, sp = mi + mj;
+        const double wdm = adm == 0 ? 1.0 : 0.70710678118654752440;
+        const double wsp = sp == 0 ? 1.0 : 0.70710678118654752440;
+        const double sgn = dm < 0 ? -1.0 : 1.0;
+        double acc = 0.0;
+        for (int k = 0; k < nrings; k++) {
+            const double2 xd = Xi[(long long)k * ldx + adm], xs = Xi[(long long)k * ldx + sp];
+            const double cm = xd.x * wdm, sm = sgn * xd.y * wdm;
+            const double cp = xs.x * wsp, smp = xs.y * wsp;
+            double t;
+            if (si == 0 && sj == 0) t = cm + cp;
+            else if (si == 1 && sj == 1) t = cm - cp;
+            else if (si == 0) t = smp - sm;
+            else t = smp + sm;
+            acc = fma(lt[(long long)k * tri + ti] * lt[(long long)k * tri + tj], t, acc);
+        }
+        const double w = (mi == 0 ? 1.0 : 1.41421356237309504880) * (mj == 0 ? 1.0 : 1.41421356237309504880);
+        const double v = bh[li] * bh[lj] * 0.5 * w * acc + (i == j ? d[li] : 0.0);
+        A[(long long)i * na + j] = v;
+        A[(long long)j * na + i] = v;
     }
 }
 
@@ -719,12 +782,6 @@ __global__ __launch_bounds__(256) void k_dense_finish(const double *__restrict__
     x[(long long)r * nalm + act_idx[i]] = s;
 }
 
-// unit vectors: x[p][idx[j0 + p]] = 1
-__global__ void k_unit_vectors(double *__restrict__ x, long long nalm,
-                               const int *__restrict__ idx, int j0, int np) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < np) x[(long long)p * nalm + idx[j0 + p]] = 1.0;
-}
 
 // ---------------------------------------------------------------------------
 // launchers
@@ -851,10 +908,19 @@ int launch_sgs_color(bool forward, const double *r, double *y, long long npix, i
     return MLCR_OK;
 }
 
-int launch_dense_gather(const double *cols, long long ld, const int *act_idx, int na, double *Ad,
+int launch_dense_lambda(const double *rz, const double *rs, int nrings, int L, double *lt,
                         hipStream_t s) {
-    hipLaunchKernelGGL(k_dense_gather, dim3(nblk((long long)na * na, 256)), dim3(256), 0, s, cols,
-                       ld, act_idx, na, Ad);
+    if (L > 127) return fail(MLCR_EUNSUPPORTED, "dense block band limit above 127");
+    hipLaunchKernelGGL(k_dense_lambda, dim3(nrings), dim3(128), 0, s, rz, rs, L, lt);
+    MLCR_HIP_CHECK(hipGetLastError());
+    return MLCR_OK;
+}
+
+int launch_dense_ringdft(const double2 *Xi, int ldx, const double *lt, int L, int nrings,
+                         const int *mode, int na, const double *d, const double *bh, double *A,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_ringdft, dim3(nblk((long long)na * na, 256)), dim3(256), 0, s, Xi,
+                       ldx, lt, L, nrings, mode, na, d, bh, A);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }
@@ -893,13 +959,6 @@ int launch_dense_apply(const double *Ainv, int n, const int *act_idx, const doub
                        s, Ainv, n, g, nrhs, part);
     hipLaunchKernelGGL(k_dense_finish, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, part, n,
                        nrhs, act_idx, x, nalm);
-    MLCR_HIP_CHECK(hipGetLastError());
-    return MLCR_OK;
-}
-
-int launch_unit_vectors(double *x, long long nalm, const int *idx, int j0, int np, hipStream_t s) {
-    MLCR_HIP_CHECK(hipMemsetAsync(x, 0, (size_t)np * nalm * sizeof(double), s));
-    hipLaunchKernelGGL(k_unit_vectors, dim3((np + 63) / 64), dim3(64), 0, s, x, nalm, idx, j0, np);
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }

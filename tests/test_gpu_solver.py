@@ -242,3 +242,31 @@ def test_sharp_filter_does_not_converge(mlcr):
     print(f"sharp filter rho after 8 cycles {info[0]['rho']:.2e}; default ladder "
           f"{info0[0]['cycles']} cycles", flush=True)
     assert info[0]["converged"] == 0 and info[0]["rho"] > 1e-8
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_bottom_block_ring_dft(mlcr, name):
+    """The dense bottom block assembled on the GPU from the ring Fourier sums
+    of eq. Ni-dense -- on the observation grid for the single dense level of
+    N_side 16, on the bottom level's Gauss-Legendre grid (downgraded N^-1,
+    Sec. 3.4) at N_side 256 -- equals the oracle's dense A_h (its own ring-DFT
+    route on the observation grid, pinned against brute force) on the active
+    modes, 1e-12."""
+    print(f"case bottom block {name}", flush=True)
+    cfg, d, g, ninv, op = _problem(mlcr, name)
+    S = mlcr.Solver(op, max_nrhs=1)
+    A, idx = S.bottom()
+    A = host(A)
+    info = S.info()
+    lb = info["lmax_bottom"]
+    if info["nlevels"] == 0:
+        ref = oop.dense_A(d["cl"], d["bl"], d["ninv"], cfg.nside)
+    else:
+        lad = mlcr.Ladder.default(cfg.nside, cfg.lmax)
+        fb = lad.filters[-1][: lb + 1]
+        ref = oop.dense_A(d["cl"], d["bl"], d["ninv"], cfg.nside, lmax_h=lb, fl=fb)
+    ref = ref[np.ix_(idx, idx)]
+    err = parity(A, ref)
+    print(f"{name}: {A.shape[0]} modes, l <= {lb}, parity {err:.2e}", flush=True)
+    assert err <= 1e-12, err
+    assert np.array_equal(A, A.T)
