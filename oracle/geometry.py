@@ -3,8 +3,9 @@
 Rings i = 1 .. 4 N_side - 1 run north to south.  For the north polar cap
 (i < N_side) a ring holds 4i pixels at z = 1 - i^2 / (3 N_side^2), the first
 at phi = pi / (4 i); belt rings (N_side <= i <= 3 N_side) hold 4 N_side pixels
-at z = 4/3 - 2 i / (3 N_side), the first at (pi / (2 N_side)) (1 - s / 2)
-with s = (i - N_side + 1) mod 2; south-cap rings mirror the north cap.
+at z = 4/3 - 2 i / (3 N_side), the first at pi / (4 N_side) when i - N_side
+is even and at phi = 0 when it is odd (the numbering of the HEALPix reference
+code, base pixel 4 centred on phi = 0); south-cap rings mirror the north cap.
 
 sin(theta) is evaluated as sqrt((1 - z)(1 + z)) with 1 - z formed exactly
 from integers, so it keeps full relative precision at the poles.
@@ -57,8 +58,7 @@ def healpix_rings(nside: int) -> RingGeometry:
             zabs = abs(Fraction(4 * nside - 2 * i, 3 * nside))
             one_minus = 1 - zabs
             nphi[i - 1] = 4 * nside
-            s = (i - nside + 1) % 2
-            phi0[i - 1] = (math.pi / (2.0 * nside)) * (1.0 - s / 2.0)
+            phi0[i - 1] = math.pi / (4.0 * nside) if (i - nside) % 2 == 0 else 0.0
         sign = -1.0 if i > 2 * nside else 1.0
         z[i - 1] = sign * float(zabs)
         st[i - 1] = math.sqrt(float(one_minus * (1 + zabs)))
@@ -114,3 +114,38 @@ def gauss_legendre_rings(nrings: int, nphi: int):
     geom = RingGeometry(0, zf, st, nph, np.zeros(n), start)
     W = (w * 2 * np.pi / int(nphi)).astype(np.float64)
     return geom, W
+
+
+def nest_to_ring(nside: int, nest) -> np.ndarray:
+    """HEALPix NESTED -> RING pixel index (Gorski et al. 2005).
+
+    A nested index holds the base face f (12 faces of nside^2 pixels) and the
+    pixel's (x, y) position inside the face, bit-interleaved.  The ring number
+    counts down from the face's northernmost corner: i = r_f nside - x - y - 1
+    with r_f = 2, 3, 4 for the northern, equatorial and southern faces; the
+    position along the ring follows from the face's longitude offset
+    (1, 3, 5, 7 or 0, 2, 4, 6 in units of pi / 4, times the ring length
+    quarter) and x - y."""
+    nest = np.asarray(nest, dtype=np.int64)
+    npf = nside * nside
+    f = nest // npf
+    p = nest % npf
+    x = np.zeros_like(p)
+    y = np.zeros_like(p)
+    for b in range(max(1, int(nside).bit_length())):
+        x |= ((p >> (2 * b)) & 1) << b
+        y |= ((p >> (2 * b + 1)) & 1) << b
+    row = f // 4
+    i = (row + 2) * nside - x - y - 1                     # ring number, 1 .. 4 nside - 1
+    lon = np.where(row == 1, 2 * (f % 4), 2 * (f % 4) + 1)
+    north, south = i < nside, i > 3 * nside
+    nr = np.where(north, i, np.where(south, 4 * nside - i, nside))
+    shift = np.where(north | south, 0, (i - nside) & 1)
+    jp = (lon * nr + x - y + 1 + shift) // 2
+    jp = np.where(jp > 4 * nr, jp - 4 * nr, jp)
+    jp = np.where(jp < 1, jp + 4 * nr, jp)
+    # pixels before ring i
+    before = np.where(north, 2 * i * (i - 1),
+                      np.where(south, 12 * npf - 2 * (4 * nside - i + 1) * (4 * nside - i),
+                               2 * nside * (nside - 1) + (i - nside) * 4 * nside))
+    return before + jp - 1

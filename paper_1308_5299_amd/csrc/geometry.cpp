@@ -84,8 +84,9 @@ int build_geometry(mlcr_geom *g, int nside, int lmax) {
             zabs = fabsl(zz);
             one_minus = 1.0L - zabs;
             r.nphi = 4 * nside;
-            int sft = (i - nside + 1) % 2;     // phi0 = (pi / (2 nside)) (1 - s/2)
-            r.phase = sft ? 1 : 2;
+            // phi0 = pi / (4 nside) when i - nside is even, 0 when odd (base
+            // pixel 4 of the HEALPix numbering is centred on phi = 0)
+            r.phase = ((i - nside) % 2 == 0) ? 1 : 0;
             cls = nside;
         }
         z[i - 1] = (double)((i > 2 * nside) ? -zabs : zabs);

@@ -13,7 +13,7 @@
 // z_t = f_2t + i f_2t+1.  When n is a power of two it is a radix-2 Stockham
 // FFT in LDS; otherwise Bluestein's chirp-z convolution with a power-of-two
 // FFT of size M >= 2n - 1 and a precomputed filter.  The phase e^{i m phi0}
-// is e^{i pi m p / N} with p in {1, 2}, so every twiddle, phase and chirp of
+// is e^{i pi m p / N} with p in {0, 1}, so every twiddle, phase and chirp of
 // a ring comes from one table T_N[j] = e^{i pi j / N}.
 //
 // In the fused operator kernel the map never leaves LDS: F is read, the map

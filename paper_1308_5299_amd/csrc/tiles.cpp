@@ -40,7 +40,7 @@ static void pix_vec_ring(int nside, long long ip, double v[3]) {
         phi = ((double)j + 0.5) * M_PI / (2.0 * (double)i);
     } else if (ip < npix - ncap) {           // equatorial belt: 4 nside pixels per ring
         const long long q = ip - ncap, i = q / (4 * ns) + ns, j = q % (4 * ns);
-        const double shift = ((i + ns) & 1) ? 1.0 : 0.5;
+        const double shift = ((i + ns) & 1) ? 0.0 : 0.5;
         z = (4.0 / 3.0) - 2.0 * (double)i / (3.0 * (double)ns);
         phi = ((double)j + shift) * M_PI / (2.0 * (double)ns);
     } else {                                 // south polar cap, mirrored
@@ -255,6 +255,25 @@ int build_tile_graph(int nside, int k, int max_nb, TileGraph &G) {
         G.n_probe = std::max(G.n_probe, G.probe_color[t] + 1);
     }
     return MLCR_OK;
+}
+
+// Unit vectors of the pixel centres of a grid in NESTED order (3 doubles per
+// pixel), and the RING index of each nested pixel; filled by several threads.
+void nested_pixel_table(int nside, std::vector<double> &vec, std::vector<int> &ring) {
+    const long long npix = 12LL * nside * nside;
+    vec.assign((size_t)npix * 3, 0.0);
+    ring.assign((size_t)npix, 0);
+    const int nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (int w = 0; w < nth; w++)
+        th.emplace_back([&, w]() {
+            for (long long n = w; n < npix; n += nth) {
+                const long long r = nest2ring(nside, n);
+                ring[n] = (int)r;
+                pix_vec_ring(nside, r, &vec[(size_t)n * 3]);
+            }
+        });
+    for (auto &t : th) t.join();
 }
 
 }  // namespace mlcr

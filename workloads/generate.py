@@ -53,8 +53,9 @@ def ring_layout(nside: int):
     Rings i = 1..4 nside - 1 from north to south (Gorski et al. 2005):
     north cap i < nside has 4i pixels at z = 1 - i^2/(3 nside^2), first pixel
     at phi = pi/(4i); the equatorial belt has 4 nside pixels at
-    z = 4/3 - 2i/(3 nside) with first pixel at (pi/(2 nside)) (1 - s/2),
-    s = (i - nside + 1) mod 2; the south cap mirrors the north cap.
+    z = 4/3 - 2i/(3 nside) with first pixel at pi/(4 nside) when i - nside is
+    even and at 0 when it is odd (base pixel 4 centred on phi = 0); the south
+    cap mirrors the north cap.
     """
     nrings = 4 * nside - 1
     z = np.empty(nrings)
@@ -69,8 +70,7 @@ def ring_layout(nside: int):
         elif i <= 3 * nside:
             npr[i - 1] = 4 * nside
             z[i - 1] = (4.0 * nside - 2.0 * i) / (3.0 * nside)
-            s = (i - nside + 1) % 2
-            phi0[i - 1] = (math.pi / (2.0 * nside)) * (1.0 - s / 2.0)
+            phi0[i - 1] = math.pi / (4.0 * nside) if (i - nside) % 2 == 0 else 0.0
         else:
             ii = 4 * nside - i
             npr[i - 1] = 4 * ii
