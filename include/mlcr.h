@@ -291,6 +291,32 @@ typedef struct {
  *   gl_levels    1: a coarse level evaluates Y^T N^-1 Y on a Gauss-Legendre
  *                grid when that grid is smaller than the observation grid
  *                (Sec. 3.4); 0: always on the observation grid.
+ *   smoother     the pixel levels' error smoother (Sec. 3.5), on the pattern of
+ *                8 x 8 tiles and their neighbour tiles:
+ *                0  the blocks of Y_h A_h Y_h^T read off the operator by
+ *                   probing, one multicolour block symmetric Gauss-Seidel sweep;
+ *                1  the paper's construction: blocks of D_hat_h (eq. Dhat) and
+ *                   B_hat_h (eq. Bhat) from addition-theorem sums (eq.
+ *                   addition-theorem), B_hat^T N^-1 B_hat by block products
+ *                   without fill-in over the observation pixels, a block
+ *                   incomplete Cholesky with no fill-in in the sweep-colour
+ *                   order with the smallest ridge alpha (bisection, then
+ *                   1.5 alpha, relative to the largest diagonal entry) that
+ *                   succeeds, but at least ridge_min; applied by the two
+ *                   triangular solves.  Needs N_side_obs / N_side^h a power
+ *                   of two.
+ *   ridge_min    (smoother 1) the smallest ridge used, relative to the largest
+ *                diagonal entry (default 1e-4, the low end of the ridges the
+ *                paper reports in Sec. 3.5).  The zero-fill factor can leave
+ *                (L L^T)^-1 A_hat with eigenvalues above 2 when the ridge is
+ *                only just large enough for the factorization to succeed, and
+ *                then the smoothing step amplifies those error components;
+ *                0 gives the paper's rule alone.
+ *   ridge_max    (smoother 1) the largest ridge alpha the search may use
+ *                (>= ridge_min); MLCR_ENOTPD if the factorization fails even
+ *                with it.
+ *   keep_blocks  (smoother 1) 1: keep the assembled blocks for
+ *                mlcr_solver_level_blocks (memory: as large as the factor).
  * The descriptor is read during mlcr_solver_create only. */
 typedef struct {
     int nlevels;
@@ -302,6 +328,10 @@ typedef struct {
     const double *filter[8];
     const double *highpass;
     int gl_levels;
+    int smoother;
+    double ridge_min;
+    double ridge_max;
+    int keep_blocks;
 } mlcr_ladder_desc;
 
 /* The ladder mlcr_solver_create uses when given NULL, for an observation
@@ -349,6 +379,19 @@ int mlcr_solver_info(const mlcr_solver *s, int *nlevels, int *lmax_bottom, int *
 int mlcr_solver_set_profile(mlcr_solver *s, int on);
 int mlcr_solver_profile(const mlcr_solver *s, int nlevels_max, double *host_ms,
                         long long *host_calls);
+
+/* The smoother blocks of pixel level `level` (1..H) of a solver built with
+ * the incomplete-Cholesky smoother: ntiles, nslots (neighbour pairs, the CSR
+ * slots of mlcr_tile_graph's ascending neighbour lists), and float32 64 x 64
+ * column-major blocks (entry (i, j) at j 64 + i, i and j the nested pixel
+ * index within the tile):
+ *   which 0: the assembled approximant, dev_diag[ntiles] = A_tt, dev_off[slot
+ *            t -> u] = A_tu (needs keep_blocks);
+ *   which 1: the factor, dev_diag[t] = L_tt^-1, dev_off[t -> u] = L_tu when u
+ *            comes earlier in the sweep colours, L_ut^T when later.
+ * Any output may be NULL.  Synchronous. */
+int mlcr_solver_level_blocks(const mlcr_solver *s, int level, int which, int *ntiles,
+                             long long *nslots, float *dev_diag, float *dev_off);
 
 /* The dense bottom level (Sec. 3.2): the number n of its active modes, the
  * assembled matrix A_B (dev_A: [n][n] float64, row-major, before factoring;

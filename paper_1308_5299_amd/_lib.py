@@ -49,6 +49,8 @@ SIGNATURES = {
                                  ctypes.POINTER(c_int), ctypes.POINTER(ctypes.c_float)]),
     "mlcr_solver_top_dinv": (c_int, [c_void_p, c_void_p, c_void_p]),
     "mlcr_solver_bottom": (c_int, [c_void_p, ctypes.POINTER(c_int), c_void_p, c_void_p]),
+    "mlcr_solver_level_blocks": (c_int, [c_void_p, c_int, c_int, ctypes.POINTER(c_int),
+                                         ctypes.POINTER(c_ll), c_void_p, c_void_p]),
     "wcycle_solve": (c_int, [c_void_p, c_int, c_void_p, c_void_p, ctypes.c_double, c_int, c_int,
                              c_void_p, c_void_p]),
     "mlcr_solver_set_graph": (c_int, [c_void_p, c_int]),
@@ -79,7 +81,9 @@ class LadderDesc(ctypes.Structure):
     """mlcr_ladder_desc (include/mlcr.h)."""
     _fields_ = [("nlevels", ctypes.c_int), ("nside", ctypes.c_int * 8), ("lmax", ctypes.c_int * 8),
                 ("nrec", ctypes.c_int * 8), ("nrec_top", ctypes.c_int), ("lmax_dense", ctypes.c_int),
-                ("filter", c_dbl_p * 8), ("highpass", c_dbl_p), ("gl_levels", ctypes.c_int)]
+                ("filter", c_dbl_p * 8), ("highpass", c_dbl_p), ("gl_levels", ctypes.c_int),
+                ("smoother", ctypes.c_int), ("ridge_min", ctypes.c_double),
+                ("ridge_max", ctypes.c_double), ("keep_blocks", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

@@ -266,7 +266,9 @@ class Ladder:
     high-pass and whether coarse levels may use Gauss-Legendre grids."""
 
     def __init__(self, nside, lmax, nrec, filters, nrec_top: int = 1, lmax_dense: int = 40,
-                 highpass=None, gl_levels: bool = True):
+                 highpass=None, gl_levels: bool = True, smoother: int = 0, ridge_max: float = 1.0,
+                 ridge_min: float = 1e-4,
+                 keep_blocks: bool = False):
         self.nside = [int(v) for v in nside]
         self.lmax = [int(v) for v in lmax]
         self.nrec = [int(v) for v in nrec]
@@ -275,6 +277,10 @@ class Ladder:
         self.lmax_dense = int(lmax_dense)
         self.highpass = None if highpass is None else np.ascontiguousarray(np.asarray(highpass, dtype=np.float64))
         self.gl_levels = bool(gl_levels)
+        self.smoother = int(smoother)
+        self.ridge_max = float(ridge_max)
+        self.ridge_min = float(ridge_min)
+        self.keep_blocks = bool(keep_blocks)
         n = len(self.nside)
         if not (len(self.lmax) == len(self.nrec) == len(self.filters) == n) or n > 8:
             raise ValueError("one nside, lmax, nrec and filter per level, at most 8 levels")
@@ -292,7 +298,8 @@ class Ladder:
         n = d.nlevels
         filt = [buf[h * (lmax + 1): h * (lmax + 1) + d.lmax[h] + 1].copy() for h in range(n)]
         return cls(list(d.nside[:n]), list(d.lmax[:n]), list(d.nrec[:n]), filt, d.nrec_top,
-                   d.lmax_dense, None, bool(d.gl_levels))
+                   d.lmax_dense, None, bool(d.gl_levels), d.smoother, d.ridge_max, d.ridge_min,
+                   bool(d.keep_blocks))
 
     def desc(self):
         """The C descriptor; its filter pointers point into this object's arrays."""
@@ -307,6 +314,10 @@ class Ladder:
         d.lmax_dense = self.lmax_dense
         d.highpass = self.highpass.ctypes.data_as(dp) if self.highpass is not None else dp()
         d.gl_levels = 1 if self.gl_levels else 0
+        d.smoother = self.smoother
+        d.ridge_max = self.ridge_max
+        d.ridge_min = self.ridge_min
+        d.keep_blocks = 1 if self.keep_blocks else 0
         return d
 
     def check(self, nside_obs: int, lmax: int) -> None:
@@ -355,6 +366,23 @@ class Solver:
                                       ctypes.byref(rg)))
         return {"nlevels": nl.value, "lmax_bottom": lb.value, "n_bottom": nb.value,
                 "max_ridge": rg.value}
+
+    def level_blocks(self, level: int, which: int = 0):
+        """Smoother blocks of pixel level `level` (incomplete-Cholesky smoother):
+        (diag [ntiles, 64, 64], off [nslots, 64, 64]) float32 tensors, stored
+        column-major per block (entry (i, j) at [j, i]); which 0 = assembled
+        approximant, 1 = factor (see mlcr_solver_level_blocks)."""
+        lib = load()
+        nt, ns = ctypes.c_int(), ctypes.c_longlong()
+        check(lib.mlcr_solver_level_blocks(self._h, int(level), int(which), ctypes.byref(nt),
+                                           ctypes.byref(ns), None, None))
+        dev = self.op.ninv.device
+        dg = torch.empty((nt.value, 64, 64), dtype=torch.float32, device=dev)
+        of = torch.empty((max(ns.value, 1), 64, 64), dtype=torch.float32, device=dev)
+        check(lib.mlcr_solver_level_blocks(self._h, int(level), int(which), ctypes.byref(nt),
+                                           ctypes.byref(ns), ctypes.c_void_p(dg.data_ptr()),
+                                           ctypes.c_void_p(of.data_ptr())))
+        return dg, of[: ns.value]
 
     def bottom(self):
         """(A_B as an [n, n] float64 tensor, packed positions of its modes)."""

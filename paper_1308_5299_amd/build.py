@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libmlcr.so")
 SOURCES = ["api.cpp", "geometry.cpp", "legendre.hip", "ringfft.hip", "solver.cpp", "tiles.cpp",
            "solver_kernels.hip", "legendre_mfma.hip",
            "legendre_b3.hip", "legendre_seg.hip",
-           "streams.cpp", "noalloc.hip"]
+           "streams.cpp", "noalloc.hip", "smoother_icc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -73,6 +73,10 @@ struct Plan {
     std::vector<double> highpass;
     double omega = 1.0, omega_top = 1.0;
     bool gl = true;         // coarse levels on Gauss-Legendre grids when cheaper
+    int smoother = 0;       // 0: probed blocks + block SGS; 1: addition theorem + block ICC(0)
+    double ridge_min = 1e-4;  // smallest ridge alpha of the ICC(0) smoother
+    double ridge_max = 1.0;   // largest ridge alpha the ICC(0) search may use
+    bool keep = false;      // keep the assembled smoother blocks (mlcr_solver_level_blocks)
 };
 
 // q_l = exp(-l^2 (l+1)^2 lambda) with q_{lstar} = 0.1 (eq. fourth-power-beam)
@@ -153,6 +157,13 @@ static int check_ladder(int nside_obs, int lmax, const mlcr_ladder_desc *d) {
     if (H < 0 || H > 8) return fail(MLCR_EINVAL, "ladder: nlevels must be in [0, 8]");
     if (d->nrec_top < 1 || d->nrec_top > 3) return fail(MLCR_EINVAL, "ladder: nrec_top must be in [1, 3]");
     if (d->gl_levels != 0 && d->gl_levels != 1) return fail(MLCR_EINVAL, "ladder: gl_levels must be 0 or 1");
+    if (d->smoother != 0 && d->smoother != 1) return fail(MLCR_EINVAL, "ladder: smoother must be 0 or 1");
+    if (d->keep_blocks != 0 && d->keep_blocks != 1)
+        return fail(MLCR_EINVAL, "ladder: keep_blocks must be 0 or 1");
+    if (!(d->ridge_max >= 0.0) || !std::isfinite(d->ridge_max))
+        return fail(MLCR_EINVAL, "ladder: ridge_max must be finite and >= 0");
+    if (!(d->ridge_min >= 0.0) || !(d->ridge_min <= d->ridge_max))
+        return fail(MLCR_EINVAL, "ladder: ridge_min must be in [0, ridge_max]");
     if (H == 0) {
         if (d->lmax_dense != lmax || lmax > kMaxDenseL)
             return fail(MLCR_EINVAL, "ladder: without pixel levels the dense solve must cover the "
@@ -167,6 +178,10 @@ static int check_ladder(int nside_obs, int lmax, const mlcr_ladder_desc *d) {
         if (d->lmax[h] < 1 || d->lmax[h] > up)
             return fail(MLCR_EINVAL, lv + "lmax must be in [1, " + std::to_string(up) + "]");
         if (d->nrec[h] < 1 || d->nrec[h] > 3) return fail(MLCR_EINVAL, lv + "nrec must be in [1, 3]");
+        if (d->smoother == 1 && (nside_obs % d->nside[h] || ((nside_obs / d->nside[h]) &
+                                                              (nside_obs / d->nside[h] - 1))))
+            return fail(MLCR_EINVAL, lv + "the addition-theorem smoother needs N_side_obs / "
+                                          "N_side^h a power of two");
         if (!d->filter[h]) return fail(MLCR_EINVAL, lv + "filter is NULL");
         const int lnext = h + 1 < H ? d->lmax[h + 1] : d->lmax_dense;
         for (int l = 0; l <= d->lmax[h]; l++) {
@@ -182,7 +197,6 @@ static int check_ladder(int nside_obs, int lmax, const mlcr_ladder_desc *d) {
     if (d->highpass)
         for (int l = 0; l <= lmax; l++)
             if (!std::isfinite(d->highpass[l])) return fail(MLCR_EINVAL, "ladder: highpass must be finite");
-    (void)nside_obs;
     return MLCR_OK;
 }
 
@@ -191,6 +205,10 @@ static void plan_from_desc(int lmax, const mlcr_ladder_desc *d, Plan &p) {
     p.H = d->nlevels;
     p.nrec_top = d->nrec_top;
     p.gl = d->gl_levels != 0;
+    p.smoother = d->smoother;
+    p.ridge_min = d->ridge_min;
+    p.ridge_max = d->ridge_max;
+    p.keep = d->keep_blocks != 0;
     if (p.H == 0) {
         p.lmax_b = lmax;
         return;
@@ -213,6 +231,10 @@ static void desc_from_plan(const Plan &p, int lmax, mlcr_ladder_desc *d, double 
     d->nrec_top = p.nrec_top;
     d->lmax_dense = p.lmax_b;
     d->gl_levels = p.gl ? 1 : 0;
+    d->smoother = p.smoother;
+    d->ridge_min = p.ridge_min;
+    d->ridge_max = p.ridge_max;
+    d->keep_blocks = p.keep ? 1 : 0;
     for (int h = 0; h < p.H; h++) {
         d->nside[h] = p.nside[h];
         d->lmax[h] = p.lmax[h];
@@ -395,6 +417,9 @@ struct PixLevel {
     int n_sweep = 0, n_probe = 0;
     std::vector<int> soff;              // host: offsets of the colours in stiles
     DevBuf wdown, act, one, tilepix, nbptr, nbs, off, scol, stiles, minv, ridge;
+    int smoother = 0;                   // 0: block SGS; 1: block ICC(0) (off, minv hold L)
+    int nslots = 0;
+    DevBuf rev, adiag, aoff;            // reverse slots; assembled blocks (kept on request)
     DevBuf x, b, r, t, map, cmap;
 };
 
@@ -418,6 +443,7 @@ struct mlcr_solver {
     DevBuf pcg_p, pcg_zo, pcg_coef;
     std::vector<float> ridge_summary;
     std::vector<Step> sched;            // one cycle's steps (build_schedule)
+    DevBuf vobs, oring;                 // observation pixel vectors and RING indices, NESTED order
     // the solver's own level operators A_h, index = level number (1..H
     // pixel levels, H + 1 the dense bottom; 0 unused: the top is the
     // operator's level 0), so solvers with different ladders can share op
@@ -520,11 +546,26 @@ struct GpuOps : CycleOps {
     int sweep(PixLevel &L, int h) {
         int rc;
         ProfScope ps(P(), s, h, 2);
+        if (L.smoother == 1) {
+            // (L L^T)^-1: forward solve over the colours ascending, backward descending
+            for (int pass = 0; pass < 2; pass++)
+                for (int j = 0; j < L.n_sweep; j++) {
+                    const int c = pass == 0 ? j : L.n_sweep - 1 - j;
+                    if ((rc = launch_sgs_color(pass == 0 ? 0 : 2, L.map.as<double>(),
+                                               L.cmap.as<double>(), L.geom->npix, R,
+                                               L.tilepix.as<int>(), L.stiles.as<int>() + L.soff[c],
+                                               L.soff[c + 1] - L.soff[c], L.nbptr.as<int>(),
+                                               L.nbs.as<int>(), L.scol.as<int>(), c,
+                                               L.off.as<float>(), L.minv.as<float>(), s)))
+                        return rc;
+                }
+            return MLCR_OK;
+        }
         for (int pass = 0; pass < 2; pass++)
             for (int j = 0; j < L.n_sweep; j++) {
                 const int c = pass == 0 ? j : L.n_sweep - 1 - j;
                 if (pass == 1 && c == L.n_sweep - 1) continue;     // no later neighbours
-                if ((rc = launch_sgs_color(pass == 0, L.map.as<double>(), L.cmap.as<double>(),
+                if ((rc = launch_sgs_color(pass == 0 ? 0 : 1, L.map.as<double>(), L.cmap.as<double>(),
                                            L.geom->npix, R, L.tilepix.as<int>(),
                                            L.stiles.as<int>() + L.soff[c],
                                            L.soff[c + 1] - L.soff[c], L.nbptr.as<int>(),
@@ -614,6 +655,158 @@ static void group_by_color(const std::vector<int> &col, int ncol, std::vector<in
     for (size_t t = 0; t < col.size(); t++) list[pos[col[t]]++] = (int)t;
 }
 
+// The paper's construction (Sec. 3.5): blocks of D_hat_h + B_hat_h^T N^-1 B_hat_h
+// on the tile pattern from tabulated addition-theorem sums, the B_hat product
+// without fill-in over the observation pixels, then a block incomplete
+// Cholesky in the sweep-colour order with the smallest ridge (bisection in
+// log alpha, relative to the largest diagonal entry, then 1.5 alpha) that
+// lets every pivot succeed.  L.off / L.minv receive the factor.
+static int setup_smoother_icc(mlcr_solver *S, PixLevel &L, const std::vector<int> &ptr,
+                              const std::vector<int> &nbs, hipStream_t s) {
+    mlcr_op *op = S->op;
+    const Plan &p = S->plan;
+    const int nt = L.ntiles, kk = L.kk;
+    const long long nslots = L.nslots;
+    int rc;
+    if (op->g->kind != 0) return fail(MLCR_EINVAL, "the addition-theorem smoother needs a HEALPix grid");
+    const int nobs = op->g->nside;
+    if (nobs % L.nside || ((nobs / L.nside) & (nobs / L.nside - 1)))
+        return fail(MLCR_EINVAL, "N_side_obs / N_side^h must be a power of two");
+    const long long sub = (long long)kk * (nobs / L.nside) * (nobs / L.nside);
+    // pixel centres in nested order: the level's (tile t = nested [64 t, 64 t + 64))
+    // and, once per solver, the observation grid's with RING indices into N^-1
+    DevBuf vlev;
+    {
+        std::vector<double> v;
+        std::vector<int> r;
+        nested_pixel_table(L.nside, v, r);
+        if ((rc = up(vlev, v.data(), v.size() * sizeof(double)))) return rc;
+    }
+    if (!S->vobs.ptr) {
+        std::vector<double> v;
+        std::vector<int> r;
+        nested_pixel_table(nobs, v, r);
+        if ((rc = up(S->vobs, v.data(), v.size() * sizeof(double)))) return rc;
+        if ((rc = up(S->oring, r.data(), r.size() * sizeof(int)))) return rc;
+    }
+    // addition-theorem kernels of the level: g_l = f^2 / C_l (D_hat), f b_l (B_hat)
+    const int lh = L.lmax;
+    const int hidx = L.opl - 1;
+    std::vector<double> gd(lh + 1), gb(lh + 1);
+    for (int l = 0; l <= lh; l++) {
+        const double f = p.fl[hidx][l];
+        gd[l] = op->cl[l] > 0 ? f * f / op->cl[l] : 0.0;
+        gb[l] = op->cl[l] > 0 ? f * op->bl[l] : 0.0;
+    }
+    DevBuf dgd, dgb, tabD, tabB;
+    if ((rc = up(dgd, gd.data(), gd.size() * sizeof(double)))) return rc;
+    if ((rc = up(dgb, gb.data(), gb.size() * sizeof(double)))) return rc;
+    // couplings within the pattern lie within a few tile widths: the table
+    // covers 64 level pixel widths
+    const int ntab = 16384;
+    const double pxw = std::sqrt(4.0 * kPi / (12.0 * (double)L.nside * L.nside));
+    const double thmax = std::min(kPi, 64.0 * pxw);
+    const double dth = thmax / (ntab - 1);
+    if ((rc = alloc(tabD, (size_t)ntab * sizeof(double))) || (rc = alloc(tabB, (size_t)ntab * sizeof(double))))
+        return rc;
+    if ((rc = launch_addthm_table(dgd.as<double>(), lh, dth, ntab, tabD.as<double>(), s))) return rc;
+    if ((rc = launch_addthm_table(dgb.as<double>(), lh, dth, ntab, tabB.as<double>(), s))) return rc;
+    AddThmTable TD{dth, ntab, tabD.as<double>()}, TB{dth, ntab, tabB.as<double>()};
+    // assembly: diagonal blocks and the pairs t < u (each also stored transposed)
+    std::vector<int> jobs;
+    for (int t = 0; t < nt; t++)
+        for (int j = ptr[t]; j < ptr[t + 1]; j++)
+            if (nbs[j] > t) jobs.push_back(j);
+    DevBuf djobs;
+    if ((rc = up(djobs, jobs.data(), std::max<size_t>(1, jobs.size()) * sizeof(int)))) return rc;
+    if ((rc = alloc(L.adiag, (size_t)nt * kk * kk * sizeof(float)))) return rc;
+    if ((rc = alloc(L.aoff, (size_t)std::max(1LL, nslots) * kk * kk * sizeof(float)))) return rc;
+    if ((rc = launch_smoother_assemble(nt, L.nbptr.as<int>(), L.nbs.as<int>(), L.rev.as<int>(),
+                                       djobs.as<int>(), (int)jobs.size(), vlev.as<double>(),
+                                       S->vobs.as<double>(), S->oring.as<int>(), op->ninv, sub, TD,
+                                       TB, L.adiag.as<float>(), L.aoff.as<float>(), s)))
+        return rc;
+    // block ICC(0) with the ridge search
+    if ((rc = alloc(L.off, (size_t)std::max(1LL, nslots) * kk * kk * sizeof(float)))) return rc;
+    if ((rc = alloc(L.minv, (size_t)nt * kk * kk * sizeof(float)))) return rc;
+    DevBuf dmx, dfail;
+    if ((rc = alloc(dmx, sizeof(double))) || (rc = alloc(dfail, (size_t)nt * sizeof(int)))) return rc;
+    if ((rc = launch_max_diag(L.adiag.as<float>(), nt, dmx.as<double>(), s))) return rc;
+    double scale = 0.0;
+    MLCR_HIP_CHECK(hipMemcpyAsync(&scale, dmx.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
+    MLCR_HIP_CHECK(hipStreamSynchronize(s));
+    if (!(scale > 0.0)) scale = 1.0;
+    std::vector<int> hfail(nt);
+    auto factor = [&](double alpha, int &nfail) -> int {
+        MLCR_HIP_CHECK(hipMemsetAsync(dfail.ptr, 0, (size_t)nt * sizeof(int), s));
+        for (int c = 0; c < L.n_sweep; c++) {
+            int r2;
+            if ((r2 = launch_icc_color(L.stiles.as<int>() + L.soff[c], L.soff[c + 1] - L.soff[c],
+                                       L.nbptr.as<int>(), L.nbs.as<int>(), L.rev.as<int>(),
+                                       L.scol.as<int>(), c, L.adiag.as<float>(), L.aoff.as<float>(),
+                                       alpha * scale, L.minv.as<float>(), L.off.as<float>(),
+                                       dfail.as<int>(), s)))
+                return r2;
+        }
+        MLCR_HIP_CHECK(hipMemcpyAsync(hfail.data(), dfail.ptr, (size_t)nt * sizeof(int),
+                                      hipMemcpyDeviceToHost, s));
+        MLCR_HIP_CHECK(hipStreamSynchronize(s));
+        nfail = 0;
+        for (int v : hfail) nfail += v != 0;
+        return MLCR_OK;
+    };
+    // the paper's rule: no ridge if the factorization succeeds, else 1.5 x the
+    // smallest ridge that lets it succeed; then at least ridge_min.  A
+    // smallest ridge below ridge_min / 1.5 ends at ridge_min either way, so
+    // the search starts there (one factorization decides it) and bisects
+    // log10 alpha to 1/300 of a decade above it.
+    int nf = 0;
+    double alpha = 0.0;
+    bool refactor = false;
+    if ((rc = factor(0.0, nf))) return rc;
+    const double floor_lo = p.ridge_min / 1.5;
+    if (nf > 0 && floor_lo > 0.0) {
+        if ((rc = factor(floor_lo, nf))) return rc;
+        if (nf == 0) alpha = floor_lo;          // raised to ridge_min below
+    }
+    if (nf > 0) {
+        int nf_hi = 0;
+        if ((rc = factor(p.ridge_max, nf_hi))) return rc;
+        if (nf_hi > 0)
+            return fail(MLCR_ENOTPD, "block incomplete Cholesky of the level N_side " +
+                                         std::to_string(L.nside) + " smoother fails on " +
+                                         std::to_string(nf_hi) + " of " + std::to_string(nt) +
+                                         " tiles even with the largest ridge " +
+                                         std::to_string(p.ridge_max) + " x max diagonal");
+        double lo = floor_lo > 0.0 ? std::log10(floor_lo) : -12.0;
+        double hi = std::log10(std::max(p.ridge_max, 1e-300));
+        while (hi - lo > 1.0 / 300.0) {
+            const double mid = 0.5 * (lo + hi);
+            if ((rc = factor(std::pow(10.0, mid), nf))) return rc;
+            if (nf == 0) hi = mid;
+            else lo = mid;
+        }
+        alpha = std::min(p.ridge_max, 1.5 * std::pow(10.0, hi));
+        refactor = true;
+    }
+    if (alpha < p.ridge_min) {
+        alpha = p.ridge_min;
+        refactor = true;
+    }
+    if (refactor) {
+        if ((rc = factor(alpha, nf))) return rc;
+        if (nf > 0) return fail(MLCR_ENOTPD, "block incomplete Cholesky failed at the chosen ridge");
+    }
+    S->ridge_summary.push_back((float)alpha);
+    L.smoother = 1;
+    if (!p.keep) {
+        L.adiag.release();
+        L.aoff.release();
+    }
+    MLCR_HIP_CHECK(hipStreamSynchronize(s));
+    return MLCR_OK;
+}
+
 static int setup_smoother(mlcr_solver *S, PixLevel &L, hipStream_t s) {
     int rc;
     const int kk = L.kk;
@@ -657,6 +850,11 @@ static int setup_smoother(mlcr_solver *S, PixLevel &L, hipStream_t s) {
     if ((rc = up(L.stiles, slist.data(), slist.size() * sizeof(int)))) return rc;
     DevBuf ptiles;
     if ((rc = up(ptiles, plist.data(), plist.size() * sizeof(int)))) return rc;
+    L.nslots = (int)nslots;
+    if (S->plan.smoother == 1) {
+        L.rev = std::move(drev);
+        return setup_smoother_icc(S, L, ptr, nbs, s);
+    }
 
     const long long npix = L.geom->npix, na = nalm_l(L.lmax);
     const int P = 16;          // probes per batch
@@ -1072,6 +1270,25 @@ int mlcr_solver_profile(const mlcr_solver *S, int nlevels_max, double *ms, long 
         if (calls) calls[i] = i < (int)S->prof.calls.size() ? S->prof.calls[i] : 0;
     }
     return S->plan.H + 2;
+}
+
+int mlcr_solver_level_blocks(const mlcr_solver *S, int level, int which, int *ntiles,
+                             long long *nslots, float *dev_diag, float *dev_off) {
+    if (!S || level < 1 || level > S->plan.H || (which != 0 && which != 1))
+        return fail(MLCR_EINVAL, "bad solver, level or kind");
+    const PixLevel &L = *S->lev[level - 1];
+    if (L.smoother != 1) return fail(MLCR_EINVAL, "the level does not use the incomplete-Cholesky smoother");
+    if (ntiles) *ntiles = L.ntiles;
+    if (nslots) *nslots = L.nslots;
+    const size_t bb = (size_t)L.kk * L.kk * sizeof(float);
+    const DevBuf &dg = which == 0 ? L.adiag : L.minv;
+    const DevBuf &of = which == 0 ? L.aoff : L.off;
+    if ((dev_diag || dev_off) && which == 0 && !L.adiag.ptr)
+        return fail(MLCR_EINVAL, "assembled blocks were not kept (ladder keep_blocks = 0)");
+    if (dev_diag) MLCR_HIP_CHECK(hipMemcpy(dev_diag, dg.ptr, (size_t)L.ntiles * bb, hipMemcpyDeviceToDevice));
+    if (dev_off && L.nslots > 0)
+        MLCR_HIP_CHECK(hipMemcpy(dev_off, of.ptr, (size_t)L.nslots * bb, hipMemcpyDeviceToDevice));
+    return MLCR_OK;
 }
 
 int mlcr_solver_bottom(const mlcr_solver *S, int *n, double *dev_A, int *host_idx) {

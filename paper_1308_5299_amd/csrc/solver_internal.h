@@ -33,7 +33,10 @@ int launch_sym_off(const int *nbptr, const int *nbs, const int *rev, float *off,
                    hipStream_t s);
 int launch_tile_factor(const double *blocks, int ntiles, int kk, float *minv, float *ridge,
                        hipStream_t s);
-int launch_sgs_color(bool forward, const double *r, double *y, long long npix, int nrhs,
+// mode 0: block Gauss-Seidel / forward triangular solve y_t = M_t (r_t - sum_{earlier} B_tu y_u);
+// 1: Gauss-Seidel backward y_t -= M_t sum_{later} B_tu y_u; 2: backward
+// triangular solve y_t = M_t^T (y_t - sum_{later} B_tu y_u)
+int launch_sgs_color(int mode, const double *r, double *y, long long npix, int nrhs,
                      const int *tilepix, const int *tiles, int ntl, const int *nbptr,
                      const int *nbs, const int *color, int kappa, const float *off,
                      const float *minv, hipStream_t s);
@@ -100,5 +103,35 @@ struct TileGraph {
     int n_sweep = 0, n_probe = 0;
 };
 int build_tile_graph(int nside, int k, int max_nb, TileGraph &G);
+// pixel-centre unit vectors [npix][3] and RING indices [npix] in NESTED order
+void nested_pixel_table(int nside, std::vector<double> &vec, std::vector<int> &ring);
+
+// smoother_icc.hip: the paper's smoother construction (Sec. 3.5) --
+// tabulated addition-theorem kernels g(theta) = sum_l (2l+1)/(4 pi) g_l P_l(cos theta),
+// the blocks of D_hat_h and of B_hat_h^T N^-1 B_hat_h (no fill-in) on the tile
+// pattern, multicolour block incomplete Cholesky and its triangular solves
+struct AddThmTable {
+    double dth = 0.0;       // table step in theta
+    int n = 0;              // points theta_i = i dth, i < n
+    const double *tab = nullptr;
+};
+int launch_addthm_table(const double *gl, int lmax, double dth, int ntab, double *tab,
+                        hipStream_t s);
+// Assembled blocks (float32, column-major 64 x 64): diag[t] = A_tt and
+// off[slot] = A_tu for the CSR slots of the tile graph.  vlev: level pixel
+// vectors (nested), vobs/oring/ninv: observation pixels (nested) with their
+// RING index into ninv; sub = obs pixels per level tile.
+int launch_smoother_assemble(int ntiles, const int *nbptr, const int *nbs, const int *rev,
+                             const int *jobs, int njobs, const double *vlev, const double *vobs,
+                             const int *oring, const double *ninv, long long sub, AddThmTable gD,
+                             AddThmTable gB, float *diag, float *off, hipStream_t s);
+// One colour of the block ICC(0) of the assembled blocks (adiag, aoff) with
+// ridge alpha * scale on the diagonal: for each tile t of the colour, L_tt
+// (its inverse into minv, column-major) and L_ut for later neighbours u
+// (L_ut at lslot[rev], L_ut^T at lslot[slot]); fail[t] = 1 on a failed pivot.
+int launch_icc_color(const int *tiles, int ntl, const int *nbptr, const int *nbs, const int *rev,
+                     const int *color, int kappa, const float *adiag, const float *aoff,
+                     double shift, float *minv, float *lslot, int *fail, hipStream_t s);
+int launch_max_diag(const float *adiag, int ntiles, double *out, hipStream_t s);
 
 }  // namespace mlcr

@@ -5,6 +5,7 @@
 
 #include "mlcr_internal.h"
 #include "solver_internal.h"
+#include "block_dev.h"
 
 namespace mlcr {
 
@@ -371,29 +372,6 @@ __global__ __launch_bounds__(256) void k_sym_off(const int *__restrict__ nbptr,
 
 // In-LDS Cholesky of a kk x kk SPD matrix (lower, row-major a[i*kk+j]);
 // returns false if a pivot is not positive.  All threads of the block.
-__device__ bool lds_cholesky(double *a, int kk, double *flag) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    if (tid == 0) *flag = 0.0;
-    __syncthreads();
-    for (int j = 0; j < kk; j++) {
-        if (tid == 0) {
-            const double piv = a[j * kk + j];
-            if (!(piv > 0.0)) *flag = 1.0;
-            a[j * kk + j] = piv > 0.0 ? sqrt(piv) : 1.0;
-        }
-        __syncthreads();
-        const double djj = a[j * kk + j];
-        for (int i = j + 1 + tid; i < kk; i += nt) a[i * kk + j] /= djj;
-        __syncthreads();
-        const int rem = kk - j - 1;
-        for (int e = tid; e < rem * rem; e += nt) {
-            const int i = j + 1 + e / rem, c = j + 1 + e % rem;
-            if (c <= i) a[i * kk + c] -= a[i * kk + j] * a[c * kk + j];
-        }
-        __syncthreads();
-    }
-    return *flag == 0.0;
-}
 
 // Per tile: symmetrize the probed block, factor with the smallest ridge
 // alpha (bisection in log alpha, then 1.5 alpha, Sec. 3.5) that makes the
@@ -474,13 +452,17 @@ __global__ __launch_bounds__(256) void k_tile_factor(const double *__restrict__ 
 // Tiles of one colour are never neighbours, so each workgroup updates one
 // tile with no ordering among them.  Lane i of each wave owns pixel i of the
 // tile; blocks are float32 (the paper's smoother precision), maps float64.
-//   forward  (colours ascending):  y_t = D_t^-1 (r_t - sum_{u earlier} A_tu y_u)
-//   backward (colours descending): y_t -= D_t^-1 sum_{u later} A_tu y_u
-// so y ends as M r with M^-1 = (D + L) D^-1 (D + L^T).
+//   mode 0, forward  (colours ascending):  y_t = D_t^-1 (r_t - sum_{u earlier} A_tu y_u)
+//   mode 1, backward (colours descending): y_t -= D_t^-1 sum_{u later} A_tu y_u
+// so y ends as M r with M^-1 = (D + L) D^-1 (D + L^T).  The same kernel runs
+// the triangular solves of a block incomplete Cholesky factor L L^T: mode 0
+// with blocks L_tu (u earlier) and L_tt^-1 is the forward solve, and
+//   mode 2, backward (colours descending): y_t = L_tt^-T (y_t - sum_{u later} L_ut^T y_u)
+// (blocks L_ut^T stored at the slot t -> u) the backward solve.
 // A tile's work is a chain of dependent block products, so it is spread over
 // NW = 4 waves: wave w takes every NW-th neighbour block and a quarter of the
 // columns of D_t^-1, and the partial sums are added in LDS (wave order).
-template <bool FWD>
+template <int MODE>
 __global__ __launch_bounds__(256) void k_sgs_color(const double *__restrict__ r,
                                                    double *__restrict__ y, long long npix,
                                                    int nrhs, const int *__restrict__ tilepix,
@@ -491,6 +473,7 @@ __global__ __launch_bounds__(256) void k_sgs_color(const double *__restrict__ r,
                                                    const float *__restrict__ off,
                                                    const float *__restrict__ minv) {
     constexpr int K2 = kTileK2, NQ = 8, NW = 4, JW = K2 / NW;
+    constexpr bool FWD = MODE == 0;
     static_assert(NQ % NW == 0 && K2 % (NW * 16) == 0, "tile shape");
     __shared__ float v[NW][NQ][K2];              // per-wave neighbour values; then the right side
     __shared__ float part[NW][NQ][K2];           // per-wave partial sums
@@ -532,7 +515,7 @@ __global__ __launch_bounds__(256) void k_sgs_color(const double *__restrict__ r,
         }
 #pragma unroll
         for (int q = 0; q < NQ; q++) part[wv][q][i] = acc[q];
-        if (!__syncthreads_or(any) && !FWD) continue;    // uniform over the workgroup
+        if (!__syncthreads_or(any) && MODE == 1) continue;    // uniform over the workgroup
         // right side for RHS q = NQ / NW * wv + qq, into v[0]
 #pragma unroll
         for (int qq = 0; qq < NQ / NW; qq++) {
@@ -540,8 +523,10 @@ __global__ __launch_bounds__(256) void k_sgs_color(const double *__restrict__ r,
             float tot = part[0][q][i];
 #pragma unroll
             for (int w = 1; w < NW; w++) tot += part[w][q][i];
-            v[0][q][i] = q < nq ? (FWD ? (float)r[(long long)(r0 + q) * npix + pix] - tot : tot)
-                                : 0.0f;
+            float rhs = tot;
+            if (q < nq && MODE == 0) rhs = (float)r[(long long)(r0 + q) * npix + pix] - tot;
+            if (q < nq && MODE == 2) rhs = (float)y[(long long)(r0 + q) * npix + pix] - tot;
+            v[0][q][i] = q < nq ? rhs : 0.0f;
         }
         __syncthreads();
         // D_t^-1 times the right side: wave w takes columns JW w .. JW w + JW - 1
@@ -552,7 +537,8 @@ __global__ __launch_bounds__(256) void k_sgs_color(const double *__restrict__ r,
         for (int j0 = JW * wv; j0 < JW * (wv + 1); j0 += 16) {
             float mm[16];
 #pragma unroll
-            for (int jj = 0; jj < 16; jj++) mm[jj] = Mi[(j0 + jj) * K2 + i];
+            for (int jj = 0; jj < 16; jj++)
+                mm[jj] = MODE == 2 ? Mi[i * K2 + (j0 + jj)] : Mi[(j0 + jj) * K2 + i];
 #pragma unroll
             for (int jj = 0; jj < 16; jj++)
 #pragma unroll
@@ -569,7 +555,7 @@ __global__ __launch_bounds__(256) void k_sgs_color(const double *__restrict__ r,
 #pragma unroll
             for (int w = 1; w < NW; w++) tot += part[w][q][i];
             double *dst = y + (long long)(r0 + q) * npix + pix;
-            *dst = FWD ? (double)tot : *dst - (double)tot;
+            *dst = MODE == 1 ? *dst - (double)tot : (double)tot;
         }
         __syncthreads();                         // LDS free for the next RHS chunk
     }
@@ -893,17 +879,18 @@ int launch_tile_factor(const double *blocks, int ntiles, int kk, float *minv, fl
     return MLCR_OK;
 }
 
-int launch_sgs_color(bool forward, const double *r, double *y, long long npix, int nrhs,
+int launch_sgs_color(int mode, const double *r, double *y, long long npix, int nrhs,
                      const int *tilepix, const int *tiles, int ntl, const int *nbptr,
                      const int *nbs, const int *color, int kappa, const float *off,
                      const float *minv, hipStream_t s) {
     if (ntl <= 0) return MLCR_OK;
-    if (forward)
-        hipLaunchKernelGGL(k_sgs_color<true>, dim3(ntl), dim3(256), 0, s, r, y, npix, nrhs, tilepix,
-                           tiles, nbptr, nbs, color, kappa, off, minv);
-    else
-        hipLaunchKernelGGL(k_sgs_color<false>, dim3(ntl), dim3(256), 0, s, r, y, npix, nrhs, tilepix,
-                           tiles, nbptr, nbs, color, kappa, off, minv);
+#define MLCR_SGS(MD)                                                                               \
+    hipLaunchKernelGGL(k_sgs_color<MD>, dim3(ntl), dim3(256), 0, s, r, y, npix, nrhs, tilepix,     \
+                       tiles, nbptr, nbs, color, kappa, off, minv)
+    if (mode == 0) MLCR_SGS(0);
+    else if (mode == 1) MLCR_SGS(1);
+    else MLCR_SGS(2);
+#undef MLCR_SGS
     MLCR_HIP_CHECK(hipGetLastError());
     return MLCR_OK;
 }

@@ -174,6 +174,14 @@ def _gauss(lmax, fwhm_px, nside):
     ("nrec_top", 4, b"nrec_top"),
     ("lmax_dense", 80, b"lmax_dense"),
     ("gl_levels", 2, b"gl_levels"),
+    ("smoother", 2, b"smoother must be 0 or 1"),
+    ("keep_blocks", 3, b"keep_blocks"),
+    ("ridge_max", -1.0, b"ridge_max"),
+    ("ridge_max", float("inf"), b"ridge_max"),
+    ("ridge_min", -1.0, b"ridge_min"),
+    ("ridge_min", 2.0, b"ridge_min"),
+    ("ridge_min", float("nan"), b"ridge_min"),
+    ("smoother_ratio", [96, 64], b"power of two"),
     ("filter0", "zero", b"filter must be > 0"),
     ("filter0", "nan", b"finite"),
 ])
@@ -189,12 +197,17 @@ def test_ladder_check_rejects(field, value, msg):
         bad = f0.copy()
         bad[10] = 0.0 if value == "zero" else np.nan
         lad.filters[0] = bad
+    elif field == "smoother_ratio":
+        # 256 / 96 is no power of two: the addition-theorem smoother's tiles
+        # would not nest in the observation grid's
+        lad.nside = value
+        lad.smoother = 1
     elif field in ("nside", "lmax", "nrec"):
         setattr(lad, field, value)
     else:
         setattr(lad, field, value)
     d = lad.desc()
-    if field in ("nlevels", "gl_levels"):
+    if field in ("nlevels", "gl_levels", "smoother", "keep_blocks"):
         setattr(d, field, value)
     lib = _lib.load()
     assert lib.mlcr_ladder_check(256, 512, ctypes.byref(d)) == -1
@@ -227,3 +240,20 @@ def test_schedule_visits_for_custom_counts():
     np.testing.assert_array_equal(c[1:4, 3], 2 * np.array(want[1:4]))
     np.testing.assert_array_equal(c[1:4, 2], 4 * np.array(want[1:4]))
     assert c[4, 3] == want[4]
+
+
+@pytest.mark.parametrize("nside", [16, 32, 64])
+def test_tiles_match_the_oracle(nside):
+    """The library's NESTED -> RING map and its tile graph (neighbour lists,
+    sweep colours) equal the oracle's, integer for integer."""
+    import paper_1308_5299_amd as m
+    from oracle import smoother as osm
+    from oracle.geometry import nest_to_ring
+    n = 12 * nside * nside
+    assert np.array_equal(m.nest2ring(nside, np.arange(n)), nest_to_ring(nside, np.arange(n)))
+    g = m.tile_graph(nside)
+    nbptr, nbs, color = osm.tile_graph(nside)
+    nt = len(nbptr) - 1
+    for t in range(nt):
+        assert sorted(int(u) for u in g["nb"][t] if u >= 0) == list(nbs[nbptr[t]: nbptr[t + 1]])
+    assert np.array_equal(np.asarray(g["sweep_color"]), color)
