@@ -44,9 +44,9 @@ DEFAULT_PATHS = "fp32,bf16x3,fp64"
 # counters were taken are listed (a changed kernel reports traffic null).
 # Key: (library timer name, Legendre path, workload, RHS per launch).
 MEASURED_TRAFFIC = {
-    ("legendre_adjoint", "fp32", "c5", 8): 8.839e9 + 4.311e9,
+    ("legendre_adjoint", "fp32", "c5", 8): 8.831e9 + 4.311e9,
     ("legendre_adjoint", "fp64", "c5", 8): 9.036e9 + 8.596e9,
-    ("legendre_synth", "fp32", "c5", 8): 8.155e9 + 9.799e9,
+    ("legendre_synth", "fp32", "c5", 8): 8.124e9 + 9.797e9,
     ("legendre_synth", "fp64", "c5", 8): 16.440e9 + 9.846e9,
     ("ring_apply", "fp32", "c5", 8): 1.836e9 + 1.074e9 + 3 * (1.278e9 + 1.075e9),
     ("ring_apply", "fp64", "c5", 8): 1.772e9 + 1.074e9 + 3 * (1.294e9 + 1.075e9),
@@ -55,8 +55,8 @@ MEASURED_TRAFFIC = {
 # 2.4 GHz x duration) of the same kernels, from
 # profiles/legendre_c5_r8_mfma_counters.md; kernels changed since are absent.
 MEASURED_MFMA_BUSY = {
-    ("legendre_synth", "fp32", "c5", 8): 0.417,
-    ("legendre_adjoint", "fp32", "c5", 8): 0.335,
+    ("legendre_synth", "fp32", "c5", 8): 0.395,
+    ("legendre_adjoint", "fp32", "c5", 8): 0.333,
     ("legendre_synth", "fp64", "c5", 8): 0.566,
     ("legendre_adjoint", "fp64", "c5", 8): 0.361,
 }
