@@ -44,9 +44,11 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
     constexpr int RW = 68;                      // floats per row: 64 rings + 4 pad; the
                                                 // 16 rows read by 16 lanes start 4 banks apart
     constexpr int LSB = 32 * RW * 4;            // bytes per wave: [p * 16 + i][RW]
+    // tiles per chunk sum: a wave's area holds 4 finished 32 x 16 tiles
+    constexpr int KG = W < 2 ? 1 : 4;
     extern __shared__ __align__(16) unsigned char smem[];
     double *sab = reinterpret_cast<double *>(smem);
-    unsigned char *lam_all = smem + kChunkM * sizeof(double2);
+    unsigned char *lam_all = smem + 2 * KG * kChunkM * sizeof(double);
     int m, chunk, rc;
     bool ok;
     decode_item_m(total, lmax, nchunks, m, chunk, rc, ok);
@@ -112,106 +114,124 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
     // mode -1: before tw (or no block), 0: all lanes range-scaled, 1: some, 2: none
     int mode = -1;
     for (int o = threadIdx.x; o < min(32 * t0, nl) * 16; o += 64 * W) Pm[o] = 0.f;
-    // coefficients of tile t + 1 are loaded while tile t computes
-    auto coef_at = [&](int t) {
-        const int l = m + t * 32 + (int)threadIdx.x;
-        return (threadIdx.x < kChunkM && l + 1 <= lmax) ? abm[l + 1] : 0.0;
+    // coefficients of a group of KG tiles; group g + 1's are loaded while
+    // group g computes
+    auto coef_at = [&](int tg) {
+        const int l = m + tg * 32 + (int)threadIdx.x;
+        return ((int)threadIdx.x < KG * kChunkM && l + 1 <= lmax) ? abm[l + 1] : 0.0;
     };
     double cpre = coef_at(t0);
-    if (threadIdx.x < kChunkM) sab[threadIdx.x] = cpre;
-    if (t0 + 1 < ntile) cpre = coef_at(t0 + 1);
+    if ((int)threadIdx.x < KG * kChunkM) sab[threadIdx.x] = cpre;
+    if (t0 + KG < ntile) cpre = coef_at(t0 + KG);
     __syncthreads();
-    for (int t = t0; t < ntile; t++) {
-        // coefficients of tile t in buffer (t - t0) & 1; those of tile t + 1
-        // go to the other buffer, whose last readers (tile t - 1) are past
-        // the barriers that ended the previous tile
-        const double *sb = sab + ((t - t0) & 1) * kChunkM;
-        if (t + 1 < ntile) {
-            if (threadIdx.x < kChunkM) sab[((t + 1 - t0) & 1) * kChunkM + threadIdx.x] = cpre;
-            if (t + 2 < ntile) cpre = coef_at(t + 2);
+    for (int tg = t0; tg < ntile; tg += KG) {
+        // coefficients of group gi in buffer gi & 1; those of group gi + 1 go
+        // to the other buffer, whose last readers (group gi - 1) are past the
+        // barriers that ended the previous group
+        const int gi = (tg - t0) / KG;
+        const double *sbg = sab + (gi & 1) * KG * kChunkM;
+        if (tg + KG < ntile) {
+            if ((int)threadIdx.x < KG * kChunkM) sab[((gi + 1) & 1) * KG * kChunkM + threadIdx.x] = cpre;
+            if (tg + 2 * KG < ntile) cpre = coef_at(tg + 2 * KG);
         }
-        if (t == tw) {
-            const long long tix = ((long long)m * nb16 + 4 * pb + (lane >> 4)) * 64 + (lane & 15);
-            const double2 s0 = st[tix];
-            L.l1 = s0.x;
-            L.l2 = s0.y;
-            L.sc = stsc[tix];
-            mode = wave_mode1(L);
-        }
-        f4b D[2] = {(f4b){0.f, 0.f, 0.f, 0.f}, (f4b){0.f, 0.f, 0.f, 0.f}};   // [parity]
-        if (mode <= 0) {
-            if (mode == 0) {
+        f4b Dg[KG][2];
 #pragma unroll
-                for (int q = 0; q < 8; q++) {
-#pragma unroll
-                    for (int s = 0; s < 4; s++) L.step(sb[4 * q + s]);
-                    L.check_range();
+        for (int j = 0; j < KG; j++) {
+            const int t = tg + j;
+            const double *sb = sbg + j * kChunkM;
+            f4b D[2] = {(f4b){0.f, 0.f, 0.f, 0.f}, (f4b){0.f, 0.f, 0.f, 0.f}};   // [parity]
+            if (t < ntile) {
+                if (t == tw) {
+                    const long long tix = ((long long)m * nb16 + 4 * pb + (lane >> 4)) * 64 + (lane & 15);
+                    const double2 s0 = st[tix];
+                    L.l1 = s0.x;
+                    L.l2 = s0.y;
+                    L.sc = stsc[tix];
+                    mode = wave_mode1(L);
                 }
-                mode = wave_mode1(L);
-            }
-        } else {
-            // steps 2 i (even l - m, row i) and 2 i + 1 (odd, row 16 + i)
-            if (mode == 1) {
+                if (mode <= 0) {
+                    if (mode == 0) {
+#pragma unroll
+                        for (int q = 0; q < 8; q++) {
+#pragma unroll
+                            for (int s = 0; s < 4; s++) L.step(sb[4 * q + s]);
+                            L.check_range();
+                        }
+                        mode = wave_mode1(L);
+                    }
+                } else {
+                    // steps 2 i (even l - m, row i) and 2 i + 1 (odd, row 16 + i)
+                    if (mode == 1) {
 #pragma unroll 4
-                for (int i = 0; i < 16; i++) {
-                    lam[i * RW + lane] = (float)L.w();
-                    L.step_rescale(sb[2 * i]);
-                    lam[(16 + i) * RW + lane] = (float)L.w();
-                    L.step_rescale(sb[2 * i + 1]);
-                }
-                mode = wave_mode1(L);
-            } else {
+                        for (int i = 0; i < 16; i++) {
+                            lam[i * RW + lane] = (float)L.w();
+                            L.step_rescale(sb[2 * i]);
+                            lam[(16 + i) * RW + lane] = (float)L.w();
+                            L.step_rescale(sb[2 * i + 1]);
+                        }
+                        mode = wave_mode1(L);
+                    } else {
 #pragma unroll 8
-                for (int i = 0; i < 16; i++) {
-                    lam[i * RW + lane] = (float)L.l1;
-                    double nv = fma(sb[2 * i] * L.z, L.l1, -L.l2);
-                    L.l2 = L.l1;
-                    L.l1 = nv;
-                    lam[(16 + i) * RW + lane] = (float)L.l1;
-                    nv = fma(sb[2 * i + 1] * L.z, L.l1, -L.l2);
-                    L.l2 = L.l1;
-                    L.l1 = nv;
+                        for (int i = 0; i < 16; i++) {
+                            lam[i * RW + lane] = (float)L.l1;
+                            double nv = fma(sb[2 * i] * L.z, L.l1, -L.l2);
+                            L.l2 = L.l1;
+                            L.l1 = nv;
+                            lam[(16 + i) * RW + lane] = (float)L.l1;
+                            nv = fma(sb[2 * i + 1] * L.z, L.l1, -L.l2);
+                            L.l2 = L.l1;
+                            L.l1 = nv;
+                        }
+                    }
+                    __builtin_amdgcn_s_waitcnt(0xc07f);     // this wave's LDS writes landed
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int p = 0; p < 2; p++)
+#pragma unroll
+                        for (int c = 0; c < 2; c++) {
+                            const float4 *src = reinterpret_cast<const float4 *>(
+                                lam + (16 * p + jc) * RW + 32 * c + 8 * kg);
+                            const float4 f0 = src[0], f1 = src[1];
+                            uint4 ah, al;
+                            split2(f0.x, f0.y, ah.x, al.x);
+                            split2(f0.z, f0.w, ah.y, al.y);
+                            split2(f1.x, f1.y, ah.z, al.z);
+                            split2(f1.z, f1.w, ah.w, al.w);
+                            D[p] = mma_b3(ah, bh[c][p], D[p]);
+                            D[p] = mma_b3(ah, bl[c][p], D[p]);
+                            D[p] = mma_b3(al, bh[c][p], D[p]);
+                        }
+                    // the next tile's lambdas overwrite this one's after its reads
+                    __builtin_amdgcn_s_waitcnt(0xc07f);
+                    __builtin_amdgcn_wave_barrier();
                 }
             }
-            __builtin_amdgcn_s_waitcnt(0xc07f);     // this wave's LDS writes landed
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int p = 0; p < 2; p++)
-#pragma unroll
-                for (int c = 0; c < 2; c++) {
-                    const float4 *src =
-                        reinterpret_cast<const float4 *>(lam + (16 * p + jc) * RW + 32 * c + 8 * kg);
-                    const float4 f0 = src[0], f1 = src[1];
-                    uint4 ah, al;
-                    split2(f0.x, f0.y, ah.x, al.x);
-                    split2(f0.z, f0.w, ah.y, al.y);
-                    split2(f1.x, f1.y, ah.z, al.z);
-                    split2(f1.z, f1.w, ah.w, al.w);
-                    D[p] = mma_b3(ah, bh[c][p], D[p]);
-                    D[p] = mma_b3(ah, bl[c][p], D[p]);
-                    D[p] = mma_b3(al, bh[c][p], D[p]);
-                }
+            Dg[j][0] = D[0];
+            Dg[j][1] = D[1];
         }
-        // the wave's tile (32 l x 16 columns) into its own LDS area; the
-        // stores take the MFMA results, so they follow the wave's own reads
-        // of its lambda tile; other waves read the area only between the
-        // two barriers of a tile
+        // the wave's KG tiles (32 l x 16 columns each) into its own LDS area;
+        // the stores take the MFMA results, so they follow the wave's own
+        // reads of its lambda tile; other waves read the area only between
+        // the two barriers of a group
 #pragma unroll
-        for (int v = 0; v < 4; v++) {
-            const int i = 4 * kg + v;
-            tile[(2 * i) * 16 + jc] = D[0][v];
-            tile[(2 * i + 1) * 16 + jc] = D[1][v];
+        for (int j = 0; j < KG; j++) {
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int i = 4 * kg + v;
+                tile[j * 512 + (2 * i) * 16 + jc] = Dg[j][0][v];
+                tile[j * 512 + (2 * i + 1) * 16 + jc] = Dg[j][1][v];
+            }
         }
         __syncthreads();
         // sum the W tiles; one store per output
-        const int lb0 = t * 32;
-        for (int o = threadIdx.x; o < 512; o += 64 * W) {
-            const int lr = o >> 4;
-            if (m + lb0 + lr > lmax) continue;
+        for (int o = threadIdx.x; o < 512 * KG; o += 64 * W) {
+            const int j = o >> 9, lr = (o & 511) >> 4;
+            const int lb = (tg + j) * 32 + lr;
+            if (tg + j >= ntile || m + lb > lmax) continue;
             float a = 0.f;
 #pragma unroll
             for (int w = 0; w < W; w++) a += reinterpret_cast<const float *>(lam_all + w * LSB)[o];
-            Pm[(long long)(lb0 + lr) * 16 + (o & 15)] = a;
+            Pm[(long long)lb * 16 + (o & 15)] = a;
         }
         __syncthreads();        // the tiles are read before the next lambdas overwrite them
     }
@@ -427,7 +447,8 @@ static int launch_ladj_b3_w(const LegendreArgs &a, const SegTable *st, const dou
     const long long total = mitems(a.lmax, nchunks, nrc);
     const long long grid = ((total + 7) / 8) * 8;
     const long long fstride = (long long)g->nrings * (a.lmax + 1);
-    const size_t lds = kChunkM * sizeof(double2) + (size_t)W * (32 * 68 * 4);
+    constexpr int KG = W < 2 ? 1 : 4;           // tiles per chunk sum
+    const size_t lds = 2 * KG * kChunkM * sizeof(double) + (size_t)W * (32 * 68 * 4);
     int rc = ensure_dynamic_lds((const void *)k_ladj_b3<W>, lds);
     if (rc) return rc;
     hipLaunchKernelGGL((k_ladj_b3<W>), dim3((unsigned)grid), dim3(64 * W), lds, a.stream, G,

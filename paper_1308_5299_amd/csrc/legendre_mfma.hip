@@ -81,9 +81,11 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 8 ? 4 : 1) void k_ladj_mfma(
     constexpr bool TWO = sizeof(T) == 8;         // two passes, half-size tile
     constexpr int LS = (TWO ? 16 : 32) * SL;
     constexpr int VW = 16 / sizeof(T);           // values per 16-byte read
+    // tiles per chunk sum: the float32 area holds 4 finished 32 x 16 tiles
+    constexpr int KG = (TWO || W < 2) ? 1 : 4;
     extern __shared__ __align__(16) unsigned char smem[];
     double *sab = reinterpret_cast<double *>(smem);
-    T *lam_all = reinterpret_cast<T *>(smem + kChunkM * sizeof(double2));
+    T *lam_all = reinterpret_cast<T *>(smem + 2 * KG * kChunkM * sizeof(double));
     int m, chunk, rc;
     bool ok;
     decode_item_m(total, lmax, nchunks, m, chunk, rc, ok);
@@ -136,136 +138,154 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 8 ? 4 : 1) void k_ladj_mfma(
     // mode -1: before tw (or no block), 0: all lanes range-scaled, 1: some, 2: none
     int mode = -1;
     for (int o = threadIdx.x; o < min(32 * t0, nl) * 16; o += 64 * W) Pm[o] = (T)0;
-    // coefficients of tile t + 1 are loaded while tile t computes
-    auto coef_at = [&](int t) {
-        const int l = m + t * 32 + (int)threadIdx.x;
-        return (threadIdx.x < kChunkM && l + 1 <= lmax) ? abm[l + 1] : 0.0;
+    // coefficients of a group of KG tiles; group g + 1's are loaded while
+    // group g computes
+    auto coef_at = [&](int tg) {
+        const int l = m + tg * 32 + (int)threadIdx.x;
+        return ((int)threadIdx.x < KG * kChunkM && l + 1 <= lmax) ? abm[l + 1] : 0.0;
     };
     double cpre = coef_at(t0);
-    if (threadIdx.x < kChunkM) sab[threadIdx.x] = cpre;
-    if (t0 + 1 < ntile) cpre = coef_at(t0 + 1);
+    if ((int)threadIdx.x < KG * kChunkM) sab[threadIdx.x] = cpre;
+    if (t0 + KG < ntile) cpre = coef_at(t0 + KG);
     __syncthreads();
-    for (int t = t0; t < ntile; t++) {
-        // coefficients of tile t in buffer (t - t0) & 1; those of tile t + 1
-        // go to the other buffer, whose last readers (tile t - 1) are past
-        // the barriers that ended the previous tile
-        const double *sb = sab + ((t - t0) & 1) * kChunkM;
-        if (t + 1 < ntile) {
-            if (threadIdx.x < kChunkM) sab[((t + 1 - t0) & 1) * kChunkM + threadIdx.x] = cpre;
-            if (t + 2 < ntile) cpre = coef_at(t + 2);
+    for (int tg = t0; tg < ntile; tg += KG) {
+        // coefficients of group gi in buffer gi & 1; those of group gi + 1 go
+        // to the other buffer, whose last readers (group gi - 1) are past the
+        // barriers that ended the previous group
+        const int gi = (tg - t0) / KG;
+        const double *sbg = sab + (gi & 1) * KG * kChunkM;
+        if (tg + KG < ntile) {
+            if ((int)threadIdx.x < KG * kChunkM) sab[((gi + 1) & 1) * KG * kChunkM + threadIdx.x] = cpre;
+            if (tg + 2 * KG < ntile) cpre = coef_at(tg + 2 * KG);
         }
-        if (t == tw) {
-            const long long tix = ((long long)m * nb16 + 4 * pb + (lane >> 4)) * 64 + (lane & 15);
-            const double2 s0 = st[tix];
-            L.l1 = s0.x;
-            L.l2 = s0.y;
-            L.sc = stsc[tix];
-            mode = wave_mode1(L);
-        }
-        typename M::acc DE = M::zero(), DO = DE;
-        if (mode <= 0) {
-            if (mode == 0) {
+        typename M::acc DEg[KG], DOg[KG];
 #pragma unroll
-                for (int q = 0; q < 8; q++) {
-#pragma unroll
-                    for (int s = 0; s < 4; s++) L.step(sb[4 * q + s]);
-                    L.check_range();
+        for (int j = 0; j < KG; j++) {
+            const int t = tg + j;
+            const double *sb = sbg + j * kChunkM;
+            typename M::acc DE = M::zero(), DO = DE;
+            if (t < ntile) {
+                if (t == tw) {
+                    const long long tix = ((long long)m * nb16 + 4 * pb + (lane >> 4)) * 64 + (lane & 15);
+                    const double2 s0 = st[tix];
+                    L.l1 = s0.x;
+                    L.l2 = s0.y;
+                    L.sc = stsc[tix];
+                    mode = wave_mode1(L);
                 }
-                mode = wave_mode1(L);
-            }
-        } else if constexpr (TWO) {
-            // pass p stores the steps of parity p (rows 0..15), then its MFMAs
-            const Lane1 L0 = L;
+                if (mode <= 0) {
+                    if (mode == 0) {
 #pragma unroll
-            for (int p = 0; p < 2; p++) {
-                if (p == 1) {
-                    L = L0;
-                    __builtin_amdgcn_wave_barrier();    // even rows read before rewriting
-                }
-                if (mode == 1) {
-#pragma unroll 4
-                    for (int s = 0; s < 32; s++) {
-                        if ((s & 1) == p) lam[(s >> 1) * SL + lane] = L.w();
-                        L.step_rescale(sb[s]);
+                        for (int q = 0; q < 8; q++) {
+#pragma unroll
+                            for (int s = 0; s < 4; s++) L.step(sb[4 * q + s]);
+                            L.check_range();
+                        }
+                        mode = wave_mode1(L);
                     }
+                } else if constexpr (TWO) {
+                    // pass p stores the steps of parity p (rows 0..15), then its MFMAs
+                    const Lane1 L0 = L;
+#pragma unroll
+                    for (int p = 0; p < 2; p++) {
+                        if (p == 1) {
+                            L = L0;
+                            __builtin_amdgcn_wave_barrier();    // even rows read before rewriting
+                        }
+                        if (mode == 1) {
+#pragma unroll 4
+                            for (int s = 0; s < 32; s++) {
+                                if ((s & 1) == p) lam[(s >> 1) * SL + lane] = L.w();
+                                L.step_rescale(sb[s]);
+                            }
+                        } else {
+#pragma unroll 8
+                            for (int s = 0; s < 32; s++) {
+                                if ((s & 1) == p) lam[(s >> 1) * SL + lane] = L.l1;
+                                const double nv = fma(sb[s] * L.z, L.l1, -L.l2);
+                                L.l2 = L.l1;
+                                L.l1 = nv;
+                            }
+                        }
+                        __builtin_amdgcn_s_waitcnt(0xc07f);     // this wave's LDS writes landed
+                        __builtin_amdgcn_wave_barrier();
+                        const T *rr = lam + jc * SL + 16 * kq;
+#pragma unroll
+                        for (int g0 = 0; g0 < 16; g0 += VW) {
+                            typedef T v16 __attribute__((ext_vector_type(VW)));
+                            const v16 a = *reinterpret_cast<const v16 *>(rr + g0);
+#pragma unroll
+                            for (int u = 0; u < VW; u++) {
+                                if (p == 0) DE = M::mma(a[u], ge[g0 + u], DE);
+                                else DO = M::mma(a[u], go[g0 + u], DO);
+                            }
+                        }
+                    }
+                    if (mode == 1) mode = wave_mode1(L);
                 } else {
-#pragma unroll 8
-                    for (int s = 0; s < 32; s++) {
-                        if ((s & 1) == p) lam[(s >> 1) * SL + lane] = L.l1;
-                        const double nv = fma(sb[s] * L.z, L.l1, -L.l2);
-                        L.l2 = L.l1;
-                        L.l1 = nv;
-                    }
-                }
-                __builtin_amdgcn_s_waitcnt(0xc07f);     // this wave's LDS writes landed
-                __builtin_amdgcn_wave_barrier();
-                const T *rr = lam + jc * SL + 16 * kq;
-#pragma unroll
-                for (int g0 = 0; g0 < 16; g0 += VW) {
-                    typedef T v16 __attribute__((ext_vector_type(VW)));
-                    const v16 a = *reinterpret_cast<const v16 *>(rr + g0);
-#pragma unroll
-                    for (int u = 0; u < VW; u++) {
-                        if (p == 0) DE = M::mma(a[u], ge[g0 + u], DE);
-                        else DO = M::mma(a[u], go[g0 + u], DO);
-                    }
-                }
-            }
-            if (mode == 1) mode = wave_mode1(L);
-        } else {
-            if (mode == 1) {
+                    if (mode == 1) {
 #pragma unroll 4
-                for (int s = 0; s < 32; s++) {
-                    lam[((s & 1) * 16 + (s >> 1)) * SL + lane] = M::cvt(L.w());
-                    L.step_rescale(sb[s]);
-                }
-                mode = wave_mode1(L);
-            } else {
-                // steady state: every lane in range, plain recurrence
+                        for (int s = 0; s < 32; s++) {
+                            lam[((s & 1) * 16 + (s >> 1)) * SL + lane] = M::cvt(L.w());
+                            L.step_rescale(sb[s]);
+                        }
+                        mode = wave_mode1(L);
+                    } else {
+                        // steady state: every lane in range, plain recurrence
 #pragma unroll 8
-                for (int s = 0; s < 32; s++) {
-                    lam[((s & 1) * 16 + (s >> 1)) * SL + lane] = M::cvt(L.l1);
-                    const double nv = fma(sb[s] * L.z, L.l1, -L.l2);
-                    L.l2 = L.l1;
-                    L.l1 = nv;
+                        for (int s = 0; s < 32; s++) {
+                            lam[((s & 1) * 16 + (s >> 1)) * SL + lane] = M::cvt(L.l1);
+                            const double nv = fma(sb[s] * L.z, L.l1, -L.l2);
+                            L.l2 = L.l1;
+                            L.l1 = nv;
+                        }
+                    }
+                    __builtin_amdgcn_s_waitcnt(0xc07f);     // this wave's LDS writes landed
+                    __builtin_amdgcn_wave_barrier();
+                    const T *re = lam + jc * SL + 16 * kq;         // row (even, jc)
+                    const T *ro = re + 16 * SL;                     // row (odd, jc)
+#pragma unroll
+                    for (int g0 = 0; g0 < 16; g0 += VW) {
+                        typedef T v16 __attribute__((ext_vector_type(VW)));
+                        const v16 ae = *reinterpret_cast<const v16 *>(re + g0);
+                        const v16 ao = *reinterpret_cast<const v16 *>(ro + g0);
+#pragma unroll
+                        for (int u = 0; u < VW; u++) {
+                            DE = M::mma(ae[u], ge[g0 + u], DE);
+                            DO = M::mma(ao[u], go[g0 + u], DO);
+                        }
+                    }
+                    // the next tile's lambdas overwrite this one's after its reads
+                    __builtin_amdgcn_s_waitcnt(0xc07f);
+                    __builtin_amdgcn_wave_barrier();
                 }
             }
-            __builtin_amdgcn_s_waitcnt(0xc07f);     // this wave's LDS writes landed
-            __builtin_amdgcn_wave_barrier();
-            const T *re = lam + jc * SL + 16 * kq;         // row (even, jc)
-            const T *ro = re + 16 * SL;                     // row (odd, jc)
-#pragma unroll
-            for (int g0 = 0; g0 < 16; g0 += VW) {
-                typedef T v16 __attribute__((ext_vector_type(VW)));
-                const v16 ae = *reinterpret_cast<const v16 *>(re + g0);
-                const v16 ao = *reinterpret_cast<const v16 *>(ro + g0);
-#pragma unroll
-                for (int u = 0; u < VW; u++) {
-                    DE = M::mma(ae[u], ge[g0 + u], DE);
-                    DO = M::mma(ao[u], go[g0 + u], DO);
-                }
-            }
+            DEg[j] = DE;
+            DOg[j] = DO;
         }
-        // the wave's tile (32 l x 16 columns) into its own LDS area; the
-        // stores take the MFMA results, so they follow the wave's own reads
-        // of its lambda tile; other waves read the area only between the
-        // two barriers of a tile
+        // the wave's KG tiles (32 l x 16 columns each) into its own LDS area;
+        // the stores take the MFMA results, so they follow the wave's own
+        // reads of its lambda tile; other waves read the area only between
+        // the two barriers of a group
 #pragma unroll
-        for (int v = 0; v < 4; v++) {
-            const int i = M::row(kq, v);
-            lam[(2 * i) * 16 + jc] = DE[v];
-            lam[(2 * i + 1) * 16 + jc] = DO[v];
+        for (int j = 0; j < KG; j++) {
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int i = M::row(kq, v);
+                lam[j * 512 + (2 * i) * 16 + jc] = DEg[j][v];
+                lam[j * 512 + (2 * i + 1) * 16 + jc] = DOg[j][v];
+            }
         }
         __syncthreads();
         // sum the W tiles; one store per output
-        const int lb0 = t * 32;
-        for (int o = threadIdx.x; o < 512; o += 64 * W) {
-            const int lr = o >> 4;
-            if (m + lb0 + lr > lmax) continue;
+        for (int o = threadIdx.x; o < 512 * KG; o += 64 * W) {
+            const int j = o >> 9, lr = (o & 511) >> 4;
+            const int lb = (tg + j) * 32 + lr;
+            if (tg + j >= ntile || m + lb > lmax) continue;
             T a = (T)0;
 #pragma unroll
             for (int w = 0; w < W; w++) a += lam_all[w * LS + o];
-            Pm[(long long)(lb0 + lr) * 16 + (o & 15)] = a;
+            Pm[(long long)lb * 16 + (o & 15)] = a;
         }
         __syncthreads();        // the tiles are read before the next lambdas overwrite them
     }
@@ -301,7 +321,8 @@ static int launch_ladj_wg(const LegendreArgs &a, const SegTable *st, const doubl
     const long long total = mitems(a.lmax, nchunks, nrc);
     const long long grid = ((total + 7) / 8) * 8;
     const long long fstride = (long long)g->nrings * (a.lmax + 1);
-    const size_t lds = kChunkM * sizeof(double2) +
+    constexpr int KG = (sizeof(T) == 8 || W < 2) ? 1 : 4;     // tiles per chunk sum
+    const size_t lds = 2 * KG * kChunkM * sizeof(double) +
                        (size_t)W * (sizeof(T) == 8 ? 16 * 66 : 32 * 68) * sizeof(T);
     int rc = ensure_dynamic_lds((const void *)k_ladj_mfma<T, W>, lds);
     if (rc) return rc;
