@@ -82,7 +82,7 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 8 ? 4 : 1) void k_ladj_mfma(
     constexpr int LS = (TWO ? 16 : 32) * SL;
     constexpr int VW = 16 / sizeof(T);           // values per 16-byte read
     // tiles per chunk sum: the float32 area holds 4 finished 32 x 16 tiles
-    constexpr int KG = (TWO || W < 2) ? 1 : 4;
+    constexpr int KG = W < 2 ? 1 : (TWO ? 2 : 4);
     extern __shared__ __align__(16) unsigned char smem[];
     double *sab = reinterpret_cast<double *>(smem);
     T *lam_all = reinterpret_cast<T *>(smem + 2 * KG * kChunkM * sizeof(double));
@@ -321,7 +321,7 @@ static int launch_ladj_wg(const LegendreArgs &a, const SegTable *st, const doubl
     const long long total = mitems(a.lmax, nchunks, nrc);
     const long long grid = ((total + 7) / 8) * 8;
     const long long fstride = (long long)g->nrings * (a.lmax + 1);
-    constexpr int KG = (sizeof(T) == 8 || W < 2) ? 1 : 4;     // tiles per chunk sum
+    constexpr int KG = W < 2 ? 1 : (sizeof(T) == 8 ? 2 : 4);     // tiles per chunk sum
     const size_t lds = 2 * KG * kChunkM * sizeof(double) +
                        (size_t)W * (sizeof(T) == 8 ? 16 * 66 : 32 * 68) * sizeof(T);
     int rc = ensure_dynamic_lds((const void *)k_ladj_mfma<T, W>, lds);
