@@ -44,21 +44,26 @@ DEFAULT_PATHS = "fp32,bf16x3,fp64"
 # counters were taken are listed (a changed kernel reports traffic null).
 # Key: (library timer name, Legendre path, workload, RHS per launch).
 MEASURED_TRAFFIC = {
-    ("legendre_adjoint", "fp32", "c5", 8): 8.831e9 + 4.311e9,
-    ("legendre_adjoint", "fp64", "c5", 8): 9.036e9 + 8.596e9,
-    ("legendre_synth", "fp32", "c5", 8): 8.124e9 + 9.797e9,
-    ("legendre_synth", "fp64", "c5", 8): 16.440e9 + 9.846e9,
+    ("legendre_adjoint", "fp32", "c5", 8): 8.902e9 + 4.315e9,
+    ("legendre_adjoint", "bf16x3", "c5", 8): 8.979e9 + 4.316e9,
+    ("legendre_adjoint", "fp64", "c5", 8): 9.091e9 + 8.596e9,
+    ("legendre_synth", "fp32", "c5", 8): 8.157e9 + 9.794e9,
+    ("legendre_synth", "bf16x3", "c5", 8): 3.882e9 + 8.156e9,
+    ("legendre_synth", "fp64", "c5", 8): 16.361e9 + 9.839e9,
     ("ring_apply", "fp32", "c5", 8): 1.836e9 + 1.074e9 + 3 * (1.278e9 + 1.075e9),
-    ("ring_apply", "fp64", "c5", 8): 1.772e9 + 1.074e9 + 3 * (1.294e9 + 1.075e9),
+    ("ring_apply", "bf16x3", "c5", 8): 1.836e9 + 1.074e9 + 3 * (1.278e9 + 1.075e9),
+    ("ring_apply", "fp64", "c5", 8): 1.771e9 + 1.074e9 + 3 * (1.284e9 + 1.075e9),
 }
 # Matrix-core busy fraction (SQ_VALU_MFMA_BUSY_CYCLES over 1024 SIMDs x
 # 2.4 GHz x duration) of the same kernels, from
 # profiles/legendre_c5_r8_mfma_counters.md; kernels changed since are absent.
 MEASURED_MFMA_BUSY = {
-    ("legendre_synth", "fp32", "c5", 8): 0.395,
-    ("legendre_adjoint", "fp32", "c5", 8): 0.333,
-    ("legendre_synth", "fp64", "c5", 8): 0.566,
-    ("legendre_adjoint", "fp64", "c5", 8): 0.361,
+    ("legendre_synth", "fp32", "c5", 8): 0.394,
+    ("legendre_adjoint", "fp32", "c5", 8): 0.348,
+    ("legendre_synth", "bf16x3", "c5", 8): 0.116,
+    ("legendre_adjoint", "bf16x3", "c5", 8): 0.086,
+    ("legendre_synth", "fp64", "c5", 8): 0.554,
+    ("legendre_adjoint", "fp64", "c5", 8): 0.372,
 }
 
 
