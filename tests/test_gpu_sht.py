@@ -138,6 +138,41 @@ def test_errors(mlcr):
         mlcr.sht_synth(g, dev(np.zeros(80)))                # not a whole vector
 
 
+def test_empty_batch_rejected(mlcr):
+    """nrhs = 0 is outside every entry point's range (nrhs >= 1): MLCR_EINVAL
+    through the C ABI, nothing launched."""
+    import ctypes
+    from paper_1308_5299_amd import _lib
+    lib = _lib.load()
+    g = mlcr.Geometry(4, 8)
+    buf = dev(np.zeros(12 * 16 + 81))
+    p = ctypes.c_void_p(buf.data_ptr())
+    for prec in (mlcr.FP64, mlcr.FP32, mlcr.BF16X3):
+        assert lib.sht_synth(g.handle, 8, 0, p, p, prec, None) == -1
+        assert lib.sht_adjoint(g.handle, 8, 0, p, p, prec, None) == -1
+    op = mlcr.Operator(g, np.ones(9), np.ones(9), dev(np.ones(12 * 16)), max_nrhs=2)
+    assert lib.apply_A(op.handle, 0, 0, p, p, mlcr.FP64, None) == -1
+    assert lib.apply_A(op.handle, 0, 3, p, p, mlcr.FP64, None) == -1        # above max_nrhs
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "fp32", "bf16x3"])
+def test_apply_without_data_is_the_prior(mlcr, prec_name):
+    """N^-1 = 0 everywhere (a fully masked sky, Sec. 2.3): A = S^-1, so the
+    apply returns x / C_l whatever the transform arithmetic (v is exactly 0)."""
+    prec = {"fp64": mlcr.FP64, "fp32": mlcr.FP32, "bf16x3": mlcr.BF16X3}[prec_name]
+    nside, lmax = 32, 64
+    rng = np.random.default_rng(77)
+    cl = rng.uniform(0.5, 2.0, lmax + 1)
+    bl = rng.uniform(0.2, 1.0, lmax + 1)
+    g = mlcr.Geometry(nside, lmax)
+    op = mlcr.Operator(g, cl, bl, dev(np.zeros(12 * nside * nside)), max_nrhs=9)
+    x = rng.standard_normal((9, osht.nalm(lmax)))
+    y = host(mlcr.apply_A(op, dev(x), prec=prec))
+    L, _, _ = osht.packed_index(lmax)
+    want = x / cl[L]
+    assert np.max(np.abs(y - want) / np.abs(want)) <= 4e-16
+
+
 # Float32 contraction on the matrix cores: lambda and the coefficients are
 # rounded to float32 (2^-24) and summed in float32 over <= lmax + 1 terms,
 # so the relative 2-norm error is ~ 2^-24 sqrt(lmax); 2e-5 covers lmax 512.
