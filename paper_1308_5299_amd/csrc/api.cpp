@@ -166,8 +166,9 @@ static bool use_mfma(int prec, int nrhs) {
     return prec != MLCR_FP64 || nrhs >= kMfmaF64MinRhs;
 }
 
+// F: complex float64 on the float64 path, complex float32 on the mixed paths
 static int legendre_synth_any(const LegendreArgs &a, const double *x, const double *dl, mlcr_geom *g,
-                              double2 *F, int prec) {
+                              void *F, int prec) {
     int rc;
     if (use_mfma(prec, a.nrhs)) {
         const SegTable *st = nullptr;
@@ -186,10 +187,10 @@ static int legendre_synth_any(const LegendreArgs &a, const double *x, const doub
         if ((rc = launch_pack_t(a.lmax, a.nrhs, synth_rc(a.nrhs), x, dl, U, a.stream))) return rc;
     }
     KTimer t("legendre_synth", a.stream);
-    return launch_legendre_synth(a, U, F);
+    return launch_legendre_synth(a, U, static_cast<double2 *>(F));
 }
 
-static int legendre_adjoint_any(const LegendreArgs &a, const double2 *G, mlcr_geom *g,
+static int legendre_adjoint_any(const LegendreArgs &a, const void *G, mlcr_geom *g,
                                 const double *x, const double *d, const double *bh, double *y,
                                 int prec) {
     int rc, nch = 0;
@@ -199,9 +200,10 @@ static int legendre_adjoint_any(const LegendreArgs &a, const double2 *G, mlcr_ge
     if (mm && (rc = seg_table(g, a.lmax, a.stream, &st))) return rc;
     {
         KTimer t("legendre_adjoint", a.stream);
-        if (prec == MLCR_BF16X3) rc = launch_legendre_adjoint_b3(a, st, G, (float *)P, &nch);
+        if (prec == MLCR_BF16X3)
+            rc = launch_legendre_adjoint_b3(a, st, static_cast<const float2 *>(G), (float *)P, &nch);
         else if (mm) rc = launch_legendre_adjoint_mfma(a, st, G, P, &nch, prec == MLCR_FP64);
-        else rc = launch_legendre_adjoint(a, G, P, &nch);
+        else rc = launch_legendre_adjoint(a, static_cast<const double2 *>(G), P, &nch);
         if (rc) return rc;
     }
     KTimer t("unpack", a.stream);
@@ -235,7 +237,7 @@ int apply_level_on(mlcr_op *op, const mlcr_level &L, int nrhs, const double *x, 
     const double *ninv = L.gl ? L.gninv.as<double>() : op->ninv;
     const int lmax = L.lmax;
     if ((rc = reserve_ws(g, lmax, nrhs))) return rc;
-    double2 *F = g->wsF.as<double2>();
+    void *F = g->wsF.ptr;
     LegendreArgs a{g, lmax, nrhs, s};
     if ((rc = legendre_synth_any(a, x, L.bh.as<double>(), g, F, prec))) return rc;
     {
@@ -396,7 +398,7 @@ int sht_synth(mlcr_geom *g, int lmax, int nrhs, const double *alm, double *map, 
     if ((rc = reserve_ws(g, lmax, nrhs))) return rc;
     hipStream_t s = (hipStream_t)stream;
     LegendreArgs a{g, lmax, nrhs, s};
-    double2 *F = g->wsF.as<double2>();
+    void *F = g->wsF.ptr;
     if ((rc = legendre_synth_any(a, alm, nullptr, g, F, prec))) return rc;
     {
         KTimer t("ring_synth", s);
@@ -416,7 +418,7 @@ int sht_adjoint(mlcr_geom *g, int lmax, int nrhs, const double *map, double *alm
     if ((rc = reserve_ws(g, lmax, nrhs))) return rc;
     hipStream_t s = (hipStream_t)stream;
     LegendreArgs a{g, lmax, nrhs, s};
-    double2 *G = g->wsF.as<double2>();
+    void *G = g->wsF.ptr;
     {
         KTimer t("ring_adjoint", s);
         if ((rc = launch_ring_adjoint(g, lmax, nrhs, map, G, prec, s))) return rc;

@@ -36,7 +36,7 @@ namespace mlcr {
 // sums, added in float64 by the unpack step).
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_ladj_b3(
-    const double2 *__restrict__ G, long long fstride, int nrhs, float *__restrict__ P, int lmax,
+    const float2 *__restrict__ G, long long fstride, int nrhs, float *__restrict__ P, int lmax,
     const double *__restrict__ rz, const double *__restrict__ alpha,
     const long long *__restrict__ aboff, const double2 *__restrict__ st,
     const int *__restrict__ stsc, const int *__restrict__ lstab, int nb16, int nrings, int npairs,
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
     // B operands [c][parity]: ring pairs 32 c + 8 kg + e of this block, column jc
     uint4 bh[2][2], bl[2][2];
     {
-        const double *Gr = reinterpret_cast<const double *>(G + (long long)rB * fstride);
+        const float *Gr = reinterpret_cast<const float *>(G + (long long)rB * fstride);
 #pragma unroll
         for (int c = 0; c < 2; c++) {
             float ev[8], od[8];
@@ -95,8 +95,8 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
                 double gn = 0.0, gs = 0.0;
                 if (active && p < npairs) {
                     const int north = p, south = nrings - 1 - p;
-                    gn = Gr[((long long)north * ld + m) * 2 + csB];
-                    if (south != north) gs = Gr[((long long)south * ld + m) * 2 + csB];
+                    gn = (double)Gr[((long long)north * ld + m) * 2 + csB];
+                    if (south != north) gs = (double)Gr[((long long)south * ld + m) * 2 + csB];
                 }
                 ev[e] = (float)(gn + gs);
                 od[e] = (float)(gn - gs);
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
 // (wave-uniform).
 template <int W, int CB>
 __global__ __launch_bounds__(64 * W) void k_ladj_b3w(
-    const double2 *__restrict__ G, long long fstride, int nrhs, float *__restrict__ P, int lmax,
+    const float2 *__restrict__ G, long long fstride, int nrhs, float *__restrict__ P, int lmax,
     const double *__restrict__ rz, const double *__restrict__ alpha,
     const long long *__restrict__ aboff, const double2 *__restrict__ st,
     const int *__restrict__ stsc, const int *__restrict__ lstab, int nb16, int nrings, int npairs,
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3w(
 #pragma unroll
     for (int cb = 0; cb < CB; cb++) {
         const int rB = min((rw * CB + cb) * 8 + (jc >> 1), nrhs - 1), csB = jc & 1;
-        const double *Gr = reinterpret_cast<const double *>(G + (long long)rB * fstride);
+        const float *Gr = reinterpret_cast<const float *>(G + (long long)rB * fstride);
 #pragma unroll
         for (int c = 0; c < 2; c++) {
             float ev[8], od[8];
@@ -307,8 +307,8 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3w(
                 double gn = 0.0, gs = 0.0;
                 if (cb < ncb && active && p < npairs) {
                     const int north = p, south = nrings - 1 - p;
-                    gn = Gr[((long long)north * ld + m) * 2 + csB];
-                    if (south != north) gs = Gr[((long long)south * ld + m) * 2 + csB];
+                    gn = (double)Gr[((long long)north * ld + m) * 2 + csB];
+                    if (south != north) gs = (double)Gr[((long long)south * ld + m) * 2 + csB];
                 }
                 ev[e] = (float)(gn + gs);
                 od[e] = (float)(gn - gs);
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3w(
 // launchers
 // ---------------------------------------------------------------------------
 template <int W>
-static int launch_ladj_b3_w(const LegendreArgs &a, const SegTable *st, const double2 *G, float *P,
+static int launch_ladj_b3_w(const LegendreArgs &a, const SegTable *st, const float2 *G, float *P,
                             int nchunks) {
     const mlcr_geom *g = a.g;
     const int npb = (g->npairs + 63) / 64;
@@ -460,7 +460,7 @@ static int launch_ladj_b3_w(const LegendreArgs &a, const SegTable *st, const dou
 }
 
 template <int W, int CB>
-static int launch_ladj_b3w(const LegendreArgs &a, const SegTable *st, const double2 *G, float *P,
+static int launch_ladj_b3w(const LegendreArgs &a, const SegTable *st, const float2 *G, float *P,
                            int nchunks) {
     const mlcr_geom *g = a.g;
     const int npb = (g->npairs + 63) / 64;
@@ -482,7 +482,7 @@ static int launch_ladj_b3w(const LegendreArgs &a, const SegTable *st, const doub
 
 // Same split-K chunking (with this path's tuned waves per workgroup) and P
 // layout as the float32 adjoint.
-int launch_legendre_adjoint_b3(const LegendreArgs &a, const SegTable *st, const double2 *G,
+int launch_legendre_adjoint_b3(const LegendreArgs &a, const SegTable *st, const float2 *G,
                                float *P, int *nchunks_out) {
     if (st->lmax != a.lmax) return fail(MLCR_EINVAL, "start-state table of another band limit");
     const int nchunks = adjoint_chunks_mfma(a.g, a.lmax, MLCR_BF16X3);

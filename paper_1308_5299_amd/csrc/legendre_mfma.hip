@@ -48,6 +48,19 @@ struct Mma<double> {
     static __device__ __forceinline__ double cvt(double v) { return v; }
 };
 
+// complex element of G: float64 pairs on the float64 path, float32 pairs on
+// the mixed path
+template <typename T>
+struct CplxOf;
+template <>
+struct CplxOf<float> {
+    typedef float2 type;
+};
+template <>
+struct CplxOf<double> {
+    typedef double2 type;
+};
+
 // ---------------------------------------------------------------------------
 // adjoint: one workgroup of W waves per (m, chunk of W ring-pair blocks, 8 RHS)
 // ---------------------------------------------------------------------------
@@ -68,7 +81,8 @@ struct Mma<double> {
 // per CU (4 waves per SIMD, registers held to 128).
 template <typename T, int W>
 __global__ __launch_bounds__(64 * W, sizeof(T) == 8 ? 4 : 1) void k_ladj_mfma(
-    const double2 *__restrict__ G, long long fstride, int nrhs, T *__restrict__ P, int lmax,
+    const typename CplxOf<T>::type *__restrict__ G, long long fstride, int nrhs,
+    T *__restrict__ P, int lmax,
     const double *__restrict__ rz, const double *__restrict__ alpha,
     const long long *__restrict__ aboff, const double2 *__restrict__ st,
     const int *__restrict__ stsc, const int *__restrict__ lstab, int nb16, int nrings, int npairs,
@@ -121,15 +135,15 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 8 ? 4 : 1) void k_ladj_mfma(
     // B operands: ring pair 16 kq + g of this block, column jc
     T ge[16], go[16];
     {
-        const double *Gr = reinterpret_cast<const double *>(G + (long long)rB * fstride);
+        const T *Gr = reinterpret_cast<const T *>(G + (long long)rB * fstride);
 #pragma unroll
         for (int g = 0; g < 16; g++) {
             const int p = pb * 64 + 16 * kq + g;
             double gn = 0.0, gs = 0.0;
             if (active && p < npairs) {
                 const int north = p, south = nrings - 1 - p;
-                gn = Gr[((long long)north * ld + m) * 2 + csB];
-                if (south != north) gs = Gr[((long long)south * ld + m) * 2 + csB];
+                gn = (double)Gr[((long long)north * ld + m) * 2 + csB];
+                if (south != north) gs = (double)Gr[((long long)south * ld + m) * 2 + csB];
             }
             ge[g] = M::cvt(gn + gs);
             go[g] = M::cvt(gn - gs);
@@ -313,7 +327,8 @@ int adjoint_chunks_mfma(const mlcr_geom *g, int lmax, int prec) {
 }
 
 template <typename T, int W>
-static int launch_ladj_wg(const LegendreArgs &a, const SegTable *st, const double2 *G, T *P,
+static int launch_ladj_wg(const LegendreArgs &a, const SegTable *st,
+                          const typename CplxOf<T>::type *G, T *P,
                           int nchunks) {
     const mlcr_geom *g = a.g;
     const int npb = (g->npairs + 63) / 64;
@@ -335,7 +350,8 @@ static int launch_ladj_wg(const LegendreArgs &a, const SegTable *st, const doubl
 }
 
 template <typename T>
-static int launch_ladj_t(const LegendreArgs &a, const SegTable *st, const double2 *G, T *P,
+static int launch_ladj_t(const LegendreArgs &a, const SegTable *st,
+                         const typename CplxOf<T>::type *G, T *P,
                          int nchunks, int prec) {
     switch (adjoint_waves(a.g, prec)) {
     case 8: return launch_ladj_wg<T, 8>(a, st, G, P, nchunks);
@@ -346,13 +362,15 @@ static int launch_ladj_t(const LegendreArgs &a, const SegTable *st, const double
 }
 
 // P: double T layout with 8 RHS per chunk
-int launch_legendre_adjoint_mfma(const LegendreArgs &a, const SegTable *st, const double2 *G,
+int launch_legendre_adjoint_mfma(const LegendreArgs &a, const SegTable *st, const void *G,
                                  void *P, int *nchunks_out, bool dbl) {
     if (st->lmax != a.lmax) return fail(MLCR_EINVAL, "start-state table of another band limit");
     const int prec = dbl ? MLCR_FP64 : MLCR_FP32;
     const int nchunks = adjoint_chunks_mfma(a.g, a.lmax, prec);
-    const int rc = dbl ? launch_ladj_t<double>(a, st, G, (double *)P, nchunks, prec)
-                       : launch_ladj_t<float>(a, st, G, (float *)P, nchunks, prec);
+    const int rc = dbl ? launch_ladj_t<double>(a, st, static_cast<const double2 *>(G), (double *)P,
+                                               nchunks, prec)
+                       : launch_ladj_t<float>(a, st, static_cast<const float2 *>(G), (float *)P,
+                                              nchunks, prec);
     if (rc) return rc;
     *nchunks_out = nchunks;
     return MLCR_OK;

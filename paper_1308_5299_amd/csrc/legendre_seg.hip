@@ -113,7 +113,7 @@ __global__ __launch_bounds__(64) void k_seg_init(int lmax, const double *__restr
 //   split bf16: [p][hl][j][8], element e at l = m + 16 q + 2 e + p.
 template <int P, int NB>
 __global__ __launch_bounds__(64) void k_lsynth_seg(
-    const void *__restrict__ Uv, int nrhs, double2 *__restrict__ F, long long fstride, int lmax,
+    const void *__restrict__ Uv, int nrhs, void *__restrict__ F, long long fstride, int lmax,
     const double *__restrict__ rz, const double *__restrict__ alpha,
     const long long *__restrict__ aboff, const double2 *__restrict__ st,
     const int *__restrict__ stsc, const int *__restrict__ lstab, int nrings, int npairs, int nb16,
@@ -298,7 +298,9 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
     const int r = rc * 8 + (jc >> 1), cs = jc & 1;
     const int ld = lmax + 1;
     if (r < nrhs) {
-        double *Fr = reinterpret_cast<double *>(F + (long long)r * fstride);
+        // F: complex float64 on the float64 path, complex float32 on the mixed paths
+        typedef typename std::conditional<P == kSegP64, double, float>::type FO;
+        FO *Fr = reinterpret_cast<FO *>(F) + 2 * (long long)r * fstride;
 #pragma unroll
         for (int nb = 0; nb < NB; nb++)
 #pragma unroll
@@ -308,8 +310,8 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
                 if (p >= npairs) continue;
                 const double e = (double)acc[nb][0][v], o = (double)acc[nb][1][v];
                 const int north = p, south = nrings - 1 - p;
-                Fr[((long long)north * ld + m) * 2 + cs] = e + o;
-                if (south != north) Fr[((long long)south * ld + m) * 2 + cs] = e - o;
+                Fr[((long long)north * ld + m) * 2 + cs] = (FO)(e + o);
+                if (south != north) Fr[((long long)south * ld + m) * 2 + cs] = (FO)(e - o);
             }
     }
 }
@@ -328,7 +330,7 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
 // (wave-uniform).  Work item order as decode_item_m with rc = rw.
 template <int NB, int CB>
 __global__ __launch_bounds__(64) void k_lsynth_b3w(
-    const uint4 *__restrict__ U, int nrhs, double2 *__restrict__ F, long long fstride, int lmax,
+    const uint4 *__restrict__ U, int nrhs, float2 *__restrict__ F, long long fstride, int lmax,
     const double *__restrict__ rz, const double *__restrict__ alpha,
     const long long *__restrict__ aboff, const double2 *__restrict__ st,
     const int *__restrict__ stsc, const int *__restrict__ lstab, int nrings, int npairs, int nb16,
@@ -465,7 +467,7 @@ __global__ __launch_bounds__(64) void k_lsynth_b3w(
     for (int cb = 0; cb < CB; cb++) {
         const int r = (rw * CB + cb) * 8 + (jc >> 1), cs = jc & 1;
         if (cb >= ncb || r >= nrhs) continue;
-        double *Fr = reinterpret_cast<double *>(F + (long long)r * fstride);
+        float *Fr = reinterpret_cast<float *>(F + (long long)r * fstride);
 #pragma unroll
         for (int nb = 0; nb < NB; nb++)
 #pragma unroll
@@ -475,8 +477,8 @@ __global__ __launch_bounds__(64) void k_lsynth_b3w(
                 if (p >= npairs) continue;
                 const double e = (double)acc[cb][nb][0][v], o = (double)acc[cb][nb][1][v];
                 const int north = p, south = nrings - 1 - p;
-                Fr[((long long)north * ld + m) * 2 + cs] = e + o;
-                if (south != north) Fr[((long long)south * ld + m) * 2 + cs] = e - o;
+                Fr[((long long)north * ld + m) * 2 + cs] = (float)(e + o);
+                if (south != north) Fr[((long long)south * ld + m) * 2 + cs] = (float)(e - o);
             }
     }
 }
@@ -617,7 +619,7 @@ int launch_pack_seg(const mlcr_geom *g, int lmax, int nrhs, const double *x, con
     return MLCR_OK;
 }
 
-int launch_legendre_synth_seg(const LegendreArgs &a, const SegTable *t, const void *U, double2 *F,
+int launch_legendre_synth_seg(const LegendreArgs &a, const SegTable *t, const void *U, void *F,
                               int prec) {
     const mlcr_geom *g = a.g;
     if (t->lmax != a.lmax) return fail(MLCR_EINVAL, "segment table of another band limit");
@@ -643,7 +645,8 @@ int launch_legendre_synth_seg(const LegendreArgs &a, const SegTable *t, const vo
         const long long gw = ((tw + 7) / 8) * 8;
 #define MLCR_B3W_LAUNCH(CBV)                                                                     \
     hipLaunchKernelGGL((k_lsynth_b3w<4, CBV>), dim3((unsigned)gw), dim3(64), 0, a.stream,          \
-                       reinterpret_cast<const uint4 *>(U), a.nrhs, F, fstride, a.lmax,               \
+                       reinterpret_cast<const uint4 *>(U), a.nrhs, static_cast<float2 *>(F), fstride, \
+                       a.lmax,                                                                      \
                        g->ring_z.as<double>(), g->alpha.as<double>(), g->aboff.as<long long>(),      \
                        t->st.as<double2>(), t->sc.as<int>(), t->ls.as<int>(), g->nrings, g->npairs,  \
                        nb16, npb, tw)

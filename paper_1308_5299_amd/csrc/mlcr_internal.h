@@ -195,22 +195,25 @@ struct LegendreArgs {
 };
 int launch_legendre_synth(const LegendreArgs &a, const double *u, double2 *F);
 int launch_legendre_adjoint(const LegendreArgs &a, const double2 *G, double *P, int *nchunks_out);
-// prec: FFTs in float32 on the mixed paths (as launch_ring_apply)
-int launch_ring_synth(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, double *map,
+// The Fourier coefficients F and G ([RHS][ring][m]) are complex float64
+// (double2) on the float64 path and complex float32 (float2) on the mixed
+// paths, whose ring FFTs run in float32 (as launch_ring_apply).
+int launch_ring_synth(const mlcr_geom *g, int lmax, int nrhs, const void *F, double *map,
                       int prec, hipStream_t s);
-int launch_ring_adjoint(const mlcr_geom *g, int lmax, int nrhs, const double *map, double2 *G,
+int launch_ring_adjoint(const mlcr_geom *g, int lmax, int nrhs, const double *map, void *G,
                         int prec, hipStream_t s);
 // prec: the arithmetic path; its FFTs run in float32 (LDS buffer and
 // Bluestein filter) on the mixed paths, fold/unfold in float64 always
-int launch_ring_apply(const mlcr_geom *g, int lmax, int nrhs, double2 *FG, const double *ninv,
+int launch_ring_apply(const mlcr_geom *g, int lmax, int nrhs, void *FG, const double *ninv,
                       int prec, hipStream_t s);
 // out[p] = W_ring(p) in[p]: a map times the grid's quadrature weights
 int launch_ring_weight(const mlcr_geom *g, const double *in, double *out, hipStream_t s);
 int adjoint_chunks(const mlcr_geom *g, int lmax);
 // matrix-core Legendre adjoint, 8 RHS per wave; dbl selects float64 MFMA
 // (else float32).
-// P holds float64 partial sums for dbl, float32 otherwise
-int launch_legendre_adjoint_mfma(const LegendreArgs &a, const SegTable *st, const double2 *G,
+// P holds float64 partial sums for dbl, float32 otherwise; G is double2 for
+// dbl, float2 otherwise
+int launch_legendre_adjoint_mfma(const LegendreArgs &a, const SegTable *st, const void *G,
                                  void *P, int *nchunks_out, bool dbl);
 int adjoint_chunks_mfma(const mlcr_geom *g, int lmax, int prec);
 int adjoint_waves(const mlcr_geom *g, int prec);
@@ -223,9 +226,10 @@ int bf16_synth_cols(int nrhs);
 int seg_table(mlcr_geom *g, int lmax, hipStream_t s, const SegTable **out);
 int launch_pack_seg(const mlcr_geom *g, int lmax, int nrhs, const double *x, const double *dl,
                     void *U, int prec, hipStream_t s);
-int launch_legendre_synth_seg(const LegendreArgs &a, const SegTable *t, const void *U, double2 *F,
+// F: double2 for MLCR_FP64, float2 for the mixed paths
+int launch_legendre_synth_seg(const LegendreArgs &a, const SegTable *t, const void *U, void *F,
                               int prec);
-int launch_legendre_adjoint_b3(const LegendreArgs &a, const SegTable *st, const double2 *G,
+int launch_legendre_adjoint_b3(const LegendreArgs &a, const SegTable *st, const float2 *G,
                                float *P, int *nchunks_out);
 // T layout ([RHS chunk][m][l - m][RC][cos, sin]) of the Legendre kernels
 int synth_rc(int nrhs);

@@ -237,12 +237,13 @@ __device__ __forceinline__ void lds_fft(C *buf, int M, bool inverse, const C *__
 }
 
 // Folded, phased coefficient  Hhat_q = sum_{m = q mod N} H_m  for 0 <= q < N.
-__device__ __forceinline__ double2 hhat(const double2 *__restrict__ Fk, int q, int N, int p,
+template <typename FT>
+__device__ __forceinline__ double2 hhat(const FT *__restrict__ Fk, int q, int N, int p,
                                         int lmax, const double2 *__restrict__ TN) {
     double ax = 0.0, ay = 0.0;
     int j = 0;
     for (int m = q; m <= lmax; m += N, j++) {
-        const double2 f = Fk[m];
+        const double2 f = to_d(Fk[m]);
         double w = (m == 0) ? 1.0 : kSqrt2;
         if ((j * p) & 1) w = -w;        // e^{i pi (q + jN) p / N} = e^{i pi q p / N} (-1)^{jp}
         ax = fma(w, f.x, ax);
@@ -254,8 +255,8 @@ __device__ __forceinline__ double2 hhat(const double2 *__restrict__ Fk, int q, i
 // Hhat_q for every q < N (N <= kFoldMax) into hb, all NT threads taking part:
 // G = max(1, NT / N) threads per residue q sum every G-th term of its fold,
 // and the G partial sums are added in a fixed order (deterministic).
-template <int NT>
-__device__ void fold_coop(const double2 *__restrict__ Fk, int N, int p, int lmax,
+template <int NT, typename FT>
+__device__ void fold_coop(const FT *__restrict__ Fk, int N, int p, int lmax,
                           const double2 *__restrict__ TN, double2 *hb, double2 *pb) {
     const int G = N >= NT ? 1 : NT / N;
     for (int t = threadIdx.x; t < G * N; t += NT) {
@@ -263,7 +264,7 @@ __device__ void fold_coop(const double2 *__restrict__ Fk, int N, int p, int lmax
         double ax = 0.0, ay = 0.0;
         int j = g;
         for (int m = q + g * N; m <= lmax; m += G * N, j += G) {
-            const double2 f = Fk[m];
+            const double2 f = to_d(Fk[m]);
             double w = (m == 0) ? 1.0 : kSqrt2;
             if ((j * p) & 1) w = -w;
             ax = fma(w, f.x, ax);
@@ -286,12 +287,12 @@ __device__ __forceinline__ double2 chirp(const double2 *__restrict__ TN, int t, 
 }
 
 // MODE 0: F -> map.  MODE 1: map -> G.  MODE 2: F -> N^-1 map -> G (G over F).
-// C: complex type of the LDS buffer, the FFTs and the Bluestein filter
-// (double2, or float2 for the mixed-precision operator step); the fold and
-// unfold with their phases run in float64 either way.
+// C: complex type of F and G in HBM, of the LDS buffer, the FFTs and the
+// Bluestein filter (double2, or float2 on the mixed-precision paths); the fold
+// and unfold with their phases run in float64 either way.
 template <int MODE, int NT, typename C>
 __global__ __launch_bounds__(NT) void k_ring(
-    const double2 *Fin, double2 *Gout, const double *__restrict__ map_in,
+    const C *Fin, C *Gout, const double *__restrict__ map_in,
     double *__restrict__ map_out, const double *__restrict__ ninv,
     const RingInfo *__restrict__ rings, const LenInfo *__restrict__ lens,
     const int *__restrict__ order, const double2 *__restrict__ T, const C *__restrict__ Bf,
@@ -344,7 +345,7 @@ __global__ __launch_bounds__(NT) void k_ring(
     };
 
     if (MODE != 1) {
-        const double2 *Fk = Fin + (long long)r * fstride + (long long)k * ld;
+        const C *Fk = Fin + (long long)r * fstride + (long long)k * ld;
         if (blue)
             for (int t = n + tid; t < M; t += NT) buf[t] = czero;
         // folded coefficients: in LDS for short rings (hoff: byte offset of
@@ -440,7 +441,7 @@ __global__ __launch_bounds__(NT) void k_ring(
         __syncthreads();
     }
     // unfold: Y_q from the half-length transform, then G_m for m = 0..lmax
-    double2 *Gk = Gout + (long long)r * fstride + (long long)k * ld;
+    C *Gk = Gout + (long long)r * fstride + (long long)k * ld;
     for (int m = tid; m <= lmax; m += NT) {
         const int q = m % N;
         const int kq = q % n;
@@ -453,13 +454,13 @@ __global__ __launch_bounds__(NT) void k_ring(
         const double2 Y = (q < n) ? cadd(E, t) : csub(E, t);
         const double2 V = cmul(TN[(m * p) % (2 * N)], cconj(Y));
         const double w = (m == 0) ? 1.0 : kSqrt2;
-        Gk[m] = make_double2(w * V.x, w * V.y);
+        Gk[m] = to_c<C>(make_double2(w * V.x, w * V.y));
     }
 }
 
 template <int MODE, int NT, typename C>
 static int launch_group(const mlcr_geom *g, const RingGroup &grp, int lmax, int nrhs,
-                        const double2 *F, double2 *G, const double *map_in, double *map_out,
+                        const C *F, C *G, const double *map_in, double *map_out,
                         const double *ninv, long long fstride, const C *Bf, const C *W,
                         hipStream_t s) {
     // FFT buffer, then (groups with short rings, synthesis direction) the
@@ -483,7 +484,7 @@ static int launch_group(const mlcr_geom *g, const RingGroup &grp, int lmax, int 
 // butterfly per thread and radix-8 pass, so a CU holding one 128 KiB float64
 // workgroup still runs 16 waves); the others use 512.
 template <int MODE, typename C>
-static int launch_ring_t(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, double2 *G,
+static int launch_ring_t(const mlcr_geom *g, int lmax, int nrhs, const C *F, C *G,
                          const double *map_in, double *map_out, const double *ninv, const C *Bf,
                          const C *W, int big_nt, hipStream_t s) {
     const long long fstride = (long long)g->nrings * (lmax + 1);
@@ -498,23 +499,27 @@ static int launch_ring_t(const mlcr_geom *g, int lmax, int nrhs, const double2 *
     return MLCR_OK;
 }
 
+// F and G hold complex float64 on the float64 path, complex float32 on the
+// mixed paths (the ring FFTs there run in float32)
 template <int MODE>
-static int launch_ring(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, double2 *G,
+static int launch_ring(const mlcr_geom *g, int lmax, int nrhs, const void *F, void *G,
                        const double *map_in, double *map_out, const double *ninv, int prec,
                        hipStream_t s) {
     const int big_nt = g->tune[prec].ring_threads;
     if (prec != MLCR_FP64)
-        return launch_ring_t<MODE>(g, lmax, nrhs, F, G, map_in, map_out, ninv, g->Bf32.as<float2>(),
-                                   g->W32.as<float2>(), big_nt, s);
-    return launch_ring_t<MODE>(g, lmax, nrhs, F, G, map_in, map_out, ninv, g->Bf.as<double2>(),
-                               g->W.as<double2>(), big_nt, s);
+        return launch_ring_t<MODE>(g, lmax, nrhs, static_cast<const float2 *>(F),
+                                   static_cast<float2 *>(G), map_in, map_out, ninv,
+                                   g->Bf32.as<float2>(), g->W32.as<float2>(), big_nt, s);
+    return launch_ring_t<MODE>(g, lmax, nrhs, static_cast<const double2 *>(F),
+                               static_cast<double2 *>(G), map_in, map_out, ninv,
+                               g->Bf.as<double2>(), g->W.as<double2>(), big_nt, s);
 }
 
-int launch_ring_synth(const mlcr_geom *g, int lmax, int nrhs, const double2 *F, double *map,
+int launch_ring_synth(const mlcr_geom *g, int lmax, int nrhs, const void *F, double *map,
                       int prec, hipStream_t s) {
     return launch_ring<0>(g, lmax, nrhs, F, nullptr, nullptr, map, nullptr, prec, s);
 }
-int launch_ring_adjoint(const mlcr_geom *g, int lmax, int nrhs, const double *map, double2 *G,
+int launch_ring_adjoint(const mlcr_geom *g, int lmax, int nrhs, const double *map, void *G,
                         int prec, hipStream_t s) {
     return launch_ring<1>(g, lmax, nrhs, nullptr, G, map, nullptr, nullptr, prec, s);
 }
@@ -535,7 +540,7 @@ int launch_ring_weight(const mlcr_geom *g, const double *in, double *out, hipStr
     return MLCR_OK;
 }
 
-int launch_ring_apply(const mlcr_geom *g, int lmax, int nrhs, double2 *FG, const double *ninv,
+int launch_ring_apply(const mlcr_geom *g, int lmax, int nrhs, void *FG, const double *ninv,
                       int prec, hipStream_t s) {
     return launch_ring<2>(g, lmax, nrhs, FG, FG, nullptr, nullptr, ninv, prec, s);
 }
