@@ -51,7 +51,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3(
     unsigned char *lam_all = smem + 2 * KG * kChunkM * sizeof(double);
     int m, chunk, rc;
     bool ok;
-    decode_item_m(total, lmax, nchunks, m, chunk, rc, ok);
+    decode_item_m<kGroupF32>(total, lmax, nchunks, m, chunk, rc, ok);
     if (!ok) return;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     float *lam = reinterpret_cast<float *>(lam_all + wv * LSB);
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(64 * W) void k_ladj_b3w(
     unsigned char *lam_all = smem + kChunkM * sizeof(double2);
     int m, chunk, rw;
     bool ok;
-    decode_item_m(total, lmax, nchunks, m, chunk, rw, ok);
+    decode_item_m<kGroupF32>(total, lmax, nchunks, m, chunk, rw, ok);
     if (!ok) return;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     float *lam = reinterpret_cast<float *>(lam_all + wv * LSB);
@@ -444,7 +444,7 @@ static int launch_ladj_b3_w(const LegendreArgs &a, const SegTable *st, const flo
     const mlcr_geom *g = a.g;
     const int npb = (g->npairs + 63) / 64;
     const int nrc = (a.nrhs + 7) / 8;
-    const long long total = mitems(a.lmax, nchunks, nrc);
+    const long long total = mitems<kGroupF32>(a.lmax, nchunks, nrc);
     const long long grid = ((total + 7) / 8) * 8;
     const long long fstride = (long long)g->nrings * (a.lmax + 1);
     constexpr int KG = W < 2 ? 1 : 4;           // tiles per chunk sum
@@ -466,7 +466,7 @@ static int launch_ladj_b3w(const LegendreArgs &a, const SegTable *st, const floa
     const int npb = (g->npairs + 63) / 64;
     const int nrc = (a.nrhs + 7) / 8;
     const int nrw = (nrc + CB - 1) / CB;
-    const long long total = mitems(a.lmax, nchunks, nrw);
+    const long long total = mitems<kGroupF32>(a.lmax, nchunks, nrw);
     const long long grid = ((total + 7) / 8) * 8;
     const long long fstride = (long long)g->nrings * (a.lmax + 1);
     const size_t lds = kChunkM * sizeof(double2) + (size_t)W * (32 * 68 * 4);

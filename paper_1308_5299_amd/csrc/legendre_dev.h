@@ -42,37 +42,43 @@ __device__ __forceinline__ void seed_lambda_m(double s, int m, double c, double 
     }
 }
 
-// Work item w = ((rc * ng + gi) * npb + pb) * 8 + mo, order m = 8 g + mo in
-// groups g of 8 consecutive orders (ng = ceil((lmax + 1) / 8) groups, items
-// past lmax exit at once).  The 8 orders of a group run side by side and
-// share the 128-byte lines of F and G (16 B per order, ring and RHS), which
-// are then fetched or written once; the ring-pair blocks of one order stay
-// close and share its coefficients and U rows through L2.  Each XCD
-// (workgroup id mod 8) gets one contiguous run of items; groups are visited
-// 0, ng-1, 1, ng-2, ... so every run holds the same mix of long and short
-// orders.
+// Work item w = ((rc * ng + gi) * npb + pb) * GO + mo, order m = GO g + mo in
+// groups g of GO consecutive orders (ng = ceil((lmax + 1) / GO) groups, items
+// past lmax exit at once).  The GO orders of a group run side by side and
+// share the 128-byte lines of F and G (16 B per order, ring and RHS on the
+// float64 path, GO = 8; 8 B on the mixed paths, GO = 16), which are then
+// fetched or written once; the ring-pair blocks of one order stay close and
+// share its coefficients and U rows through L2.  Each XCD (workgroup id mod
+// 8) gets one contiguous run of items; groups are visited 0, ng-1, 1, ng-2,
+// ... so every run holds the same mix of long and short orders.
+template <int GO = 8>
 __host__ __device__ inline long long mitems(int lmax, int npb, int nrc) {
-    return (long long)((lmax + 8) / 8) * 8 * npb * nrc;
+    return (long long)((lmax + GO) / GO) * GO * npb * nrc;
 }
 
+template <int GO = 8>
 __device__ __forceinline__ void decode_item_m(long long total, int lmax, int npb, int &m, int &pb,
                                               int &rc, bool &ok) {
+    static_assert((GO & (GO - 1)) == 0, "orders per group: a power of two");
     const long long b = blockIdx.x;
     const long long per = (total + 7) / 8;
     const long long w = (b & 7) * per + (b >> 3);
     ok = w < total;
     if (!ok) return;
-    const int ng = (lmax + 8) / 8;
-    const int mo = (int)(w & 7);
-    long long rest = w >> 3;
+    const int ng = (lmax + GO) / GO;
+    const int mo = (int)(w & (GO - 1));
+    long long rest = w / GO;
     pb = (int)(rest % npb);
     rest /= npb;
     const int gi = (int)(rest % ng);
     rc = (int)(rest / ng);
     const int g = (gi & 1) ? (ng - 1 - (gi >> 1)) : (gi >> 1);
-    m = 8 * g + mo;
+    m = GO * g + mo;
     ok = m <= lmax;
 }
+
+// orders per work group: 16 when F / G hold complex float32 (mixed paths)
+constexpr int kGroupF64 = 8, kGroupF32 = 16;
 
 __device__ __forceinline__ long long tri_off_m(int m, int lmax) {
     return (long long)m * (lmax + 1) - (long long)m * (m - 1) / 2;

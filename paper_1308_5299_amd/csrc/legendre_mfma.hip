@@ -102,7 +102,7 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 8 ? 4 : 1) void k_ladj_mfma(
     T *lam_all = reinterpret_cast<T *>(smem + 2 * KG * kChunkM * sizeof(double));
     int m, chunk, rc;
     bool ok;
-    decode_item_m(total, lmax, nchunks, m, chunk, rc, ok);
+    decode_item_m<sizeof(T) == 8 ? kGroupF64 : kGroupF32>(total, lmax, nchunks, m, chunk, rc, ok);
     if (!ok) return;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     T *lam = lam_all + wv * LS;
@@ -333,7 +333,7 @@ static int launch_ladj_wg(const LegendreArgs &a, const SegTable *st,
     const mlcr_geom *g = a.g;
     const int npb = (g->npairs + 63) / 64;
     const int nrc = (a.nrhs + 7) / 8;
-    const long long total = mitems(a.lmax, nchunks, nrc);
+    const long long total = mitems<sizeof(T) == 8 ? kGroupF64 : kGroupF32>(a.lmax, nchunks, nrc);
     const long long grid = ((total + 7) / 8) * 8;
     const long long fstride = (long long)g->nrings * (a.lmax + 1);
     constexpr int KG = W < 2 ? 1 : (sizeof(T) == 8 ? 2 : 4);     // tiles per chunk sum

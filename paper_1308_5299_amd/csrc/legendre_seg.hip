@@ -126,7 +126,7 @@ __global__ __launch_bounds__(64) void k_lsynth_seg(
     __shared__ double sab[4 * CS];
     int m, pb, rc;
     bool ok;
-    decode_item_m(total, lmax, npb * NH, m, pb, rc, ok);
+    decode_item_m<P == kSegP64 ? kGroupF64 : kGroupF32>(total, lmax, npb * NH, m, pb, rc, ok);
     if (!ok) return;
     const int g0 = (pb % NH) * NB;              // first 16-pair group of the block
     pb /= NH;
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(64) void k_lsynth_b3w(
     __shared__ double sab[4 * CS];
     int m, pb, rw;
     bool ok;
-    decode_item_m(total, lmax, npb * NH, m, pb, rw, ok);
+    decode_item_m<kGroupF32>(total, lmax, npb * NH, m, pb, rw, ok);
     if (!ok) return;
     const int g0 = (pb % NH) * NB;
     pb /= NH;
@@ -627,7 +627,8 @@ int launch_legendre_synth_seg(const LegendreArgs &a, const SegTable *t, const vo
     const int npb = (g->npairs + 63) / 64;
     const int nrc = (a.nrhs + 7) / 8;
     const int nb = g->tune[prec].synth_chains;          // chains per lane: 4 or 2
-    const long long total = mitems(a.lmax, npb * (4 / nb), nrc);
+    const long long total = prec == MLCR_FP64 ? mitems<kGroupF64>(a.lmax, npb * (4 / nb), nrc)
+                                              : mitems<kGroupF32>(a.lmax, npb * (4 / nb), nrc);
     const long long grid = ((total + 7) / 8) * 8;
     const long long fstride = (long long)g->nrings * (a.lmax + 1);
 #define MLCR_SEG_ARGS                                                                           \
@@ -641,7 +642,7 @@ int launch_legendre_synth_seg(const LegendreArgs &a, const SegTable *t, const vo
     if (prec == MLCR_BF16X3 && cbw > 1) {
         // CB column blocks per wave share each lambda (two chains per lane)
         const int nrw = (nrc + cbw - 1) / cbw;
-        const long long tw = mitems(a.lmax, npb, nrw);
+        const long long tw = mitems<kGroupF32>(a.lmax, npb, nrw);
         const long long gw = ((tw + 7) / 8) * 8;
 #define MLCR_B3W_LAUNCH(CBV)                                                                     \
     hipLaunchKernelGGL((k_lsynth_b3w<4, CBV>), dim3((unsigned)gw), dim3(64), 0, a.stream,          \
