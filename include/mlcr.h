@@ -50,7 +50,7 @@ enum {
     MLCR_EHIP = -3,         /* HIP runtime error                                   */
     MLCR_ENOTPD = -4,       /* Cholesky of a matrix that is not positive definite  */
     MLCR_ENOCONV = -5,      /* solver did not reach the tolerance                  */
-    MLCR_EUNSUPPORTED = -6  /* valid request this build does not implement        */
+    MLCR_EUNSUPPORTED = -6  /* valid request the library does not implement      */
 };
 
 /* Arithmetic of the Legendre contraction:
