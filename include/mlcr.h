@@ -289,8 +289,10 @@ typedef struct {
  *                diagonal correction, or NULL for 1 - f~^0_l (0 above lmax[0]
  *                taken as f~ = 0).
  *   gl_levels    1: a coarse level evaluates Y^T N^-1 Y on a Gauss-Legendre
- *                grid when that grid is smaller than the observation grid
- *                (Sec. 3.4); 0: always on the observation grid.
+ *                grid (Sec. 3.4) when 2 lmax_h <= lmax, the grid's rings
+ *                are at most 16384 pixels long, and it has fewer rings and at
+ *                most twice the pixels of the observation grid; 0: always on
+ *                the observation grid.
  *   smoother     the pixel levels' error smoother (Sec. 3.5), on the pattern of
  *                8 x 8 tiles and their neighbour tiles:
  *                0  the blocks of Y_h A_h Y_h^T read off the operator by
