@@ -247,13 +247,33 @@ def roofline(kernels, cfg, R, path: str):
     return roof
 
 
+def level_profile(S, b, prec):
+    """Per-level time of one W-cycle (mlcr_solver_profile): profiles of a
+    3-cycle and a 1-cycle solve, halved difference, so that the starting
+    residual drops out and the top level holds the cycle's float64 residual.
+    Rows: top, pixel levels, dense bottom; columns: applications of A_h,
+    level SHTs (Y_h), smoother (dense solve at the bottom), transfers."""
+    runs = {}
+    for n in (1, 3):
+        S.set_profile(True)
+        S.solve(b, rtol=0.0, max_cycles=n, prec=prec, raise_on_noconv=False)
+        runs[n] = S.profile()
+        S.set_profile(False)
+    ms = (runs[3]["ms"] - runs[1]["ms"]) / 2
+    calls = (runs[3]["calls"] - runs[1]["calls"]) // 2
+    return {"kinds": ["A_h", "level SHTs", "smoother", "transfers"],
+            "ms_per_cycle": [[round(float(v), 3) for v in row] for row in ms],
+            "calls_per_cycle": [[int(v) for v in row] for row in calls],
+            "cycle_ms": round(float(ms.sum()), 2)}
+
+
 def solve_bench(mlcr, torch, cfg, geom, op, xt, R, paths, max_cycles, target=1e-3, pcg=False,
-                graph=False):
+                graph=False, levels=False):
     """W-cycle solves of b = A x_true (x_true ~ N(0, S), b by the float64
     apply); cycle by cycle, the max pixel error |Y (x - x_true)| (float64
     synthesis, all pixels) until every RHS is within `target` uK.  Reports
-    the time to get there per path (setup excluded) and the speedup of each
-    path over float64."""
+    the time to get there per path (setup excluded), the speedup of each
+    path over float64 and, if asked, the per-level time of one cycle."""
     precs = {"fp64": mlcr.FP64, "fp32": mlcr.FP32, "bf16x3": mlcr.BF16X3}
     t0 = time.time()
     S = mlcr.Solver(op, max_nrhs=R)
@@ -307,6 +327,13 @@ def solve_bench(mlcr, torch, cfg, geom, op, xt, R, paths, max_cycles, target=1e-
         S.set_graph(False)
         out["paths"][p] = {"time_s": times[False] if ok else None, "cycles": nc, "reached": ok,
                            "history": hist}
+        if levels:
+            lv = level_profile(S, b, precs[p])
+            out["paths"][p]["levels"] = lv
+            log(f"[bench] {p}: per-level ms per cycle (A_h, SHTs, smoother, transfers), "
+                f"cycle {lv['cycle_ms']} ms:")
+            for h, (row, cr) in enumerate(zip(lv["ms_per_cycle"], lv["calls_per_cycle"])):
+                log(f"[bench]   level {h}: {row}  calls {cr}")
         if graph:
             out["paths"][p]["graph_time_s"] = times[True] if ok else None
             out["paths"][p]["graph_stats"] = S.graph_stats()
@@ -473,6 +500,8 @@ def main():
                     help="with --solve: also time whole solves with the cycle replayed from a HIP graph")
     ap.add_argument("--pcg", action="store_true",
                     help="with --solve: also time CG with the cycle as preconditioner")
+    ap.add_argument("--levels", action="store_true",
+                    help="with --solve: also the per-level time of one W-cycle per path")
     ap.add_argument("--mixed", action="store_true",
                     help="time the mixed batch of independent problems solved one after another "
                          "and as one grouped solve")
@@ -533,7 +562,8 @@ def main():
 
     if args.solve:
         print(json.dumps(solve_bench(mlcr, torch, cfg, geom, op, x, R, paths, args.max_cycles,
-                                     pcg=args.pcg, graph=args.graph)), flush=True)
+                                     pcg=args.pcg, graph=args.graph, levels=args.levels)),
+              flush=True)
         return
 
     res, outs, tuned = {}, {}, {}
