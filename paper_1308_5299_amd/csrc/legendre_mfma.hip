@@ -161,17 +161,26 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 8 ? 4 : 1) void k_ladj_mfma(
     double cpre = coef_at(t0);
     if ((int)threadIdx.x < KG * kChunkM) sab[threadIdx.x] = cpre;
     if (t0 + KG < ntile) cpre = coef_at(t0 + KG);
+    // the block's recurrence start state, read once here so that no global
+    // load is pending inside the tile loop
+    double2 s0 = make_double2(0.0, 0.0);
+    int sc0 = 1;
+    if (active && tw < ntile) {
+        const long long tix = ((long long)m * nb16 + 4 * pb + (lane >> 4)) * 64 + (lane & 15);
+        s0 = st[tix];
+        sc0 = stsc[tix];
+    }
+    __builtin_amdgcn_s_waitcnt(0x0f70);         // vmcnt(0): G, the start state, coefficients
     __syncthreads();
     for (int tg = t0; tg < ntile; tg += KG) {
-        // coefficients of group gi in buffer gi & 1; those of group gi + 1 go
-        // to the other buffer, whose last readers (group gi - 1) are past the
-        // barriers that ended the previous group
+        // Coefficients of group gi sit in buffer gi & 1.  Those of group gi + 1
+        // (loaded during group gi - 1's stores) go to the other buffer once this
+        // group's tiles are done, before the first barrier: that buffer's last
+        // readers (group gi - 1) are past the barriers that ended it, and by
+        // then the load and the stores issued before it have long completed,
+        // so the wait for it costs nothing.
         const int gi = (tg - t0) / KG;
         const double *sbg = sab + (gi & 1) * KG * kChunkM;
-        if (tg + KG < ntile) {
-            if ((int)threadIdx.x < KG * kChunkM) sab[((gi + 1) & 1) * KG * kChunkM + threadIdx.x] = cpre;
-            if (tg + 2 * KG < ntile) cpre = coef_at(tg + 2 * KG);
-        }
         typename M::acc DEg[KG], DOg[KG];
 #pragma unroll
         for (int j = 0; j < KG; j++) {
@@ -180,11 +189,9 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 8 ? 4 : 1) void k_ladj_mfma(
             typename M::acc DE = M::zero(), DO = DE;
             if (t < ntile) {
                 if (t == tw) {
-                    const long long tix = ((long long)m * nb16 + 4 * pb + (lane >> 4)) * 64 + (lane & 15);
-                    const double2 s0 = st[tix];
                     L.l1 = s0.x;
                     L.l2 = s0.y;
-                    L.sc = stsc[tix];
+                    L.sc = sc0;
                     mode = wave_mode1(L);
                 }
                 if (mode <= 0) {
@@ -290,6 +297,12 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 8 ? 4 : 1) void k_ladj_mfma(
                 lam[j * 512 + (2 * i + 1) * 16 + jc] = DOg[j][v];
             }
         }
+        // on every path: the coefficient load and the previous group's stores
+        // are retired here, one group after they were issued, so that neither
+        // the write below nor the next load waits on the stores issued next
+        __builtin_amdgcn_s_waitcnt(0x0f70);     // vmcnt(0)
+        if (tg + KG < ntile && (int)threadIdx.x < KG * kChunkM)
+            sab[((gi + 1) & 1) * KG * kChunkM + threadIdx.x] = cpre;
         __syncthreads();
         // sum the W tiles; one store per output
         for (int o = threadIdx.x; o < 512 * KG; o += 64 * W) {
@@ -301,6 +314,8 @@ __global__ __launch_bounds__(64 * W, sizeof(T) == 8 ? 4 : 1) void k_ladj_mfma(
             for (int w = 0; w < W; w++) a += lam_all[w * LS + o];
             Pm[(long long)lb * 16 + (o & 15)] = a;
         }
+        // group gi + 2's coefficients, issued after this group's stores
+        if (tg + 2 * KG < ntile) cpre = coef_at(tg + 2 * KG);
         __syncthreads();        // the tiles are read before the next lambdas overwrite them
     }
 }
