@@ -416,7 +416,9 @@ int mlcr_solver_top_dinv(const mlcr_solver *s, double *dev_out, void *stream);
  * float32 cycle is iterative refinement.
  *   dev_b, dev_x: [nrhs][(lmax+1)^2] packed; dev_x holds the start vector
  *   on entry (zeros allowed) and the solution on return.  Excluded modes of
- *   x are set to 0.  host_info: [nrhs] or NULL.
+ *   x are set to 0.  When the start vector is zero for every RHS the start
+ *   residual is b itself and no operator application is made for it.
+ *   host_info: [nrhs] or NULL.
  * Returns MLCR_ENOCONV (x and info still valid) if rtol is not reached. */
 int wcycle_solve(mlcr_solver *s, int nrhs, const double *dev_b, double *dev_x, double rtol,
                  int max_cycles, int prec, mlcr_solve_info *host_info, void *stream);

@@ -1361,12 +1361,34 @@ struct SolveRun {
             out[r] = hn[2 * r + 1] > 0 ? std::sqrt(hn[2 * r] / hn[2 * r + 1]) : 0.0;
         return MLCR_OK;
     }
+    // The start: x holds the start vector (excluded modes projected out).  Its
+    // S^-1 norms decide whether r = b - A x needs the operator: from x = 0
+    // (every RHS) the residual is b itself and the float64 apply is skipped.
+    // Three steps so that a group of solves enqueues each step for all its
+    // problems before waiting on any.
     int enqueue_start() {
         int rc;
-        // x holds the start vector; excluded modes are projected out
         if ((rc = launch_residual(x, nullptr, x, S->top_act.as<double>(), S->op->lmax, nrhs, s)))
             return rc;
-        return enqueue_residual();
+        if ((rc = launch_wnorms(x, nullptr, S->sinv.as<double>(), S->op->lmax, nrhs,
+                                S->partial.as<double>(), S->norms.as<double>(), s)))
+            return rc;
+        MLCR_HIP_CHECK(hipMemcpyAsync(hn.data(), S->norms.ptr, 2 * nrhs * sizeof(double),
+                                      hipMemcpyDeviceToHost, s));
+        return MLCR_OK;
+    }
+    int enqueue_start_residual() {
+        MLCR_HIP_CHECK(hipStreamSynchronize(s));
+        bool xzero = true;
+        for (int r = 0; r < nrhs; r++) xzero = xzero && hn[2 * r] == 0.0;
+        if (!xzero) return enqueue_residual();
+        int rc;
+        mlcr_op *op = S->op;
+        if ((rc = launch_residual(b, nullptr, S->ro.as<double>(), S->top_act.as<double>(), op->lmax,
+                                  nrhs, s)))
+            return rc;
+        return launch_wnorms(S->ro.as<double>(), b, S->sinv.as<double>(), op->lmax, nrhs,
+                             S->partial.as<double>(), S->norms.as<double>(), s);
     }
     int finish_start() {
         int rc;
@@ -1513,7 +1535,8 @@ int wcycle_solve(mlcr_solver *S, int nrhs, const double *b, double *x, double rt
     }
     {
         SolveRun run(S, nrhs, b, x, rtol, prec, s);
-        if (!(rc = run.enqueue_start()) && !(rc = run.finish_start()))
+        if (!(rc = run.enqueue_start()) && !(rc = run.enqueue_start_residual()) &&
+            !(rc = run.finish_start()))
             while (!run.all && run.it < max_cycles)
                 if ((rc = run.enqueue_cycle()) || (rc = run.finish_cycle())) break;
         if (!rc) rc = run.finish(info);
@@ -1565,6 +1588,8 @@ int wcycle_solve_grouped(int nprob, mlcr_solver *const *S, const int *nrhs, cons
     for (auto &r : runs)
         if (!rc) rc = r->enqueue_start();
     for (auto &r : runs)
+        if (!rc) rc = r->enqueue_start_residual();
+    for (auto &r : runs)
         if (!rc) rc = r->finish_start();
     for (int c = 0; c < max_cycles && !rc; c++) {
         bool any = false;
@@ -1609,7 +1634,9 @@ int pcg_solve(mlcr_solver *S, int nrhs, const double *b, double *x, double rtol,
         S->pcg_coef.reserve(4 * (size_t)S->max_nrhs * sizeof(double)))
         return fail(MLCR_ENOMEM, "conjugate-gradient workspace allocation failed");
     SolveRun run(S, nrhs, b, x, rtol, prec, s);
-    if ((rc = run.enqueue_start()) || (rc = run.finish_start())) return rc;
+    if ((rc = run.enqueue_start()) || (rc = run.enqueue_start_residual()) ||
+        (rc = run.finish_start()))
+        return rc;
     double *r = S->ro.as<double>(), *q = S->to.as<double>(), *z = S->x0.as<double>();
     double *p = S->pcg_p.as<double>(), *zo = S->pcg_zo.as<double>();
     double *al = S->pcg_coef.as<double>(), *be = al + S->max_nrhs;

@@ -172,14 +172,22 @@ def test_solver_profile_counts(mlcr):
     calls, ms = prof["calls"], prof["ms"]
     H = plan["nlevels"]
     assert calls.shape == (H + 2, 4)
-    # A_h applications (the start residual adds one top apply)
-    want_apply = counts[:, 1].copy()
-    want_apply[0] += 1
-    np.testing.assert_array_equal(calls[:, 0], want_apply)
+    # A_h applications: from x = 0 the start residual is b itself, no apply
+    np.testing.assert_array_equal(calls[:, 0], counts[:, 1])
     np.testing.assert_array_equal(calls[1:H + 1, 1], counts[1:H + 1, 2])      # level transforms
     np.testing.assert_array_equal(calls[:, 2], counts[:, 3])                  # smoother / bottom
     assert np.all(ms[calls > 0] > 0)
     print("per-level ms [apply, transforms, smoother, transfer]:\n", np.round(ms, 3), flush=True)
+    # from a nonzero start the start residual takes one float64 apply at the top
+    S.set_profile(True)
+    x2, info2 = S.solve(dev(b[None]), x0=x, rtol=0.0, max_cycles=1, raise_on_noconv=False)
+    calls2 = S.profile()["calls"]
+    S.set_profile(False)
+    counts1 = mlcr.cycle_counts(plan["nrec"], plan["nrec_top"], 1)
+    assert calls2[0, 0] == counts1[0, 1] + 1
+    np.testing.assert_array_equal(calls2[1:, 0], counts1[1:, 1])
+    # and it continues the first solve: its start residual is the first solve's last
+    assert abs(info2[0]["rho0"] - info[0]["rho"]) <= 1e-12 * info[0]["rho0"]
 
 
 def test_set_prior_and_band_gradient(mlcr):
