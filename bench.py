@@ -44,25 +44,25 @@ DEFAULT_PATHS = "fp32,bf16x3,fp64"
 # counters were taken are listed (a changed kernel reports traffic null).
 # Key: (library timer name, Legendre path, workload, RHS per launch).
 MEASURED_TRAFFIC = {
-    ("legendre_adjoint", "fp32", "c5", 8): 4.921e9 + 4.304e9,
-    ("legendre_adjoint", "bf16x3", "c5", 8): 4.914e9 + 4.301e9,
-    ("legendre_adjoint", "fp64", "c5", 8): 9.090e9 + 8.596e9,
-    ("legendre_synth", "fp32", "c5", 8): 10.455e9 + 9.065e9,
-    ("legendre_synth", "bf16x3", "c5", 8): 6.721e9 + 5.001e9,
-    ("legendre_synth", "fp64", "c5", 8): 16.386e9 + 9.931e9,
-    ("ring_apply", "fp32", "c5", 8): 1.215e9 + 0.537e9 + 3 * (0.718e9 + 0.537e9),
-    ("ring_apply", "bf16x3", "c5", 8): 1.215e9 + 0.537e9 + 3 * (0.718e9 + 0.537e9),
-    ("ring_apply", "fp64", "c5", 8): 1.772e9 + 1.074e9 + 3 * (1.284e9 + 1.075e9),
+    ("legendre_adjoint", "fp32", "c5", 8): 4.919e9 + 4.303e9,
+    ("legendre_adjoint", "bf16x3", "c5", 8): 4.932e9 + 4.301e9,
+    ("legendre_adjoint", "fp64", "c5", 8): 9.106e9 + 8.596e9,
+    ("legendre_synth", "fp32", "c5", 8): 10.441e9 + 9.056e9,
+    ("legendre_synth", "bf16x3", "c5", 8): 6.720e9 + 4.995e9,
+    ("legendre_synth", "fp64", "c5", 8): 16.365e9 + 9.934e9,
+    ("ring_apply", "fp32", "c5", 8): 1.216e9 + 0.537e9 + 3 * (0.718e9 + 0.537e9),
+    ("ring_apply", "bf16x3", "c5", 8): 1.219e9 + 0.537e9 + 3 * (0.718e9 + 0.537e9),
+    ("ring_apply", "fp64", "c5", 8): 1.772e9 + 1.074e9 + 3 * (1.285e9 + 1.075e9),
 }
 # Matrix-core busy fraction (SQ_VALU_MFMA_BUSY_CYCLES over 1024 SIMDs x
 # 2.4 GHz x duration) of the same kernels, from
 # profiles/legendre_c5_r8_mfma_counters.md; kernels changed since are absent.
 MEASURED_MFMA_BUSY = {
-    ("legendre_synth", "fp32", "c5", 8): 0.406,
-    ("legendre_adjoint", "fp32", "c5", 8): 0.357,
-    ("legendre_synth", "bf16x3", "c5", 8): 0.121,
-    ("legendre_adjoint", "bf16x3", "c5", 8): 0.090,
-    ("legendre_synth", "fp64", "c5", 8): 0.560,
+    ("legendre_synth", "fp32", "c5", 8): 0.404,
+    ("legendre_adjoint", "fp32", "c5", 8): 0.353,
+    ("legendre_synth", "bf16x3", "c5", 8): 0.119,
+    ("legendre_adjoint", "bf16x3", "c5", 8): 0.089,
+    ("legendre_synth", "fp64", "c5", 8): 0.551,
     ("legendre_adjoint", "fp64", "c5", 8): 0.372,
 }
 
